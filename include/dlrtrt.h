@@ -1,0 +1,160 @@
+/*
+ * dlrtrt -- SN-like dynamic low-rank (DLR) gray thermal radiative transfer on
+ * 2D structured meshes, HIP library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Haut, Loffeld, Einkemmer, Guthrey, Brunner, Schill, "Efficient SN-like
+ * and PN-like Dynamic Low Rank methods for Thermal Radiative Transfer",
+ * arXiv 2601.18705.  One call of dlr_step advances the state by one backward-
+ * Euler step of Algorithm 1 (Sec. 4.3): Newton-linearised emission (Sec. 2.2),
+ * DEIM angle selection on the angular basis W (Sec. 4.2), source iteration with
+ * upwind sweeps over the r selected directions (eq. "steady state collocation"),
+ * Gram-Schmidt of the swept columns into X, the Galerkin L-step for every
+ * ordinate (eq. "L step"), orthonormalisation L = S W, an SVD of S that orders
+ * the angular modes, and the temperature update (eq. "temperature update").
+ *
+ * Discretisation (the lowest-order member of the upwind DG family of Sec. 4.4):
+ * nx x ny uniform cells, cell e = j*nx + i, one value per cell and ordinate.
+ * Ordinates: product of n_polar Gauss-Legendre polar cosines on (0,1) (upper
+ * hemisphere, xy symmetry) and n_azim azimuths (2k-1) pi / n_azim; weights sum to
+ * 4 pi; ordinate index q = p*n_azim + k.  Planck function B(T) = a c T^4 / (4 pi).
+ *
+ * Conventions for every call:
+ *  - No C++ exception crosses this interface; every call returns dlr_status and
+ *    leaves a human-readable detail in dlr_last_error() (thread-local).
+ *  - All host pointers are caller-owned; the library copies what it keeps.
+ *  - Device work runs on the HIP stream given at creation.  Calls on one handle
+ *    must be serialised by the caller; distinct handles are independent.
+ *  - Arrays are row-major; per-cell arrays follow e = j*nx + i.
+ */
+#ifndef DLRTRT_H
+#define DLRTRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DLR_ABI_VERSION 1
+
+typedef enum {
+    DLR_OK = 0,
+    DLR_ERR_ARG = -1,            /* invalid argument or shape */
+    DLR_ERR_OOM = -2,            /* device memory exhausted (batch: retry later) */
+    DLR_ERR_HIP = -3,            /* a HIP runtime call failed */
+    DLR_ERR_NOT_CONVERGED = -4,  /* source iteration reached si_max_iter */
+    DLR_ERR_NONFINITE = -5,      /* NaN/Inf in the mean intensity or temperature */
+    DLR_ERR_STATE = -6,          /* handle poisoned by an earlier device error */
+    DLR_ERR_UNSUPPORTED = -7,    /* option not available on the GPU path */
+    DLR_ERR_NUMERIC = -8         /* numerically rank-deficient factor (QR breakdown) */
+} dlr_status;
+
+enum { DLR_BC_VACUUM = 0, DLR_BC_INFLOW = 1, DLR_BC_REFLECT = 2 };
+
+/* Arithmetic of the step.  Selection (DEIM), QR, SVD, the L-step solves, the
+ * temperature update and all conservation sums are FP64 in every mode. */
+enum {
+    DLR_FP64 = 0,                 /* sweeps and projections in FP64 */
+    DLR_FP32_SWEEP = 1,           /* sweeps and projections in FP32 (FP64 accumulation of sums) */
+    DLR_FP32_SWEEP_BF16_PROJ = 2  /* FP32 sweeps, BF16 projection operands, FP32 accumulation */
+};
+
+/*
+ * Problem statement (Sec. 2.1-2.2 of the paper, gray TRT):
+ *   (1/c) d psi/dt + Omega . grad psi + sigma psi = sigma B(T) + q_ext/(4 pi)
+ *   rho c_v dT/dt = sigma (phi - 4 pi B(T)),  phi = int psi dOmega
+ * with opacity and heat capacity frozen at their given values.
+ *  sigma_a, rho_cv, T_init: [ny*nx], required, sigma_a > 0, rho_cv > 0, T_init >= 0.
+ *  q_ext: [ny*nx] or NULL (zero); an isotropic source integrated over angle.
+ *  bc[side], side = 0 left, 1 right, 2 bottom, 3 top: DLR_BC_VACUUM or
+ *  DLR_BC_INFLOW (isotropic inflow B(T_b[side])).  DLR_BC_REFLECT is
+ *  rejected with DLR_ERR_UNSUPPORTED (reference checks only).
+ *  rank: 1 <= rank <= min(n_polar*n_azim, nx*ny, 64).  n_azim % 4 == 0.
+ *  si_tol: relative 2-norm change of phi that ends source iteration.
+ *  deim_tie_tol: DEIM picks among |R| >= (1 - tol) max|R| go to the smallest index.
+ * Initial state: psi = B(T_init) isotropic (rank one), completed by graded
+ * monomials in space (cell centres mapped to [-1,1]^2) and angle (mu, eta).
+ */
+typedef struct {
+    int32_t abi_version;          /* must be DLR_ABI_VERSION */
+    int32_t nx, ny;
+    double x0, x1, y0, y1;
+    int32_t n_polar, n_azim, rank;
+    double dt, c, a;
+    const double *sigma_a, *rho_cv, *q_ext, *T_init;
+    int32_t bc[4];
+    double T_b[4];
+    int32_t precision;            /* DLR_FP64 / DLR_FP32_SWEEP / DLR_FP32_SWEEP_BF16_PROJ */
+    double si_tol;
+    int32_t si_max_iter;
+    double deim_tie_tol;
+} dlr_problem;
+
+typedef struct dlr_instance *dlr_handle;
+
+/* Per-step diagnostics of the most recent step (FP64). */
+typedef struct {
+    int64_t steps_done;           /* steps completed since create / load */
+    int32_t si_iters;             /* source iterations of the last step */
+    int32_t rank;
+    double si_residual;           /* last relative ||phi_k+1 - phi_k||_2 / ||phi_k+1||_2 */
+    double deim_min_margin;       /* smallest relative margin of a DEIM pick (1 = no competitor) */
+    double sum_abs_cw_over_4pi;   /* sum |c_d| / (4 pi) of the DEIM quadrature weights */
+    double energy;                /* sum over cells of area * (rho c_v T + phi / c) */
+    double sweep_ms;              /* device time in the sweep kernels of the last step */
+    double step_ms;               /* device time of the whole last step */
+} dlr_step_stats;
+
+/* Create an instance: validates the problem, copies fields to the device and
+ * builds the initial factors.  hip_stream: a hipStream_t or NULL (default
+ * stream).  Errors: DLR_ERR_ARG (shape/values), DLR_ERR_UNSUPPORTED
+ * (reflecting walls), DLR_ERR_OOM, DLR_ERR_HIP.  *out is NULL on error. */
+dlr_status dlr_create(const dlr_problem *prob, void *hip_stream, dlr_handle *out);
+
+/* Advance n_steps >= 0 time steps (Algorithm 1).  Errors detected on the
+ * device (non-convergence, non-finite values, rank breakdown) poison the
+ * handle: this call and every later one except reads of the last good state
+ * return the error or DLR_ERR_STATE. */
+dlr_status dlr_step(dlr_handle h, int32_t n_steps);
+
+/* Wait for all work queued on the handle's stream. */
+dlr_status dlr_sync(dlr_handle h);
+
+/* Radiation energy density E_r = phi / c and material temperature T, [ny*nx]
+ * each (caller-allocated; either may be NULL).  Synchronises the stream. */
+dlr_status dlr_read_fields(dlr_handle h, double *E_r, double *T);
+
+/* Low-rank factors psi = X S W^T with <X_i, X_j> = delta_ij (cell-area
+ * weighted), sum_q w_q W_qi W_qj = delta_ij and S = diag(sigma) descending:
+ * X [ny*nx][rank], S [rank][rank], W [n_polar*n_azim][rank], sel [rank] = the
+ * DEIM ordinates of the last step (-1 before the first step).  Any pointer may be NULL. */
+dlr_status dlr_read_factors(dlr_handle h, double *X, double *S, double *W, int32_t *sel);
+
+/* Replace the state (same layouts as dlr_read_factors; S may be any r x r
+ * matrix); resets steps_done.  For checkpoint/resume. */
+dlr_status dlr_load_factors(dlr_handle h, const double *X, const double *S, const double *W,
+                            const double *T);
+
+/* Diagnostics of the last step. */
+dlr_status dlr_read_stats(dlr_handle h, dlr_step_stats *out);
+
+/* Replay hook for parity checks: the next dlr_step uses these rank ordinate
+ * indices instead of its own DEIM picks (one step only).  sel: [rank] distinct
+ * indices in [0, n_polar*n_azim); NULL clears a pending override. */
+dlr_status dlr_force_selection(dlr_handle h, const int32_t *sel);
+
+/* Free everything.  NULL-safe. */
+dlr_status dlr_destroy(dlr_handle h);
+
+/* Static description of a status code. */
+const char *dlr_status_string(dlr_status s);
+
+/* Detail of the most recent error on the calling thread ("" if none). */
+const char *dlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLRTRT_H */

@@ -1,0 +1,668 @@
+// C-ABI of the dlrtrt library (include/dlrtrt.h) and the host orchestration of
+// one SN-like DLR time step (Algorithm 1 of the paper) as a sequence of HIP
+// kernel launches on the instance's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dlrtrt.h"
+#include "dlr_internal.h"
+#include "host_setup.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dlr_status fail(dlr_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// One device allocation carved into 256-byte aligned pieces.
+struct Arena {
+    char* base = nullptr;
+    size_t used = 0, cap = 0;
+    template <typename T>
+    T* take(size_t count) {
+        const size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
+        if (base == nullptr) {   // sizing pass
+            used += bytes;
+            return nullptr;
+        }
+        if (used + bytes > cap) throw HipError("arena overflow");
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+}  // namespace
+
+struct dlr_instance {
+    // ---- problem (host copies)
+    int nx = 0, ny = 0, N = 0, npol = 0, naz = 0, nq = 0, r = 0, prec = 0;
+    double x0 = 0, x1 = 0, y0 = 0, y1 = 0, hx = 0, hy = 0, area = 0, dt = 0, c = 0, a = 0;
+    double si_tol = 0, tie = 0;
+    int si_max_iter = 0;
+    int bc[4] = {0, 0, 0, 0};
+    double Tb[4] = {0, 0, 0, 0}, psib[4] = {0, 0, 0, 0};
+    bool has_qext = false;
+    hipStream_t stream = nullptr;
+    std::vector<double> h_mu, h_eta, h_w;
+    // ---- status
+    bool poisoned = false;
+    dlr_status poison_code = DLR_OK;
+    bool s_is_usigma = false;   // S columns are U_k sigma_k (true after a step)
+    bool have_sel = false;
+    bool force_pending = false;
+    int64_t steps_done = 0;
+    dlr_step_stats stats{};
+    // ---- device memory
+    Arena arena;
+    double *mu = nullptr, *eta = nullptr, *w = nullptr;
+    double *sigma = nullptr, *rho_cv = nullptr, *q_ext = nullptr, *T = nullptr;
+    double *D = nullptr, *sig_s = nullptr, *q = nullptr, *sig_t = nullptr;
+    float* sig_t32 = nullptr;
+    double *X = nullptr, *Xn = nullptr, *Xt = nullptr;
+    double *S = nullptr, *Sn = nullptr;
+    double *W = nullptr, *Wt = nullptr, *Wq = nullptr, *L = nullptr;
+    void *psi = nullptr, *src0 = nullptr, *s_e = nullptr;
+    double *phi = nullptr, *phi2 = nullptr;
+    int *sel = nullptr, *forced = nullptr;
+    double *cw = nullptr, *C0 = nullptr, *a0 = nullptr, *margins = nullptr, *sel_mu = nullptr, *sel_eta = nullptr;
+    double *inflow_x = nullptr, *inflow_y = nullptr, *deim_work = nullptr;
+    void* edge = nullptr;
+    unsigned long long* progress = nullptr;
+    unsigned* ticket = nullptr;
+    unsigned long long launch_id = 0;
+    int nstrips = 0;
+    double* partials = nullptr;
+    size_t partials_count = 0;
+    double* norm_out = nullptr;
+    double* energy_out = nullptr;
+    unsigned* counters = nullptr;
+    double *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
+    double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
+    double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr;
+    int* status = nullptr;
+    // pinned host mirrors
+    double* h_norm = nullptr;
+    int* h_status = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // launch shapes
+    int nb_cells = 256, nb_gram = 256, nb_proj = 256, red_blocks = 64;
+
+    bool fp32() const { return prec != DLR_FP64; }
+    size_t sweep_bytes() const { return fp32() ? sizeof(float) : sizeof(double); }
+
+    void carve(Arena& A) {
+        const size_t n = (size_t)N, R = (size_t)r, Q = (size_t)nq;
+        mu = A.take<double>(Q);
+        eta = A.take<double>(Q);
+        w = A.take<double>(Q);
+        sigma = A.take<double>(n);
+        rho_cv = A.take<double>(n);
+        q_ext = has_qext ? A.take<double>(n) : nullptr;
+        T = A.take<double>(n);
+        D = A.take<double>(n);
+        sig_s = A.take<double>(n);
+        q = A.take<double>(n);
+        sig_t = A.take<double>(n);
+        sig_t32 = fp32() ? A.take<float>(n) : nullptr;
+        X = A.take<double>(R * n);
+        Xn = A.take<double>(R * n);
+        Xt = A.take<double>(R * n);
+        S = A.take<double>(R * R);
+        Sn = A.take<double>(R * R);
+        W = A.take<double>(R * Q);
+        Wt = A.take<double>(R * Q);
+        Wq = A.take<double>(R * Q);
+        L = A.take<double>(R * Q);
+        psi = A.take<char>(R * n * sweep_bytes());
+        src0 = A.take<char>(R * n * sweep_bytes());
+        s_e = A.take<char>(n * sweep_bytes());
+        phi = A.take<double>(n);
+        phi2 = A.take<double>(n);
+        sel = A.take<int>(R);
+        forced = A.take<int>(R);
+        cw = A.take<double>(R);
+        C0 = A.take<double>(R * R);
+        a0 = A.take<double>(R);
+        margins = A.take<double>(R);
+        sel_mu = A.take<double>(R);
+        sel_eta = A.take<double>(R);
+        inflow_x = A.take<double>(R);
+        inflow_y = A.take<double>(R);
+        deim_work = A.take<double>(R * Q);
+        edge = A.take<char>(R * (size_t)nstrips * ny * sweep_bytes());
+        progress = A.take<unsigned long long>(R * (size_t)nstrips);
+        ticket = A.take<unsigned>(4);
+        partials = A.take<double>(partials_count);
+        norm_out = A.take<double>(4);
+        energy_out = A.take<double>(2);
+        counters = A.take<unsigned>(8);
+        R1 = A.take<double>(R * R);
+        R1i = A.take<double>(R * R);
+        R2 = A.take<double>(R * R);
+        R2i = A.take<double>(R * R);
+        ops = A.take<double>(12 * R * R + 10 * R);
+        Binv = A.take<double>(Q * R * R);
+        yv = A.take<double>(Q * R);
+        red = A.take<double>((size_t)red_blocks * (R * R + R));
+        vv = A.take<double>(R);
+        Vsvd = A.take<double>(R * R);
+        beta = A.take<double>(R);
+        coef = A.take<double>(R);
+        status = A.take<int>(4);
+    }
+};
+
+namespace {
+
+dlr_status validate(const dlr_problem* p) {
+    if (!p) return fail(DLR_ERR_ARG, "problem is NULL");
+    if (p->abi_version != DLR_ABI_VERSION) return fail(DLR_ERR_ARG, "abi_version mismatch");
+    if (p->nx < 1 || p->ny < 1) return fail(DLR_ERR_ARG, "nx, ny must be >= 1");
+    if ((long long)p->nx * p->ny > (1LL << 30)) return fail(DLR_ERR_ARG, "grid too large");
+    if (!(p->x1 > p->x0) || !(p->y1 > p->y0)) return fail(DLR_ERR_ARG, "empty domain");
+    if (p->n_polar < 1 || p->n_azim < 4 || p->n_azim % 4 != 0)
+        return fail(DLR_ERR_ARG, "n_polar >= 1 and n_azim a positive multiple of 4 required");
+    const long long nq = (long long)p->n_polar * p->n_azim;
+    if (nq > 16384) return fail(DLR_ERR_ARG, "at most 16384 ordinates");
+    const long long ncell = (long long)p->nx * p->ny;
+    if (p->rank < 1 || p->rank > dlr::kMaxRank || p->rank > nq || p->rank > ncell)
+        return fail(DLR_ERR_ARG, "rank must satisfy 1 <= rank <= min(64, ordinates, cells)");
+    if (!(p->dt > 0) || !(p->c > 0) || !(p->a >= 0) || !std::isfinite(p->dt) || !std::isfinite(p->c) ||
+        !std::isfinite(p->a))
+        return fail(DLR_ERR_ARG, "dt, c > 0 and a >= 0 required");
+    if (!p->sigma_a || !p->rho_cv || !p->T_init) return fail(DLR_ERR_ARG, "sigma_a, rho_cv, T_init required");
+    for (long long e = 0; e < ncell; ++e) {
+        if (!(p->sigma_a[e] > 0) || !std::isfinite(p->sigma_a[e])) return fail(DLR_ERR_ARG, "sigma_a must be > 0");
+        if (!(p->rho_cv[e] > 0) || !std::isfinite(p->rho_cv[e])) return fail(DLR_ERR_ARG, "rho_cv must be > 0");
+        if (!(p->T_init[e] >= 0) || !std::isfinite(p->T_init[e])) return fail(DLR_ERR_ARG, "T_init must be >= 0");
+        if (p->q_ext && (!(p->q_ext[e] >= 0) || !std::isfinite(p->q_ext[e])))
+            return fail(DLR_ERR_ARG, "q_ext must be >= 0");
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc[s] == DLR_BC_REFLECT)
+            return fail(DLR_ERR_UNSUPPORTED, "reflecting walls are not available on the GPU path");
+        if (p->bc[s] != DLR_BC_VACUUM && p->bc[s] != DLR_BC_INFLOW) return fail(DLR_ERR_ARG, "unknown bc");
+        if (!(p->T_b[s] >= 0) || !std::isfinite(p->T_b[s])) return fail(DLR_ERR_ARG, "T_b must be >= 0");
+    }
+    if (p->precision == DLR_FP32_SWEEP_BF16_PROJ)
+        return fail(DLR_ERR_UNSUPPORTED, "BF16 projections are not available in this build");
+    if (p->precision != DLR_FP64 && p->precision != DLR_FP32_SWEEP) return fail(DLR_ERR_ARG, "unknown precision");
+    if (!(p->si_tol > 0) || p->si_max_iter < 1) return fail(DLR_ERR_ARG, "si_tol > 0 and si_max_iter >= 1");
+    if (!(p->deim_tie_tol >= 0) || !(p->deim_tie_tol < 1)) return fail(DLR_ERR_ARG, "0 <= deim_tie_tol < 1");
+    return DLR_OK;
+}
+
+template <typename TS>
+dlr_status step_once(dlr_instance* I);
+
+dlr_status check_device_status(dlr_instance* I) {
+    hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, I->stream), "status copy");
+    hip_check(hipStreamSynchronize(I->stream), "stream sync");
+    const int st = *I->h_status;
+    if (st == 0) return DLR_OK;
+    std::string m = "device status";
+    dlr_status code = DLR_ERR_NUMERIC;
+    if (st & dlr::kStatusNonfinite) { m += " non-finite"; code = DLR_ERR_NONFINITE; }
+    if (st & dlr::kStatusQrBreakdownX) m += " spatial-QR-breakdown";
+    if (st & dlr::kStatusQrBreakdownW) m += " angular-QR-breakdown";
+    if (st & dlr::kStatusSingularSolve) m += " singular-solve";
+    if (st & dlr::kStatusSvdNoConv) m += " svd-not-converged";
+    if (st & dlr::kStatusSweepStall) m += " sweep-wait-stalled";
+    if (st & dlr::kStatusNoCompletion) m += " no-completion-vector";
+    if (st & dlr::kStatusBadForcedSel) { m += " bad-forced-selection"; code = DLR_ERR_ARG; }
+    I->poisoned = true;
+    I->poison_code = code;
+    return fail(code, m);
+}
+
+template <typename TS>
+dlr_status step_once(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    const int N = I->N, r = I->r, nq = I->nq;
+    const double cdt = I->c * I->dt;
+    TS* psi = static_cast<TS*>(I->psi);
+    TS* src0 = static_cast<TS*>(I->src0);
+    TS* s_e = static_cast<TS*>(I->s_e);
+    hip_check(hipEventRecord(I->ev[0], s), "event");
+
+    // 1. effective scattering and source
+    dlr::launch_linearize(s, N, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s, I->q,
+                          I->sig_t, I->sig_t32);
+    // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
+    dlr::DeimArgs da{};
+    da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
+    da.forced = I->force_pending ? I->forced : nullptr;
+    da.work = I->deim_work; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
+    da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
+    da.mu = I->mu; da.eta = I->eta;
+    for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];
+    da.status = I->status;
+    dlr::launch_deim(s, da);
+    I->force_pending = false;
+    // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
+    dlr::launch_psi0<TS>(s, N, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, src0, I->phi, s_e);
+    // 4. source iteration with sweeps
+    dlr::SweepArgs<TS> sa{};
+    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nstrips = I->nstrips; sa.total_units = I->nstrips * r;
+    sa.src0 = src0; sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
+    sa.s_e = s_e; sa.psi = psi; sa.mu = I->sel_mu; sa.eta = I->sel_eta;
+    sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
+    sa.inv_hx = 1.0 / I->hx; sa.inv_hy = 1.0 / I->hy;
+    sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress; sa.ticket = I->ticket;
+    sa.grid_waves = std::min(sa.total_units, 4096);
+    sa.status = I->status;
+    sa.spin_limit = 1u << 20;
+    double* phi_cur = I->phi;
+    double* phi_nxt = I->phi2;
+    int it = 0;
+    bool conv = false;
+    float sweep_ms = 0.f;
+    for (it = 1; it <= I->si_max_iter; ++it) {
+        sa.launch_id = ++I->launch_id;
+        hip_check(hipEventRecord(I->ev[2], s), "event");
+        dlr::launch_sweep<TS>(s, sa);
+        hip_check(hipEventRecord(I->ev[3], s), "event");
+        dlr::launch_phi<TS>(s, N, r, psi, I->cw, I->sig_s, phi_cur, phi_nxt, s_e, I->partials, I->nb_cells,
+                            I->counters + 0, I->norm_out);
+        std::swap(phi_cur, phi_nxt);
+        hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
+        hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        if (*I->h_status != 0) return check_device_status(I);
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+        sweep_ms += ms;
+        const double rel = I->h_norm[2];
+        if (!std::isfinite(rel)) {
+            I->poisoned = true;
+            I->poison_code = DLR_ERR_NONFINITE;
+            return fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
+        }
+        I->stats.si_residual = rel;
+        if (rel <= I->si_tol) { conv = true; break; }
+    }
+    if (phi_cur != I->phi) std::swap(I->phi, I->phi2);
+    if (!conv) {
+        I->poisoned = true;
+        I->poison_code = DLR_ERR_NOT_CONVERGED;
+        return fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
+    }
+    const dlr_status ds = check_device_status(I);   // DEIM status before using its output further
+    if (ds != DLR_OK) return ds;
+
+    // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
+    dlr::launch_gram<TS>(s, N, r, psi, nullptr, I->area, I->partials, I->nb_gram);
+    dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_trmm<TS>(s, N, r, psi, I->R1i, I->Xt);
+    dlr::launch_gram<double>(s, N, r, I->Xt, nullptr, I->area, I->partials, I->nb_gram);
+    dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_trmm<double>(s, N, r, I->Xt, I->R2i, I->Xn);
+    // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
+    dlr::launch_cgs2<TS>(s, N, r, psi, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn, I->R1, I->status,
+                         dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
+    // 6-7. projections on the new basis and the L-step for every ordinate
+    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->area, I->hx, I->hy, I->partials,
+                        I->nb_proj);
+    dlr::launch_project_finalize(s, r, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops);
+    dlr::LstepArgs la{};
+    la.nq = nq; la.r = r; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;
+    la.inv_cdt = 1.0 / cdt;
+    for (int k = 0; k < 4; ++k) la.psib[k] = I->psib[k];
+    la.Binv = I->Binv; la.y = I->yv; la.red_partials = I->red; la.red_blocks = I->red_blocks; la.v = I->vv;
+    la.L = I->L; la.status = I->status;
+    dlr::launch_lstep(s, la);
+    // 8. L = W S^T in the quadrature inner product (CGS2 with angular completion), then the SVD of S
+    dlr::launch_cgs2<double>(s, nq, r, I->L, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->R2, nullptr, 0,
+                             I->status, dlr::kStatusNoCompletion);
+    dlr::launch_svd(s, r, I->R2, I->Vsvd, I->Sn, I->status);
+    dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
+    dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef);
+    // 9. temperature update with the mean intensity of the new factors
+    dlr::launch_tupdate(s, N, r, I->Xn, I->coef, I->sigma, I->rho_cv, I->D, I->dt, I->a, I->c, I->area, I->T, I->phi,
+                        I->partials, I->nb_cells, I->counters + 1, I->energy_out, I->status);
+    std::swap(I->X, I->Xn);
+    std::swap(I->S, I->Sn);
+    hip_check(hipEventRecord(I->ev[1], s), "event");
+    const dlr_status st = check_device_status(I);
+    if (st != DLR_OK) return st;
+    double en = 0.0;
+    hip_check(hipMemcpy(&en, I->energy_out, sizeof(double), hipMemcpyDeviceToHost), "energy copy");
+    std::vector<double> marg(r);
+    hip_check(hipMemcpy(marg.data(), I->margins, r * sizeof(double), hipMemcpyDeviceToHost), "margin copy");
+    std::vector<double> cwv(r);
+    hip_check(hipMemcpy(cwv.data(), I->cw, r * sizeof(double), hipMemcpyDeviceToHost), "cw copy");
+    float step_ms = 0.f;
+    hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
+    I->stats.si_iters = it;
+    I->stats.energy = en;
+    I->stats.deim_min_margin = *std::min_element(marg.begin(), marg.end());
+    double sa_ = 0.0;
+    for (double v : cwv) sa_ += std::fabs(v);
+    I->stats.sum_abs_cw_over_4pi = sa_ / dlr::kFourPi;
+    I->stats.sweep_ms = sweep_ms;
+    I->stats.step_ms = step_ms;
+    I->s_is_usigma = true;
+    I->have_sel = true;
+    ++I->steps_done;
+    I->stats.steps_done = I->steps_done;
+    return DLR_OK;
+}
+
+void upload(void* dst, const void* src, size_t bytes) { hip_check(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "upload"); }
+void download(void* dst, const void* src, size_t bytes) {
+    hip_check(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "download");
+}
+
+// Mean intensity of the current factors, for E_r before the first step / after a load.
+void refresh_phi_host(dlr_instance* I) {
+    const size_t n = I->N, R = I->r, Q = I->nq;
+    std::vector<double> X(R * n), S(R * R), W(R * Q);
+    download(X.data(), I->X, X.size() * sizeof(double));
+    download(S.data(), I->S, S.size() * sizeof(double));
+    download(W.data(), I->W, W.size() * sizeof(double));
+    std::vector<double> beta(R, 0.0), cf(R, 0.0), phi(n, 0.0);
+    for (size_t k = 0; k < R; ++k)
+        for (size_t q = 0; q < Q; ++q) beta[k] += I->h_w[q] * W[k * Q + q];
+    for (size_t i = 0; i < R; ++i)
+        for (size_t j = 0; j < R; ++j) cf[i] += S[i * R + j] * beta[j];
+    for (size_t k = 0; k < R; ++k)
+        for (size_t e = 0; e < n; ++e) phi[e] += X[k * n + e] * cf[k];
+    upload(I->phi, phi.data(), n * sizeof(double));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dlr_status_string(dlr_status s) {
+    switch (s) {
+        case DLR_OK: return "ok";
+        case DLR_ERR_ARG: return "invalid argument";
+        case DLR_ERR_OOM: return "out of device memory";
+        case DLR_ERR_HIP: return "HIP runtime error";
+        case DLR_ERR_NOT_CONVERGED: return "source iteration did not converge";
+        case DLR_ERR_NONFINITE: return "non-finite values";
+        case DLR_ERR_STATE: return "handle poisoned by an earlier error";
+        case DLR_ERR_UNSUPPORTED: return "unsupported option";
+        case DLR_ERR_NUMERIC: return "numerical breakdown";
+    }
+    return "unknown status";
+}
+
+const char* dlr_last_error(void) { return g_last_error.c_str(); }
+
+dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
+    if (!out) return fail(DLR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    g_last_error.clear();
+    const dlr_status v = validate(p);
+    if (v != DLR_OK) return v;
+    dlr_instance* I = new (std::nothrow) dlr_instance();
+    if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
+    try {
+        I->nx = p->nx; I->ny = p->ny; I->N = p->nx * p->ny; I->npol = p->n_polar; I->naz = p->n_azim;
+        I->nq = p->n_polar * p->n_azim; I->r = p->rank; I->prec = p->precision;
+        I->x0 = p->x0; I->x1 = p->x1; I->y0 = p->y0; I->y1 = p->y1;
+        I->hx = (p->x1 - p->x0) / p->nx; I->hy = (p->y1 - p->y0) / p->ny; I->area = I->hx * I->hy;
+        I->dt = p->dt; I->c = p->c; I->a = p->a;
+        I->si_tol = p->si_tol; I->si_max_iter = p->si_max_iter; I->tie = p->deim_tie_tol;
+        for (int k = 0; k < 4; ++k) {
+            I->bc[k] = p->bc[k];
+            I->Tb[k] = p->T_b[k];
+            const double t = p->T_b[k];
+            I->psib[k] = (p->bc[k] == DLR_BC_INFLOW) ? p->a * p->c * t * t * t * t / dlr::kFourPi : 0.0;
+        }
+        I->has_qext = p->q_ext != nullptr;
+        I->stream = static_cast<hipStream_t>(hip_stream);
+        I->nstrips = (I->nx + 63) / 64;
+        const size_t rr = (size_t)I->r * I->r;
+        I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
+                                      (size_t)I->nb_cells * 2});
+        dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
+        Arena sizing;
+        I->carve(sizing);
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        if (sizing.used + (64u << 20) > free_b) {
+            delete I;
+            return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
+        }
+        hipError_t e = hipMalloc(&I->arena.base, sizing.used);
+        if (e != hipSuccess) {
+            delete I;
+            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        I->arena.cap = sizing.used;
+        I->carve(I->arena);
+        hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
+        hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, sizeof(int), hipHostMallocDefault), "pinned");
+        for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
+        const size_t n = I->N;
+        upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
+        upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
+        upload(I->w, I->h_w.data(), I->nq * sizeof(double));
+        upload(I->sigma, p->sigma_a, n * sizeof(double));
+        upload(I->rho_cv, p->rho_cv, n * sizeof(double));
+        if (p->q_ext) upload(I->q_ext, p->q_ext, n * sizeof(double));
+        upload(I->T, p->T_init, n * sizeof(double));
+        dlr::ProblemHost ph{I->nx, I->ny, I->r, I->hx, I->hy, I->a, I->c, p->T_init};
+        std::vector<double> X, S, W;
+        dlr::build_initial_factors(ph, I->h_mu, I->h_eta, I->h_w, X, S, W);
+        upload(I->X, X.data(), X.size() * sizeof(double));
+        upload(I->S, S.data(), S.size() * sizeof(double));
+        upload(I->W, W.data(), W.size() * sizeof(double));
+        refresh_phi_host(I);
+        I->s_is_usigma = true;   // S = diag(s, 0, ...)
+        hip_check(hipDeviceSynchronize(), "sync");
+    } catch (const std::exception& ex) {
+        dlr_destroy(I);
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    *out = I;
+    return DLR_OK;
+}
+
+dlr_status dlr_step(dlr_handle h, int32_t n_steps) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (n_steps < 0) return fail(DLR_ERR_ARG, "n_steps must be >= 0");
+    if (h->poisoned) return fail(DLR_ERR_STATE, std::string("handle poisoned: ") + dlr_status_string(h->poison_code));
+    try {
+        for (int k = 0; k < n_steps; ++k) {
+            const dlr_status st = h->fp32() ? step_once<float>(h) : step_once<double>(h);
+            if (st != DLR_OK) return st;
+        }
+    } catch (const std::exception& ex) {
+        h->poisoned = true;
+        h->poison_code = DLR_ERR_HIP;
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_sync(dlr_handle h) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(DLR_ERR_HIP, hipGetErrorString(e));
+    return DLR_OK;
+}
+
+dlr_status dlr_read_fields(dlr_handle h, double* E_r, double* T) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    try {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        if (E_r) {
+            download(E_r, h->phi, (size_t)h->N * sizeof(double));
+            for (int e = 0; e < h->N; ++e) E_r[e] /= h->c;
+        }
+        if (T) download(T, h->T, (size_t)h->N * sizeof(double));
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, int32_t* selo) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    try {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const size_t n = h->N, R = h->r, Q = h->nq;
+        std::vector<double> X(R * n), S(R * R), W(R * Q);
+        download(X.data(), h->X, X.size() * sizeof(double));
+        download(S.data(), h->S, S.size() * sizeof(double));
+        download(W.data(), h->W, W.size() * sizeof(double));
+        std::vector<double> U(R * R, 0.0), sig(R, 0.0);
+        if (h->s_is_usigma) {
+            // S holds U Sigma column-wise: sigma_k = ||S_k||, U_k = S_k / sigma_k; zero
+            // columns are completed with unit vectors orthogonalised against the others.
+            for (size_t k = 0; k < R; ++k) {
+                double s2 = 0.0;
+                for (size_t i = 0; i < R; ++i) s2 += S[i * R + k] * S[i * R + k];
+                sig[k] = std::sqrt(s2);
+                if (sig[k] > 0.0)
+                    for (size_t i = 0; i < R; ++i) U[i * R + k] = S[i * R + k] / sig[k];
+            }
+            for (size_t k = 0; k < R; ++k) {
+                if (sig[k] > 0.0) continue;
+                for (size_t cand = 0; cand < R; ++cand) {
+                    std::vector<double> v(R, 0.0);
+                    v[cand] = 1.0;
+                    for (int pass = 0; pass < 2; ++pass)
+                        for (size_t j = 0; j < R; ++j) {
+                            if (j == k || (sig[j] == 0.0 && j > k)) continue;
+                            double d = 0.0;
+                            for (size_t i = 0; i < R; ++i) d += U[i * R + j] * v[i];
+                            for (size_t i = 0; i < R; ++i) v[i] -= d * U[i * R + j];
+                        }
+                    double nv = 0.0;
+                    for (double x : v) nv += x * x;
+                    nv = std::sqrt(nv);
+                    if (nv > 1e-8) {
+                        for (size_t i = 0; i < R; ++i) U[i * R + k] = v[i] / nv;
+                        break;
+                    }
+                }
+            }
+        } else {
+            for (size_t k = 0; k < R; ++k) U[k * R + k] = 1.0;
+        }
+        if (Xo)
+            for (size_t e = 0; e < n; ++e)
+                for (size_t k = 0; k < R; ++k) {
+                    double s = 0.0;
+                    for (size_t j = 0; j < R; ++j) s += X[j * n + e] * U[j * R + k];
+                    Xo[e * R + k] = s;
+                }
+        if (So)
+            for (size_t i = 0; i < R; ++i)
+                for (size_t j = 0; j < R; ++j) So[i * R + j] = h->s_is_usigma ? (i == j ? sig[i] : 0.0) : S[i * R + j];
+        if (Wo)
+            for (size_t qq = 0; qq < Q; ++qq)
+                for (size_t k = 0; k < R; ++k) Wo[qq * R + k] = W[k * Q + qq];
+        if (selo) {
+            if (h->have_sel) {
+                std::vector<int> sv(R);
+                download(sv.data(), h->sel, R * sizeof(int));
+                for (size_t k = 0; k < R; ++k) selo[k] = sv[k];
+            } else {
+                for (size_t k = 0; k < R; ++k) selo[k] = -1;
+            }
+        }
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, const double* Wi, const double* Ti) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (!Xi || !Si || !Wi || !Ti) return fail(DLR_ERR_ARG, "X, S, W and T are required");
+    try {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const size_t n = h->N, R = h->r, Q = h->nq;
+        std::vector<double> X(R * n), W(R * Q);
+        for (size_t e = 0; e < n; ++e)
+            for (size_t k = 0; k < R; ++k) X[k * n + e] = Xi[e * R + k];
+        for (size_t qq = 0; qq < Q; ++qq)
+            for (size_t k = 0; k < R; ++k) W[k * Q + qq] = Wi[qq * R + k];
+        upload(h->X, X.data(), X.size() * sizeof(double));
+        upload(h->S, Si, R * R * sizeof(double));
+        upload(h->W, W.data(), W.size() * sizeof(double));
+        upload(h->T, Ti, n * sizeof(double));
+        refresh_phi_host(h);
+        hip_check(hipDeviceSynchronize(), "sync");
+        h->s_is_usigma = false;
+        h->have_sel = false;
+        h->poisoned = false;
+        h->poison_code = DLR_OK;
+        h->steps_done = 0;
+        h->stats = dlr_step_stats{};
+        int zero = 0;
+        upload(h->status, &zero, sizeof(int));
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_read_stats(dlr_handle h, dlr_step_stats* out) {
+    if (!h || !out) return fail(DLR_ERR_ARG, "NULL argument");
+    *out = h->stats;
+    out->steps_done = h->steps_done;
+    out->rank = h->r;
+    return DLR_OK;
+}
+
+dlr_status dlr_force_selection(dlr_handle h, const int32_t* selv) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (!selv) {
+        h->force_pending = false;
+        return DLR_OK;
+    }
+    std::vector<char> seen(h->nq, 0);
+    for (int k = 0; k < h->r; ++k) {
+        if (selv[k] < 0 || selv[k] >= h->nq || seen[selv[k]]) return fail(DLR_ERR_ARG, "invalid forced selection");
+        seen[selv[k]] = 1;
+    }
+    try {
+        upload(h->forced, selv, h->r * sizeof(int));
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    h->force_pending = true;
+    return DLR_OK;
+}
+
+dlr_status dlr_destroy(dlr_handle h) {
+    if (!h) return DLR_OK;
+    if (h->stream || h->arena.base) (void)hipStreamSynchronize(h->stream);
+    for (auto& ev : h->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->h_norm) (void)hipHostFree(h->h_norm);
+    if (h->h_status) (void)hipHostFree(h->h_status);
+    if (h->arena.base) (void)hipFree(h->arena.base);
+    delete h;
+    return DLR_OK;
+}
+
+}  // extern "C"

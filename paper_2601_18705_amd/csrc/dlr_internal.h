@@ -1,0 +1,160 @@
+// Internal declarations of the dlrtrt HIP library (gfx950).
+//
+// Storage layout on the device (one instance):
+//   per-cell fields          [N] float64, N = nx*ny, e = j*nx + i
+//   spatial basis X          [r][N] float64 (column k of X contiguous)
+//   swept columns Psi, src0  [r][N] in the sweep precision (double or float)
+//   angular basis W, L       [r][nq] float64 (column k contiguous over ordinates)
+//   coupling S               [r][r] float64, row-major S[i*r + j]
+// The state is psi = X S W^T with X, W orthonormal; S is kept as a general
+// r x r matrix (the SVD rotation of the angular modes is applied to W and S
+// only, which leaves psi and X unchanged).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dlr {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kFourPi = 4.0 * kPi;
+constexpr int kMaxRank = 64;
+constexpr int kSweepChunk = 32;   // rows published per edge-flag update in the sweep
+
+// ----------------------------------------------------------------------------- per-cell kernels
+void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
+                      const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
+                      double* sig_t, float* sig_t32);
+
+template <typename TS>
+void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0,
+                 const double* q, const double* sig_s, double inv_cdt, TS* src0, double* phi, TS* s_e);
+
+template <typename TS>
+void launch_phi(hipStream_t s, int n, int r, const TS* psi, const double* cw, const double* sig_s,
+                const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks,
+                unsigned* counter, double* out);
+
+void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
+                    const double* rho_cv, const double* D, double dt, double a, double c, double area,
+                    double* T, double* phi, double* partials, int nblocks, unsigned* counter, double* out,
+                    int* status);
+
+// ----------------------------------------------------------------------------- sweep
+template <typename TS>
+struct SweepArgs {
+    int nx, ny, nd, nstrips, total_units;
+    const TS* src0;      // [nd][N] fixed source q + psi0 / (c dt)
+    const TS* sig_t;     // [N]
+    const TS* s_e;       // [N] sigma_s phi / (4 pi)
+    TS* psi;             // [nd][N]
+    const double* mu;    // [nd] direction cosines of the swept directions
+    const double* eta;   // [nd]
+    const double* inflow_x;  // [nd] isotropic inflow on the x-inflow face (0 = vacuum)
+    const double* inflow_y;  // [nd]
+    double inv_hx, inv_hy;
+    TS* edge;                        // [nd][nstrips][ny] outgoing x-face values of each strip
+    unsigned long long* progress;    // [nd][nstrips] (launch << 32) | rows published
+    unsigned* ticket;                // [2] work ticket, retired waves
+    unsigned long long launch_id;
+    int grid_waves;
+    int* status;                     // kStatusSweepStall is raised if a wait exceeds spin_limit polls
+    unsigned spin_limit;
+};
+template <typename TS>
+void launch_sweep(hipStream_t s, const SweepArgs<TS>& a);
+
+// ----------------------------------------------------------------------------- reductions
+template <typename TV>
+void launch_gram(hipStream_t s, int n, int r, const TV* V, const double* weight, double scalar_weight,
+                 double* partials, int nblocks);
+void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,
+                 int* status, int status_code);
+template <typename TV>
+void launch_trmm(hipStream_t s, int n, int r, const TV* V, const double* Rinv, double* X);
+
+struct ProjectOut {
+    // raw sums (split-K partials reduced by launch_project_finalize)
+    double* partials;   // [nblocks][5 r^2 + 5 r]
+    int nblocks;
+};
+void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
+                    const double* sig_s, const double* q, double area, double hx, double hy, double* partials,
+                    int nblocks);
+// Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r]
+void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
+                             double inv_cdt, const double* S0, double* ops);
+
+// ----------------------------------------------------------------------------- small dense FP64 work
+struct DeimArgs {
+    int nq, r;
+    const double* W;       // [r][nq]
+    const double* S;       // [r][r]
+    const double* w;       // [nq]
+    double tie_tol;
+    const int* forced;     // [r] or nullptr
+    double* work;          // [r][nq] scratch
+    int* sel;              // [r]
+    double* cw;            // [r]
+    double* C0;            // [r][r]  C0[k*r + d] = sum_j S[k][j] W[j][sel_d]
+    double* a0;            // [r]     S beta
+    double* margins;       // [r]
+    double* sel_mu;        // [r]
+    double* sel_eta;       // [r]
+    double* inflow_x;      // [r]
+    double* inflow_y;      // [r]
+    const double* mu;      // [nq]
+    const double* eta;     // [nq]
+    double psib[4];        // inflow intensity per side (0 for vacuum)
+    int* status;
+};
+void launch_deim(hipStream_t s, const DeimArgs& a);
+
+struct LstepArgs {
+    int nq, r;
+    const double* mu;
+    const double* eta;
+    const double* w;
+    const double* ops;     // layout of launch_project_finalize
+    const double* W0;      // [r][nq] old angular basis
+    double inv_cdt;
+    double psib[4];        // inflow intensity per side (0 when not an inflow side)
+    double* Binv;          // [nq][r][r]
+    double* y;             // [nq][r]
+    double* red_partials;  // [nblocks][r*r + r]
+    int red_blocks;
+    double* v;             // [r] M_s Lbar / (4 pi)
+    double* L;             // [r][nq]
+    int* status;
+};
+void launch_lstep(hipStream_t s, const LstepArgs& a);
+
+// one-sided Jacobi SVD of S = R^T; writes V [r][r] and S' = S V (columns U_k sigma_k)
+void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status);
+// weighted CGS2 with monomial completion, one workgroup: V [r][n] -> Q [r][n], R [r][r] upper.
+// comp_kind 0: spatial monomials on the nx x ny cell centres, 1: angular monomials in (mu, eta).
+// With flag != nullptr the kernel runs only if (*flag & flag_mask) and then clears those bits.
+template <typename TV>
+void launch_cgs2(hipStream_t s, long n, int r, const TV* V, const double* weight, double wscalar, int comp_kind,
+                 int nx, int ny, const double* mu, const double* eta, double* Q, double* R, int* flag,
+                 int flag_mask, int* status, int status_code);
+// X[k][c] = sum_j V[j][c] M[j][k] for a [r][n] column-major V (general r x r right multiply)
+void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X);
+// beta[k] = sum_q w_q W[k][q];  coef = S beta
+void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
+                 double* coef);
+
+// status words written by kernels
+enum DeviceStatus : int {
+    kStatusOk = 0,
+    kStatusQrBreakdownX = 1,
+    kStatusQrBreakdownW = 2,
+    kStatusNonfinite = 4,
+    kStatusSingularSolve = 8,
+    kStatusBadForcedSel = 16,
+    kStatusSvdNoConv = 32,
+    kStatusSweepStall = 64,
+    kStatusNoCompletion = 128,
+};
+
+}  // namespace dlr

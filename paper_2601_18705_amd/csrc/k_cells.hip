@@ -1,0 +1,236 @@
+// Per-cell kernels of the DLR step: linearisation, reconstruction of the old
+// solution at the selected ordinates, the scalar-flux update inside source
+// iteration, and the temperature update.  All are bandwidth-bound streams over
+// the N cells; X and Psi are column-major ([r][N]) so a thread reads its cell's
+// r values with unit stride across the wavefront.
+#include "dlr_internal.h"
+
+namespace dlr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Deterministic block sum of one double (fixed tree order).
+__device__ double block_sum(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Last-block-done reduction: each block stores its partial(s); the block that
+// retires last sums all partials in index order and resets the counter.
+__device__ bool retire_block(unsigned* counter) {
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();   // acquire: see every other block's partials (per-XCD L2s)
+    return last;
+}
+
+__device__ double ordered_sum(const double* p, int count, int stride, double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += p[(size_t)i * stride];
+    return block_sum(acc, sh);
+}
+
+// ---------------------------------------------------------------------------------------------- linearise
+// Newton linearisation of backward Euler for the material energy (Sec. 2.2):
+//   D = rho c_v + 4 pi dt sigma dB/dT, sigma_s = (4 pi dt sigma dB/dT / D) sigma,
+//   q = sigma B(T0) rho c_v / D + q_ext / (4 pi), sigma_t = sigma + 1/(c dt).
+__global__ void k_linearize(int n, const double* __restrict__ sigma, const double* __restrict__ rho_cv,
+                            const double* __restrict__ q_ext, const double* __restrict__ T, double dt, double a,
+                            double c, double* __restrict__ D, double* __restrict__ sig_s, double* __restrict__ q,
+                            double* __restrict__ sig_t, float* __restrict__ sig_t32) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double t = T[e], s = sigma[e], C = rho_cv[e];
+    const double t3 = t * t * t;
+    const double B0 = a * c * t3 * t / kFourPi;
+    const double dB = a * c * t3 / kPi;
+    const double d = C + kFourPi * dt * s * dB;
+    D[e] = d;
+    sig_s[e] = (kFourPi * dt * s * dB / d) * s;
+    q[e] = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
+    const double st = s + 1.0 / (c * dt);
+    sig_t[e] = st;
+    if (sig_t32) sig_t32[e] = (float)st;
+}
+
+// ---------------------------------------------------------------------------------------------- psi0
+// Algorithm 1 step 3: psi_d^(0) = sum_k X0_k L0_k(Omega^(d)) = (X0 C0)[:, d] with
+// C0 = S0 W0[sel]^T, folded into the fixed sweep source src0 = q + psi^(0)/(c dt).
+// Also the source-iteration start phi = X0 S0 beta and s_e = sigma_s phi / (4 pi).
+template <typename TS, int RMAX>
+__global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __restrict__ X,
+                                                 const double* __restrict__ C0, const double* __restrict__ a0,
+                                                 const double* __restrict__ q, const double* __restrict__ sig_s,
+                                                 double inv_cdt, TS* __restrict__ src0, double* __restrict__ phi,
+                                                 TS* __restrict__ s_e) {
+    __shared__ double sC[RMAX * RMAX];
+    __shared__ double sa[RMAX];
+    for (int i = threadIdx.x; i < r * r; i += blockDim.x) sC[(i / r) * RMAX + (i % r)] = C0[i];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) sa[i] = a0[i];
+    __syncthreads();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double x[RMAX];
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) x[k] = (k < r) ? X[(size_t)k * n + e] : 0.0;
+    double ph = 0.0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+        if (k < r) ph += x[k] * sa[k];
+    phi[e] = ph;
+    s_e[e] = (TS)(sig_s[e] * ph / kFourPi);
+    const double qe = q[e];
+#pragma unroll 4
+    for (int d = 0; d < r; ++d) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+            if (k < r) acc += x[k] * sC[k * RMAX + d];
+        src0[(size_t)d * n + e] = (TS)(qe + acc * inv_cdt);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------- phi
+// Scalar flux of the collocation system (Sec. 4.1): phi = beta^T What^{-1} Psi =
+// sum_d cw_d psi_d, its pseudo-scattering source, and the relative change
+// ||phi_new - phi_old||_2 / ||phi_new||_2 written to out[2] by the last block.
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_phi(int n, int r, const TS* __restrict__ psi,
+                                                const double* __restrict__ cw, const double* __restrict__ sig_s,
+                                                const double* __restrict__ phi_old, double* __restrict__ phi_new,
+                                                TS* __restrict__ s_e, double* __restrict__ partials,
+                                                unsigned* counter, double* out) {
+    __shared__ double sh[kBlock];
+    __shared__ double scw[kMaxRank];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) scw[i] = cw[i];
+    __syncthreads();
+    double d2 = 0.0, p2 = 0.0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        double ph = 0.0;
+        for (int d = 0; d < r; ++d) ph += scw[d] * (double)psi[(size_t)d * n + e];
+        const double diff = ph - phi_old[e];
+        d2 += diff * diff;
+        p2 += ph * ph;
+        phi_new[e] = ph;
+        s_e[e] = (TS)(sig_s[e] * ph / kFourPi);
+    }
+    d2 = block_sum(d2, sh);
+    p2 = block_sum(p2, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = d2;
+        partials[2 * blockIdx.x + 1] = p2;
+    }
+    if (retire_block(counter)) {
+        const double D2 = ordered_sum(partials, gridDim.x, 2, sh);
+        const double P2 = ordered_sum(partials + 1, gridDim.x, 2, sh);
+        if (threadIdx.x == 0) {
+            out[0] = D2;
+            out[1] = P2;
+            out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
+            *counter = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------- T update
+// Algorithm 1 step 9 with the mean intensity of the new factors phi = X (S beta):
+//   T = T0 + dt sigma (phi - a c T0^4) / D,  and energy sum area * (rho c_v T + phi / c).
+__global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* __restrict__ X,
+                                                    const double* __restrict__ coef, const double* __restrict__ sigma,
+                                                    const double* __restrict__ rho_cv, const double* __restrict__ D,
+                                                    double dt, double a, double c, double area, double* __restrict__ T,
+                                                    double* __restrict__ phi, double* __restrict__ partials,
+                                                    unsigned* counter, double* out, int* status) {
+    __shared__ double sh[kBlock];
+    __shared__ double sc[kMaxRank];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) sc[i] = coef[i];
+    __syncthreads();
+    double en = 0.0;
+    bool bad = false;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        double ph = 0.0;
+        for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * sc[k];
+        const double t0 = T[e];
+        const double emis = a * c * t0 * t0 * t0 * t0;
+        const double t = t0 + dt * sigma[e] * (ph - emis) / D[e];
+        T[e] = t;
+        phi[e] = ph;
+        en += rho_cv[e] * t + ph / c;
+        bad |= !(isfinite(ph) && isfinite(t));
+    }
+    if (bad) atomicOr(status, (int)kStatusNonfinite);
+    en = block_sum(en, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = en;
+    if (retire_block(counter)) {
+        const double E = ordered_sum(partials, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            out[0] = E * area;
+            *counter = 0u;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------- launchers
+void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
+                      const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
+                      double* sig_t, float* sig_t32) {
+    hipLaunchKernelGGL(k_linearize, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, sigma, rho_cv, q_ext, T,
+                       dt, a, c, D, sig_s, q, sig_t, sig_t32);
+}
+
+template <typename TS>
+void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0, const double* q,
+                 const double* sig_s, double inv_cdt, TS* src0, double* phi, TS* s_e) {
+    dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
+    if (r <= 8)
+        hipLaunchKernelGGL((k_psi0<TS, 8>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+    else if (r <= 16)
+        hipLaunchKernelGGL((k_psi0<TS, 16>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+    else if (r <= 32)
+        hipLaunchKernelGGL((k_psi0<TS, 32>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+    else
+        hipLaunchKernelGGL((k_psi0<TS, 64>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+}
+template void launch_psi0<double>(hipStream_t, int, int, const double*, const double*, const double*,
+                                  const double*, const double*, double, double*, double*, double*);
+template void launch_psi0<float>(hipStream_t, int, int, const double*, const double*, const double*, const double*,
+                                 const double*, double, float*, double*, float*);
+
+template <typename TS>
+void launch_phi(hipStream_t s, int n, int r, const TS* psi, const double* cw, const double* sig_s,
+                const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter,
+                double* out) {
+    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, n, r, psi, cw, sig_s, phi_old, phi_new, s_e,
+                       partials, counter, out);
+}
+template void launch_phi<double>(hipStream_t, int, int, const double*, const double*, const double*, const double*,
+                                 double*, double*, double*, int, unsigned*, double*);
+template void launch_phi<float>(hipStream_t, int, int, const float*, const double*, const double*, const double*,
+                                double*, float*, double*, int, unsigned*, double*);
+
+void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
+                    const double* rho_cv, const double* D, double dt, double a, double c, double area, double* T,
+                    double* phi, double* partials, int nblocks, unsigned* counter, double* out, int* status) {
+    hipLaunchKernelGGL(k_tupdate, dim3(nblocks), dim3(kBlock), 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area,
+                       T, phi, partials, counter, out, status);
+}
+
+}  // namespace dlr

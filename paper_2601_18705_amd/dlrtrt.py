@@ -1,0 +1,187 @@
+"""ctypes binding of libdlrtrt.so (include/dlrtrt.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts numpy
+arrays and problem dicts to the C structs and back.  Importing the functions
+here fails loudly if the library has not been built -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdlrtrt.so")
+
+DLR_ABI_VERSION = 1
+DLR_OK = 0
+STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_HIP", -4: "DLR_ERR_NOT_CONVERGED",
+                -5: "DLR_ERR_NONFINITE", -6: "DLR_ERR_STATE", -7: "DLR_ERR_UNSUPPORTED", -8: "DLR_ERR_NUMERIC"}
+DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
+
+EXPORTED = ["dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
+            "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_status_string", "dlr_last_error"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class DlrProblem(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("n_polar", ctypes.c_int32), ("n_azim", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double), ("a", ctypes.c_double),
+                ("sigma_a", _dp), ("rho_cv", _dp), ("q_ext", _dp), ("T_init", _dp),
+                ("bc", ctypes.c_int32 * 4), ("T_b", ctypes.c_double * 4),
+                ("precision", ctypes.c_int32), ("si_tol", ctypes.c_double), ("si_max_iter", ctypes.c_int32),
+                ("deim_tie_tol", ctypes.c_double)]
+
+
+class DlrStepStats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int64), ("si_iters", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("si_residual", ctypes.c_double), ("deim_min_margin", ctypes.c_double),
+                ("sum_abs_cw_over_4pi", ctypes.c_double), ("energy", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+
+
+class DlrError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {detail}")
+
+
+_lib = None
+
+
+def library():
+    """Load libdlrtrt.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the HIP library is the only implementation)")
+        lib = ctypes.CDLL(LIB_PATH)
+        h = ctypes.c_void_p
+        lib.dlr_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
+        lib.dlr_step.argtypes = [h, ctypes.c_int32]
+        lib.dlr_sync.argtypes = [h]
+        lib.dlr_read_fields.argtypes = [h, _dp, _dp]
+        lib.dlr_read_factors.argtypes = [h, _dp, _dp, _dp, _ip]
+        lib.dlr_load_factors.argtypes = [h, _dp, _dp, _dp, _dp]
+        lib.dlr_read_stats.argtypes = [h, ctypes.POINTER(DlrStepStats)]
+        lib.dlr_force_selection.argtypes = [h, _ip]
+        lib.dlr_destroy.argtypes = [h]
+        lib.dlr_status_string.argtypes = [ctypes.c_int]
+        lib.dlr_status_string.restype = ctypes.c_char_p
+        lib.dlr_last_error.argtypes = []
+        lib.dlr_last_error.restype = ctypes.c_char_p
+        for name in ("dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
+                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != DLR_OK:
+        raise DlrError(status, library().dlr_last_error().decode())
+
+
+def _f64(a, n=None):
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and arr.size != n:
+        raise ValueError(f"expected {n} values, got {arr.size}")
+    return arr
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class Instance:
+    """One problem resident on the device (dlr_create ... dlr_destroy)."""
+
+    def __init__(self, problem, stream=None):
+        lib = library()
+        n = int(problem["nx"]) * int(problem["ny"])
+        self.nx, self.ny, self.n = int(problem["nx"]), int(problem["ny"]), n
+        self.rank = int(problem["rank"])
+        self.nq = int(problem["n_polar"]) * int(problem["n_azim"])
+        self._keep = [_f64(problem["sigma_a"], n), _f64(problem["rho_cv"], n), _f64(problem["T_init"], n)]
+        qext = problem.get("q_ext")
+        self._keep.append(None if qext is None else _f64(qext, n))
+        p = DlrProblem()
+        p.abi_version = DLR_ABI_VERSION
+        p.nx, p.ny = self.nx, self.ny
+        p.x0, p.x1, p.y0, p.y1 = (float(problem[k]) for k in ("x0", "x1", "y0", "y1"))
+        p.n_polar, p.n_azim, p.rank = int(problem["n_polar"]), int(problem["n_azim"]), self.rank
+        p.dt, p.c, p.a = float(problem["dt"]), float(problem["c"]), float(problem["a"])
+        p.sigma_a, p.rho_cv, p.T_init = (_ptr(a) for a in self._keep[:3])
+        p.q_ext = _ptr(self._keep[3])
+        for k in range(4):
+            p.bc[k] = int(problem["bc"][k])
+            p.T_b[k] = float(problem["T_b"][k])
+        p.precision = int(problem.get("precision", DLR_FP64))
+        p.si_tol = float(problem.get("si_tol", 1e-14))
+        p.si_max_iter = int(problem.get("si_max_iter", 10000))
+        p.deim_tie_tol = float(problem.get("deim_tie_tol", 1e-6))
+        self._p = p
+        self._h = ctypes.c_void_p()
+        _check(lib.dlr_create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))
+
+    def step(self, n_steps=1):
+        _check(library().dlr_step(self._h, int(n_steps)))
+
+    def sync(self):
+        _check(library().dlr_sync(self._h))
+
+    def read_fields(self):
+        E = np.empty(self.n)
+        T = np.empty(self.n)
+        _check(library().dlr_read_fields(self._h, _ptr(E), _ptr(T)))
+        return E, T
+
+    def read_factors(self):
+        X = np.empty((self.n, self.rank))
+        S = np.empty((self.rank, self.rank))
+        W = np.empty((self.nq, self.rank))
+        sel = np.empty(self.rank, dtype=np.int32)
+        _check(library().dlr_read_factors(self._h, _ptr(X), _ptr(S), _ptr(W), sel.ctypes.data_as(_ip)))
+        return X, S, W, sel
+
+    def load_factors(self, X, S, W, T):
+        Xa = _f64(X, self.n * self.rank)
+        Sa = _f64(S, self.rank * self.rank)
+        Wa = _f64(W, self.nq * self.rank)
+        Ta = _f64(T, self.n)
+        _check(library().dlr_load_factors(self._h, _ptr(Xa), _ptr(Sa), _ptr(Wa), _ptr(Ta)))
+
+    def read_stats(self):
+        s = DlrStepStats()
+        _check(library().dlr_read_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in DlrStepStats._fields_}
+
+    def force_selection(self, sel):
+        if sel is None:
+            _check(library().dlr_force_selection(self._h, None))
+            return
+        a = np.ascontiguousarray(sel, dtype=np.int32)
+        _check(library().dlr_force_selection(self._h, a.ctypes.data_as(_ip)))
+
+    def close(self):
+        if self._h:
+            library().dlr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

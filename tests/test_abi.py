@@ -1,0 +1,62 @@
+"""CPU-side checks of the C-ABI: the library loads, exports every symbol the
+header declares, and rejects invalid problems before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_18705_amd import dlrtrt
+from synth import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "dlrtrt.h")).read()
+    return sorted(set(re.findall(r"\b(dlr_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _header_functions() == sorted(dlrtrt.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    lib = dlrtrt.library()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+    assert lib.dlr_status_string(-4).decode() == "source iteration did not converge"
+
+
+def _bad(**kw):
+    p = problems.slab_beam(nx=8, n_polar=2, n_azim=4, rank=2)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(rank=0), -1), (dict(rank=65), -1), (dict(rank=9), -1),          # rank > ordinates (8)
+    (dict(n_azim=6), -1), (dict(dt=0.0), -1),
+    (dict(bc=[2, 0, 0, 0]), -7), (dict(precision=2), -7), (dict(precision=5), -1),
+    (dict(si_max_iter=0), -1), (dict(deim_tie_tol=1.0), -1),
+])
+def test_create_rejects_invalid_problems(kw, status):
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    p = _bad(**kw)
+    with pytest.raises(dlrtrt.DlrError) as ei:
+        dlrtrt.Instance(p)
+    assert ei.value.status == status
+
+
+def test_create_rejects_nonpositive_fields():
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    p = _bad()
+    p["sigma_a"] = p["sigma_a"].copy()
+    p["sigma_a"][3] = 0.0
+    with pytest.raises(dlrtrt.DlrError) as ei:
+        dlrtrt.Instance(p)
+    assert ei.value.status == -1
