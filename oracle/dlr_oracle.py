@@ -356,9 +356,10 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
     triangular with R_kk >= 0.  A column whose residual norm is at most
     defect_tol times its own norm is replaced by the next completion vector
     (orthogonalised twice, skipped when dependent) and gets R_kk = 0.
+    (The accepted columns are kept as contiguous rows of Qt = Q^T.)
     """
     n, r = V.shape
-    Q = np.zeros((n, r))
+    Qt = np.zeros((r, n))
     R = np.zeros((r, r))
     comp = iter(completion)
 
@@ -366,8 +367,8 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
         return float(np.dot(weight * u, v))
 
     def project_out(v, k):
-        h = Q[:, :k].T @ (weight * v)
-        return v - Q[:, :k] @ h, h
+        h = Qt[:k] @ (weight * v)
+        return v - Qt[:k].T @ h, h
 
     for k in range(r):
         v = V[:, k].astype(np.float64)
@@ -377,7 +378,7 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
         R[:k, k] = h1 + h2
         nrm = math.sqrt(max(ip(v2, v2), 0.0))
         if own > 0.0 and nrm > defect_tol * own:
-            Q[:, k] = v2 / nrm
+            Qt[k] = v2 / nrm
             R[k, k] = nrm
             continue
         while True:
@@ -387,10 +388,10 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
             u2, _ = project_out(u1, k)
             n2 = math.sqrt(max(ip(u2, u2), 0.0))
             if n2 > skip_tol * un:
-                Q[:, k] = u2 / n2
+                Qt[k] = u2 / n2
                 R[k, k] = 0.0
                 break
-    return Q, R
+    return Qt.T, R
 
 
 def deim(W, tie_tol):
