@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""Benchmark of the SN-like DLR step on one MI355X.
+
+Workload: the 1024 x 1024 log-normal random medium (sigma_a = exp(1.5 g), 16-cell
+Gaussian correlation, seed 3), left-edge inflow at T_b = 1, 32 x 64 product
+ordinates (2048 directions), rank 32, dt = 0.002; FP32 sweeps and projections
+with FP64 selection, QR/SVD, L-step and temperature update (SI tolerance 1e-6).
+One "step" is one DLR time step (Algorithm 1) with all inputs resident in HBM.
+
+Prints one JSON line: cell-angle sweep updates per second of the whole timed run
+(value), DLR steps/s, the sweep kernel against the HBM roofline (HIP-event
+timed inside the library on its own stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-angle sweep updates/s + DLR steps/s at 1024², r=32; p50/p99 solve latency"
+
+
+def sweep_source_hash():
+    with open(os.path.join(ROOT, "paper_2601_18705_amd", "csrc", "k_sweep.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload, bytes_per_launch):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    when it was taken on the current sweep kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_counters_" + workload + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sweep_source_sha") != sweep_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_problem(name):
+    from synth import problems
+    if name == "random_medium":
+        p = problems.random_medium()
+    elif name == "checkerboard":
+        p = problems.checkerboard()
+    elif name == "slab_beam":
+        p = problems.slab_beam()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p
+
+
+def cpu_baseline(p, steps, warm=0):
+    """The FP64 oracle on the host: `steps` DLR steps from the cold start
+    (initial factors not timed), single thread (BLAS pinned to one thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dlr_oracle as O
+    with threadpool_limits(limits=1):
+        quad = O.quadrature(p["n_polar"], p["n_azim"])
+        st = O.dlr_initial_state(p, quad)
+        ca = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, s = O.dlr_step(p, quad, st)
+            ca += s["si_iters"] * p["nx"] * p["ny"] * p["rank"]
+        dt = time.perf_counter() - t0
+    return {"value": ca / dt, "unit": "cell-angle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} DLR step(s) of the same workload from its cold start, FP64, 1 thread "
+                      f"({dt:.1f} s, {ca} cell-angle updates)",
+            "steps_per_s": steps / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="random_medium")
+    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed run, copy a buffer of this size with torch (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in the design notes, not implemented)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2601_18705_amd import dlrtrt
+
+    p = make_problem(args.workload)
+    if args.fp64:
+        p["precision"], p["si_tol"] = dlrtrt.DLR_FP64, 1e-14
+    else:
+        p["precision"], p["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+    N, r = p["nx"] * p["ny"], p["rank"]
+    print(f"[bench] workload {p['name']} precision {'fp64' if args.fp64 else 'fp32-sweep'} "
+          f"warmup {args.warmup} steps {args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.init()
+    inst = dlrtrt.Instance(p)
+    for _ in range(args.warmup):
+        inst.step(1)
+    torch.cuda.synchronize()
+    ca = 0
+    sweep_ms = 0.0
+    launches = 0
+    step_ms = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        inst.step(1)
+        st = inst.read_stats()
+        ca += st["si_iters"] * N * r
+        sweep_ms += st["sweep_ms"]
+        launches += st["si_iters"]
+        step_ms += st["step_ms"]
+        if k % 5 == 4:
+            print(f"[bench] step {k + 1}/{args.steps} si {st['si_iters']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    E, T = inst.read_fields()
+    inst.close()
+
+    sweep_bytes = 4 if not args.fp64 else 8
+    bytes_per_launch = N * r * 2 * sweep_bytes + N * 2 * sweep_bytes   # src0 read, psi write; sigma_t, s_e read
+    avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = load_traffic(p["name"] + ("_fp64" if args.fp64 else "_fp32"), bytes_per_launch)
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": ca / wall,
+        "unit": "cell-angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.fp64 else "f32",
+        "data": "synthetic (seeded log-normal random medium; no dataset)",
+        "config": {"workload": p["name"], "nx": p["nx"], "ny": p["ny"], "directions": p["n_polar"] * p["n_azim"],
+                   "rank": r, "dt": p["dt"], "si_tol": p["si_tol"],
+                   "precision": "fp64" if args.fp64 else "fp32 sweeps+projections, fp64 selection/QR/SVD/L-step/T"},
+        "dlr_steps_per_s": args.steps / wall,
+        "sweep_cell_angle_updates_per_s": ca / (sweep_ms / 1e3),
+        "si_iterations_per_step": launches / args.steps,
+        "device_ms_per_step": step_ms / args.steps,
+        "latency_p50_p99_s": None,
+        "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
+        "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
+    }
+    if args.cpu_steps > 0:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(make_problem(args.workload), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

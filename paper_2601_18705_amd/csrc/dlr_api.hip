@@ -90,7 +90,8 @@ struct dlr_instance {
     unsigned long long* progress = nullptr;
     unsigned* ticket = nullptr;
     unsigned long long launch_id = 0;
-    int nstrips = 0;
+    int nsuper = 0;
+    size_t ld = 0;   // elements of one padded-column sweep plane (psi, src0, s_e, sigma_t)
     double* partials = nullptr;
     size_t partials_count = 0;
     double* norm_out = nullptr;
@@ -122,8 +123,8 @@ struct dlr_instance {
         D = A.take<double>(n);
         sig_s = A.take<double>(n);
         q = A.take<double>(n);
-        sig_t = A.take<double>(n);
-        sig_t32 = fp32() ? A.take<float>(n) : nullptr;
+        sig_t = fp32() ? nullptr : A.take<double>(ld);
+        sig_t32 = fp32() ? A.take<float>(ld) : nullptr;
         X = A.take<double>(R * n);
         Xn = A.take<double>(R * n);
         Xt = A.take<double>(R * n);
@@ -133,9 +134,9 @@ struct dlr_instance {
         Wt = A.take<double>(R * Q);
         Wq = A.take<double>(R * Q);
         L = A.take<double>(R * Q);
-        psi = A.take<char>(R * n * sweep_bytes());
-        src0 = A.take<char>(R * n * sweep_bytes());
-        s_e = A.take<char>(n * sweep_bytes());
+        psi = A.take<char>(R * ld * sweep_bytes());
+        src0 = A.take<char>(R * ld * sweep_bytes());
+        s_e = A.take<char>(ld * sweep_bytes());
         phi = A.take<double>(n);
         phi2 = A.take<double>(n);
         sel = A.take<int>(R);
@@ -149,8 +150,8 @@ struct dlr_instance {
         inflow_x = A.take<double>(R);
         inflow_y = A.take<double>(R);
         deim_work = A.take<double>(R * Q);
-        edge = A.take<char>(R * (size_t)nstrips * ny * sweep_bytes());
-        progress = A.take<unsigned long long>(R * (size_t)nstrips);
+        edge = A.take<char>(R * (size_t)nsuper * ny * sweep_bytes());
+        progress = A.take<unsigned long long>(R * (size_t)nsuper);
         ticket = A.take<unsigned>(4);
         partials = A.take<double>(partials_count);
         norm_out = A.take<double>(4);
@@ -247,7 +248,7 @@ dlr_status step_once(dlr_instance* I) {
 
     // 1. effective scattering and source
     dlr::launch_linearize(s, N, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s, I->q,
-                          I->sig_t, I->sig_t32);
+                          I->sig_t, I->sig_t32, I->ny);
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
@@ -260,16 +261,16 @@ dlr_status step_once(dlr_instance* I) {
     dlr::launch_deim(s, da);
     I->force_pending = false;
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
-    dlr::launch_psi0<TS>(s, N, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, src0, I->phi, s_e);
+    dlr::launch_psi0<TS>(s, N, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, src0, I->ld, I->phi, s_e, I->ny);
     // 4. source iteration with sweeps
     dlr::SweepArgs<TS> sa{};
-    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nstrips = I->nstrips; sa.total_units = I->nstrips * r;
+    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * r; sa.ld = I->ld;
     sa.src0 = src0; sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
     sa.s_e = s_e; sa.psi = psi; sa.mu = I->sel_mu; sa.eta = I->sel_eta;
     sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
     sa.inv_hx = 1.0 / I->hx; sa.inv_hy = 1.0 / I->hy;
     sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress; sa.ticket = I->ticket;
-    sa.grid_waves = std::min(sa.total_units, 4096);
+    sa.grid_blocks = std::min(sa.total_units, 512);
     sa.status = I->status;
     sa.spin_limit = 1u << 20;
     double* phi_cur = I->phi;
@@ -282,8 +283,8 @@ dlr_status step_once(dlr_instance* I) {
         hip_check(hipEventRecord(I->ev[2], s), "event");
         dlr::launch_sweep<TS>(s, sa);
         hip_check(hipEventRecord(I->ev[3], s), "event");
-        dlr::launch_phi<TS>(s, N, r, psi, I->cw, I->sig_s, phi_cur, phi_nxt, s_e, I->partials, I->nb_cells,
-                            I->counters + 0, I->norm_out);
+        dlr::launch_phi<TS>(s, N, r, psi, I->ld, I->cw, I->sig_s, phi_cur, phi_nxt, s_e, I->partials, I->nb_cells,
+                            I->counters + 0, I->norm_out, I->ny);
         std::swap(phi_cur, phi_nxt);
         hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
         hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
@@ -311,15 +312,15 @@ dlr_status step_once(dlr_instance* I) {
     if (ds != DLR_OK) return ds;
 
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
-    dlr::launch_gram<TS>(s, N, r, psi, nullptr, I->area, I->partials, I->nb_gram);
+    dlr::launch_gram<TS>(s, N, r, psi, I->ld, I->ny, nullptr, I->area, I->partials, I->nb_gram);
     dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<TS>(s, N, r, psi, I->R1i, I->Xt);
-    dlr::launch_gram<double>(s, N, r, I->Xt, nullptr, I->area, I->partials, I->nb_gram);
+    dlr::launch_trmm<TS>(s, N, r, psi, I->ld, I->ny, I->R1i, I->Xt);
+    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, nullptr, I->area, I->partials, I->nb_gram);
     dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<double>(s, N, r, I->Xt, I->R2i, I->Xn);
+    dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, 0, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
-    dlr::launch_cgs2<TS>(s, N, r, psi, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn, I->R1, I->status,
-                         dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
+    dlr::launch_cgs2<TS>(s, N, r, psi, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
+                         I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
     // 6-7. projections on the new basis and the L-step for every ordinate
     dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->area, I->hx, I->hy, I->partials,
                         I->nb_proj);
@@ -332,8 +333,8 @@ dlr_status step_once(dlr_instance* I) {
     la.L = I->L; la.status = I->status;
     dlr::launch_lstep(s, la);
     // 8. L = W S^T in the quadrature inner product (CGS2 with angular completion), then the SVD of S
-    dlr::launch_cgs2<double>(s, nq, r, I->L, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->R2, nullptr, 0,
-                             I->status, dlr::kStatusNoCompletion);
+    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->R2,
+                             nullptr, 0, I->status, dlr::kStatusNoCompletion);
     dlr::launch_svd(s, r, I->R2, I->Vsvd, I->Sn, I->status);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
     dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef);
@@ -366,6 +367,18 @@ dlr_status step_once(dlr_instance* I) {
     ++I->steps_done;
     I->stats.steps_done = I->steps_done;
     return DLR_OK;
+}
+
+// row-major cells (e = j*nx + i, the C interface) <-> column-major cells (e = i*ny + j, device)
+std::vector<double> to_cm(const double* src, int nx, int ny) {
+    std::vector<double> out((size_t)nx * ny);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) out[(size_t)i * ny + j] = src[(size_t)j * nx + i];
+    return out;
+}
+void to_rm(const double* src, double* dst, int nx, int ny) {
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) dst[(size_t)j * nx + i] = src[(size_t)i * ny + j];
 }
 
 void upload(void* dst, const void* src, size_t bytes) { hip_check(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "upload"); }
@@ -434,7 +447,8 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         }
         I->has_qext = p->q_ext != nullptr;
         I->stream = static_cast<hipStream_t>(hip_stream);
-        I->nstrips = (I->nx + 63) / 64;
+        I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
+        I->ld = dlr::padded_plane(I->nx, I->ny);
         const size_t rr = (size_t)I->r * I->r;
         I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
                                       (size_t)I->nb_cells * 2});
@@ -462,13 +476,17 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
         upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
         upload(I->w, I->h_w.data(), I->nq * sizeof(double));
-        upload(I->sigma, p->sigma_a, n * sizeof(double));
-        upload(I->rho_cv, p->rho_cv, n * sizeof(double));
-        if (p->q_ext) upload(I->q_ext, p->q_ext, n * sizeof(double));
-        upload(I->T, p->T_init, n * sizeof(double));
+        upload(I->sigma, to_cm(p->sigma_a, I->nx, I->ny).data(), n * sizeof(double));
+        upload(I->rho_cv, to_cm(p->rho_cv, I->nx, I->ny).data(), n * sizeof(double));
+        if (p->q_ext) upload(I->q_ext, to_cm(p->q_ext, I->nx, I->ny).data(), n * sizeof(double));
+        upload(I->T, to_cm(p->T_init, I->nx, I->ny).data(), n * sizeof(double));
         dlr::ProblemHost ph{I->nx, I->ny, I->r, I->hx, I->hy, I->a, I->c, p->T_init};
         std::vector<double> X, S, W;
         dlr::build_initial_factors(ph, I->h_mu, I->h_eta, I->h_w, X, S, W);
+        for (int k = 0; k < I->r; ++k) {
+            const std::vector<double> col = to_cm(&X[(size_t)k * n], I->nx, I->ny);
+            std::copy(col.begin(), col.end(), X.begin() + (size_t)k * n);
+        }
         upload(I->X, X.data(), X.size() * sizeof(double));
         upload(I->S, S.data(), S.size() * sizeof(double));
         upload(I->W, W.data(), W.size() * sizeof(double));
@@ -511,11 +529,16 @@ dlr_status dlr_read_fields(dlr_handle h, double* E_r, double* T) {
     if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
     try {
         hip_check(hipStreamSynchronize(h->stream), "sync");
+        std::vector<double> buf((size_t)h->N);
         if (E_r) {
-            download(E_r, h->phi, (size_t)h->N * sizeof(double));
+            download(buf.data(), h->phi, (size_t)h->N * sizeof(double));
+            to_rm(buf.data(), E_r, h->nx, h->ny);
             for (int e = 0; e < h->N; ++e) E_r[e] /= h->c;
         }
-        if (T) download(T, h->T, (size_t)h->N * sizeof(double));
+        if (T) {
+            download(buf.data(), h->T, (size_t)h->N * sizeof(double));
+            to_rm(buf.data(), T, h->nx, h->ny);
+        }
     } catch (const std::exception& ex) {
         return fail(DLR_ERR_HIP, ex.what());
     }
@@ -566,13 +589,17 @@ dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, in
         } else {
             for (size_t k = 0; k < R; ++k) U[k * R + k] = 1.0;
         }
-        if (Xo)
-            for (size_t e = 0; e < n; ++e)
+        if (Xo) {
+            const size_t nx = h->nx, ny = h->ny;
+            for (size_t e = 0; e < n; ++e) {
+                const size_t erm = (e % ny) * nx + (e / ny);   // device cell e = i*ny + j -> j*nx + i
                 for (size_t k = 0; k < R; ++k) {
                     double s = 0.0;
                     for (size_t j = 0; j < R; ++j) s += X[j * n + e] * U[j * R + k];
-                    Xo[e * R + k] = s;
+                    Xo[erm * R + k] = s;
                 }
+            }
+        }
         if (So)
             for (size_t i = 0; i < R; ++i)
                 for (size_t j = 0; j < R; ++j) So[i * R + j] = h->s_is_usigma ? (i == j ? sig[i] : 0.0) : S[i * R + j];
@@ -601,14 +628,17 @@ dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, co
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const size_t n = h->N, R = h->r, Q = h->nq;
         std::vector<double> X(R * n), W(R * Q);
-        for (size_t e = 0; e < n; ++e)
-            for (size_t k = 0; k < R; ++k) X[k * n + e] = Xi[e * R + k];
+        const size_t nx = h->nx, ny = h->ny;
+        for (size_t e = 0; e < n; ++e) {
+            const size_t erm = (e % ny) * nx + (e / ny);
+            for (size_t k = 0; k < R; ++k) X[k * n + e] = Xi[erm * R + k];
+        }
         for (size_t qq = 0; qq < Q; ++qq)
             for (size_t k = 0; k < R; ++k) W[k * Q + qq] = Wi[qq * R + k];
         upload(h->X, X.data(), X.size() * sizeof(double));
         upload(h->S, Si, R * R * sizeof(double));
         upload(h->W, W.data(), W.size() * sizeof(double));
-        upload(h->T, Ti, n * sizeof(double));
+        upload(h->T, to_cm(Ti, h->nx, h->ny).data(), n * sizeof(double));
         refresh_phi_host(h);
         hip_check(hipDeviceSynchronize(), "sync");
         h->s_is_usigma = false;

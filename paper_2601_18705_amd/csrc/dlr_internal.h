@@ -1,9 +1,14 @@
 // Internal declarations of the dlrtrt HIP library (gfx950).
 //
-// Storage layout on the device (one instance):
-//   per-cell fields          [N] float64, N = nx*ny, e = j*nx + i
+// Storage layout on the device (one instance).  Cells are numbered column-major,
+// e = i*ny + j (a grid column is contiguous); the C interface uses e = j*nx + i
+// and the library transposes at creation and read-back only.
+//   per-cell fields          [N] float64, N = nx*ny
 //   spatial basis X          [r][N] float64 (column k of X contiguous)
-//   swept columns Psi, src0  [r][N] in the sweep precision (double or float)
+//   sweep planes             Psi, src0 [r][ld], sigma_t, s_e: in the sweep precision (double or
+//                            float), "padded columns": cell (i, j) at i*ldc + kColGuard + j with
+//                            ldc = ny + 2 kColGuard, so every column has kColGuard spare rows
+//                            above and below its data
 //   angular basis W, L       [r][nq] float64 (column k contiguous over ordinates)
 //   coupling S               [r][r] float64, row-major S[i*r + j]
 // The state is psi = X S W^T with X, W orthonormal; S is kept as a general
@@ -24,16 +29,17 @@ constexpr int kSweepChunk = 32;   // rows published per edge-flag update in the 
 // ----------------------------------------------------------------------------- per-cell kernels
 void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t, float* sig_t32);
+                      double* sig_t_pad, float* sig_t32_pad, int ny);
 
 template <typename TS>
 void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0,
-                 const double* q, const double* sig_s, double inv_cdt, TS* src0, double* phi, TS* s_e);
+                 const double* q, const double* sig_s, double inv_cdt, TS* src0, size_t ld, double* phi, TS* s_e,
+                 int ny);
 
 template <typename TS>
-void launch_phi(hipStream_t s, int n, int r, const TS* psi, const double* cw, const double* sig_s,
+void launch_phi(hipStream_t s, int n, int r, const TS* psi, size_t ld, const double* cw, const double* sig_s,
                 const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks,
-                unsigned* counter, double* out);
+                unsigned* counter, double* out, int ny);
 
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area,
@@ -41,23 +47,36 @@ void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* 
                     int* status);
 
 // ----------------------------------------------------------------------------- sweep
+constexpr int kSweepWaves = 4;     // compute wavefronts (64-column strips) per sweep workgroup
+constexpr int kColGuard = 16;      // spare rows above and below each column of a sweep plane
+
+// index of column-major cell e = i*ny + j in a padded-column sweep plane
+__host__ __device__ inline size_t padded_cell(long e, int ny) {
+    const long i = e / ny;
+    return (size_t)i * (ny + 2 * kColGuard) + kColGuard + (e - i * ny);
+}
+// elements of one padded sweep plane, plus a kColGuard-element trash slot, rounded to 64
+__host__ __device__ inline size_t padded_plane(int nx, int ny) {
+    return (((size_t)nx * (ny + 2 * kColGuard) + kColGuard) + 63) / 64 * 64;
+}
 template <typename TS>
 struct SweepArgs {
-    int nx, ny, nd, nstrips, total_units;
-    const TS* src0;      // [nd][N] fixed source q + psi0 / (c dt)
-    const TS* sig_t;     // [N]
-    const TS* s_e;       // [N] sigma_s phi / (4 pi)
-    TS* psi;             // [nd][N]
+    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of 4 x 64 columns
+    size_t ld;                             // plane stride of src0 / psi (elements), padded_plane
+    const TS* src0;      // [nd][ld] fixed source q + psi0 / (c dt), padded columns
+    const TS* sig_t;     // padded plane
+    const TS* s_e;       // padded plane, sigma_s phi / (4 pi)
+    TS* psi;             // [nd][ld]
     const double* mu;    // [nd] direction cosines of the swept directions
     const double* eta;   // [nd]
     const double* inflow_x;  // [nd] isotropic inflow on the x-inflow face (0 = vacuum)
     const double* inflow_y;  // [nd]
     double inv_hx, inv_hy;
-    TS* edge;                        // [nd][nstrips][ny] outgoing x-face values of each strip
-    unsigned long long* progress;    // [nd][nstrips] (launch << 32) | rows published
-    unsigned* ticket;                // [2] work ticket, retired waves
+    TS* edge;                        // [nd][nsuper][ny] outgoing x-face values of each superstrip
+    unsigned long long* progress;    // [nd][nsuper] (launch << 32) | rows published
+    unsigned* ticket;                // [2] work ticket, retired workgroups
     unsigned long long launch_id;
-    int grid_waves;
+    int grid_blocks;
     int* status;                     // kStatusSweepStall is raised if a wait exceeds spin_limit polls
     unsigned spin_limit;
 };
@@ -65,13 +84,14 @@ template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>& a);
 
 // ----------------------------------------------------------------------------- reductions
+// V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny)
 template <typename TV>
-void launch_gram(hipStream_t s, int n, int r, const TV* V, const double* weight, double scalar_weight,
-                 double* partials, int nblocks);
+void launch_gram(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
+                 double scalar_weight, double* partials, int nblocks);
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,
                  int* status, int status_code);
 template <typename TV>
-void launch_trmm(hipStream_t s, int n, int r, const TV* V, const double* Rinv, double* X);
+void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X);
 
 struct ProjectOut {
     // raw sums (split-K partials reduced by launch_project_finalize)
@@ -135,7 +155,8 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 // comp_kind 0: spatial monomials on the nx x ny cell centres, 1: angular monomials in (mu, eta).
 // With flag != nullptr the kernel runs only if (*flag & flag_mask) and then clears those bits.
 template <typename TV>
-void launch_cgs2(hipStream_t s, long n, int r, const TV* V, const double* weight, double wscalar, int comp_kind,
+void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double wscalar,
+                 int comp_kind,
                  int nx, int ny, const double* mu, const double* eta, double* Q, double* R, int* flag,
                  int flag_mask, int* status, int status_code);
 // X[k][c] = sum_j V[j][c] M[j][k] for a [r][n] column-major V (general r x r right multiply)

@@ -53,7 +53,7 @@ __device__ double ordered_sum(const double* p, int count, int stride, double* sh
 __global__ void k_linearize(int n, const double* __restrict__ sigma, const double* __restrict__ rho_cv,
                             const double* __restrict__ q_ext, const double* __restrict__ T, double dt, double a,
                             double c, double* __restrict__ D, double* __restrict__ sig_s, double* __restrict__ q,
-                            double* __restrict__ sig_t, float* __restrict__ sig_t32) {
+                            double* __restrict__ sig_t, float* __restrict__ sig_t32, int ny) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const double t = T[e], s = sigma[e], C = rho_cv[e];
@@ -65,8 +65,9 @@ __global__ void k_linearize(int n, const double* __restrict__ sigma, const doubl
     sig_s[e] = (kFourPi * dt * s * dB / d) * s;
     q[e] = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
     const double st = s + 1.0 / (c * dt);
-    sig_t[e] = st;
-    if (sig_t32) sig_t32[e] = (float)st;
+    const size_t pe = padded_cell(e, ny);
+    if (sig_t) sig_t[pe] = st;
+    if (sig_t32) sig_t32[pe] = (float)st;
 }
 
 // ---------------------------------------------------------------------------------------------- psi0
@@ -77,8 +78,8 @@ template <typename TS, int RMAX>
 __global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __restrict__ X,
                                                  const double* __restrict__ C0, const double* __restrict__ a0,
                                                  const double* __restrict__ q, const double* __restrict__ sig_s,
-                                                 double inv_cdt, TS* __restrict__ src0, double* __restrict__ phi,
-                                                 TS* __restrict__ s_e) {
+                                                 double inv_cdt, TS* __restrict__ src0, size_t ld,
+                                                 double* __restrict__ phi, TS* __restrict__ s_e, int ny) {
     __shared__ double sC[RMAX * RMAX];
     __shared__ double sa[RMAX];
     for (int i = threadIdx.x; i < r * r; i += blockDim.x) sC[(i / r) * RMAX + (i % r)] = C0[i];
@@ -94,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __r
     for (int k = 0; k < RMAX; ++k)
         if (k < r) ph += x[k] * sa[k];
     phi[e] = ph;
-    s_e[e] = (TS)(sig_s[e] * ph / kFourPi);
+    const size_t pe = padded_cell(e, ny);
+    s_e[pe] = (TS)(sig_s[e] * ph / kFourPi);
     const double qe = q[e];
 #pragma unroll 4
     for (int d = 0; d < r; ++d) {
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __r
 #pragma unroll
         for (int k = 0; k < RMAX; ++k)
             if (k < r) acc += x[k] * sC[k * RMAX + d];
-        src0[(size_t)d * n + e] = (TS)(qe + acc * inv_cdt);
+        src0[(size_t)d * ld + pe] = (TS)(qe + acc * inv_cdt);
     }
 }
 
@@ -111,24 +113,25 @@ __global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __r
 // sum_d cw_d psi_d, its pseudo-scattering source, and the relative change
 // ||phi_new - phi_old||_2 / ||phi_new||_2 written to out[2] by the last block.
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_phi(int n, int r, const TS* __restrict__ psi,
+__global__ __launch_bounds__(kBlock) void k_phi(int n, int r, const TS* __restrict__ psi, size_t ld,
                                                 const double* __restrict__ cw, const double* __restrict__ sig_s,
                                                 const double* __restrict__ phi_old, double* __restrict__ phi_new,
                                                 TS* __restrict__ s_e, double* __restrict__ partials,
-                                                unsigned* counter, double* out) {
+                                                unsigned* counter, double* out, int ny) {
     __shared__ double sh[kBlock];
     __shared__ double scw[kMaxRank];
     for (int i = threadIdx.x; i < r; i += blockDim.x) scw[i] = cw[i];
     __syncthreads();
     double d2 = 0.0, p2 = 0.0;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const size_t pe = padded_cell(e, ny);
         double ph = 0.0;
-        for (int d = 0; d < r; ++d) ph += scw[d] * (double)psi[(size_t)d * n + e];
+        for (int d = 0; d < r; ++d) ph += scw[d] * (double)psi[(size_t)d * ld + pe];
         const double diff = ph - phi_old[e];
         d2 += diff * diff;
         p2 += ph * ph;
         phi_new[e] = ph;
-        s_e[e] = (TS)(sig_s[e] * ph / kFourPi);
+        s_e[pe] = (TS)(sig_s[e] * ph / kFourPi);
     }
     d2 = block_sum(d2, sh);
     p2 = block_sum(p2, sh);
@@ -191,40 +194,40 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
 // ---------------------------------------------------------------------------------------------- launchers
 void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t, float* sig_t32) {
+                      double* sig_t, float* sig_t32, int ny) {
     hipLaunchKernelGGL(k_linearize, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, sigma, rho_cv, q_ext, T,
-                       dt, a, c, D, sig_s, q, sig_t, sig_t32);
+                       dt, a, c, D, sig_s, q, sig_t, sig_t32, ny);
 }
 
 template <typename TS>
 void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0, const double* q,
-                 const double* sig_s, double inv_cdt, TS* src0, double* phi, TS* s_e) {
+                 const double* sig_s, double inv_cdt, TS* src0, size_t ld, double* phi, TS* s_e, int ny) {
     dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
     if (r <= 8)
-        hipLaunchKernelGGL((k_psi0<TS, 8>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+        hipLaunchKernelGGL((k_psi0<TS, 8>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
     else if (r <= 16)
-        hipLaunchKernelGGL((k_psi0<TS, 16>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+        hipLaunchKernelGGL((k_psi0<TS, 16>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_psi0<TS, 32>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+        hipLaunchKernelGGL((k_psi0<TS, 32>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
     else
-        hipLaunchKernelGGL((k_psi0<TS, 64>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, phi, s_e);
+        hipLaunchKernelGGL((k_psi0<TS, 64>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
 }
 template void launch_psi0<double>(hipStream_t, int, int, const double*, const double*, const double*,
-                                  const double*, const double*, double, double*, double*, double*);
+                                  const double*, const double*, double, double*, size_t, double*, double*, int);
 template void launch_psi0<float>(hipStream_t, int, int, const double*, const double*, const double*, const double*,
-                                 const double*, double, float*, double*, float*);
+                                 const double*, double, float*, size_t, double*, float*, int);
 
 template <typename TS>
-void launch_phi(hipStream_t s, int n, int r, const TS* psi, const double* cw, const double* sig_s,
+void launch_phi(hipStream_t s, int n, int r, const TS* psi, size_t ld, const double* cw, const double* sig_s,
                 const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter,
-                double* out) {
-    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, n, r, psi, cw, sig_s, phi_old, phi_new, s_e,
-                       partials, counter, out);
+                double* out, int ny) {
+    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, n, r, psi, ld, cw, sig_s, phi_old, phi_new,
+                       s_e, partials, counter, out, ny);
 }
-template void launch_phi<double>(hipStream_t, int, int, const double*, const double*, const double*, const double*,
-                                 double*, double*, double*, int, unsigned*, double*);
-template void launch_phi<float>(hipStream_t, int, int, const float*, const double*, const double*, const double*,
-                                double*, float*, double*, int, unsigned*, double*);
+template void launch_phi<double>(hipStream_t, int, int, const double*, size_t, const double*, const double*,
+                                 const double*, double*, double*, double*, int, unsigned*, double*, int);
+template void launch_phi<float>(hipStream_t, int, int, const float*, size_t, const double*, const double*,
+                                const double*, double*, float*, double*, int, unsigned*, double*, int);
 
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area, double* T,

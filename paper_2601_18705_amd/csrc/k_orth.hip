@@ -79,7 +79,7 @@ __device__ double wnorm(const OrthCtx& c, int k, double* sh) {
 }
 
 template <typename TV>
-__global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* __restrict__ V,
+__global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
                                                        const double* __restrict__ weight, double wscalar,
                                                        int comp_kind, int nx, int ny, const double* __restrict__ mu,
                                                        const double* __restrict__ eta, double* __restrict__ Q,
@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
     bool out_of_completions = false;
     for (int k = 0; k < r; ++k) {
         double* v = Q + (size_t)k * n;
-        for (long e = t; e < n; e += kOrthThreads) v[e] = (double)V[(size_t)k * n + e];
+        for (long e = t; e < n; e += kOrthThreads)
+            v[e] = (double)V[(size_t)k * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
         __syncthreads();
         const double own = wnorm(c, k, sh);
         project_twice(c, k, hsum, red, h);
@@ -122,8 +123,8 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
             }
             for (long e = t; e < n; e += kOrthThreads) {
                 double bx, by;
-                if (comp_kind == 0) {
-                    const long i = e % nx, j = e / nx;
+                if (comp_kind == 0) {   // column-major cells e = i*ny + j
+                    const long i = e / ny, j = e % ny;
                     bx = -1.0 + (i + 0.5) * 2.0 / nx;
                     by = -1.0 + (j + 0.5) * 2.0 / ny;
                 } else {
@@ -156,15 +157,15 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
 }  // namespace
 
 template <typename TV>
-void launch_cgs2(hipStream_t s, long n, int r, const TV* V, const double* weight, double wscalar, int comp_kind,
-                 int nx, int ny, const double* mu, const double* eta, double* Q, double* R, int* flag,
-                 int flag_mask, int* status, int status_code) {
-    hipLaunchKernelGGL((k_cgs2<TV>), dim3(1), dim3(kOrthThreads), 0, s, n, r, V, weight, wscalar, comp_kind, nx, ny,
-                       mu, eta, Q, R, flag, flag_mask, status, status_code);
+void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
+                 double wscalar, int comp_kind, int nx, int ny, const double* mu, const double* eta, double* Q,
+                 double* R, int* flag, int flag_mask, int* status, int status_code) {
+    hipLaunchKernelGGL((k_cgs2<TV>), dim3(1), dim3(kOrthThreads), 0, s, n, r, V, ldv, pad_ny, weight, wscalar,
+                       comp_kind, nx, ny, mu, eta, Q, R, flag, flag_mask, status, status_code);
 }
-template void launch_cgs2<double>(hipStream_t, long, int, const double*, const double*, double, int, int, int,
-                                  const double*, const double*, double*, double*, int*, int, int*, int);
-template void launch_cgs2<float>(hipStream_t, long, int, const float*, const double*, double, int, int, int,
-                                 const double*, const double*, double*, double*, int*, int, int*, int);
+template void launch_cgs2<double>(hipStream_t, long, int, const double*, size_t, int, const double*, double, int, int,
+                                  int, const double*, const double*, double*, double*, int*, int, int*, int);
+template void launch_cgs2<float>(hipStream_t, long, int, const float*, size_t, int, const double*, double, int, int,
+                                 int, const double*, const double*, double*, double*, int*, int, int*, int);
 
 }  // namespace dlr

@@ -16,7 +16,7 @@ constexpr int kGramChunk = 64;
 // ---------------------------------------------------------------------------------------------- Gram
 // partial_b[i*r + j] = scalar * sum_{e in block b} wgt_e V_i(e) V_j(e), V [r][n].
 template <typename TV, int EPT>
-__global__ __launch_bounds__(kBlock) void k_gram(int n, int r, const TV* __restrict__ V,
+__global__ __launch_bounds__(kBlock) void k_gram(int n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
                                                  const double* __restrict__ weight, double scalar,
                                                  double* __restrict__ partials) {
     __shared__ double sV[kMaxRank * kGramChunk];
@@ -36,7 +36,9 @@ __global__ __launch_bounds__(kBlock) void k_gram(int n, int r, const TV* __restr
         __syncthreads();
         for (int idx = threadIdx.x; idx < r * kGramChunk; idx += kBlock) {
             const int k = idx / kGramChunk, c = idx % kGramChunk;
-            sV[k * kGramChunk + c] = (c < cn) ? (double)V[(size_t)k * n + c0 + c] : 0.0;
+            const long e = c0 + c;
+            sV[k * kGramChunk + c] =
+                (c < cn) ? (double)V[(size_t)k * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)] : 0.0;
         }
         for (int c = threadIdx.x; c < kGramChunk; c += kBlock) sw[c] = (c < cn) ? (weight ? weight[c0 + c] : 1.0) : 0.0;
         __syncthreads();
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_chol(int r, const double* __restrict
 
 // ---------------------------------------------------------------------------------------------- X = V Rinv
 template <typename TV, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restrict__ V,
+__global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
                                                  const double* __restrict__ Rinv, double* __restrict__ X) {
     __shared__ double sR[RMAX * RMAX];
     for (int o = threadIdx.x; o < r * r; o += kBlock) sR[(o / r) * RMAX + o % r] = Rinv[o];
@@ -132,8 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double v[RMAX];
+    const size_t ve = pad_ny ? padded_cell(e, pad_ny) : (size_t)e;
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) v[j] = (j < r) ? (double)V[(size_t)j * n + e] : 0.0;
+    for (int j = 0; j < RMAX; ++j) v[j] = (j < r) ? (double)V[(size_t)j * ldv + ve] : 0.0;
 #pragma unroll 4
     for (int k = 0; k < r; ++k) {
         double acc = 0.0;
@@ -146,8 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
 
 // ---------------------------------------------------------------------------------------------- projections
 // Raw split-K sums per block, layout [5 r^2 matrices][5 r vectors]:
-//   M0 = sum X_i(e) X_j(e - 1)        (x-upwind neighbour for mu > 0, 0 on column 0)
-//   M1 = sum X_i(e) X_j(e - nx)       (y-upwind neighbour for eta > 0, 0 on row 0)
+//   M0 = sum X_i(i,j) X_j(i-1,j)      (x-upwind neighbour for mu > 0, 0 on column 0)
+//   M1 = sum X_i(i,j) X_j(i,j-1)      (y-upwind neighbour for eta > 0, 0 on row 0)
+// with column-major cells e = i*ny + j, so (i-1,j) = e - ny and (i,j-1) = e - 1.
 //   M2 = sum sigma_e X_i X_j,  M3 = sum sigma_s,e X_i X_j,  M4 = sum X0_i X_j
 //   v0 = sum q_e X_i,  v1..v4 = sum over the left/right/bottom/top cells of X_i
 constexpr int kProjChunk = 32;
@@ -184,11 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_project(int nx, int ny, int r, const
             double x = 0.0, xl = 0.0, xd = 0.0, x0 = 0.0;
             if (c < cn) {
                 const long e = c0 + c;
-                const int i = (int)(e % nx), j = (int)(e / nx);
+                const int i = (int)(e / ny), j = (int)(e % ny);
                 const double* col = X + (size_t)k * n;
                 x = col[e];
-                xl = (i > 0) ? col[e - 1] : 0.0;
-                xd = (j > 0) ? col[e - nx] : 0.0;
+                xl = (i > 0) ? col[e - ny] : 0.0;
+                xd = (j > 0) ? col[e - 1] : 0.0;
                 x0 = X0[(size_t)k * n + e];
             }
             sX[k * kProjChunk + c] = x;
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_project(int nx, int ny, int r, const
             sq[c] = ok ? q[e] : 0.0;
             int f = 0;
             if (ok) {
-                const int i = (int)(e % nx), j = (int)(e / nx);
+                const int i = (int)(e / ny), j = (int)(e % ny);
                 f = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
             }
             sside[c] = f;
@@ -308,19 +312,22 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
 }  // namespace
 
 template <typename TV>
-void launch_gram(hipStream_t s, int n, int r, const TV* V, const double* weight, double scalar_weight,
-                 double* partials, int nblocks) {
+void launch_gram(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
+                 double scalar_weight, double* partials, int nblocks) {
     const int ept = (r * r + kBlock - 1) / kBlock;
     if (ept <= 1)
-        hipLaunchKernelGGL((k_gram<TV, 1>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, weight, scalar_weight, partials);
+        hipLaunchKernelGGL((k_gram<TV, 1>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
+                           partials);
     else if (ept <= 4)
-        hipLaunchKernelGGL((k_gram<TV, 4>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, weight, scalar_weight, partials);
+        hipLaunchKernelGGL((k_gram<TV, 4>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
+                           partials);
     else
-        hipLaunchKernelGGL((k_gram<TV, 16>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, weight, scalar_weight,
+        hipLaunchKernelGGL((k_gram<TV, 16>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
                            partials);
 }
-template void launch_gram<double>(hipStream_t, int, int, const double*, const double*, double, double*, int);
-template void launch_gram<float>(hipStream_t, int, int, const float*, const double*, double, double*, int);
+template void launch_gram<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double, double*,
+                                  int);
+template void launch_gram<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double, double*, int);
 
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv, int* status,
                  int status_code) {
@@ -328,19 +335,19 @@ void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, doub
 }
 
 template <typename TV>
-void launch_trmm(hipStream_t s, int n, int r, const TV* V, const double* Rinv, double* X) {
+void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X) {
     dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
     if (r <= 8)
-        hipLaunchKernelGGL((k_trmm<TV, 8>), g, b, 0, s, n, r, V, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 8>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
     else if (r <= 16)
-        hipLaunchKernelGGL((k_trmm<TV, 16>), g, b, 0, s, n, r, V, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 16>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_trmm<TV, 32>), g, b, 0, s, n, r, V, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 32>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
     else
-        hipLaunchKernelGGL((k_trmm<TV, 64>), g, b, 0, s, n, r, V, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 64>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
 }
-template void launch_trmm<double>(hipStream_t, int, int, const double*, const double*, double*);
-template void launch_trmm<float>(hipStream_t, int, int, const float*, const double*, double*);
+template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double*);
+template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double*);
 
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
                     const double* sig_s, const double* q, double area, double hx, double hy, double* partials,
