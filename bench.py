@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="after the timed run, copy a buffer of this size with torch (counter calibration)")
+                    help="after the timed run, run a plain elementwise kernel over a buffer of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -142,7 +142,7 @@ def main():
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)   # one elementwise kernel: reads and writes n * 4 bytes
         torch.cuda.synchronize()
 
     out = {
