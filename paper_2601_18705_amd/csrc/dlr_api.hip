@@ -97,7 +97,7 @@ struct dlr_instance {
     double* norm_out = nullptr;
     double* energy_out = nullptr;
     unsigned* counters = nullptr;
-    double *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
+    double *Gm = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
     double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
     double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr;
     int* status = nullptr;
@@ -106,7 +106,7 @@ struct dlr_instance {
     int* h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch shapes
-    int nb_cells = 256, nb_gram = 256, nb_proj = 256, red_blocks = 64;
+    int nb_cells = 256, nb_gram = 512, nb_proj = 512, red_blocks = 64;
 
     bool fp32() const { return prec != DLR_FP64; }
     size_t sweep_bytes() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -157,6 +157,7 @@ struct dlr_instance {
         norm_out = A.take<double>(4);
         energy_out = A.take<double>(2);
         counters = A.take<unsigned>(8);
+        Gm = A.take<double>(R * R);
         R1 = A.take<double>(R * R);
         R1i = A.take<double>(R * R);
         R2 = A.take<double>(R * R);
@@ -312,18 +313,17 @@ dlr_status step_once(dlr_instance* I) {
     if (ds != DLR_OK) return ds;
 
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
-    dlr::launch_gram<TS>(s, N, r, psi, I->ld, I->ny, nullptr, I->area, I->partials, I->nb_gram);
-    dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_gram<TS>(s, N, r, psi, I->ld, I->ny, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<TS>(s, N, r, psi, I->ld, I->ny, I->R1i, I->Xt);
-    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, nullptr, I->area, I->partials, I->nb_gram);
-    dlr::launch_chol(s, r, I->partials, I->nb_gram, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, 0, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
     dlr::launch_cgs2<TS>(s, N, r, psi, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
     // 6-7. projections on the new basis and the L-step for every ordinate
-    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->area, I->hx, I->hy, I->partials,
-                        I->nb_proj);
+    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj);
     dlr::launch_project_finalize(s, r, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops);
     dlr::LstepArgs la{};
     la.nq = nq; la.r = r; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;

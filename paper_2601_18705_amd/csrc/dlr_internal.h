@@ -84,23 +84,23 @@ template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>& a);
 
 // ----------------------------------------------------------------------------- reductions
-// V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny)
+// V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny).
+// G = scale * V^T V (r x r, row-major), via per-block partials in work [nblocks][r^2].
 template <typename TV>
-void launch_gram(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
-                 double scalar_weight, double* partials, int nblocks);
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, double scale, double* work,
+                 int nblocks, double* G);
+// Cholesky QR step: G (the sum of nblocks partial Gram matrices) -> R, Rinv; a pivot
+// too small for Cholesky QR sets status_code in *status
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,
                  int* status, int status_code);
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X);
 
-struct ProjectOut {
-    // raw sums (split-K partials reduced by launch_project_finalize)
-    double* partials;   // [nblocks][5 r^2 + 5 r]
-    int nblocks;
-};
+// Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip)
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double area, double hx, double hy, double* partials,
-                    int nblocks);
+                    const double* sig_s, const double* q, double* partials, int nblocks);
+// raw[o] = area * sum over blocks of partials[b][o]
+void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw);
 // Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r]
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
                              double inv_cdt, const double* S0, double* ops);

@@ -1,0 +1,279 @@
+// Tall-skinny contractions over the cells on the FP64 matrix cores:
+//   * Gram matrices V^T V of the swept columns (Cholesky QR of Algorithm 1 step 5);
+//   * the Galerkin projections of the L-step (Sec. 4.3): <X_i, X_j(left neighbour)>,
+//     <X_i, X_j(lower neighbour)>, <X_i, sigma X_j>, <X_i, sigma_s X_j>, <X0_i, X_j>,
+//     and the vectors <q, X_i> and the sums of X_i over the four boundary sides.
+//
+// Each block walks chunks of 64 consecutive (column-major) cells, stages the r
+// basis columns of a chunk in LDS as FP64, and its four wavefronts each own a
+// fixed set of 16 x 16 output tiles, accumulated with v_mfma_f64_16x16x4 over
+// the 16 four-cell k-steps of the chunk.  Partial sums are written per block and
+// added by k_sum_partials in a fixed order, so every result is bitwise
+// reproducible.
+#include "dlr_internal.h"
+
+namespace dlr {
+
+namespace {
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;   // four wavefronts
+constexpr int kPC = 64;         // cells per chunk = 16 k-steps of 4 cells
+constexpr int kPS = kPC + 4;    // LDS row stride (doubles): one leading neighbour slot, spreads the banks
+
+__device__ __forceinline__ dv4 mfma4(double a, double b, dv4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Operands of v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; its accumulator
+// element v holds D[4*v + l/16][l%16] (measured on gfx950; the FP32 16x16x4 form differs).
+__device__ __forceinline__ void store_tile(double* out, int r, int ti, int tj, dv4 acc, double scale) {
+    const int lane = threadIdx.x & 63;
+    const int j = tj * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + 4 * v + (lane >> 4);
+        if (i < r && j < r) out[i * r + j] = acc[v] * scale;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------ Gram
+// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) V_j(e)
+template <typename TV, int RT>
+__global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV* __restrict__ V, size_t ldv,
+                                                        int pad_ny, double scale, double* __restrict__ partials) {
+    constexpr int RP = 16 * RT, NT = RT * RT, TPW = (NT + 3) / 4;
+    __shared__ double sV[RP * kPS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    dv4 acc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) acc[s] = dv4{0.0, 0.0, 0.0, 0.0};
+    const long nch = (n + kPC - 1) / kPC;
+    for (long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const long c0 = ch * kPC;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < RP * kPC; idx += kThreads) {
+            const int p = idx / kPC, c = idx % kPC;
+            const long e = c0 + c;
+            double v = 0.0;
+            if (p < r && e < n) v = (double)V[(size_t)p * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
+            sV[p * kPS + c] = v;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kPC / 4; ++ks) {
+            const int c = 4 * ks + (lane >> 4);
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const int t = w + 4 * s;
+                if (t < NT) {
+                    const int ti = t / RT, tj = t % RT;
+                    acc[s] = mfma4(sV[(ti * 16 + (lane & 15)) * kPS + c], sV[(tj * 16 + (lane & 15)) * kPS + c],
+                                   acc[s]);
+                }
+            }
+        }
+    }
+    double* out = partials + (size_t)blockIdx.x * r * r;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + 4 * s;
+        if (t < NT) store_tile(out, r, t / RT, t % RT, acc[s], scale);
+    }
+}
+
+// ------------------------------------------------------------------------------------------ projections
+// Partial layout per block: [5 r^2 matrices][5 r vectors]
+//   M0 = sum X_i(i,j) X_j(i-1,j)   (x-upwind neighbour, 0 on column 0)
+//   M1 = sum X_i(i,j) X_j(i,j-1)   (y-upwind neighbour, 0 on row 0)
+//   M2 = sum sigma X_i X_j,  M3 = sum sigma_s X_i X_j,  M4 = sum X0_i X_j
+//   v0 = sum q X_i,  v1..v4 = sums of X_i over the left / right / bottom / top cells
+// Column-major cells e = i*ny + j: (i-1,j) = e - ny and (i,j-1) = e - 1.
+template <int RT>
+__global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r, const double* __restrict__ X,
+                                                           const double* __restrict__ X0,
+                                                           const double* __restrict__ sigma,
+                                                           const double* __restrict__ sig_s,
+                                                           const double* __restrict__ q,
+                                                           double* __restrict__ partials) {
+    constexpr int RP = 16 * RT, NT = 5 * RT * RT, TPW = (NT + 3) / 4;
+    constexpr int TPP = kThreads / RP;   // threads per basis column for the vectors
+    __shared__ double sX[RP * kPS];      // slot c+1 holds cell c0+c, slot 0 the cell before the chunk
+    __shared__ double sXl[RP * kPS];     // X at the left neighbour (e - ny)
+    __shared__ double sX0[RP * kPS];
+    __shared__ double sSig[kPC], sSs[kPC], sQ[kPC];
+    __shared__ int sFlag[kPC];           // bit0 left side, bit1 right, bit2 bottom, bit3 top
+    __shared__ double red[5][kThreads];
+    const long n = (long)nx * ny;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    dv4 acc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) acc[s] = dv4{0.0, 0.0, 0.0, 0.0};
+    const int pv = threadIdx.x % RP, cv = threadIdx.x / RP;
+    double vq = 0.0, vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
+    const long nch = (n + kPC - 1) / kPC;
+    for (long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const long c0 = ch * kPC;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < RP * (kPC + 1); idx += kThreads) {
+            const int p = idx / (kPC + 1), c = idx % (kPC + 1) - 1;
+            const long e = c0 + c;
+            double v = 0.0;
+            if (p < r && e >= 0 && e < n) v = X[(size_t)p * n + e];
+            sX[p * kPS + c + 1] = v;
+        }
+        for (int idx = threadIdx.x; idx < RP * kPC; idx += kThreads) {
+            const int p = idx / kPC, c = idx % kPC;
+            const long e = c0 + c;
+            double vx = 0.0, v0 = 0.0;
+            if (p < r && e < n) {
+                if (e >= ny) vx = X[(size_t)p * n + e - ny];
+                v0 = X0[(size_t)p * n + e];
+            }
+            sXl[p * kPS + c] = vx;
+            sX0[p * kPS + c] = v0;
+        }
+        for (int c = threadIdx.x; c < kPC; c += kThreads) {
+            const long e = c0 + c;
+            double sg = 0.0, ss = 0.0, qq = 0.0;
+            int f = 0;
+            if (e < n) {
+                sg = sigma[e];
+                ss = sig_s[e];
+                qq = q[e];
+                const long i = e / ny, j = e % ny;
+                f = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
+            }
+            sSig[c] = sg;
+            sSs[c] = ss;
+            sQ[c] = qq;
+            sFlag[c] = f;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kPC / 4; ++ks) {
+            const int c = 4 * ks + (lane >> 4);
+            const bool bottom = (sFlag[c] & 4) != 0;   // no lower neighbour
+            const double sg = sSig[c], ss = sSs[c];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const int t = w + 4 * s;
+                if (t < NT) {
+                    const int m = t / (RT * RT), ti = (t / RT) % RT, tj = t % RT;
+                    const int pa = ti * 16 + (lane & 15), pb = tj * 16 + (lane & 15);
+                    const double a = (m == 4) ? sX0[pa * kPS + c] : sX[pa * kPS + c + 1];
+                    const double xb = sX[pb * kPS + c + 1];
+                    double b;
+                    if (m == 0) b = sXl[pb * kPS + c];
+                    else if (m == 1) b = bottom ? 0.0 : sX[pb * kPS + c];
+                    else if (m == 2) b = sg * xb;
+                    else if (m == 3) b = ss * xb;
+                    else b = xb;
+                    acc[s] = mfma4(a, b, acc[s]);
+                }
+            }
+        }
+        if (pv < r) {
+            for (int c = cv; c < kPC; c += TPP) {
+                const double x = sX[pv * kPS + c + 1];
+                const int f = sFlag[c];
+                vq += sQ[c] * x;
+                if (f & 1) vl += x;
+                if (f & 2) vr += x;
+                if (f & 4) vb += x;
+                if (f & 8) vt += x;
+            }
+        }
+    }
+    const int rr = r * r;
+    double* out = partials + (size_t)blockIdx.x * (5 * rr + 5 * r);
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + 4 * s;
+        if (t < NT) {
+            const int m = t / (RT * RT), ti = (t / RT) % RT, tj = t % RT;
+            store_tile(out + m * rr, r, ti, tj, acc[s], 1.0);
+        }
+    }
+    __syncthreads();
+    red[0][threadIdx.x] = vq;
+    red[1][threadIdx.x] = vl;
+    red[2][threadIdx.x] = vr;
+    red[3][threadIdx.x] = vb;
+    red[4][threadIdx.x] = vt;
+    __syncthreads();
+    for (int o = threadIdx.x; o < 5 * r; o += kThreads) {
+        const int kind = o / r, p = o % r;
+        double acc_v = 0.0;
+        for (int k = 0; k < TPP; ++k) acc_v += red[kind][p + k * RP];
+        out[5 * rr + o] = acc_v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------ partial sums
+// out[o] = scale * sum_b partials[b*total + o]: 16 slices of blocks (fixed stride order) per output, the
+// slices added in order; 64 outputs per workgroup.
+__global__ __launch_bounds__(1024) void k_sum_partials(int total, const double* __restrict__ partials, int nblocks,
+                                                       double scale, double* __restrict__ out) {
+    __shared__ double red[16][64];
+    const int ol = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + ol;
+    double a0 = 0.0, a1 = 0.0;
+    if (o < total) {
+        int b = sl;
+        for (; b + 16 < nblocks; b += 32) {
+            a0 += partials[(size_t)b * total + o];
+            a1 += partials[(size_t)(b + 16) * total + o];
+        }
+        if (b < nblocks) a0 += partials[(size_t)b * total + o];
+    }
+    red[sl][ol] = a0 + a1;
+    __syncthreads();
+    if (sl == 0 && o < total) {
+        double s = 0.0;
+        for (int k = 0; k < 16; ++k) s += red[k][ol];
+        out[o] = s * scale;
+    }
+}
+
+void sum_partials(hipStream_t s, int total, const double* partials, int nblocks, double scale, double* out) {
+    hipLaunchKernelGGL(k_sum_partials, dim3((total + 63) / 64), dim3(1024), 0, s, total, partials, nblocks, scale,
+                       out);
+}
+
+}  // namespace
+
+template <typename TV>
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, double scale, double* work,
+                 int nblocks, double* G) {
+    const dim3 g(nblocks), b(kThreads);
+    if (r <= 16)
+        hipLaunchKernelGGL((k_gram_mfma<TV, 1>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+    else if (r <= 32)
+        hipLaunchKernelGGL((k_gram_mfma<TV, 2>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+    else if (r <= 48)
+        hipLaunchKernelGGL((k_gram_mfma<TV, 3>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+    else
+        hipLaunchKernelGGL((k_gram_mfma<TV, 4>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+    sum_partials(s, r * r, work, nblocks, 1.0, G);
+}
+template void launch_gram<double>(hipStream_t, long, int, const double*, size_t, int, double, double*, int, double*);
+template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, int, double, double*, int, double*);
+
+void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
+                    const double* sig_s, const double* q, double* partials, int nblocks) {
+    const dim3 g(nblocks), b(kThreads);
+    if (r <= 16)
+        hipLaunchKernelGGL((k_project_mfma<1>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+    else if (r <= 32)
+        hipLaunchKernelGGL((k_project_mfma<2>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+    else if (r <= 48)
+        hipLaunchKernelGGL((k_project_mfma<3>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+    else
+        hipLaunchKernelGGL((k_project_mfma<4>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+}
+
+void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw) {
+    sum_partials(s, 5 * r * r + 5 * r, partials, nblocks, area, raw);
+}
+
+}  // namespace dlr

@@ -1,9 +1,8 @@
-// Tall-skinny reductions over cells (or ordinates): Gram matrices for the
-// Cholesky-QR orthonormalisation of the swept columns and of L, the triangular
-// right-multiply that forms the orthonormal factor, and the Galerkin
-// projections of the L-step (A(Omega), M_t, M_s, <X0, X>, <X, q>, inflow faces).
-// Every sum is split over blocks and the partials are added in a fixed order,
-// so results are bitwise reproducible run to run.
+// Cholesky QR of the swept columns (Algorithm 1 step 5): the Cholesky factor of
+// the Gram matrix and the triangular right-multiply that forms the orthonormal
+// factor; and the assembly of the L-step operators (Sec. 4.3) from the raw
+// projection sums.  The Gram matrices and projection sums themselves are formed
+// on the matrix cores (k_mfma.hip).
 #include "dlr_internal.h"
 
 namespace dlr {
@@ -11,52 +10,6 @@ namespace dlr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kGramChunk = 64;
-
-// ---------------------------------------------------------------------------------------------- Gram
-// partial_b[i*r + j] = scalar * sum_{e in block b} wgt_e V_i(e) V_j(e), V [r][n].
-template <typename TV, int EPT>
-__global__ __launch_bounds__(kBlock) void k_gram(int n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
-                                                 const double* __restrict__ weight, double scalar,
-                                                 double* __restrict__ partials) {
-    __shared__ double sV[kMaxRank * kGramChunk];
-    __shared__ double sw[kGramChunk];
-    const int rr = r * r;
-    double acc[EPT];
-    int oi[EPT], oj[EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        acc[k] = 0.0;
-        const int o = threadIdx.x + k * kBlock;
-        oi[k] = (o < rr) ? o / r : 0;
-        oj[k] = (o < rr) ? o % r : 0;
-    }
-    for (long c0 = (long)blockIdx.x * kGramChunk; c0 < n; c0 += (long)gridDim.x * kGramChunk) {
-        const int cn = (int)min((long)kGramChunk, n - c0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < r * kGramChunk; idx += kBlock) {
-            const int k = idx / kGramChunk, c = idx % kGramChunk;
-            const long e = c0 + c;
-            sV[k * kGramChunk + c] =
-                (c < cn) ? (double)V[(size_t)k * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)] : 0.0;
-        }
-        for (int c = threadIdx.x; c < kGramChunk; c += kBlock) sw[c] = (c < cn) ? (weight ? weight[c0 + c] : 1.0) : 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            const double* vi = sV + oi[k] * kGramChunk;
-            const double* vj = sV + oj[k] * kGramChunk;
-            double a = acc[k];
-            for (int c = 0; c < kGramChunk; ++c) a += (vi[c] * sw[c]) * vj[c];
-            acc[k] = a;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        const int o = threadIdx.x + k * kBlock;
-        if (o < rr) partials[(size_t)blockIdx.x * rr + o] = acc[k] * scalar;
-    }
-}
 
 // ---------------------------------------------------------------------------------------------- Cholesky
 // G = sum of partials (block order); column scaling s_k = 1/sqrt(G_kk); upper Cholesky
@@ -147,135 +100,6 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
     }
 }
 
-// ---------------------------------------------------------------------------------------------- projections
-// Raw split-K sums per block, layout [5 r^2 matrices][5 r vectors]:
-//   M0 = sum X_i(i,j) X_j(i-1,j)      (x-upwind neighbour for mu > 0, 0 on column 0)
-//   M1 = sum X_i(i,j) X_j(i,j-1)      (y-upwind neighbour for eta > 0, 0 on row 0)
-// with column-major cells e = i*ny + j, so (i-1,j) = e - ny and (i,j-1) = e - 1.
-//   M2 = sum sigma_e X_i X_j,  M3 = sum sigma_s,e X_i X_j,  M4 = sum X0_i X_j
-//   v0 = sum q_e X_i,  v1..v4 = sum over the left/right/bottom/top cells of X_i
-constexpr int kProjChunk = 32;
-
-template <int EPT>
-__global__ __launch_bounds__(kBlock) void k_project(int nx, int ny, int r, const double* __restrict__ X,
-                                                    const double* __restrict__ X0, const double* __restrict__ sigma,
-                                                    const double* __restrict__ sig_s, const double* __restrict__ q,
-                                                    double* __restrict__ partials) {
-    __shared__ double sX[kMaxRank * kProjChunk];
-    __shared__ double sL[kMaxRank * kProjChunk];
-    __shared__ double sD[kMaxRank * kProjChunk];
-    __shared__ double s0[kMaxRank * kProjChunk];
-    __shared__ double ss[kProjChunk], sss[kProjChunk], sq[kProjChunk];
-    __shared__ int sside[kProjChunk];
-    const long n = (long)nx * ny;
-    const int rr = r * r;
-    double a0[EPT], a1[EPT], a2[EPT], a3[EPT], a4[EPT];
-    int oi[EPT], oj[EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        a0[k] = a1[k] = a2[k] = a3[k] = a4[k] = 0.0;
-        const int o = threadIdx.x + k * kBlock;
-        oi[k] = (o < rr) ? o / r : 0;
-        oj[k] = (o < rr) ? o % r : 0;
-    }
-    // vector entries: slot = threadIdx.x + m * kBlock < 5 r (two slots cover r <= 64)
-    double vacc[2] = {0.0, 0.0};
-    for (long c0 = (long)blockIdx.x * kProjChunk; c0 < n; c0 += (long)gridDim.x * kProjChunk) {
-        const int cn = (int)min((long)kProjChunk, n - c0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < r * kProjChunk; idx += kBlock) {
-            const int k = idx / kProjChunk, c = idx % kProjChunk;
-            double x = 0.0, xl = 0.0, xd = 0.0, x0 = 0.0;
-            if (c < cn) {
-                const long e = c0 + c;
-                const int i = (int)(e / ny), j = (int)(e % ny);
-                const double* col = X + (size_t)k * n;
-                x = col[e];
-                xl = (i > 0) ? col[e - ny] : 0.0;
-                xd = (j > 0) ? col[e - 1] : 0.0;
-                x0 = X0[(size_t)k * n + e];
-            }
-            sX[k * kProjChunk + c] = x;
-            sL[k * kProjChunk + c] = xl;
-            sD[k * kProjChunk + c] = xd;
-            s0[k * kProjChunk + c] = x0;
-        }
-        for (int c = threadIdx.x; c < kProjChunk; c += kBlock) {
-            const long e = c0 + c;
-            const bool ok = c < cn;
-            ss[c] = ok ? sigma[e] : 0.0;
-            sss[c] = ok ? sig_s[e] : 0.0;
-            sq[c] = ok ? q[e] : 0.0;
-            int f = 0;
-            if (ok) {
-                const int i = (int)(e / ny), j = (int)(e % ny);
-                f = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
-            }
-            sside[c] = f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            const double* xi = sX + oi[k] * kProjChunk;
-            const double* xj = sX + oj[k] * kProjChunk;
-            const double* xlj = sL + oj[k] * kProjChunk;
-            const double* xdj = sD + oj[k] * kProjChunk;
-            const double* x0i = s0 + oi[k] * kProjChunk;
-            double b0 = a0[k], b1 = a1[k], b2 = a2[k], b3 = a3[k], b4 = a4[k];
-            for (int c = 0; c < kProjChunk; ++c) {
-                const double u = xi[c];
-                const double v = xj[c];
-                b0 += u * xlj[c];
-                b1 += u * xdj[c];
-                b2 += (u * ss[c]) * v;
-                b3 += (u * sss[c]) * v;
-                b4 += x0i[c] * v;
-            }
-            a0[k] = b0; a1[k] = b1; a2[k] = b2; a3[k] = b3; a4[k] = b4;
-        }
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int vslot = threadIdx.x + m * kBlock;
-            if (vslot < 5 * r) {
-                const int vkind = vslot / r, vi = vslot % r;
-                const double* xi = sX + vi * kProjChunk;
-                double acc = vacc[m];
-                for (int c = 0; c < kProjChunk; ++c) {
-                    if (vkind == 0) acc += sq[c] * xi[c];
-                    else if (sside[c] & (1 << (vkind - 1))) acc += xi[c];
-                }
-                vacc[m] = acc;
-            }
-        }
-    }
-    double* out = partials + (size_t)blockIdx.x * (5 * rr + 5 * r);
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        const int o = threadIdx.x + k * kBlock;
-        if (o < rr) {
-            out[o] = a0[k];
-            out[rr + o] = a1[k];
-            out[2 * rr + o] = a2[k];
-            out[3 * rr + o] = a3[k];
-            out[4 * rr + o] = a4[k];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const int vslot = threadIdx.x + m * kBlock;
-        if (vslot < 5 * r) out[5 * rr + vslot] = vacc[m];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_project_reduce(int total, const double* __restrict__ partials,
-                                                           int nblocks, double area, double* __restrict__ raw) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= total) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) acc += partials[(size_t)b * total + o];
-    raw[o] = acc * area;
-}
-
 // ops layout: Axp, Axm, Ayp, Aym, Mt, Ms, G (r x r each), qX[r], b[4][r]
 //   A_x^+ = <X, D_x^+ X> = (I - M0)/hx   (X orthonormal), A_x^- = (I - M0^T)/hx, same for y;
 //   M_t = <X, sigma X> + I/(c dt);  G = S0^T P with P_ik = <X0_i, X_k> (old solution onto new X)
@@ -311,24 +135,6 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
 
 }  // namespace
 
-template <typename TV>
-void launch_gram(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
-                 double scalar_weight, double* partials, int nblocks) {
-    const int ept = (r * r + kBlock - 1) / kBlock;
-    if (ept <= 1)
-        hipLaunchKernelGGL((k_gram<TV, 1>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
-                           partials);
-    else if (ept <= 4)
-        hipLaunchKernelGGL((k_gram<TV, 4>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
-                           partials);
-    else
-        hipLaunchKernelGGL((k_gram<TV, 16>), dim3(nblocks), dim3(kBlock), 0, s, n, r, V, ldv, pad_ny, weight, scalar_weight,
-                           partials);
-}
-template void launch_gram<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double, double*,
-                                  int);
-template void launch_gram<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double, double*, int);
-
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv, int* status,
                  int status_code) {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kBlock), 0, s, r, partials, nblocks, R, Rinv, status, status_code);
@@ -349,29 +155,13 @@ void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_n
 template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double*);
 template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double*);
 
-void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double area, double hx, double hy, double* partials,
-                    int nblocks) {
-    (void)area; (void)hx; (void)hy;
-    const int ept = (r * r + kBlock - 1) / kBlock;
-    if (ept <= 1)
-        hipLaunchKernelGGL((k_project<1>), dim3(nblocks), dim3(kBlock), 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
-    else if (ept <= 4)
-        hipLaunchKernelGGL((k_project<4>), dim3(nblocks), dim3(kBlock), 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
-    else
-        hipLaunchKernelGGL((k_project<16>), dim3(nblocks), dim3(kBlock), 0, s, nx, ny, r, X, X0, sigma, sig_s, q,
-                           partials);
-}
-
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
                              double inv_cdt, const double* S0, double* ops) {
     // raw sums go into the tail of ops (beyond the operator block) as scratch
     const int rr = r * r;
-    const int total = 5 * rr + 5 * r;
     double* raw = ops + 7 * rr + 5 * r;
     const double area = hx * hy;
-    hipLaunchKernelGGL(k_project_reduce, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s, total, partials,
-                       nblocks, area, raw);
+    launch_project_sum(s, r, partials, nblocks, area, raw);
     hipLaunchKernelGGL(k_project_ops, dim3(1), dim3(kBlock), 0, s, r, raw, hx, hy, inv_cdt, S0, ops);
 }
 
