@@ -81,7 +81,7 @@ struct dlr_instance {
     double *X = nullptr, *Xn = nullptr, *Xt = nullptr;
     double *S = nullptr, *Sn = nullptr;
     double *W = nullptr, *Wt = nullptr, *Wq = nullptr, *L = nullptr;
-    void *psi = nullptr, *src0 = nullptr, *s_e = nullptr;
+    void *psi = nullptr, *src0 = nullptr, *s_e = nullptr, *psi_cm = nullptr;
     double *phi = nullptr, *phi2 = nullptr;
     int *sel = nullptr, *forced = nullptr;
     double *cw = nullptr, *C0 = nullptr, *a0 = nullptr, *margins = nullptr, *sel_mu = nullptr, *sel_eta = nullptr;
@@ -91,7 +91,8 @@ struct dlr_instance {
     unsigned* ticket = nullptr;
     unsigned long long launch_id = 0;
     int nsuper = 0;
-    size_t ld = 0;   // elements of one padded-column sweep plane (psi, src0, s_e, sigma_t)
+    size_t ld = 0;    // elements of one padded-column plane (Psi handed to the QR)
+    size_t ldg = 0;   // elements of one diagonal sweep plane (psi, src0, and the 4 copies of sigma_t, s_e)
     double* partials = nullptr;
     size_t partials_count = 0;
     double* norm_out = nullptr;
@@ -106,7 +107,7 @@ struct dlr_instance {
     int* h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch shapes
-    int nb_cells = 256, nb_gram = 512, nb_proj = 512, red_blocks = 64;
+    int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_proj = 512, red_blocks = 64;
 
     bool fp32() const { return prec != DLR_FP64; }
     size_t sweep_bytes() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -123,8 +124,8 @@ struct dlr_instance {
         D = A.take<double>(n);
         sig_s = A.take<double>(n);
         q = A.take<double>(n);
-        sig_t = fp32() ? nullptr : A.take<double>(ld);
-        sig_t32 = fp32() ? A.take<float>(ld) : nullptr;
+        sig_t = fp32() ? nullptr : A.take<double>(4 * ldg);
+        sig_t32 = fp32() ? A.take<float>(4 * ldg) : nullptr;
         X = A.take<double>(R * n);
         Xn = A.take<double>(R * n);
         Xt = A.take<double>(R * n);
@@ -134,9 +135,10 @@ struct dlr_instance {
         Wt = A.take<double>(R * Q);
         Wq = A.take<double>(R * Q);
         L = A.take<double>(R * Q);
-        psi = A.take<char>(R * ld * sweep_bytes());
-        src0 = A.take<char>(R * ld * sweep_bytes());
-        s_e = A.take<char>(ld * sweep_bytes());
+        psi = A.take<char>(R * ldg * sweep_bytes());
+        src0 = A.take<char>(R * ldg * sweep_bytes());
+        s_e = A.take<char>(4 * ldg * sweep_bytes());
+        psi_cm = A.take<char>(R * ld * sweep_bytes());
         phi = A.take<double>(n);
         phi2 = A.take<double>(n);
         sel = A.take<int>(R);
@@ -243,13 +245,14 @@ dlr_status step_once(dlr_instance* I) {
     const int N = I->N, r = I->r, nq = I->nq;
     const double cdt = I->c * I->dt;
     TS* psi = static_cast<TS*>(I->psi);
+    TS* psi_cm = static_cast<TS*>(I->psi_cm);
     TS* src0 = static_cast<TS*>(I->src0);
     TS* s_e = static_cast<TS*>(I->s_e);
     hip_check(hipEventRecord(I->ev[0], s), "event");
 
     // 1. effective scattering and source
-    dlr::launch_linearize(s, N, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s, I->q,
-                          I->sig_t, I->sig_t32, I->ny);
+    dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
+                          I->q, I->sig_t, I->sig_t32, I->ldg);
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
@@ -262,10 +265,11 @@ dlr_status step_once(dlr_instance* I) {
     dlr::launch_deim(s, da);
     I->force_pending = false;
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
-    dlr::launch_psi0<TS>(s, N, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, src0, I->ld, I->phi, s_e, I->ny);
+    dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta, src0,
+                         I->ldg, I->phi, s_e);
     // 4. source iteration with sweeps
     dlr::SweepArgs<TS> sa{};
-    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * r; sa.ld = I->ld;
+    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * r; sa.ldg = I->ldg;
     sa.src0 = src0; sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
     sa.s_e = s_e; sa.psi = psi; sa.mu = I->sel_mu; sa.eta = I->sel_eta;
     sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
@@ -284,8 +288,8 @@ dlr_status step_once(dlr_instance* I) {
         hip_check(hipEventRecord(I->ev[2], s), "event");
         dlr::launch_sweep<TS>(s, sa);
         hip_check(hipEventRecord(I->ev[3], s), "event");
-        dlr::launch_phi<TS>(s, N, r, psi, I->ld, I->cw, I->sig_s, phi_cur, phi_nxt, s_e, I->partials, I->nb_cells,
-                            I->counters + 0, I->norm_out, I->ny);
+        dlr::launch_phi<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, I->cw, I->sig_s, phi_cur, phi_nxt,
+                            s_e, I->partials, I->nb_phi, I->counters + 0, I->norm_out);
         std::swap(phi_cur, phi_nxt);
         hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
         hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
@@ -313,14 +317,15 @@ dlr_status step_once(dlr_instance* I) {
     if (ds != DLR_OK) return ds;
 
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
-    dlr::launch_gram<TS>(s, N, r, psi, I->ld, I->ny, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
+    dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, I->ny, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<TS>(s, N, r, psi, I->ld, I->ny, I->R1i, I->Xt);
+    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->ny, I->R1i, I->Xt);
     dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, 0, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
-    dlr::launch_cgs2<TS>(s, N, r, psi, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
+    dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
     // 6-7. projections on the new basis and the L-step for every ordinate
     dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj);
@@ -449,9 +454,11 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         I->stream = static_cast<hipStream_t>(hip_stream);
         I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
         I->ld = dlr::padded_plane(I->nx, I->ny);
+        I->ldg = dlr::diag_plane(I->nx, I->ny);
+        I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
         const size_t rr = (size_t)I->r * I->r;
         I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
-                                      (size_t)I->nb_cells * 2});
+                                      (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});
         dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
         Arena sizing;
         I->carve(sizing);

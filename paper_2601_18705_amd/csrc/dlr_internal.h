@@ -5,10 +5,11 @@
 // and the library transposes at creation and read-back only.
 //   per-cell fields          [N] float64, N = nx*ny
 //   spatial basis X          [r][N] float64 (column k of X contiguous)
-//   sweep planes             Psi, src0 [r][ld], sigma_t, s_e: in the sweep precision (double or
-//                            float), "padded columns": cell (i, j) at i*ldc + kColGuard + j with
-//                            ldc = ny + 2 kColGuard, so every column has kColGuard spare rows
-//                            above and below its data
+//   sweep planes             in the sweep precision (double or float), diagonal layout (below):
+//                            Psi, src0 [r][ldg] each in its own direction's orientation; sigma_t,
+//                            s_e [4][ldg], one copy per orientation
+//   Psi for the QR           [r][ld] "padded columns": cell (i, j) at i*ldc + kColGuard + j with
+//                            ldc = ny + 2 kColGuard (kColGuard spare rows above and below a column)
 //   angular basis W, L       [r][nq] float64 (column k contiguous over ordinates)
 //   coupling S               [r][r] float64, row-major S[i*r + j]
 // The state is psi = X S W^T with X, W orthonormal; S is kept as a general
@@ -26,20 +27,41 @@ constexpr double kFourPi = 4.0 * kPi;
 constexpr int kMaxRank = 64;
 constexpr int kSweepChunk = 32;   // rows published per edge-flag update in the sweep
 
+// ----------------------------------------------------------------------------- diagonal sweep layout
+// A direction's orientation o has bit 0 set when mu <= 0 and bit 1 when eta <= 0.  In its swept
+// coordinates i' = i or nx-1-i, j' = j or ny-1-j the grid is cut into strips of 64 columns; the
+// cell (i', j') of strip s = i'/64 is on lane l = i' % 64 and diagonal t = j' + l.  Element (s, t, l)
+// is stored at ((s*ndg + t/4)*64 + l)*4 + t%4, ndg = diagonal groups of four per strip, so the 64
+// lanes of a wavefront at four consecutive diagonals touch one contiguous block.
+__host__ __device__ inline int orient_of(double mu, double eta) { return (mu > 0.0 ? 0 : 1) | (eta > 0.0 ? 0 : 2); }
+__host__ __device__ inline int diag_groups(int ny) { return (ny + 63 + 15) / 16 * 4; }
+__host__ __device__ inline size_t diag_plane(int nx, int ny) { return (size_t)((nx + 63) / 64) * diag_groups(ny) * 256; }
+__host__ __device__ inline size_t diag_pos(int nx, int ny, int o, int i, int j) {
+    const int ip = (o & 1) ? nx - 1 - i : i, jp = (o & 2) ? ny - 1 - j : j;
+    const int l = ip & 63, t = jp + l;
+    return ((size_t)((ip >> 6) * diag_groups(ny) + (t >> 2)) * 64 + l) * 4 + (t & 3);
+}
+
 // ----------------------------------------------------------------------------- per-cell kernels
-void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
+// The kernels that touch the diagonal layout walk tiles of 8 columns x 128 rows.
+void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t_pad, float* sig_t32_pad, int ny);
+                      double* sig_t64, float* sig_t32, size_t ldg);
 
 template <typename TS>
-void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0,
-                 const double* q, const double* sig_s, double inv_cdt, TS* src0, size_t ld, double* phi, TS* s_e,
-                 int ny);
+void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
+                 const double* q, const double* sig_s, double inv_cdt, const double* mu, const double* eta,
+                 TS* src0, size_t ldg, double* phi, TS* s_e);
 
 template <typename TS>
-void launch_phi(hipStream_t s, int n, int r, const TS* psi, size_t ld, const double* cw, const double* sig_s,
-                const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks,
-                unsigned* counter, double* out, int ny);
+void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
+                const double* cw, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
+                double* partials, int nblocks, unsigned* counter, double* out);
+
+// Psi (diagonal layouts) -> padded-column planes [r][ld]
+template <typename TS>
+void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
+                      const double* eta, TS* psi_cm, size_t ld);
 
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area,
@@ -47,7 +69,7 @@ void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* 
                     int* status);
 
 // ----------------------------------------------------------------------------- sweep
-constexpr int kSweepWaves = 4;     // compute wavefronts (64-column strips) per sweep workgroup
+constexpr int kSweepWaves = 2;     // compute wavefronts (64-column strips) per sweep workgroup
 constexpr int kColGuard = 16;      // spare rows above and below each column of a sweep plane
 
 // index of column-major cell e = i*ny + j in a padded-column sweep plane
@@ -61,12 +83,12 @@ __host__ __device__ inline size_t padded_plane(int nx, int ny) {
 }
 template <typename TS>
 struct SweepArgs {
-    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of 4 x 64 columns
-    size_t ld;                             // plane stride of src0 / psi (elements), padded_plane
-    const TS* src0;      // [nd][ld] fixed source q + psi0 / (c dt), padded columns
-    const TS* sig_t;     // padded plane
-    const TS* s_e;       // padded plane, sigma_s phi / (4 pi)
-    TS* psi;             // [nd][ld]
+    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of kSweepWaves x 64 columns
+    size_t ldg;                            // diagonal plane stride (elements), diag_plane
+    const TS* src0;      // [nd][ldg] fixed source q + psi0 / (c dt), each in its direction's orientation
+    const TS* sig_t;     // [4][ldg] one copy per orientation
+    const TS* s_e;       // [4][ldg] sigma_s phi / (4 pi), one copy per orientation
+    TS* psi;             // [nd][ldg]
     const double* mu;    // [nd] direction cosines of the swept directions
     const double* eta;   // [nd]
     const double* inflow_x;  // [nd] isotropic inflow on the x-inflow face (0 = vacuum)

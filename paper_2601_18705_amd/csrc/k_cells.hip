@@ -1,9 +1,14 @@
 // Per-cell kernels of the DLR step: linearisation, reconstruction of the old
 // solution at the selected ordinates, the scalar-flux update inside source
 // iteration, and the temperature update.  All are bandwidth-bound streams over
-// the N cells; X and Psi are column-major ([r][N]) so a thread reads its cell's
-// r values with unit stride across the wavefront.
+// the N cells.  Column-major fields ([r][N] for X) are read with unit stride
+// across a wavefront.  The kernels that read or write the diagonal sweep layout
+// walk tiles of 8 columns x 128 rows (32 threads per column, consecutive rows):
+// a 128-byte line of that layout holds 8 lanes x 4 diagonals, so a workgroup
+// writes and reads whole lines.
 #include "dlr_internal.h"
+
+#include <algorithm>
 
 namespace dlr {
 
@@ -46,65 +51,110 @@ __device__ double ordered_sum(const double* p, int count, int stride, double* sh
     return block_sum(acc, sh);
 }
 
+// ---------------------------------------------------------------------------------------------- tiles
+constexpr int kTileCols = 8, kTileRows = 128;
+
+struct TileGrid {
+    int nx, ny, ntx, nty;
+    __device__ int count() const { return ntx * nty; }
+    // cell k (0..3) of thread threadIdx.x in tile b; false outside the grid
+    __device__ bool cell(int b, int k, int& i, int& j) const {
+        const int tx = b / nty, ty = b % nty;
+        i = tx * kTileCols + (threadIdx.x >> 5);
+        j = ty * kTileRows + (threadIdx.x & 31) + 32 * k;
+        return i < nx && j < ny;
+    }
+};
+inline TileGrid tile_grid(int nx, int ny) {
+    return TileGrid{nx, ny, (nx + kTileCols - 1) / kTileCols, (ny + kTileRows - 1) / kTileRows};
+}
+static_assert(kBlock * 4 == kTileCols * kTileRows, "four cells per thread");
+
 // ---------------------------------------------------------------------------------------------- linearise
 // Newton linearisation of backward Euler for the material energy (Sec. 2.2):
 //   D = rho c_v + 4 pi dt sigma dB/dT, sigma_s = (4 pi dt sigma dB/dT / D) sigma,
 //   q = sigma B(T0) rho c_v / D + q_ext / (4 pi), sigma_t = sigma + 1/(c dt).
-__global__ void k_linearize(int n, const double* __restrict__ sigma, const double* __restrict__ rho_cv,
-                            const double* __restrict__ q_ext, const double* __restrict__ T, double dt, double a,
-                            double c, double* __restrict__ D, double* __restrict__ sig_s, double* __restrict__ q,
-                            double* __restrict__ sig_t, float* __restrict__ sig_t32, int ny) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const double t = T[e], s = sigma[e], C = rho_cv[e];
-    const double t3 = t * t * t;
-    const double B0 = a * c * t3 * t / kFourPi;
-    const double dB = a * c * t3 / kPi;
-    const double d = C + kFourPi * dt * s * dB;
-    D[e] = d;
-    sig_s[e] = (kFourPi * dt * s * dB / d) * s;
-    q[e] = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
-    const double st = s + 1.0 / (c * dt);
-    const size_t pe = padded_cell(e, ny);
-    if (sig_t) sig_t[pe] = st;
-    if (sig_t32) sig_t32[pe] = (float)st;
+// sigma_t goes to the four orientation copies of the diagonal layout.
+__global__ __launch_bounds__(kBlock) void k_linearize(TileGrid g, const double* __restrict__ sigma,
+                                                      const double* __restrict__ rho_cv,
+                                                      const double* __restrict__ q_ext, const double* __restrict__ T,
+                                                      double dt, double a, double c, double* __restrict__ D,
+                                                      double* __restrict__ sig_s, double* __restrict__ q,
+                                                      double* __restrict__ sig_t64, float* __restrict__ sig_t32,
+                                                      size_t ldg) {
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int i, j;
+            if (!g.cell(b, k, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            const double t = T[e], s = sigma[e], C = rho_cv[e];
+            const double t3 = t * t * t;
+            const double B0 = a * c * t3 * t / kFourPi;
+            const double dB = a * c * t3 / kPi;
+            const double d = C + kFourPi * dt * s * dB;
+            D[e] = d;
+            sig_s[e] = (kFourPi * dt * s * dB / d) * s;
+            q[e] = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
+            const double st = s + 1.0 / (c * dt);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const size_t pe = (size_t)o * ldg + diag_pos(g.nx, g.ny, o, i, j);
+                if (sig_t64) sig_t64[pe] = st;
+                if (sig_t32) sig_t32[pe] = (float)st;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------------- psi0
 // Algorithm 1 step 3: psi_d^(0) = sum_k X0_k L0_k(Omega^(d)) = (X0 C0)[:, d] with
-// C0 = S0 W0[sel]^T, folded into the fixed sweep source src0 = q + psi^(0)/(c dt).
-// Also the source-iteration start phi = X0 S0 beta and s_e = sigma_s phi / (4 pi).
+// C0 = S0 W0[sel]^T, folded into the fixed sweep source src0 = q + psi^(0)/(c dt),
+// written in direction d's diagonal layout.  Also the source-iteration start
+// phi = X0 S0 beta and s_e = sigma_s phi / (4 pi) (four orientation copies).
 template <typename TS, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __restrict__ X,
+__global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double* __restrict__ X,
                                                  const double* __restrict__ C0, const double* __restrict__ a0,
                                                  const double* __restrict__ q, const double* __restrict__ sig_s,
-                                                 double inv_cdt, TS* __restrict__ src0, size_t ld,
-                                                 double* __restrict__ phi, TS* __restrict__ s_e, int ny) {
+                                                 double inv_cdt, const double* __restrict__ mu,
+                                                 const double* __restrict__ eta, TS* __restrict__ src0, size_t ldg,
+                                                 double* __restrict__ phi, TS* __restrict__ s_e) {
     __shared__ double sC[RMAX * RMAX];
     __shared__ double sa[RMAX];
+    __shared__ int so[RMAX];
     for (int i = threadIdx.x; i < r * r; i += blockDim.x) sC[(i / r) * RMAX + (i % r)] = C0[i];
-    for (int i = threadIdx.x; i < r; i += blockDim.x) sa[i] = a0[i];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
+        sa[i] = a0[i];
+        so[i] = orient_of(mu[i], eta[i]);
+    }
     __syncthreads();
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double x[RMAX];
+    const long n = (long)g.nx * g.ny;
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            double x[RMAX];
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) x[k] = (k < r) ? X[(size_t)k * n + e] : 0.0;
-    double ph = 0.0;
+            for (int k = 0; k < RMAX; ++k) x[k] = (k < r) ? X[(size_t)k * n + e] : 0.0;
+            double ph = 0.0;
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k)
-        if (k < r) ph += x[k] * sa[k];
-    phi[e] = ph;
-    const size_t pe = padded_cell(e, ny);
-    s_e[pe] = (TS)(sig_s[e] * ph / kFourPi);
-    const double qe = q[e];
+            for (int k = 0; k < RMAX; ++k)
+                if (k < r) ph += x[k] * sa[k];
+            phi[e] = ph;
+            const TS se = (TS)(sig_s[e] * ph / kFourPi);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + diag_pos(g.nx, g.ny, o, i, j)] = se;
+            const double qe = q[e];
 #pragma unroll 4
-    for (int d = 0; d < r; ++d) {
-        double acc = 0.0;
+            for (int d = 0; d < r; ++d) {
+                double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k)
-            if (k < r) acc += x[k] * sC[k * RMAX + d];
-        src0[(size_t)d * ld + pe] = (TS)(qe + acc * inv_cdt);
+                for (int k = 0; k < RMAX; ++k)
+                    if (k < r) acc += x[k] * sC[k * RMAX + d];
+                src0[(size_t)d * ldg + diag_pos(g.nx, g.ny, so[d], i, j)] = (TS)(qe + acc * inv_cdt);
+            }
+        }
     }
 }
 
@@ -113,25 +163,44 @@ __global__ __launch_bounds__(kBlock) void k_psi0(int n, int r, const double* __r
 // sum_d cw_d psi_d, its pseudo-scattering source, and the relative change
 // ||phi_new - phi_old||_2 / ||phi_new||_2 written to out[2] by the last block.
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_phi(int n, int r, const TS* __restrict__ psi, size_t ld,
+__global__ __launch_bounds__(kBlock) void k_phi(TileGrid g, int r, const TS* __restrict__ psi, size_t ldg,
+                                                const double* __restrict__ mu, const double* __restrict__ eta,
                                                 const double* __restrict__ cw, const double* __restrict__ sig_s,
                                                 const double* __restrict__ phi_old, double* __restrict__ phi_new,
                                                 TS* __restrict__ s_e, double* __restrict__ partials,
-                                                unsigned* counter, double* out, int ny) {
+                                                unsigned* counter, double* out) {
     __shared__ double sh[kBlock];
     __shared__ double scw[kMaxRank];
-    for (int i = threadIdx.x; i < r; i += blockDim.x) scw[i] = cw[i];
+    __shared__ int so[kMaxRank];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
+        scw[i] = cw[i];
+        so[i] = orient_of(mu[i], eta[i]);
+    }
     __syncthreads();
     double d2 = 0.0, p2 = 0.0;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const size_t pe = padded_cell(e, ny);
-        double ph = 0.0;
-        for (int d = 0; d < r; ++d) ph += scw[d] * (double)psi[(size_t)d * ld + pe];
-        const double diff = ph - phi_old[e];
-        d2 += diff * diff;
-        p2 += ph * ph;
-        phi_new[e] = ph;
-        s_e[pe] = (TS)(sig_s[e] * ph / kFourPi);
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            size_t pos[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
+            double ph = 0.0;
+            for (int d = 0; d < r; ++d) {
+                const int o = so[d];
+                const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
+                ph += scw[d] * (double)psi[(size_t)d * ldg + pd];
+            }
+            const double diff = ph - phi_old[e];
+            d2 += diff * diff;
+            p2 += ph * ph;
+            phi_new[e] = ph;
+            const TS se = (TS)(sig_s[e] * ph / kFourPi);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
+        }
     }
     d2 = block_sum(d2, sh);
     p2 = block_sum(p2, sh);
@@ -147,6 +216,32 @@ __global__ __launch_bounds__(kBlock) void k_phi(int n, int r, const TS* __restri
             out[1] = P2;
             out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
             *counter = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------- Psi relayout
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const TS* __restrict__ psi, size_t ldg,
+                                                      const double* __restrict__ mu, const double* __restrict__ eta,
+                                                      TS* __restrict__ psi_cm, size_t ld) {
+    __shared__ int so[kMaxRank];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) so[i] = orient_of(mu[i], eta[i]);
+    __syncthreads();
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const size_t pe = padded_cell((long)i * g.ny + j, g.ny);
+            size_t pos[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
+            for (int d = 0; d < r; ++d) {
+                const int o = so[d];
+                const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
+                psi_cm[(size_t)d * ld + pe] = psi[(size_t)d * ldg + pd];
+            }
         }
     }
 }
@@ -192,42 +287,64 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------- launchers
-void launch_linearize(hipStream_t s, int n, const double* sigma, const double* rho_cv, const double* q_ext,
+constexpr int kMaxTileBlocks = 1024;
+
+void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t, float* sig_t32, int ny) {
-    hipLaunchKernelGGL(k_linearize, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, sigma, rho_cv, q_ext, T,
-                       dt, a, c, D, sig_s, q, sig_t, sig_t32, ny);
+                      double* sig_t64, float* sig_t32, size_t ldg) {
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL(k_linearize, dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, sigma,
+                       rho_cv, q_ext, T, dt, a, c, D, sig_s, q, sig_t64, sig_t32, ldg);
 }
 
 template <typename TS>
-void launch_psi0(hipStream_t s, int n, int r, const double* X, const double* C0, const double* a0, const double* q,
-                 const double* sig_s, double inv_cdt, TS* src0, size_t ld, double* phi, TS* s_e, int ny) {
-    dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
+void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
+                 const double* q, const double* sig_s, double inv_cdt, const double* mu, const double* eta,
+                 TS* src0, size_t ldg, double* phi, TS* s_e) {
+    const TileGrid g = tile_grid(nx, ny);
+    dim3 gr(std::min(g.ntx * g.nty, kMaxTileBlocks)), b(kBlock);
     if (r <= 8)
-        hipLaunchKernelGGL((k_psi0<TS, 8>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
+        hipLaunchKernelGGL((k_psi0<TS, 8>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
     else if (r <= 16)
-        hipLaunchKernelGGL((k_psi0<TS, 16>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
+        hipLaunchKernelGGL((k_psi0<TS, 16>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_psi0<TS, 32>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
+        hipLaunchKernelGGL((k_psi0<TS, 32>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
     else
-        hipLaunchKernelGGL((k_psi0<TS, 64>), g, b, 0, s, n, r, X, C0, a0, q, sig_s, inv_cdt, src0, ld, phi, s_e, ny);
+        hipLaunchKernelGGL((k_psi0<TS, 64>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
 }
-template void launch_psi0<double>(hipStream_t, int, int, const double*, const double*, const double*,
-                                  const double*, const double*, double, double*, size_t, double*, double*, int);
-template void launch_psi0<float>(hipStream_t, int, int, const double*, const double*, const double*, const double*,
-                                 const double*, double, float*, size_t, double*, float*, int);
+template void launch_psi0<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
+                                  const double*, const double*, double, const double*, const double*, double*, size_t,
+                                  double*, double*);
+template void launch_psi0<float>(hipStream_t, int, int, int, const double*, const double*, const double*,
+                                 const double*, const double*, double, const double*, const double*, float*, size_t,
+                                 double*, float*);
 
 template <typename TS>
-void launch_phi(hipStream_t s, int n, int r, const TS* psi, size_t ld, const double* cw, const double* sig_s,
-                const double* phi_old, double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter,
-                double* out, int ny) {
-    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, n, r, psi, ld, cw, sig_s, phi_old, phi_new,
-                       s_e, partials, counter, out, ny);
+void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
+                const double* cw, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
+                double* partials, int nblocks, unsigned* counter, double* out) {
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, r, psi, ldg, mu, eta, cw, sig_s, phi_old,
+                       phi_new, s_e, partials, counter, out);
 }
-template void launch_phi<double>(hipStream_t, int, int, const double*, size_t, const double*, const double*,
-                                 const double*, double*, double*, double*, int, unsigned*, double*, int);
-template void launch_phi<float>(hipStream_t, int, int, const float*, size_t, const double*, const double*,
-                                const double*, double*, float*, double*, int, unsigned*, double*, int);
+template void launch_phi<double>(hipStream_t, int, int, int, const double*, size_t, const double*, const double*,
+                                 const double*, const double*, const double*, double*, double*, double*, int,
+                                 unsigned*, double*);
+template void launch_phi<float>(hipStream_t, int, int, int, const float*, size_t, const double*, const double*,
+                                const double*, const double*, const double*, double*, float*, double*, int, unsigned*,
+                                double*);
+
+template <typename TS>
+void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
+                      const double* eta, TS* psi_cm, size_t ld) {
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL((k_psi_to_cm<TS>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, r, psi,
+                       ldg, mu, eta, psi_cm, ld);
+}
+template void launch_psi_to_cm<double>(hipStream_t, int, int, int, const double*, size_t, const double*,
+                                       const double*, double*, size_t);
+template void launch_psi_to_cm<float>(hipStream_t, int, int, int, const float*, size_t, const double*, const double*,
+                                      float*, size_t);
 
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area, double* T,

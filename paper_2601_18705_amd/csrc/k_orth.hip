@@ -16,66 +16,115 @@ namespace dlr {
 namespace {
 
 constexpr int kOrthThreads = 1024;
-constexpr int kSlices = kOrthThreads / kMaxRank;   // 16 slices x 64 columns for the dot products
-
-__device__ double orth_block_sum(double v, double* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int w = kOrthThreads / 2; w > 0; w >>= 1) {
-        if (t < w) sh[t] += sh[t + w];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
+constexpr int kOrthWaves = kOrthThreads / 64;
+constexpr int kGrp = 16;                                   // dot products reduced together
+constexpr int kMaxGroups = (kMaxRank + 1 + kGrp - 1) / kGrp;
 
 struct OrthCtx {
     long n;
     const double* weight;   // per element or nullptr
     double wscalar;
-    double* Q;              // [r][n]
+    double* Q;              // [r][n]; column k doubles as the working vector v
 };
 
-__device__ inline double wt(const OrthCtx& c, long e) { return c.weight ? c.weight[e] : c.wscalar; }
+__device__ __forceinline__ double wt(const OrthCtx& c, long e) { return c.weight ? c.weight[e] : c.wscalar; }
 
-// Two passes of v <- v - Q_{<k} (Q_{<k}^T W v); accumulates the coefficients in hsum.
-__device__ void project_twice(const OrthCtx& c, int k, double* hsum, double* red, double* h) {
-    const int t = threadIdx.x;
-    double* v = c.Q + (size_t)k * c.n;
-    for (int j = t; j < k; j += kOrthThreads) hsum[j] = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-        __syncthreads();
-        const int j = t % kMaxRank, slice = t / kMaxRank;
-        double acc = 0.0;
-        if (j < k) {
-            const double* qj = c.Q + (size_t)j * c.n;
-            for (long e = slice; e < c.n; e += kSlices) acc += qj[e] * (wt(c, e) * v[e]);
+// Sum of a[0..16) over the 64 lanes of a wavefront, scattered: four exchange stages
+// halve the live values (17 shuffles instead of 96); the lanes with (lane & 3) == 0
+// return the total of value 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of the lane id).
+__device__ __forceinline__ double wave_reduce_scatter16(double (&a)[kGrp], int lane) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int o = 32 >> st, c = 8 >> st;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < c; ++i) {
+            const double send = up ? a[i] : a[i + c];
+            const double keep = up ? a[i + c] : a[i];
+            a[i] = keep + __shfl_xor(send, o);
         }
-        red[slice * kMaxRank + j] = acc;
-        __syncthreads();
-        for (int jj = t; jj < k; jj += kOrthThreads) {
-            double s = 0.0;
-            for (int sl = 0; sl < kSlices; ++sl) s += red[sl * kMaxRank + jj];
-            h[jj] = s;
-            hsum[jj] += s;
+    }
+    double x = a[0];
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 1);
+    return x;
+}
+
+// hs[j] = sum_e Q_j(e) w(e) v(e) for j < k, and hs[k] = sum_e w(e) v(e)^2 when with_norm,
+// where v = column kv of Q (kv >= k).  Each thread owns the elements e = t (mod kOrthThreads); the per-wave
+// partials are added over the wavefronts in a fixed order.
+__device__ void block_dots(const OrthCtx& c, int k, int kv, bool with_norm, double* hs, double* wsum) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int cnt = k + (with_norm ? 1 : 0);
+    const double* v = c.Q + (size_t)kv * c.n;
+    for (int g0 = 0; g0 < cnt; g0 += kGrp) {
+        double a[kGrp];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) a[i] = 0.0;
+        const unsigned n32 = (unsigned)c.n;
+        const int jend = min(k, g0 + kGrp) - g0;   // number of projections in this group
+        const bool norm_here = with_norm && k >= g0 && k < g0 + kGrp;
+#pragma unroll 1
+        for (unsigned e = t; e < n32; e += kOrthThreads) {
+            const double ve = v[e];
+            const double wve = wt(c, e) * ve;
+            unsigned off = (unsigned)g0 * n32 + e;
+            const int inorm = norm_here ? k - g0 : -1;
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i, off += n32) {
+                if (i < jend) a[i] += c.Q[off] * wve;
+                if (i == inorm) a[i] += wve * ve;
+            }
         }
-        __syncthreads();
-        for (long e = t; e < c.n; e += kOrthThreads) {
-            double x = v[e];
-            for (int jj = 0; jj < k; ++jj) x -= h[jj] * c.Q[(size_t)jj * c.n + e];
-            v[e] = x;
+        const double tot = wave_reduce_scatter16(a, lane);
+        if ((lane & 3) == 0) {
+            const int idx = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+            wsum[((g0 / kGrp) * kOrthWaves + wv) * kGrp + idx] = tot;
         }
+    }
+    __syncthreads();
+    if (t < cnt) {
+        double s = 0.0;
+        for (int w = 0; w < kOrthWaves; ++w) s += wsum[((t / kGrp) * kOrthWaves + w) * kGrp + t % kGrp];
+        hs[t] = s;
     }
     __syncthreads();
 }
 
-__device__ double wnorm(const OrthCtx& c, int k, double* sh) {
-    const double* v = c.Q + (size_t)k * c.n;
-    double acc = 0.0;
-    for (long e = threadIdx.x; e < c.n; e += kOrthThreads) acc += wt(c, e) * v[e] * v[e];
-    return sqrt(orth_block_sum(acc, sh));
+// v <- v - Q_{<k} h on the thread's own elements
+__device__ void block_update(const OrthCtx& c, int k, const double* h) {
+    double* v = c.Q + (size_t)k * c.n;
+    const unsigned n32 = (unsigned)c.n;
+    for (unsigned e = threadIdx.x; e < n32; e += kOrthThreads) {
+        double x = v[e];
+        unsigned off = e;
+        for (int j = 0; j < k; ++j, off += n32) x -= h[j] * c.Q[off];
+        v[e] = x;
+    }
+}
+
+__device__ void block_scale(const OrthCtx& c, int k, double inv) {
+    double* v = c.Q + (size_t)k * c.n;
+    for (long e = threadIdx.x; e < c.n; e += kOrthThreads) v[e] *= inv;
+}
+
+// Column k of Q holds the candidate v.  Three reductions: (dots with Q_{<k}, |v|^2), update,
+// (dots), update, |v|^2 -- the two projection passes of CGS2; a single code path so the
+// reduction is instantiated once.
+__device__ void project_twice(const OrthCtx& c, int k, double* hs, double* hsum, double* wsum, double& own,
+                              double& nrm) {
+    for (int pass = 0; pass < 3; ++pass) {
+        const int kk = (pass < 2) ? k : 0;
+        block_dots(c, kk, k, pass != 1, hs, wsum);
+        if (pass == 0) own = sqrt(fmax(hs[k], 0.0));
+        if (pass == 2) {
+            nrm = sqrt(fmax(hs[0], 0.0));
+            break;
+        }
+        for (int j = threadIdx.x; j < k; j += kOrthThreads) hsum[j] = (pass == 0 ? 0.0 : hsum[j]) + hs[j];
+        block_update(c, k, hs);
+        __syncthreads();   // hs is read by every thread before the next pass overwrites it
+    }
 }
 
 template <typename TV>
@@ -85,9 +134,8 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
                                                        const double* __restrict__ eta, double* __restrict__ Q,
                                                        double* __restrict__ R, int* flag, int flag_mask,
                                                        int* status, int status_code) {
-    __shared__ double sh[kOrthThreads];
-    __shared__ double red[kSlices * kMaxRank];
-    __shared__ double h[kMaxRank], hsum[kMaxRank];
+    __shared__ double hs[kMaxRank + 1], hsum[kMaxRank];
+    __shared__ double wsum[kMaxGroups * kOrthWaves * kGrp];
     __shared__ int deg, ax;
     if (flag) {   // fallback mode: run only when the fast path flagged a breakdown
         const int f = *flag;
@@ -103,22 +151,29 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
         double* v = Q + (size_t)k * n;
         for (long e = t; e < n; e += kOrthThreads)
             v[e] = (double)V[(size_t)k * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
-        __syncthreads();
-        const double own = wnorm(c, k, sh);
-        project_twice(c, k, hsum, red, h);
-        const double nrm = wnorm(c, k, sh);
-        for (int j = t; j < k; j += kOrthThreads) R[j * r + k] = hsum[j];
-        if (own > 0.0 && nrm > 1e-12 * own) {
-            for (long e = t; e < n; e += kOrthThreads) v[e] /= nrm;
-            if (t == 0) R[k * r + k] = nrm;
-            __syncthreads();
-            continue;
-        }
-        // completion: next graded monomial that is independent of the accepted columns
-        for (int guard = 0; guard < 100000; ++guard) {
+        // attempt 0 is the column itself; later attempts are completion vectors
+        for (int attempt = 0; attempt <= 100000; ++attempt) {
+            double own, nrm;
+            project_twice(c, k, hs, hsum, wsum, own, nrm);
+            if (attempt == 0) {
+                for (int j = t; j < k; j += kOrthThreads) R[j * r + k] = hsum[j];
+                if (own > 0.0 && nrm > 1e-12 * own) {   // accepted: R_kk = nrm
+                    block_scale(c, k, 1.0 / nrm);
+                    if (t == 0) R[k * r + k] = nrm;
+                    break;
+                }
+            } else if (nrm > 1e-10 * own) {             // completion accepted: R_kk stays 0
+                block_scale(c, k, 1.0 / nrm);
+                break;
+            }
+            if (attempt == 100000) {
+                out_of_completions = true;
+                break;
+            }
+            // next graded monomial: (deg, ax) -> (deg, ax-1) or (deg+1, deg+1)
             const int d = deg, a = ax;
             __syncthreads();
-            if (t == 0) {   // advance the iterator: (deg, ax) -> (deg, ax-1) or (deg+1, deg+1)
+            if (t == 0) {
                 if (ax > 0) ax = ax - 1; else { deg = deg + 1; ax = deg; }
             }
             for (long e = t; e < n; e += kOrthThreads) {
@@ -136,16 +191,6 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
                 for (int p = 0; p < d - a; ++p) m *= by;
                 v[e] = m;
             }
-            __syncthreads();
-            const double un = wnorm(c, k, sh);
-            project_twice(c, k, hsum, red, h);
-            const double n2 = wnorm(c, k, sh);
-            if (n2 > 1e-10 * un) {
-                for (long e = t; e < n; e += kOrthThreads) v[e] /= n2;
-                __syncthreads();
-                break;
-            }
-            if (guard == 99999) out_of_completions = true;
         }
     }
     if (t == 0) {

@@ -3,33 +3,30 @@
 //   psi_e = (src0_e + s_e + ax psi_upwind_x + ay psi_upwind_y) / (sigma_t,e + ax + ay),
 // ax = |mu|/hx, ay = |eta|/hy, for every swept direction d and cell e.
 //
-// Layout.  Cells are column-major, and every column of a sweep plane carries
-// kColGuard spare rows above and below its data (cell (i, j) at
-// i*(ny + 2 kColGuard) + kColGuard + j), so any sixteen-row segment that meets
-// a column lies inside that column's padded range; consecutive planes are ld
-// apart and each plane ends with a spare slot that absorbs redirected stores.
-//
 // Work decomposition.  In each direction's own sweep coordinates (i', j') --
 // i' = i for mu > 0 else nx-1-i, likewise j' -- the grid is cut into strips of
-// 64 columns, four consecutive strips forming a superstrip.  A workgroup takes
-// one (superstrip S, direction d) unit with four compute wavefronts and one
-// helper wavefront.  Compute wavefront w owns strip 4S + w; its lane l owns
-// column i' = 64 (4S + w) + l and at step t updates row j' = t - l, so the
-// x-upwind value is lane l-1's result of the previous step (a DPP wave shift)
-// and the y-upwind value is the lane's own previous result.
+// 64 columns, kSweepWaves consecutive strips forming a superstrip.  A workgroup
+// takes one (superstrip S, direction d) unit with one compute wavefront per
+// strip and one helper wavefront.  Lane l of a compute wavefront owns column
+// i' = 64 strip + l and at step t updates row j' = t - l: the x-upwind value is
+// lane l-1's result of the previous step (a DPP wave shift) and the y-upwind
+// value the lane's own previous result.
 //
-// Each lane streams its own column: sixteen rows of src0, sigma_t and s_e per
-// chunk as 16-byte loads issued a chunk ahead (register double-buffering),
-// sixteen results per chunk as 16-byte stores.  Compute wavefronts issue these
-// memory operations unconditionally (a segment that misses the column is
-// redirected to the column start or to the spare slot rather than branched
-// around) and exchange boundary fluxes only through LDS rings, so the compiler
-// can count outstanding loads exactly and the prefetch is never drained.  The helper wavefront alone talks to the other
-// workgroups: it copies the incoming edge of superstrip S-1 from global memory
-// into the LDS ring of wavefront 0 and the outgoing edge of wavefront 3 to
-// global memory, publishing progress words tagged with the launch id.  Units
-// come from an atomic ticket in (superstrip, direction) order, so a workgroup
-// only waits on a unit with a smaller ticket, which is already running.
+// Layout.  All sweep planes use the diagonal layout of the direction's
+// orientation, in which the value of lane l at step t sits next to those of the
+// other lanes at the same step: the sixteen steps of a chunk are four 16-byte
+// loads per lane per plane, each a contiguous kilobyte across the wavefront
+// (FP32), issued a chunk or two ahead (register double-buffering) and stored the
+// same way.  Steps outside the grid (the skewed head and tail of a strip) read
+// and write the layout's padding, so no memory operation is predicated.
+//
+// Hand-off.  Compute wavefronts exchange boundary fluxes only through LDS rings.
+// The helper wavefront alone talks to other workgroups: it copies the incoming
+// edge of superstrip S-1 from global memory into the ring of wavefront 0 and
+// the outgoing edge of the last wavefront to global memory, publishing progress
+// words tagged with the launch id.  Units come from an atomic ticket in
+// (superstrip, direction) order, so a workgroup only waits on a unit with a
+// smaller ticket, which is already running.
 #include "dlr_internal.h"
 
 namespace dlr {
@@ -39,20 +36,19 @@ namespace {
 constexpr int kWaves = kSweepWaves;   // compute wavefronts per workgroup
 constexpr int kC = 16;                // rows per chunk
 constexpr int kRing = 256;            // LDS ring length (rows)
-static_assert(kC <= kColGuard, "a live segment may reach kC-1 rows past either end of its column");
 
 template <typename TS>
 struct Vec4 {
     typedef TS type __attribute__((ext_vector_type(4), aligned(sizeof(TS))));
 };
 
+// Chunk m of a lane: diagonal groups 4m..4m+3 at p + g*256 elements, four values each.
 template <typename TS>
-__device__ __forceinline__ void load16(const TS* p, TS (&v)[kC]) {
+__device__ __forceinline__ void load_chunk(const TS* p, TS (&v)[kC]) {
     typedef typename Vec4<TS>::type V;
-    const V* q = reinterpret_cast<const V*>(p);
 #pragma unroll
     for (int c = 0; c < kC / 4; ++c) {
-        const V x = q[c];
+        const V x = *reinterpret_cast<const V*>(p + (size_t)c * 256);
         v[4 * c + 0] = x[0];
         v[4 * c + 1] = x[1];
         v[4 * c + 2] = x[2];
@@ -61,9 +57,8 @@ __device__ __forceinline__ void load16(const TS* p, TS (&v)[kC]) {
 }
 
 template <typename TS>
-__device__ __forceinline__ void store16(TS* p, const TS (&v)[kC]) {
+__device__ __forceinline__ void store_chunk(TS* p, const TS (&v)[kC]) {
     typedef typename Vec4<TS>::type V;
-    V* q = reinterpret_cast<V*>(p);
 #pragma unroll
     for (int c = 0; c < kC / 4; ++c) {
         V x;
@@ -71,7 +66,7 @@ __device__ __forceinline__ void store16(TS* p, const TS (&v)[kC]) {
         x[1] = v[4 * c + 1];
         x[2] = v[4 * c + 2];
         x[3] = v[4 * c + 3];
-        q[c] = x;
+        *reinterpret_cast<V*>(p + (size_t)c * 256) = x;
     }
 }
 
@@ -98,78 +93,76 @@ __device__ __forceinline__ double step_value(double rhs, double sig, double axy,
 
 template <typename TS>
 struct Shared {
-    TS ring[kWaves + 1][kRing];   // ring[w]: left inflow of compute wave w; ring[kWaves]: outgoing edge
+    TS ring[kWaves + 1][kRing] __attribute__((aligned(16)));   // ring[w]: left inflow of compute wave w;
+                                                                // ring[kWaves]: outgoing edge; row j in slot (j+63) % kRing
     int prod[kWaves + 1];         // rows published into ring[w]
     int cons[kWaves + 1];         // rows consumed from ring[w]
     int stall;
     unsigned task;
 };
 
-__device__ __forceinline__ int lds_load(int* p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+// Progress words of the LDS rings.  The LDS unit executes a wavefront's LDS instructions in
+// issue order, so a ring write followed by a progress store is seen in that order by any
+// wavefront that reads the progress word first and the ring afterwards; compiler barriers keep
+// the compiler from reordering them.  Relaxed atomics are used on purpose: a release or acquire
+// at workgroup scope would also wait for this wavefront's outstanding global loads (the
+// prefetched chunks), which is what the rings must not do.
+__device__ __forceinline__ int lds_load(int* p) {
+    const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return v;
+}
 __device__ __forceinline__ void lds_store(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Per-wavefront constant data of one strip.
 template <typename TS>
 struct Strip {
-    const TS* sp;   // src0 column (row 0)
-    const TS* qp;   // sigma_t column (row 0)
-    const TS* ep;   // s_e column (row 0)
-    TS* op;         // psi column (row 0)
-    TS* trash;      // spare slot (kC elements) that absorbs redirected stores
+    const TS* sp;   // src0: this lane's element of diagonal group 0
+    const TS* qp;   // sigma_t
+    const TS* ep;   // s_e
+    TS* op;         // psi
     TS ax, ay, axy, bx, by;
-    int lane, ny, nch;
-    bool col_ok;
-    bool REV;
+    int lane, nch;
 };
 
-template <typename TS, bool REV>
-__device__ __forceinline__ int seg_start(const Strip<TS>& s, int m) {
-    return REV ? (s.ny - kC * m + s.lane - kC) : (kC * m - s.lane);
-}
-
-// issue the loads of chunk m into buffers (unconditionally; dead segments read the padded column start)
-template <typename TS, bool REV>
+// issue the loads of chunk m (clamped to the last chunk, so a prefetch past the end stays in the plane)
+template <typename TS>
 __device__ __forceinline__ void issue_loads(const Strip<TS>& s, int m, TS (&bs)[kC], TS (&bq)[kC], TS (&be)[kC]) {
-    const int s0 = seg_start<TS, REV>(s, m);
-    const bool live = s.col_ok && m < s.nch && s0 < s.ny && s0 + kC > 0;
-    const int off = live ? s0 : -kColGuard;
-    load16<TS>(s.sp + off, bs);
-    load16<TS>(s.qp + off, bq);
-    load16<TS>(s.ep + off, be);
+    const size_t off = (size_t)min(m, s.nch - 1) * (kC / 4) * 256;
+    load_chunk<TS>(s.sp + off, bs);
+    load_chunk<TS>(s.qp + off, bq);
+    load_chunk<TS>(s.ep + off, be);
 }
 
-// One chunk of sixteen steps.  FAST: every lane with a valid column is inside
-// the column for all sixteen rows (no masking, vector stores).
-template <typename TS, bool REV, bool FAST>
+// One chunk of sixteen steps.  MASK: steps before the lane's first row (t < lane) keep the
+// inflow value; later steps past the last row compute padding that nothing reads.
+template <typename TS, bool MASK>
 __device__ __forceinline__ void run_chunk(const Strip<TS>& s, int m, const TS (&bs)[kC], const TS (&bq)[kC],
-                                 const TS (&be)[kC], const TS (&edgev)[kC], TS& mine, TS (&ob)[kC]) {
-    const int r0 = kC * m;
+                                          const TS (&be)[kC], const TS (&edgev)[kC], TS& mine, TS (&ob)[kC]) {
+    const int t0 = kC * m;
 #pragma unroll
     for (int k = 0; k < kC; ++k) {
-        const int kk = REV ? kC - 1 - k : k;
         const TS left = shift_in(edgev[k], mine);
-        const TS val = step_value(bs[kk] + be[kk], bq[kk], s.axy, s.ax, s.ay, left, mine);
-        if (FAST) {
+        const TS val = step_value(bs[k] + be[k], bq[k], s.axy, s.ax, s.ay, left, mine);
+        if (MASK)
+            mine = (t0 + k >= s.lane) ? val : mine;
+        else
             mine = val;
-        } else {
-            const int jp = r0 + k - s.lane;
-            mine = (s.col_ok && jp >= 0 && jp < s.ny) ? val : mine;
-        }
-        ob[kk] = val;
+        ob[k] = val;
     }
-    // rows of a live segment outside [0, ny) land in the column's spare rows
-    const int s0 = seg_start<TS, REV>(s, m);
-    const bool live = s.col_ok && (FAST || (s0 < s.ny && s0 + kC > 0));
-    store16<TS>(live ? s.op + s0 : s.trash, ob);
+    store_chunk<TS>(s.op + (size_t)m * (kC / 4) * 256, ob);
 }
 
-template <typename TS, bool REV, int P>
+template <typename TS, int P>
 __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>& sh, int S, int d, int w, int lane) {
-    const int nx = a.nx, ny = a.ny;
+    const int ny = a.ny;
     const int strip = S * kWaves + w;
     const double mu = a.mu[d], eta = a.eta[d];
+    const int o = orient_of(mu, eta);
+    const int ndg = diag_groups(ny);
     Strip<TS> s;
     s.ax = (TS)(fabs(mu) * a.inv_hx);
     s.ay = (TS)(fabs(eta) * a.inv_hy);
@@ -177,33 +170,22 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
     s.bx = (TS)a.inflow_x[d];
     s.by = (TS)a.inflow_y[d];
     s.lane = lane;
-    s.ny = ny;
-    s.nch = (ny + 63 + kC - 1) / kC;
-    s.REV = REV;
-    const int ip = strip * 64 + lane;
-    s.col_ok = ip < nx;
-    const int col = s.col_ok ? (mu > 0.0 ? ip : nx - 1 - ip) : 0;
-    const size_t ldc = (size_t)ny + 2 * kColGuard;
-    const size_t cb = (size_t)col * ldc + kColGuard;
-    s.sp = a.src0 + (size_t)d * a.ld + cb;
-    s.qp = a.sig_t + cb;
-    s.ep = a.s_e + cb;
-    s.op = a.psi + (size_t)d * a.ld + cb;
-    s.trash = a.psi + (size_t)d * a.ld + (size_t)nx * ldc;   // spare slot after this plane's columns
+    s.nch = ndg / (kC / 4);
+    const size_t lane_base = (size_t)strip * ndg * 256 + (size_t)lane * 4;
+    s.sp = a.src0 + (size_t)d * a.ldg + lane_base;
+    s.qp = a.sig_t + (size_t)o * a.ldg + lane_base;
+    s.ep = a.s_e + (size_t)o * a.ldg + lane_base;
+    s.op = a.psi + (size_t)d * a.ldg + lane_base;
     const bool from_ring = strip > 0;
-    const bool has_next = (strip + 1) * 64 < nx;
+    const bool has_next = (strip + 1) * 64 < a.nx;
     const int out_ring = (w < kWaves - 1) ? w + 1 : kWaves;
     const int nch = s.nch;
-    // Chunk ranges: [0, m0) prologue, [m0, m1) fast, [m1, nch) epilogue, with m0 and m1 - m0
-    // multiples of P.  A chunk m is fast when every lane's rows [16m - l, 16m - l + 16) lie in
-    // [0, ny): m >= 4 (lane 63) and 16m + 16 <= ny (lane 0), i.e. 4 <= m < mf.
+    // chunks [0, m0) carry the skewed head (masked), with m0 a multiple of P; nch >= 4 always
     const int m0 = (4 + P - 1) / P * P;
-    const int mf = (ny >= kC) ? (ny - kC) / kC + 1 : 0;
-    const int m1 = (mf > m0) ? m0 + (mf - m0) / P * P : m0;   // m1 <= mf < nch
 
     TS bs[P][kC], bq[P][kC], be[P][kC];
 #pragma unroll
-    for (int p = 0; p < P; ++p) issue_loads<TS, REV>(s, p, bs[p], bq[p], be[p]);
+    for (int p = 0; p < P; ++p) issue_loads<TS>(s, p, bs[p], bq[p], be[p]);
     TS mine = s.by;
 
     auto left_values = [&](int m, TS (&edgev)[kC]) {
@@ -223,7 +205,7 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
             }
         }
 #pragma unroll
-        for (int k = 0; k < kC; ++k) edgev[k] = sh.ring[w][(r0 + k) & (kRing - 1)];
+        for (int k = 0; k < kC; ++k) edgev[k] = sh.ring[w][(r0 + k + 63) & (kRing - 1)];
         lds_store(&sh.cons[w], need);
     };
     auto publish = [&](int m, const TS (&ob)[kC]) {
@@ -239,47 +221,69 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
             }
         }
         if (lane == 63) {
+            // row j lives in slot (j + 63) mod kRing, so lane 63's sixteen rows r0-63 .. r0-48 are
+            // one aligned block; rows outside [0, ny) land in slots no pending row occupies
+            typedef typename Vec4<TS>::type V;
+            V* dst = reinterpret_cast<V*>(&sh.ring[out_ring][r0 & (kRing - 1)]);
 #pragma unroll
-            for (int k = 0; k < kC; ++k) {
-                const int row = r0 + k - 63;
-                if (row >= 0 && row < ny) sh.ring[out_ring][row & (kRing - 1)] = ob[REV ? kC - 1 - k : k];
+            for (int c = 0; c < kC / 4; ++c) {
+                V x;
+                x[0] = ob[4 * c + 0];
+                x[1] = ob[4 * c + 1];
+                x[2] = ob[4 * c + 2];
+                x[3] = ob[4 * c + 3];
+                dst[c] = x;
             }
             lds_store(&sh.prod[out_ring], min(max(r0 + kC - 63, 0), ny));
         }
     };
 
-    // prologue and epilogue: masked steps, element stores
-    auto generic = [&](int mbeg, int mend) {
-        for (int mb = mbeg; mb < mend; mb += P) {
+    for (int mb = 0; mb < m0; mb += P) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int m = mb + p;
-                if (m >= mend) break;
-                TS edgev[kC], ob[kC];
-                left_values(m, edgev);
-                run_chunk<TS, REV, false>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
-                issue_loads<TS, REV>(s, m + P, bs[p], bq[p], be[p]);
-                publish(m, ob);
-            }
+        for (int p = 0; p < P; ++p) {
+            const int m = mb + p;
+            TS edgev[kC], ob[kC];
+            left_values(m, edgev);
+            run_chunk<TS, true>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
+            issue_loads<TS>(s, m + P, bs[p], bq[p], be[p]);
+            publish(m, ob);
         }
-    };
-    if (m1 <= m0) {   // no full fast group: the whole strip takes the masked path
-        generic(0, nch);
-        return;
     }
-    generic(0, m0);
+    // [m0, m1): whole groups of P chunks without a bound check; then the remaining < P chunks
+    const int m1 = m0 + (nch - m0) / P * P;
     for (int mb = m0; mb < m1; mb += P) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int m = mb + p;
             TS edgev[kC], ob[kC];
             left_values(m, edgev);
-            run_chunk<TS, REV, true>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
-            issue_loads<TS, REV>(s, m + P, bs[p], bq[p], be[p]);
+            run_chunk<TS, false>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
+            issue_loads<TS>(s, m + P, bs[p], bq[p], be[p]);
             publish(m, ob);
         }
     }
-    generic(m1, nch);
+#pragma unroll
+    for (int p = 0; p < P - 1; ++p) {
+        const int m = m1 + p;
+        if (m < nch) {
+            TS edgev[kC], ob[kC];
+            left_values(m, edgev);
+            run_chunk<TS, false>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
+            publish(m, ob);
+        }
+    }
+}
+
+// Cross-workgroup hand-off.  Edge values and progress words are agent-scope atomics, which are
+// performed at the device coherence point instead of in an XCD's L2, so neither side needs the
+// L2-wide writeback / invalidate of a release or acquire at agent scope (both would also stall
+// every other wavefront sharing that L2).  The writer waits for its edge stores to complete
+// before it stores the progress word; the reader loads the edge values only after it has seen
+// that word.
+__device__ __forceinline__ void wait_vm_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Helper wavefront: incoming edge (global -> ring[0]) and outgoing edge (ring[kWaves] -> global).
@@ -304,9 +308,10 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& 
             avail = min(avail, lds_load(&sh.cons[0]) + kRing);   // ring space
             avail = min(avail, rin + 64);
             if (avail > rin) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 const int row = rin + lane;
-                if (row < avail) sh.ring[0][row & (kRing - 1)] = edge_in[row];
+                if (row < avail)
+                    sh.ring[0][(row + 63) & (kRing - 1)] =
+                        __hip_atomic_load(&edge_in[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 rin = avail;
                 lds_store(&sh.prod[0], rin);
                 moved = true;
@@ -316,10 +321,13 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& 
             const int avail = min(lds_load(&sh.prod[kWaves]), rout + 64);
             if (avail > rout) {
                 const int row = rout + lane;
-                if (row < avail) edge_out[row] = sh.ring[kWaves][row & (kRing - 1)];
+                if (row < avail)
+                    __hip_atomic_store(&edge_out[row], sh.ring[kWaves][(row + 63) & (kRing - 1)], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 rout = avail;
                 lds_store(&sh.cons[kWaves], rout);
-                __hip_atomic_store(prog_out, tag | (unsigned long long)rout, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                wait_vm_stores();   // the edge values are performed before the progress word
+                __hip_atomic_store(prog_out, tag | (unsigned long long)rout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 moved = true;
             }
         }
@@ -358,12 +366,7 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(SweepArgs<TS> a) {
         const int S = (int)(n / (unsigned)a.nd);
         const int d = (int)(n % (unsigned)a.nd);
         if (w < kWaves) {
-            if ((S * kWaves + w) * 64 < a.nx) {
-                if (a.eta[d] > 0.0)
-                    compute_wave<TS, false, P>(a, sh, S, d, w, lane);
-                else
-                    compute_wave<TS, true, P>(a, sh, S, d, w, lane);
-            }
+            if ((S * kWaves + w) * 64 < a.nx) compute_wave<TS, P>(a, sh, S, d, w, lane);
         } else if ((S * kWaves) * 64 < a.nx) {
             helper_wave<TS>(a, sh, S, d, lane);
         }
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(SweepArgs<TS> a) {
 
 template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>& a) {
-    constexpr int P = sizeof(TS) == 4 ? 2 : 1;
+    constexpr int P = sizeof(TS) == 4 ? 2 : 2;
     hipLaunchKernelGGL((k_sweep<TS, P>), dim3(a.grid_blocks), dim3(64 * (kWaves + 1)), 0, s, a);
 }
 template void launch_sweep<double>(hipStream_t, const SweepArgs<double>&);
