@@ -98,7 +98,7 @@ struct dlr_instance {
     double* norm_out = nullptr;
     double* energy_out = nullptr;
     unsigned* counters = nullptr;
-    double *Gm = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
+    double *Gm = nullptr, *Ra = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
     double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
     double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr;
     int* status = nullptr;
@@ -107,7 +107,7 @@ struct dlr_instance {
     int* h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch shapes
-    int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_proj = 512, red_blocks = 64;
+    int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
 
     bool fp32() const { return prec != DLR_FP64; }
     size_t sweep_bytes() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -160,6 +160,7 @@ struct dlr_instance {
         energy_out = A.take<double>(2);
         counters = A.take<unsigned>(8);
         Gm = A.take<double>(R * R);
+        Ra = A.take<double>(R * R);
         R1 = A.take<double>(R * R);
         R1i = A.take<double>(R * R);
         R2 = A.take<double>(R * R);
@@ -318,10 +319,10 @@ dlr_status step_once(dlr_instance* I) {
 
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
-    dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, I->ny, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->ny, I->R1i, I->Xt);
-    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, 0, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
@@ -337,10 +338,18 @@ dlr_status step_once(dlr_instance* I) {
     la.Binv = I->Binv; la.y = I->yv; la.red_partials = I->red; la.red_blocks = I->red_blocks; la.v = I->vv;
     la.L = I->L; la.status = I->status;
     dlr::launch_lstep(s, la);
-    // 8. L = W S^T in the quadrature inner product (CGS2 with angular completion), then the SVD of S
-    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->R2,
-                             nullptr, 0, I->status, dlr::kStatusNoCompletion);
-    dlr::launch_svd(s, r, I->R2, I->Vsvd, I->Sn, I->status);
+    // 8. L = W S^T in the quadrature inner product: Cholesky QR twice, R = R2 R1; the CGS2 with
+    // angular completion recomputes W and R on the device when a pivot flagged near-dependent columns
+    dlr::launch_gram<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_trmm<double>(s, nq, r, I->L, (size_t)nq, 0, I->R1i, I->Wt);
+    dlr::launch_gram<double>(s, nq, r, I->Wt, (size_t)nq, 0, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_trmm<double>(s, nq, r, I->Wt, (size_t)nq, 0, I->R2i, I->Wq);
+    dlr::launch_small_matmul(s, r, I->R2, I->R1, I->Ra);
+    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
+                             I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
+    dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
     dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef);
     // 9. temperature update with the mean intensity of the new factors

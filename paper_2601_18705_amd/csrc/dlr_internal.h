@@ -107,10 +107,13 @@ void launch_sweep(hipStream_t s, const SweepArgs<TS>& a);
 
 // ----------------------------------------------------------------------------- reductions
 // V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny).
-// G = scale * V^T V (r x r, row-major), via per-block partials in work [nblocks][r^2].
+// G = scale * V^T diag(weight) V (r x r, row-major; weight nullable = 1), via per-block partials in
+// work [nblocks][r^2].
 template <typename TV>
-void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, double scale, double* work,
-                 int nblocks, double* G);
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double scale,
+                 double* work, int nblocks, double* G);
+// C = A B for r x r row-major matrices
+void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C);
 // Cholesky QR step: G (the sum of nblocks partial Gram matrices) -> R, Rinv; a pivot
 // too small for Cholesky QR sets status_code in *status
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,

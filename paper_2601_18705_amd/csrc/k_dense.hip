@@ -17,71 +17,73 @@ namespace dlr {
 namespace {
 
 // ---------------------------------------------------------------------------------------------- block reductions
-template <int NT>
-__device__ double block_max(double v, double* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-template <int NT>
-__device__ int block_min_int(int v, int* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (t < w) sh[t] = min(sh[t], sh[t + w]);
-        __syncthreads();
-    }
-    const int r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 constexpr int kDeimThreads = 1024;
+constexpr int kDeimWaves = kDeimThreads / 64;
 constexpr int kMaxOrdinates = 16384;
+
+// Reductions over the workgroup: wavefront shuffles, one slot per wavefront in LDS, one barrier;
+// every thread then combines the slots in wavefront order, so all threads hold the same result.
+__device__ double block_max1(double v, double* slots) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = slots[0];
+    for (int w = 1; w < kDeimWaves; ++w) m = fmax(m, slots[w]);
+    return m;
+}
+__device__ void block_minidx_max(int& p, double& v, int* islots, double* dslots) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        p = min(p, __shfl_xor(p, off));
+        v = fmax(v, __shfl_xor(v, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        islots[threadIdx.x >> 6] = p;
+        dslots[threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    p = islots[0];
+    v = dslots[0];
+    for (int w = 1; w < kDeimWaves; ++w) {
+        p = min(p, islots[w]);
+        v = fmax(v, dslots[w]);
+    }
+}
 
 // ---------------------------------------------------------------------------------------------- DEIM
 __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     __shared__ double shd[kDeimThreads];
     __shared__ int shi[kDeimThreads];
+    __shared__ double slotA[kDeimWaves], slotB[kDeimWaves];
+    __shared__ int islot[kDeimWaves];
     __shared__ unsigned char piv[kMaxOrdinates];
     __shared__ double beta[kMaxRank];
     __shared__ double M[kMaxRank * (kMaxRank + 1)];
     __shared__ int sel[kMaxRank];
     __shared__ int bad;
     const int nq = a.nq, r = a.r, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const double* __restrict__ W = a.W;
     double* __restrict__ U = a.work;
     if (tid == 0) bad = 0;
     for (int q = tid; q < nq; q += kDeimThreads) piv[q] = 0;
     for (int i = tid; i < r * nq; i += kDeimThreads) U[i] = W[i];
-    // beta_j = int W_j = sum_q w_q W_j(q)
-    for (int j = 0; j < r; ++j) {
+    // beta_j = int W_j = sum_q w_q W_j(q): wavefront j % 16 sums column j in lane order
+    for (int j = wv; j < r; j += kDeimWaves) {
         double acc = 0.0;
-        for (int q = tid; q < nq; q += kDeimThreads) acc += a.w[q] * W[(size_t)j * nq + q];
-        shd[tid] = acc;
-        __syncthreads();
-        for (int w = kDeimThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) shd[tid] += shd[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) beta[j] = shd[0];
-        __syncthreads();
+        for (int q = lane; q < nq; q += 64) acc += a.w[q] * W[(size_t)j * nq + q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) beta[j] = acc;
     }
+    __syncthreads();
     for (int j = 0; j < r; ++j) {
         const double* col = U + (size_t)j * nq;
         double m = 0.0;
         for (int q = tid; q < nq; q += kDeimThreads)
             if (!piv[q]) m = fmax(m, fabs(col[q]));
-        m = block_max<kDeimThreads>(m, shd);
+        m = block_max1(m, slotA);   // also orders the previous elimination before these reads
         const double thr = (1.0 - a.tie_tol) * m;
         int p = 0x7fffffff;
         double second = 0.0;
@@ -91,8 +93,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             if (v >= thr) p = min(p, q);
             else second = fmax(second, v);
         }
-        p = block_min_int<kDeimThreads>(p, shi);
-        second = block_max<kDeimThreads>(second, shd);
+        block_minidx_max(p, second, islot, slotB);
         if (a.forced) {
             const int f = a.forced[j];
             if (tid == 0 && (f < 0 || f >= nq || piv[f])) bad = 1;
@@ -100,20 +101,31 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         }
         if (tid == 0) {
             sel[j] = p;
-            piv[p] = 1;
             a.margins[j] = (m > 0.0) ? (m - second) / m : 0.0;
             if (!(m > 0.0)) bad = 1;
         }
-        __syncthreads();
-        // eliminate column j from the remaining rows, columns k > j
+        // the owner of row p marks it; every thread only tests the rows it owns
+        if (p % kDeimThreads == tid) piv[p] = 1;
+        // eliminate column j from the remaining rows, columns k > j, eight columns at a time so the
+        // loads of a batch are in flight together
         const double pv = col[p];
-        for (int q = tid; q < nq; q += kDeimThreads) {
-            if (piv[q]) continue;
-            const double l = col[q] / pv;
-            for (int k = j + 1; k < r; ++k) U[(size_t)k * nq + q] -= l * U[(size_t)k * nq + p];
+        for (int k0 = j + 1; k0 < r; k0 += 8) {
+            double up[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) up[b] = (k0 + b < r) ? U[(size_t)(k0 + b) * nq + p] : 0.0;
+            for (int q = tid; q < nq; q += kDeimThreads) {
+                if (piv[q]) continue;
+                const double l = col[q] / pv;
+                double x[8];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) x[b] = (k0 + b < r) ? U[(size_t)(k0 + b) * nq + q] : 0.0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (k0 + b < r) U[(size_t)(k0 + b) * nq + q] = x[b] - l * up[b];
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // c = What^{-T} beta: solve M c = beta with M[i][j] = What[j][i] = W_i(Omega^(j))
     const int ld = r + 1;
     for (int o = tid; o < r * r; o += kDeimThreads) {
@@ -315,18 +327,21 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_apply(LstepArgs a) {
 // every pair is orthogonal to working precision; then sort by column norm
 // (descending), sign each V column so its largest-magnitude entry is positive,
 // and return V and S' = S V (column k = U_k sigma_k).
-constexpr int kSvdThreads = 1024;
+//
+// Round-robin (circle) schedule: in round t slot 0 holds column 0 and slot i >= 1
+// holds column 1 + (i - 1 + t) mod (re - 1); slots k and re-1-k form pair k.  The
+// pairs of a round are disjoint, so the eight lanes of pair k compute its rotation
+// from their own rows and apply it at once: one barrier per round.
+constexpr int kSvdThreads = 256;
+constexpr int kSvdLanes = 8;   // lanes per column pair; kSvdThreads / kSvdLanes >= kMaxRank / 2
 
 __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __restrict__ Rin,
                                                      double* __restrict__ Vout, double* __restrict__ Sout,
                                                      int* status) {
     __shared__ double S[kMaxRank * kMaxRank];
     __shared__ double V[kMaxRank * kMaxRank];
-    __shared__ double rc[kMaxRank / 2 + 1], rs[kMaxRank / 2 + 1];
-    __shared__ int pos[kMaxRank + 1];
     __shared__ double nrm[kMaxRank];
     __shared__ int order[kMaxRank];
-    __shared__ int rotated;
     const int tid = threadIdx.x;
     const int rr = r * r;
     for (int o = tid; o < rr; o += kSvdThreads) {
@@ -335,147 +350,112 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
         V[o] = (i == j) ? 1.0 : 0.0;
     }
     const double tol = fmax(1e-15, r * 2.3e-16);
-    const int re = r + (r & 1);   // even number of positions; position r (if any) is a dummy
+    const int re = r + (r & 1);   // even number of slots; column r (if any) is a dummy
     const int np = re / 2;
-    const int G = (r <= 32) ? 32 : 64;   // lanes per pair (rows handled per lane: ceil(r / G))
+    const int k = tid / kSvdLanes, lane = tid % kSvdLanes;
     __syncthreads();
     int sweep = 0;
-    for (; sweep < 40; ++sweep) {
-        if (tid == 0) rotated = 0;
-        for (int i = tid; i < re; i += kSvdThreads) pos[i] = i;
-        __syncthreads();
+    bool converged = false;
+    for (; sweep < 40 && !converged; ++sweep) {
+        int rotated = 0;
         for (int round = 0; round < re - 1; ++round) {
-            // pairs (pos[k], pos[re-1-k]); pair k handled by lanes [k*G, k*G+G)
-            for (int base = 0; base < np * G; base += kSvdThreads) {
-                const int t = base + tid;
-                const int k = t / G, lane = t % G;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                int p = -1, qq = -1;
-                if (k < np) {
-                    p = pos[k];
-                    qq = pos[re - 1 - k];
-                    if (p < r && qq < r)
-                        for (int i = lane; i < r; i += G) {
-                            const double sp = S[i * r + p], sq = S[i * r + qq];
-                            al += sp * sp;
-                            be += sq * sq;
-                            ga += sp * sq;
-                        }
-                }
-                for (int off = G / 2; off > 0; off >>= 1) {
-                    al += __shfl_xor(al, off, G);
-                    be += __shfl_xor(be, off, G);
-                    ga += __shfl_xor(ga, off, G);
-                }
-                if (k < np && lane == 0) {
-                    double c = 1.0, s = 0.0;
-                    if (p < r && qq < r && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            if (k < np) {
+                const int sa = k, sb = re - 1 - k;
+                const int p = (sa == 0) ? 0 : 1 + (sa - 1 + round) % (re - 1);
+                const int q = 1 + (sb - 1 + round) % (re - 1);
+                if (p < r && q < r) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = lane; i < r; i += kSvdLanes) {
+                        const double sp = S[i * r + p], sq = S[i * r + q];
+                        al += sp * sp;
+                        be += sq * sq;
+                        ga += sp * sq;
+                    }
+#pragma unroll
+                    for (int off = kSvdLanes / 2; off > 0; off >>= 1) {
+                        al += __shfl_xor(al, off, kSvdLanes);
+                        be += __shfl_xor(be, off, kSvdLanes);
+                        ga += __shfl_xor(ga, off, kSvdLanes);
+                    }
+                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
                         const double zeta = (be - al) / (2.0 * ga);
                         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = c * tt;
+                        const double c = 1.0 / sqrt(1.0 + tt * tt);
+                        const double sn = c * tt;
                         rotated = 1;
+                        for (int i = lane; i < r; i += kSvdLanes) {
+                            const double sp = S[i * r + p], sq = S[i * r + q];
+                            S[i * r + p] = c * sp - sn * sq;
+                            S[i * r + q] = sn * sp + c * sq;
+                            const double vp = V[i * r + p], vq = V[i * r + q];
+                            V[i * r + p] = c * vp - sn * vq;
+                            V[i * r + q] = sn * vp + c * vq;
+                        }
                     }
-                    rc[k] = c;
-                    rs[k] = s;
                 }
             }
             __syncthreads();
-            for (int o = tid; o < np * r; o += kSvdThreads) {
-                const int k = o / r, i = o % r;
-                const int p = pos[k], qq = pos[re - 1 - k];
-                if (p < r && qq < r && rs[k] != 0.0) {
-                    const double c = rc[k], s = rs[k];
-                    const double sp = S[i * r + p], sq = S[i * r + qq];
-                    S[i * r + p] = c * sp - s * sq;
-                    S[i * r + qq] = s * sp + c * sq;
-                    const double vp = V[i * r + p], vq = V[i * r + qq];
-                    V[i * r + p] = c * vp - s * vq;
-                    V[i * r + qq] = s * vp + c * vq;
-                }
-            }
-            __syncthreads();
-            // round-robin rotation of positions 1..re-1
-            if (tid == 0) {
-                const int last = pos[re - 1];
-                for (int i = re - 1; i > 1; --i) pos[i] = pos[i - 1];
-                pos[1] = last;
-            }
-            __syncthreads();
         }
-        const int rot = rotated;
-        __syncthreads();
-        if (!rot) break;
+        converged = !__syncthreads_or(rotated);
     }
-    if (tid == 0 && sweep >= 40) atomicOr(status, (int)kStatusSvdNoConv);
-    for (int k = tid; k < r; k += kSvdThreads) {
-        double s = 0.0;
-        for (int i = 0; i < r; ++i) s += S[i * r + k] * S[i * r + k];
-        nrm[k] = sqrt(s);
+    if (tid == 0 && !converged) atomicOr(status, (int)kStatusSvdNoConv);
+    for (int c = tid; c < r; c += kSvdThreads) {
+        double sum = 0.0;
+        for (int i = 0; i < r; ++i) sum += S[i * r + c] * S[i * r + c];
+        nrm[c] = sqrt(sum);
     }
     __syncthreads();
-    if (tid == 0) {   // stable selection sort, descending
-        for (int k = 0; k < r; ++k) order[k] = k;
-        for (int k = 0; k < r; ++k) {
-            int best = k;
-            for (int m = k + 1; m < r; ++m)
-                if (nrm[order[m]] > nrm[order[best]]) best = m;
-            const int t = order[best];
-            for (int m = best; m > k; --m) order[m] = order[m - 1];
-            order[k] = t;
-        }
+    // stable descending order: rank of column c = columns with a larger norm, or an equal norm
+    // and a smaller index
+    for (int c = tid; c < r; c += kSvdThreads) {
+        int rank = 0;
+        for (int m = 0; m < r; ++m) rank += (nrm[m] > nrm[c] || (nrm[m] == nrm[c] && m < c)) ? 1 : 0;
+        order[rank] = c;
     }
     __syncthreads();
-    for (int k = tid; k < r; k += kSvdThreads) {
-        const int src = order[k];
+    for (int c = tid; c < r; c += kSvdThreads) {
+        const int src = order[c];
         int m = 0;
         double best = -1.0;
         for (int i = 0; i < r; ++i)
             if (fabs(V[i * r + src]) > best) { best = fabs(V[i * r + src]); m = i; }
         const double sg = (V[m * r + src] < 0.0) ? -1.0 : 1.0;
         for (int i = 0; i < r; ++i) {
-            Vout[i * r + k] = sg * V[i * r + src];
-            Sout[i * r + k] = sg * S[i * r + src];
+            Vout[i * r + c] = sg * V[i * r + src];
+            Sout[i * r + c] = sg * S[i * r + src];
         }
     }
 }
 
-// X[k][c] = sum_j V[j][c] M[j][k]
+// X[k][c] = sum_j V[j][c] M[j][k]; one thread per output, consecutive threads along c
 __global__ __launch_bounds__(256) void k_rmul(int n, int r, const double* __restrict__ V, const double* __restrict__ M,
                                               double* __restrict__ X) {
     __shared__ double sM[kMaxRank * kMaxRank];
     for (int o = threadIdx.x; o < r * r; o += blockDim.x) sM[o] = M[o];
     __syncthreads();
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    double v[kMaxRank];
-    for (int j = 0; j < r; ++j) v[j] = V[(size_t)j * n + c];
-    for (int k = 0; k < r; ++k) {
-        double s = 0.0;
-        for (int j = 0; j < r; ++j) s += v[j] * sM[j * r + k];
-        X[(size_t)k * n + c] = s;
-    }
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)n * r) return;
+    const int k = (int)(o / n), c = (int)(o % n);
+    double s = 0.0;
+    for (int j = 0; j < r; ++j) s += V[(size_t)j * n + c] * sM[j * r + k];
+    X[(size_t)k * n + c] = s;
 }
 
-// beta_k = sum_q w_q W_k(q), coef = S beta
-__global__ __launch_bounds__(256) void k_wsum(int nq, int r, const double* __restrict__ W,
-                                              const double* __restrict__ w, const double* __restrict__ S,
-                                              double* __restrict__ beta, double* __restrict__ coef) {
-    __shared__ double sh[256];
+// beta_k = sum_q w_q W_k(q), coef = S beta; wavefront k sums column k (fixed lane order)
+__global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __restrict__ W,
+                                               const double* __restrict__ w, const double* __restrict__ S,
+                                               double* __restrict__ beta, double* __restrict__ coef) {
     __shared__ double sb[kMaxRank];
-    for (int k = 0; k < r; ++k) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = wv; k < r; k += 16) {
         double acc = 0.0;
-        for (int q = threadIdx.x; q < nq; q += 256) acc += w[q] * W[(size_t)k * nq + q];
-        sh[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) sb[k] = sh[0];
-        __syncthreads();
+        for (int q = lane; q < nq; q += 64) acc += w[q] * W[(size_t)k * nq + q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) sb[k] = acc;
     }
-    for (int i = threadIdx.x; i < r; i += 256) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
         beta[i] = sb[i];
         double s = 0.0;
         for (int j = 0; j < r; ++j) s += S[i * r + j] * sb[j];
@@ -507,12 +487,12 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 }
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
-    hipLaunchKernelGGL(k_rmul, dim3((n + 255) / 256), dim3(256), 0, s, n, r, V, M, X);
+    hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * r + 255) / 256)), dim3(256), 0, s, n, r, V, M, X);
 }
 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
                  double* coef) {
-    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(256), 0, s, nq, r, W, w, S, beta, coef);
+    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef);
 }
 
 }  // namespace dlr

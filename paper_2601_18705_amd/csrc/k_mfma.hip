@@ -39,12 +39,14 @@ __device__ __forceinline__ void store_tile(double* out, int r, int ti, int tj, d
 }
 
 // ------------------------------------------------------------------------------------------------ Gram
-// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) V_j(e)
+// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) wt(e) V_j(e), wt = weight or 1
 template <typename TV, int RT>
 __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV* __restrict__ V, size_t ldv,
-                                                        int pad_ny, double scale, double* __restrict__ partials) {
+                                                        int pad_ny, const double* __restrict__ weight, double scale,
+                                                        double* __restrict__ partials) {
     constexpr int RP = 16 * RT, NT = RT * RT, TPW = (NT + 3) / 4;
     __shared__ double sV[RP * kPS];
+    __shared__ double sW[kPC];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     dv4 acc[TPW];
 #pragma unroll
@@ -60,16 +62,18 @@ __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV*
             if (p < r && e < n) v = (double)V[(size_t)p * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
             sV[p * kPS + c] = v;
         }
+        for (int c = threadIdx.x; c < kPC; c += kThreads) sW[c] = (weight && c0 + c < n) ? weight[c0 + c] : 1.0;
         __syncthreads();
         for (int ks = 0; ks < kPC / 4; ++ks) {
             const int c = 4 * ks + (lane >> 4);
+            const double wc = sW[c];
 #pragma unroll
             for (int s = 0; s < TPW; ++s) {
                 const int t = w + 4 * s;
                 if (t < NT) {
                     const int ti = t / RT, tj = t % RT;
-                    acc[s] = mfma4(sV[(ti * 16 + (lane & 15)) * kPS + c], sV[(tj * 16 + (lane & 15)) * kPS + c],
-                                   acc[s]);
+                    acc[s] = mfma4(sV[(ti * 16 + (lane & 15)) * kPS + c],
+                                   wc * sV[(tj * 16 + (lane & 15)) * kPS + c], acc[s]);
                 }
             }
         }
@@ -243,21 +247,23 @@ void sum_partials(hipStream_t s, int total, const double* partials, int nblocks,
 }  // namespace
 
 template <typename TV>
-void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, double scale, double* work,
-                 int nblocks, double* G) {
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double scale,
+                 double* work, int nblocks, double* G) {
     const dim3 g(nblocks), b(kThreads);
     if (r <= 16)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 1>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 1>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 2>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 2>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
     else if (r <= 48)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 3>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 3>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
     else
-        hipLaunchKernelGGL((k_gram_mfma<TV, 4>), g, b, 0, s, n, r, V, ldv, pad_ny, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 4>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
     sum_partials(s, r * r, work, nblocks, 1.0, G);
 }
-template void launch_gram<double>(hipStream_t, long, int, const double*, size_t, int, double, double*, int, double*);
-template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, int, double, double*, int, double*);
+template void launch_gram<double>(hipStream_t, long, int, const double*, size_t, int, const double*, double, double*,
+                                  int, double*);
+template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, int, const double*, double, double*, int,
+                                 double*);
 
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
                     const double* sig_s, const double* q, double* partials, int nblocks) {

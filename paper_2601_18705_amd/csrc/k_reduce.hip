@@ -155,6 +155,20 @@ void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_n
 template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double*);
 template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double*);
 
+__global__ __launch_bounds__(kBlock) void k_small_matmul(int r, const double* __restrict__ A,
+                                                         const double* __restrict__ B, double* __restrict__ C) {
+    for (int o = threadIdx.x; o < r * r; o += blockDim.x) {
+        const int i = o / r, j = o % r;
+        double s = 0.0;
+        for (int k = 0; k < r; ++k) s += A[i * r + k] * B[k * r + j];
+        C[o] = s;
+    }
+}
+
+void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C) {
+    hipLaunchKernelGGL(k_small_matmul, dim3(1), dim3(kBlock), 0, s, r, A, B, C);
+}
+
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
                              double inv_cdt, const double* S0, double* ops) {
     // raw sums go into the tail of ops (beyond the operator block) as scratch
