@@ -39,12 +39,14 @@ __device__ __forceinline__ void store_tile(double* out, int r, int ti, int tj, d
 }
 
 // ------------------------------------------------------------------------------------------------ Gram
-// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) wt(e) V_j(e), wt = weight or 1
+// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) wt(e) V_j(e), wt = weight or 1.
+// The next chunk's global loads are staged in registers while the current chunk's MFMAs run.
 template <typename TV, int RT>
 __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV* __restrict__ V, size_t ldv,
                                                         int pad_ny, const double* __restrict__ weight, double scale,
                                                         double* __restrict__ partials) {
     constexpr int RP = 16 * RT, NT = RT * RT, TPW = (NT + 3) / 4;
+    constexpr int NV = (RP * kPC + kThreads - 1) / kThreads;
     __shared__ double sV[RP * kPS];
     __shared__ double sW[kPC];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -52,18 +54,34 @@ __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV*
 #pragma unroll
     for (int s = 0; s < TPW; ++s) acc[s] = dv4{0.0, 0.0, 0.0, 0.0};
     const long nch = (n + kPC - 1) / kPC;
-    for (long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    double g[NV];
+    double gw = 1.0;
+    auto stage = [&](long ch) {
         const long c0 = ch * kPC;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < RP * kPC; idx += kThreads) {
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
             const int p = idx / kPC, c = idx % kPC;
             const long e = c0 + c;
-            double v = 0.0;
-            if (p < r && e < n) v = (double)V[(size_t)p * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
-            sV[p * kPS + c] = v;
+            g[u] = (p < r && e < n) ? (double)V[(size_t)p * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)] : 0.0;
         }
-        for (int c = threadIdx.x; c < kPC; c += kThreads) sW[c] = (weight && c0 + c < n) ? weight[c0 + c] : 1.0;
+        if (threadIdx.x < kPC) {
+            const long e = c0 + threadIdx.x;
+            gw = (weight && e < n) ? weight[e] : 1.0;
+        }
+    };
+    long ch = blockIdx.x;
+    if (ch < nch) stage(ch);
+    for (; ch < nch; ch += gridDim.x) {
         __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
+            if (idx < RP * kPC) sV[(idx / kPC) * kPS + idx % kPC] = g[u];
+        }
+        if (threadIdx.x < kPC) sW[threadIdx.x] = gw;
+        __syncthreads();
+        if (ch + gridDim.x < nch) stage(ch + gridDim.x);
         for (int ks = 0; ks < kPC / 4; ++ks) {
             const int c = 4 * ks + (lane >> 4);
             const double wc = sW[c];
@@ -93,6 +111,22 @@ __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV*
 //   M2 = sum sigma X_i X_j,  M3 = sum sigma_s X_i X_j,  M4 = sum X0_i X_j
 //   v0 = sum q X_i,  v1..v4 = sums of X_i over the left / right / bottom / top cells
 // Column-major cells e = i*ny + j: (i-1,j) = e - ny and (i,j-1) = e - 1.
+//
+// A wavefront owns whole 16 x 16 tile pairs (ti, tj) and accumulates all five matrices of each,
+// so per four-cell k-step it reads two A operands (X, X0 at ti) and three B operands (X at the
+// left neighbour, the lower neighbour and the cell, at tj) once for five MFMAs.  With one tile
+// pair (r <= 16) the four wavefronts split the k-steps instead and are added at the end.  The
+// next chunk's global loads are issued before the current chunk's MFMAs (register staging).
+template <int RT>
+struct ProjShape {
+    static constexpr int RP = 16 * RT;
+    static constexpr int NPAIR = RT * RT;
+    static constexpr int KS = NPAIR >= 4 ? 1 : 4;                       // k-step split across wavefronts
+    static constexpr int PPW = NPAIR >= 4 ? (NPAIR + 3) / 4 : 1;         // tile pairs per wavefront
+    static constexpr int NX = (RP * (kPC + 1) + kThreads - 1) / kThreads;   // staged X values per thread
+    static constexpr int NL = (RP * kPC + kThreads - 1) / kThreads;         // staged X(left) / X0 per thread
+};
+
 template <int RT>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r, const double* __restrict__ X,
                                                            const double* __restrict__ X0,
@@ -100,7 +134,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
                                                            const double* __restrict__ sig_s,
                                                            const double* __restrict__ q,
                                                            double* __restrict__ partials) {
-    constexpr int RP = 16 * RT, NT = 5 * RT * RT, TPW = (NT + 3) / 4;
+    using Sh = ProjShape<RT>;
+    constexpr int RP = Sh::RP, PPW = Sh::PPW, KS = Sh::KS;
     constexpr int TPP = kThreads / RP;   // threads per basis column for the vectors
     __shared__ double sX[RP * kPS];      // slot c+1 holds cell c0+c, slot 0 the cell before the chunk
     __shared__ double sXl[RP * kPS];     // X at the left neighbour (e - ny)
@@ -110,69 +145,101 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     __shared__ double red[5][kThreads];
     const long n = (long)nx * ny;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    dv4 acc[TPW];
+    dv4 acc[PPW][5];
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) acc[s] = dv4{0.0, 0.0, 0.0, 0.0};
+    for (int pp = 0; pp < PPW; ++pp)
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[pp][m] = dv4{0.0, 0.0, 0.0, 0.0};
     const int pv = threadIdx.x % RP, cv = threadIdx.x / RP;
     double vq = 0.0, vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
     const long nch = (n + kPC - 1) / kPC;
-    for (long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+
+    // register staging of one chunk
+    double gX[Sh::NX], gL[Sh::NL], g0[Sh::NL];
+    double gs = 0.0, gss = 0.0, gq = 0.0;
+    int gf = 0;
+    auto stage = [&](long ch) {
         const long c0 = ch * kPC;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < RP * (kPC + 1); idx += kThreads) {
-            const int p = idx / (kPC + 1), c = idx % (kPC + 1) - 1;
+#pragma unroll
+        for (int u = 0; u < Sh::NX; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
+            const int p = idx / (kPC + 1), c = idx - p * (kPC + 1) - 1;
             const long e = c0 + c;
-            double v = 0.0;
-            if (p < r && e >= 0 && e < n) v = X[(size_t)p * n + e];
-            sX[p * kPS + c + 1] = v;
+            gX[u] = (p < r && e >= 0 && e < n) ? X[(size_t)p * n + e] : 0.0;
         }
-        for (int idx = threadIdx.x; idx < RP * kPC; idx += kThreads) {
+#pragma unroll
+        for (int u = 0; u < Sh::NL; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
             const int p = idx / kPC, c = idx % kPC;
             const long e = c0 + c;
-            double vx = 0.0, v0 = 0.0;
-            if (p < r && e < n) {
-                if (e >= ny) vx = X[(size_t)p * n + e - ny];
-                v0 = X0[(size_t)p * n + e];
-            }
-            sXl[p * kPS + c] = vx;
-            sX0[p * kPS + c] = v0;
+            const bool ok = p < r && e < n;
+            gL[u] = (ok && e >= ny) ? X[(size_t)p * n + e - ny] : 0.0;
+            g0[u] = ok ? X0[(size_t)p * n + e] : 0.0;
         }
-        for (int c = threadIdx.x; c < kPC; c += kThreads) {
-            const long e = c0 + c;
-            double sg = 0.0, ss = 0.0, qq = 0.0;
-            int f = 0;
+        if (threadIdx.x < kPC) {
+            const long e = c0 + threadIdx.x;
+            gs = gss = gq = 0.0;
+            gf = 0;
             if (e < n) {
-                sg = sigma[e];
-                ss = sig_s[e];
-                qq = q[e];
+                gs = sigma[e];
+                gss = sig_s[e];
+                gq = q[e];
                 const long i = e / ny, j = e % ny;
-                f = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
+                gf = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
             }
-            sSig[c] = sg;
-            sSs[c] = ss;
-            sQ[c] = qq;
-            sFlag[c] = f;
         }
+    };
+    auto commit = [&]() {
+#pragma unroll
+        for (int u = 0; u < Sh::NX; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
+            if (idx < RP * (kPC + 1)) {
+                const int p = idx / (kPC + 1), c1 = idx - p * (kPC + 1);
+                sX[p * kPS + c1] = gX[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < Sh::NL; ++u) {
+            const int idx = threadIdx.x + u * kThreads;
+            if (idx < RP * kPC) {
+                const int p = idx / kPC, c = idx % kPC;
+                sXl[p * kPS + c] = gL[u];
+                sX0[p * kPS + c] = g0[u];
+            }
+        }
+        if (threadIdx.x < kPC) {
+            sSig[threadIdx.x] = gs;
+            sSs[threadIdx.x] = gss;
+            sQ[threadIdx.x] = gq;
+            sFlag[threadIdx.x] = gf;
+        }
+    };
+
+    long ch = blockIdx.x;
+    if (ch < nch) stage(ch);
+    for (; ch < nch; ch += gridDim.x) {
+        __syncthreads();   // the previous chunk's LDS reads are done
+        commit();
         __syncthreads();
-        for (int ks = 0; ks < kPC / 4; ++ks) {
+        if (ch + gridDim.x < nch) stage(ch + gridDim.x);   // in flight during the MFMAs below
+        for (int ks = (KS == 1 ? 0 : w); ks < kPC / 4; ks += KS) {
             const int c = 4 * ks + (lane >> 4);
             const bool bottom = (sFlag[c] & 4) != 0;   // no lower neighbour
             const double sg = sSig[c], ss = sSs[c];
 #pragma unroll
-            for (int s = 0; s < TPW; ++s) {
-                const int t = w + 4 * s;
-                if (t < NT) {
-                    const int m = t / (RT * RT), ti = (t / RT) % RT, tj = t % RT;
-                    const int pa = ti * 16 + (lane & 15), pb = tj * 16 + (lane & 15);
-                    const double a = (m == 4) ? sX0[pa * kPS + c] : sX[pa * kPS + c + 1];
-                    const double xb = sX[pb * kPS + c + 1];
-                    double b;
-                    if (m == 0) b = sXl[pb * kPS + c];
-                    else if (m == 1) b = bottom ? 0.0 : sX[pb * kPS + c];
-                    else if (m == 2) b = sg * xb;
-                    else if (m == 3) b = ss * xb;
-                    else b = xb;
-                    acc[s] = mfma4(a, b, acc[s]);
+            for (int pp = 0; pp < PPW; ++pp) {
+                const int pr = (KS == 1) ? w + 4 * pp : 0;
+                if (pr < Sh::NPAIR) {
+                    const int pa = (pr / RT) * 16 + (lane & 15), pb = (pr % RT) * 16 + (lane & 15);
+                    const double ax = sX[pa * kPS + c + 1], a0 = sX0[pa * kPS + c];
+                    const double bx = sX[pb * kPS + c + 1];
+                    const double bl = sXl[pb * kPS + c];
+                    const double bd = bottom ? 0.0 : sX[pb * kPS + c];
+                    acc[pp][0] = mfma4(ax, bl, acc[pp][0]);
+                    acc[pp][1] = mfma4(ax, bd, acc[pp][1]);
+                    acc[pp][2] = mfma4(ax, sg * bx, acc[pp][2]);
+                    acc[pp][3] = mfma4(ax, ss * bx, acc[pp][3]);
+                    acc[pp][4] = mfma4(a0, bx, acc[pp][4]);
                 }
             }
         }
@@ -190,12 +257,33 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     }
     const int rr = r * r;
     double* out = partials + (size_t)blockIdx.x * (5 * rr + 5 * r);
+    if (KS == 1) {
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-        const int t = w + 4 * s;
-        if (t < NT) {
-            const int m = t / (RT * RT), ti = (t / RT) % RT, tj = t % RT;
-            store_tile(out + m * rr, r, ti, tj, acc[s], 1.0);
+        for (int pp = 0; pp < PPW; ++pp) {
+            const int pr = w + 4 * pp;
+            if (pr < Sh::NPAIR)
+#pragma unroll
+                for (int m = 0; m < 5; ++m) store_tile(out + m * rr, r, pr / RT, pr % RT, acc[pp][m], 1.0);
+        }
+    } else {
+        // four wavefronts hold k-step partials of the same tiles: add them in wavefront order via LDS
+        __syncthreads();
+        __shared__ double sacc[KS > 1 ? 4 * 5 * 256 : 1];
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sacc[((w * 5 + m) * 4 + v) * 64 + lane] = acc[0][m][v];
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                dv4 t = acc[0][m];
+#pragma unroll
+                for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) t[v] += sacc[((ww * 5 + m) * 4 + v) * 64 + lane];
+                store_tile(out + m * rr, r, 0, 0, t, 1.0);
+            }
         }
     }
     __syncthreads();

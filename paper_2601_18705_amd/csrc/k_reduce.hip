@@ -17,64 +17,71 @@ constexpr int kBlock = 256;
 // breakdown threshold (relative residual 1e-6 of a column against the previous
 // ones) flags status_code: the columns are too close to dependent for Cholesky QR
 // and the CGS2 fallback recomputes the factor.
-__global__ __launch_bounds__(kBlock) void k_chol(int r, const double* __restrict__ partials, int nblocks,
-                                                 double* __restrict__ R, double* __restrict__ Rinv, int* status,
-                                                 int status_code) {
+// The factorisation is right-looking with one barrier per column (row k of R' is
+// formed by the threads of row k's entries); R'^{-1} is formed column by column,
+// one wavefront per column, by back substitution in the wavefront's lanes.
+constexpr int kCholThreads = 1024;
+
+__global__ __launch_bounds__(kCholThreads) void k_chol(int r, const double* __restrict__ partials, int nblocks,
+                                                       double* __restrict__ R, double* __restrict__ Rinv,
+                                                       int* status, int status_code) {
     __shared__ double A[kMaxRank * kMaxRank];
     __shared__ double Rp[kMaxRank * kMaxRank];
+    __shared__ double Ri[kMaxRank * kMaxRank];
     __shared__ double sc[kMaxRank];
     __shared__ int bad;
     const int rr = r * r;
-    if (threadIdx.x == 0) bad = 0;
-    for (int o = threadIdx.x; o < rr; o += kBlock) {
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    for (int o = tid; o < rr; o += kCholThreads) {
         double g = 0.0;
         for (int b = 0; b < nblocks; ++b) g += partials[(size_t)b * rr + o];
         A[o] = g;
         Rp[o] = 0.0;
+        Ri[o] = 0.0;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < r; k += kBlock) {
+    for (int k = tid; k < r; k += kCholThreads) {
         const double gkk = A[k * r + k];
         if (!(gkk > 0.0) || !isfinite(gkk)) bad = 1;
         sc[k] = (gkk > 0.0) ? 1.0 / sqrt(gkk) : 0.0;
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < rr; o += kBlock) A[o] *= sc[o / r] * sc[o % r];
+    for (int o = tid; o < rr; o += kCholThreads) A[o] *= sc[o / r] * sc[o % r];
     __syncthreads();
     for (int k = 0; k < r; ++k) {
+        // every thread reads the pivot; row k of R' and the trailing update of the upper triangle
+        // both read row k of A, which this iteration does not change
         const double piv = A[k * r + k];
-        if (threadIdx.x == 0 && !(piv > 1e-12)) bad = 1;
         const double rkk = sqrt(fmax(piv, 1e-300));
-        for (int j = threadIdx.x; j < r; j += kBlock)
-            if (j >= k) Rp[k * r + j] = (j == k) ? rkk : A[k * r + j] / rkk;
-        __syncthreads();
-        for (int o = threadIdx.x; o < rr; o += kBlock) {
+        if (tid == 0 && !(piv > 1e-12)) bad = 1;
+        for (int o = tid; o < rr; o += kCholThreads) {
             const int i = o / r, j = o % r;
-            if (i > k && j > k) A[o] -= Rp[k * r + i] * Rp[k * r + j];
+            if (i == k && j >= k) Rp[k * r + j] = (j == k) ? rkk : A[k * r + j] / rkk;
+            if (i > k && j > k && j >= i) A[o] -= (A[k * r + i] / rkk) * (A[k * r + j] / rkk);
         }
-        __syncthreads();
+        __syncthreads();   // only the upper triangle of A is read or updated
     }
-    // inverse of the upper-triangular R' column by column (back substitution)
-    for (int j = threadIdx.x; j < r; j += kBlock) {
-        for (int i = r - 1; i >= 0; --i) {
-            double v;
-            if (i > j) {
-                v = 0.0;
-            } else {
-                v = (i == j) ? 1.0 : 0.0;
-                for (int m = i + 1; m <= j; ++m) v -= Rp[i * r + m] * A[m * r + j];
-                v /= Rp[i * r + i];
-            }
-            A[i * r + j] = v;   // A now holds R'^{-1}; column j is written only by thread j
+    // R'^{-1}: column j solved by wavefront j % 16 (lanes over rows, back substitution over i)
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int j = wv; j < r; j += kCholThreads / 64) {
+        for (int i = j; i >= 0; --i) {
+            // v_i = (delta_ij - sum_{m=i+1..j} R'_im v_m) / R'_ii, with v_m (m > i) already in Ri
+            double part = 0.0;
+            for (int m = i + 1 + lane; m <= j; m += 64) part += Rp[i * r + m] * Ri[m * r + j];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if (lane == 0) Ri[i * r + j] = (((i == j) ? 1.0 : 0.0) - part) / Rp[i * r + i];
+            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < rr; o += kBlock) {
+    for (int o = tid; o < rr; o += kCholThreads) {
         const int i = o / r, j = o % r;
         R[o] = (sc[j] > 0.0) ? Rp[o] / sc[j] : 0.0;
-        Rinv[o] = sc[i] * A[o];
+        Rinv[o] = sc[i] * Ri[o];
     }
-    if (threadIdx.x == 0 && bad) atomicOr(status, status_code);
+    if (tid == 0 && bad) atomicOr(status, status_code);
 }
 
 // ---------------------------------------------------------------------------------------------- X = V Rinv
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
 
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv, int* status,
                  int status_code) {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kBlock), 0, s, r, partials, nblocks, R, Rinv, status, status_code);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), 0, s, r, partials, nblocks, R, Rinv, status, status_code);
 }
 
 template <typename TV>
