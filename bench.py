@@ -80,6 +80,57 @@ def cpu_baseline(p, steps, warm=0):
             "steps_per_s": steps / dt}
 
 
+def serving_leg(n_requests, max_s, budget_gib):
+    """Continuous batching over the first n_requests of the seeded Poisson request stream
+    (FP32 sweeps); p50/p99 time-to-solution and aggregate cell-angle updates/s."""
+    from paper_2601_18705_amd import dlrtrt, serve
+    from synth import problems
+    reqs = []
+    for t, prob in problems.request_stream(count=n_requests):
+        prob["precision"], prob["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+        reqs.append((t, prob, int(prob["nsteps"])))
+
+    def progress(passes, done, inflight, queued):
+        if passes % 50 == 0:
+            print(f"[bench] serving pass {passes}: done {done} in flight {inflight} queued {queued}",
+                  file=sys.stderr, flush=True)
+
+    res = serve.serve(reqs, hbm_budget=int(budget_gib * (1 << 30)), max_wall_s=max_s, progress=progress)
+    return {"requests": n_requests, "completed": res["completed"], "unfinished": res["unfinished"],
+            "p50_s": res["p50_s"], "p99_s": res["p99_s"], "ca_per_s": res["ca_per_s"], "wall_s": res["wall_s"],
+            "hbm_budget_gib": budget_gib,
+            "stream": "seeded Poisson 200 req/s; 64^2-1024^2 grids, ranks 8-32, 20-200 steps, 512 ordinates, "
+                      "checkerboard or log-normal medium"}
+
+
+def batch_run(count, steps):
+    """The batched-instances workload: count independent problems admitted at once and
+    advanced together for `steps` steps (FP32 sweeps, FP64 energy update)."""
+    from paper_2601_18705_amd import dlrtrt
+    from synth import problems
+    insts = problems.batch_instances(count=count, nsteps=steps)
+    import torch
+    torch.cuda.init()
+    with dlrtrt.Batch() as b:
+        slots = {}
+        for prob in insts:
+            prob["precision"], prob["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+            slots[b.admit(prob, steps)] = prob
+        ca = 0
+        t0 = time.perf_counter()
+        for k in range(steps):
+            b.advance()
+            for slot, prob in slots.items():
+                st = b.read_stats(slot)
+                ca += int(st["si_iters"]) * int(prob["nx"]) * int(prob["ny"]) * int(prob["rank"])
+            if k % 10 == 9:
+                print(f"[bench] batch step {k + 1}/{steps}", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        done = b.poll()
+    return {"instances": count, "steps": steps, "wall_s": wall, "ca_per_s": ca / wall,
+            "instance_steps_per_s": count * steps / wall, "finished": len(done)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +139,12 @@ def main():
     ap.add_argument("--workload", default="random_medium")
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving leg (0 = skip); p50/p99 time-to-solution")
+    ap.add_argument("--serve-max-s", type=float, default=60.0, help="wall-time cap of the serving leg")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving batch")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="run the batched-instances workload (COUNT problems, 50 steps) instead")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed run, run a plain elementwise kernel over a buffer of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -98,6 +155,15 @@ def main():
 
     import torch
     from paper_2601_18705_amd import dlrtrt
+
+    if args.batch:
+        res = batch_run(args.batch, 50)
+        print(json.dumps({"metric": "batched cell-angle updates/s (independent instances, one sweep launch per "
+                                    "source iteration)", "value": res["ca_per_s"], "unit": "cell-angle updates/s",
+                          "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": f"batch_{args.batch}_instances_64-256sq_r4-24_512ord_50steps"},
+                          **res}), flush=True)
+        return
 
     p = make_problem(args.workload)
     if args.fp64:
@@ -166,11 +232,17 @@ def main():
         "si_iterations_per_step": launches / args.steps,
         "device_ms_per_step": step_ms / args.steps,
         "latency_p50_p99_s": None,
+        "serving": None,
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
         "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
     }
+    if args.serve_requests > 0:
+        print(f"[bench] serving leg: {args.serve_requests} requests", file=sys.stderr, flush=True)
+        sv = serving_leg(args.serve_requests, args.serve_max_s, args.serve_budget_gib)
+        out["serving"] = sv
+        out["latency_p50_p99_s"] = [sv["p50_s"], sv["p99_s"]]
     if args.cpu_steps > 0:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(make_problem(args.workload), args.cpu_steps)

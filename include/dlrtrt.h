@@ -147,6 +147,52 @@ dlr_status dlr_force_selection(dlr_handle h, const int32_t *sel);
 /* Free everything.  NULL-safe. */
 dlr_status dlr_destroy(dlr_handle h);
 
+/* ------------------------------------------------------------------------------------------
+ * Batches and serving: many independent problems of uneven size and rank, resident on the
+ * device, advanced together.  A batch owns an HBM budget; a problem is admitted into a slot
+ * while its footprint fits (otherwise DLR_ERR_OOM: retry after a release) and keeps its
+ * factors on the device until the slot is released.  Each dlr_batch_advance moves every active
+ * slot one DLR step: the phases of all slots are issued on per-slot streams so their work
+ * overlaps on the device, and every source iteration sweeps the directions of all unconverged
+ * slots in one persistent launch.  Slots do not interact: a slot's results are bitwise those
+ * of the same problem stepped alone with dlr_step.  The same stepping rules (Algorithm 1) and
+ * error semantics apply per slot; a failed slot is finished with its error status and the
+ * others go on.  Calls on one batch must be serialised by the caller. */
+typedef struct dlr_batch_s *dlr_batch;
+
+/* Device bytes a problem occupies once admitted (validates the problem like dlr_create). */
+dlr_status dlr_batch_footprint(const dlr_problem *prob, size_t *bytes);
+
+/* hbm_budget: bytes the batch may hold at once (0 = free device memory minus 1 GiB).
+ * hip_stream: stream that orders the batch's shared sweep launches (NULL = default stream). */
+dlr_status dlr_batch_create(size_t hbm_budget, void *hip_stream, dlr_batch *out);
+
+/* Admit a problem for n_steps >= 1 steps.  *slot receives its id (increasing, never reused).
+ * DLR_ERR_OOM: the footprint does not fit in what the budget has left; nothing was admitted. */
+dlr_status dlr_batch_admit(dlr_batch b, const dlr_problem *prob, int32_t n_steps, int64_t *slot);
+
+/* One DLR step of every active slot (slots that still have steps to take). */
+dlr_status dlr_batch_advance(dlr_batch b);
+
+/* Slots that finished (all steps taken, or failed) since the last poll, oldest first:
+ * up to cap ids in done[], their number in *n. */
+dlr_status dlr_batch_poll(dlr_batch b, int64_t *done, int32_t cap, int32_t *n);
+
+/* Fields of a slot (as dlr_read_fields); returns the slot's failure status if it failed. */
+dlr_status dlr_batch_read(dlr_batch b, int64_t slot, double *E_r, double *T);
+
+/* Statistics of the slot's most recent step (as dlr_read_stats). */
+dlr_status dlr_batch_read_stats(dlr_batch b, int64_t slot, dlr_step_stats *out);
+
+/* Free the slot and return its bytes to the budget. */
+dlr_status dlr_batch_release(dlr_batch b, int64_t slot);
+
+/* Active slots and bytes in use. */
+dlr_status dlr_batch_usage(dlr_batch b, int32_t *active_slots, size_t *bytes_in_use);
+
+/* Release every slot and free the batch.  NULL-safe. */
+dlr_status dlr_batch_destroy(dlr_batch b);
+
 /* Static description of a status code. */
 const char *dlr_status_string(dlr_status s);
 

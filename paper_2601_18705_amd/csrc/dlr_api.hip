@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -72,6 +74,12 @@ struct dlr_instance {
     bool force_pending = false;
     int64_t steps_done = 0;
     dlr_step_stats stats{};
+    // ---- source-iteration state of the step in progress
+    double* phi_cur = nullptr;
+    double* phi_nxt = nullptr;
+    int si_it = 0;
+    bool si_conv = false;
+    float sweep_ms_acc = 0.f;
     // ---- device memory
     Arena arena;
     double *mu = nullptr, *eta = nullptr, *w = nullptr;
@@ -89,7 +97,9 @@ struct dlr_instance {
     void* edge = nullptr;
     unsigned long long* progress = nullptr;
     unsigned* ticket = nullptr;
-    unsigned long long launch_id = 0;
+    char* sweep_rec = nullptr;       // device SweepArgs record of this instance
+    unsigned* unit_end = nullptr;    // [1] sweep units of this instance
+    std::vector<char> h_sweep_rec;   // host copy of the sweep record (SweepArgs of the instance's precision)
     int nsuper = 0;
     size_t ld = 0;    // elements of one padded-column plane (Psi handed to the QR)
     size_t ldg = 0;   // elements of one diagonal sweep plane (psi, src0, and the 4 copies of sigma_t, s_e)
@@ -155,6 +165,8 @@ struct dlr_instance {
         edge = A.take<char>(R * (size_t)nsuper * ny * sweep_bytes());
         progress = A.take<unsigned long long>(R * (size_t)nsuper);
         ticket = A.take<unsigned>(4);
+        sweep_rec = A.take<char>(sizeof(dlr::SweepArgs<double>));
+        unit_end = A.take<unsigned>(4);
         partials = A.take<double>(partials_count);
         norm_out = A.take<double>(4);
         energy_out = A.take<double>(2);
@@ -240,17 +252,53 @@ dlr_status check_device_status(dlr_instance* I) {
     return fail(code, m);
 }
 
+// The sweep record of an instance (fixed for its life; DEIM rewrites the pointed-to direction data).
 template <typename TS>
-dlr_status step_once(dlr_instance* I) {
-    hipStream_t s = I->stream;
-    const int N = I->N, r = I->r, nq = I->nq;
-    const double cdt = I->c * I->dt;
-    TS* psi = static_cast<TS*>(I->psi);
-    TS* psi_cm = static_cast<TS*>(I->psi_cm);
-    TS* src0 = static_cast<TS*>(I->src0);
-    TS* s_e = static_cast<TS*>(I->s_e);
-    hip_check(hipEventRecord(I->ev[0], s), "event");
+dlr::SweepArgs<TS> make_sweep_record(const dlr_instance* I) {
+    dlr::SweepArgs<TS> sa{};
+    sa.nx = I->nx; sa.ny = I->ny; sa.nd = I->r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * I->r;
+    sa.ldg = I->ldg;
+    sa.src0 = static_cast<const TS*>(I->src0);
+    sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
+    sa.s_e = static_cast<const TS*>(I->s_e);
+    sa.psi = static_cast<TS*>(I->psi);
+    sa.mu = I->sel_mu; sa.eta = I->sel_eta;
+    sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
+    sa.inv_hx = 1.0 / I->hx; sa.inv_hy = 1.0 / I->hy;
+    sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress;
+    sa.status = I->status;
+    sa.spin_limit = 1u << 20;
+    return sa;
+}
 
+void upload_sweep_record(dlr_instance* I) {
+    I->h_sweep_rec.resize(sizeof(dlr::SweepArgs<double>));
+    if (I->fp32()) {
+        const dlr::SweepArgs<float> a = make_sweep_record<float>(I);
+        std::memcpy(I->h_sweep_rec.data(), &a, sizeof(a));
+    } else {
+        const dlr::SweepArgs<double> a = make_sweep_record<double>(I);
+        std::memcpy(I->h_sweep_rec.data(), &a, sizeof(a));
+    }
+    const unsigned units = (unsigned)(I->nsuper * I->r);
+    hip_check(hipMemcpy(I->sweep_rec, I->h_sweep_rec.data(), I->h_sweep_rec.size(), hipMemcpyHostToDevice), "record");
+    hip_check(hipMemcpy(I->unit_end, &units, sizeof(units), hipMemcpyHostToDevice), "record");
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// One DLR step in phases, so that a batch can interleave the phases of many instances:
+//   phase_begin  linearise, DEIM, old solution at the new ordinates (Algorithm 1 steps 1-3)
+//   [sweep]      one persistent launch per source iteration, alone or shared by a batch (step 4)
+//   si_phi       scalar flux, convergence norm and status -> pinned host memory (step 4)
+//   si_check     after the stream has reached si_phi: converged / failed / go on
+//   phase_end    X, projections, L-step, W and S, temperature (steps 5-9)
+//   step_finish  status check and statistics
+template <typename TS>
+void phase_begin(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    const int r = I->r, nq = I->nq;
+    const double cdt = I->c * I->dt;
+    hip_check(hipEventRecord(I->ev[0], s), "event");
     // 1. effective scattering and source
     dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
                           I->q, I->sig_t, I->sig_t32, I->ldg);
@@ -266,57 +314,73 @@ dlr_status step_once(dlr_instance* I) {
     dlr::launch_deim(s, da);
     I->force_pending = false;
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
-    dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta, src0,
-                         I->ldg, I->phi, s_e);
-    // 4. source iteration with sweeps
-    dlr::SweepArgs<TS> sa{};
-    sa.nx = I->nx; sa.ny = I->ny; sa.nd = r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * r; sa.ldg = I->ldg;
-    sa.src0 = src0; sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
-    sa.s_e = s_e; sa.psi = psi; sa.mu = I->sel_mu; sa.eta = I->sel_eta;
-    sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
-    sa.inv_hx = 1.0 / I->hx; sa.inv_hy = 1.0 / I->hy;
-    sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress; sa.ticket = I->ticket;
-    sa.grid_blocks = std::min(sa.total_units, 512);
-    sa.status = I->status;
-    sa.spin_limit = 1u << 20;
-    double* phi_cur = I->phi;
-    double* phi_nxt = I->phi2;
-    int it = 0;
-    bool conv = false;
-    float sweep_ms = 0.f;
-    for (it = 1; it <= I->si_max_iter; ++it) {
-        sa.launch_id = ++I->launch_id;
-        hip_check(hipEventRecord(I->ev[2], s), "event");
-        dlr::launch_sweep<TS>(s, sa);
-        hip_check(hipEventRecord(I->ev[3], s), "event");
-        dlr::launch_phi<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, I->cw, I->sig_s, phi_cur, phi_nxt,
-                            s_e, I->partials, I->nb_phi, I->counters + 0, I->norm_out);
-        std::swap(phi_cur, phi_nxt);
-        hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
-        hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
-        hip_check(hipStreamSynchronize(s), "sync");
-        if (*I->h_status != 0) return check_device_status(I);
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
-        sweep_ms += ms;
-        const double rel = I->h_norm[2];
-        if (!std::isfinite(rel)) {
-            I->poisoned = true;
-            I->poison_code = DLR_ERR_NONFINITE;
-            return fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
-        }
-        I->stats.si_residual = rel;
-        if (rel <= I->si_tol) { conv = true; break; }
+    dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
+                         static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e));
+    I->phi_cur = I->phi;
+    I->phi_nxt = I->phi2;
+    I->si_it = 0;
+    I->si_conv = false;
+    I->sweep_ms_acc = 0.f;
+}
+
+// this instance alone: one sweep launch on its own stream, timed with events
+template <typename TS>
+void sweep_alone(dlr_instance* I) {
+    dlr::SweepLaunch L{};
+    L.ninst = 1;
+    L.total_units = (unsigned)(I->nsuper * I->r);
+    L.unit_end = I->unit_end;
+    L.ticket = I->ticket;
+    L.launch_id = dlr::next_sweep_launch_id();
+    L.grid_blocks = (int)std::min<unsigned>(L.total_units, 512u);
+    hip_check(hipEventRecord(I->ev[2], I->stream), "event");
+    dlr::launch_sweep<TS>(I->stream, reinterpret_cast<const dlr::SweepArgs<TS>*>(I->sweep_rec), L);
+    hip_check(hipEventRecord(I->ev[3], I->stream), "event");
+}
+
+template <typename TS>
+void si_phi(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    dlr::launch_phi<TS>(s, I->nx, I->ny, I->r, static_cast<const TS*>(I->psi), I->ldg, I->sel_mu, I->sel_eta, I->cw,
+                        I->sig_s, I->phi_cur, I->phi_nxt, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
+                        I->counters + 0, I->norm_out);
+    std::swap(I->phi_cur, I->phi_nxt);
+    hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
+    hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
+}
+
+// After the stream has passed si_phi.  Returns DLR_OK with I->si_conv set, or an error (handle poisoned).
+dlr_status si_check(dlr_instance* I) {
+    ++I->si_it;
+    if (*I->h_status != 0) return check_device_status(I);
+    const double rel = I->h_norm[2];
+    if (!std::isfinite(rel)) {
+        I->poisoned = true;
+        I->poison_code = DLR_ERR_NONFINITE;
+        return fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
     }
-    if (phi_cur != I->phi) std::swap(I->phi, I->phi2);
-    if (!conv) {
+    I->stats.si_residual = rel;
+    if (rel <= I->si_tol) {
+        I->si_conv = true;
+        if (I->phi_cur != I->phi) std::swap(I->phi, I->phi2);
+        return DLR_OK;
+    }
+    if (I->si_it >= I->si_max_iter) {
+        if (I->phi_cur != I->phi) std::swap(I->phi, I->phi2);
         I->poisoned = true;
         I->poison_code = DLR_ERR_NOT_CONVERGED;
         return fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
     }
-    const dlr_status ds = check_device_status(I);   // DEIM status before using its output further
-    if (ds != DLR_OK) return ds;
+    return DLR_OK;
+}
 
+template <typename TS>
+void phase_end(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    const int N = I->N, r = I->r, nq = I->nq;
+    const double cdt = I->c * I->dt;
+    TS* psi = static_cast<TS*>(I->psi);
+    TS* psi_cm = static_cast<TS*>(I->psi_cm);
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
     dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
@@ -358,6 +422,10 @@ dlr_status step_once(dlr_instance* I) {
     std::swap(I->X, I->Xn);
     std::swap(I->S, I->Sn);
     hip_check(hipEventRecord(I->ev[1], s), "event");
+}
+
+dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
+    const int r = I->r;
     const dlr_status st = check_device_status(I);
     if (st != DLR_OK) return st;
     double en = 0.0;
@@ -368,19 +436,38 @@ dlr_status step_once(dlr_instance* I) {
     hip_check(hipMemcpy(cwv.data(), I->cw, r * sizeof(double), hipMemcpyDeviceToHost), "cw copy");
     float step_ms = 0.f;
     hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
-    I->stats.si_iters = it;
+    I->stats.si_iters = I->si_it;
     I->stats.energy = en;
     I->stats.deim_min_margin = *std::min_element(marg.begin(), marg.end());
     double sa_ = 0.0;
     for (double v : cwv) sa_ += std::fabs(v);
     I->stats.sum_abs_cw_over_4pi = sa_ / dlr::kFourPi;
-    I->stats.sweep_ms = sweep_ms;
+    I->stats.sweep_ms = timed_sweeps ? I->sweep_ms_acc : 0.f;
     I->stats.step_ms = step_ms;
     I->s_is_usigma = true;
     I->have_sel = true;
     ++I->steps_done;
     I->stats.steps_done = I->steps_done;
     return DLR_OK;
+}
+
+template <typename TS>
+dlr_status step_once(dlr_instance* I) {
+    phase_begin<TS>(I);
+    while (!I->si_conv) {
+        sweep_alone<TS>(I);
+        si_phi<TS>(I);
+        hip_check(hipStreamSynchronize(I->stream), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+        I->sweep_ms_acc += ms;
+        const dlr_status st = si_check(I);
+        if (st != DLR_OK) return st;
+    }
+    const dlr_status ds = check_device_status(I);   // DEIM status before using its output further
+    if (ds != DLR_OK) return ds;
+    phase_end<TS>(I);
+    return step_finish(I, true);
 }
 
 // row-major cells (e = j*nx + i, the C interface) <-> column-major cells (e = i*ny + j, device)
@@ -417,6 +504,134 @@ void refresh_phi_host(dlr_instance* I) {
     upload(I->phi, phi.data(), n * sizeof(double));
 }
 
+// Problem fields, launch shapes and the quadrature of a new instance (no device work).
+void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream) {
+    I->nx = p->nx; I->ny = p->ny; I->N = p->nx * p->ny; I->npol = p->n_polar; I->naz = p->n_azim;
+    I->nq = p->n_polar * p->n_azim; I->r = p->rank; I->prec = p->precision;
+    I->x0 = p->x0; I->x1 = p->x1; I->y0 = p->y0; I->y1 = p->y1;
+    I->hx = (p->x1 - p->x0) / p->nx; I->hy = (p->y1 - p->y0) / p->ny; I->area = I->hx * I->hy;
+    I->dt = p->dt; I->c = p->c; I->a = p->a;
+    I->si_tol = p->si_tol; I->si_max_iter = p->si_max_iter; I->tie = p->deim_tie_tol;
+    for (int k = 0; k < 4; ++k) {
+        I->bc[k] = p->bc[k];
+        I->Tb[k] = p->T_b[k];
+        const double t = p->T_b[k];
+        I->psib[k] = (p->bc[k] == DLR_BC_INFLOW) ? p->a * p->c * t * t * t * t / dlr::kFourPi : 0.0;
+    }
+    I->has_qext = p->q_ext != nullptr;
+    I->stream = stream;
+    I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
+    I->ld = dlr::padded_plane(I->nx, I->ny);
+    I->ldg = dlr::diag_plane(I->nx, I->ny);
+    I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
+    const size_t rr = (size_t)I->r * I->r;
+    I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
+                                  (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});
+    dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
+}
+
+// Device bytes of an instance's arena.
+size_t arena_bytes(dlr_instance* I) {
+    Arena sizing;
+    I->carve(sizing);
+    return sizing.used;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------------------
+// Batches
+struct BatchSlot {
+    int64_t id = 0;
+    dlr_instance* I = nullptr;
+    size_t bytes = 0;
+    int remaining = 0;
+    bool finished = false;
+    dlr_status fail_status = DLR_OK;
+    std::string fail_msg;
+    hipEvent_t ev = nullptr;   // slot stream -> shared sweep stream
+};
+
+struct dlr_batch_s {
+    size_t budget = 0, used = 0;
+    hipStream_t main = nullptr;
+    std::vector<hipStream_t> pool;   // per-slot streams (slot id modulo the pool)
+    std::map<int64_t, BatchSlot> slots;
+    std::deque<int64_t> done;
+    int64_t next_id = 1;
+    // shared sweep launches: one table region per precision
+    size_t cap = 0;                  // table entries per region
+    char* d_table[2] = {nullptr, nullptr};
+    unsigned* d_unit_end[2] = {nullptr, nullptr};
+    char* h_table[2] = {nullptr, nullptr};
+    unsigned* h_unit_end[2] = {nullptr, nullptr};
+    unsigned* d_ticket = nullptr;
+    hipEvent_t ev_main = nullptr;
+};
+
+namespace {
+
+constexpr int kBatchStreams = 8;
+constexpr size_t kRecBytes = sizeof(dlr::SweepArgs<double>);
+static_assert(sizeof(dlr::SweepArgs<float>) == sizeof(dlr::SweepArgs<double>), "one record size");
+
+void batch_reserve(dlr_batch_s* B, size_t entries) {
+    if (entries <= B->cap) return;
+    size_t cap = std::max<size_t>(64, B->cap);
+    while (cap < entries) cap *= 2;
+    for (int g = 0; g < 2; ++g) {
+        if (B->d_table[g]) (void)hipFree(B->d_table[g]);
+        if (B->d_unit_end[g]) (void)hipFree(B->d_unit_end[g]);
+        if (B->h_table[g]) (void)hipHostFree(B->h_table[g]);
+        if (B->h_unit_end[g]) (void)hipHostFree(B->h_unit_end[g]);
+        hip_check(hipMalloc(&B->d_table[g], cap * kRecBytes), "batch table");
+        hip_check(hipMalloc(&B->d_unit_end[g], cap * sizeof(unsigned)), "batch table");
+        hip_check(hipHostMalloc((void**)&B->h_table[g], cap * kRecBytes, hipHostMallocDefault), "batch table");
+        hip_check(hipHostMalloc((void**)&B->h_unit_end[g], cap * sizeof(unsigned), hipHostMallocDefault),
+                  "batch table");
+    }
+    B->cap = cap;
+}
+
+// One persistent sweep launch over the pending slots of one precision (g = 0 FP64, 1 FP32).
+template <typename TS>
+void batch_sweep(dlr_batch_s* B, const std::vector<BatchSlot*>& pending) {
+    const int g = sizeof(TS) == 4 ? 1 : 0;
+    size_t n = 0;
+    unsigned acc = 0;
+    for (BatchSlot* sl : pending) {
+        if (sl->I->fp32() != (g == 1)) continue;
+        std::memcpy(B->h_table[g] + n * kRecBytes, sl->I->h_sweep_rec.data(), kRecBytes);
+        acc += (unsigned)(sl->I->nsuper * sl->I->r);
+        B->h_unit_end[g][n] = acc;
+        ++n;
+    }
+    if (n == 0) return;
+    hip_check(hipMemcpyAsync(B->d_table[g], B->h_table[g], n * kRecBytes, hipMemcpyHostToDevice, B->main), "table");
+    hip_check(hipMemcpyAsync(B->d_unit_end[g], B->h_unit_end[g], n * sizeof(unsigned), hipMemcpyHostToDevice, B->main),
+              "table");
+    dlr::SweepLaunch L{};
+    L.ninst = (int)n;
+    L.total_units = acc;
+    L.unit_end = B->d_unit_end[g];
+    L.ticket = B->d_ticket;
+    L.launch_id = dlr::next_sweep_launch_id();
+    L.grid_blocks = (int)std::min<unsigned>(acc, 1024u);
+    dlr::launch_sweep<TS>(B->main, reinterpret_cast<const dlr::SweepArgs<TS>*>(B->d_table[g]), L);
+}
+
+void slot_fail(dlr_batch_s* B, BatchSlot* sl, dlr_status st) {
+    sl->finished = true;
+    sl->fail_status = st;
+    sl->fail_msg = g_last_error;
+    B->done.push_back(sl->id);
+}
+
+BatchSlot* find_slot(dlr_batch_s* B, int64_t id) {
+    auto it = B->slots.find(id);
+    return it == B->slots.end() ? nullptr : &it->second;
+}
+
 }  // namespace
 
 extern "C" {
@@ -447,44 +662,23 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
     dlr_instance* I = new (std::nothrow) dlr_instance();
     if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
     try {
-        I->nx = p->nx; I->ny = p->ny; I->N = p->nx * p->ny; I->npol = p->n_polar; I->naz = p->n_azim;
-        I->nq = p->n_polar * p->n_azim; I->r = p->rank; I->prec = p->precision;
-        I->x0 = p->x0; I->x1 = p->x1; I->y0 = p->y0; I->y1 = p->y1;
-        I->hx = (p->x1 - p->x0) / p->nx; I->hy = (p->y1 - p->y0) / p->ny; I->area = I->hx * I->hy;
-        I->dt = p->dt; I->c = p->c; I->a = p->a;
-        I->si_tol = p->si_tol; I->si_max_iter = p->si_max_iter; I->tie = p->deim_tie_tol;
-        for (int k = 0; k < 4; ++k) {
-            I->bc[k] = p->bc[k];
-            I->Tb[k] = p->T_b[k];
-            const double t = p->T_b[k];
-            I->psib[k] = (p->bc[k] == DLR_BC_INFLOW) ? p->a * p->c * t * t * t * t / dlr::kFourPi : 0.0;
-        }
-        I->has_qext = p->q_ext != nullptr;
-        I->stream = static_cast<hipStream_t>(hip_stream);
-        I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
-        I->ld = dlr::padded_plane(I->nx, I->ny);
-        I->ldg = dlr::diag_plane(I->nx, I->ny);
-        I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
-        const size_t rr = (size_t)I->r * I->r;
-        I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
-                                      (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});
-        dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
-        Arena sizing;
-        I->carve(sizing);
+        init_fields(I, p, static_cast<hipStream_t>(hip_stream));
+        const size_t need = arena_bytes(I);
         size_t free_b = 0, total_b = 0;
         hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-        if (sizing.used + (64u << 20) > free_b) {
+        if (need + (64u << 20) > free_b) {
             delete I;
             return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
         }
-        hipError_t e = hipMalloc(&I->arena.base, sizing.used);
+        hipError_t e = hipMalloc(&I->arena.base, need);
         if (e != hipSuccess) {
             delete I;
             return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
-        I->arena.cap = sizing.used;
+        I->arena.cap = need;
         I->carve(I->arena);
         hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
+        upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
@@ -708,6 +902,203 @@ dlr_status dlr_destroy(dlr_handle h) {
     if (h->h_status) (void)hipHostFree(h->h_status);
     if (h->arena.base) (void)hipFree(h->arena.base);
     delete h;
+    return DLR_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Batches
+
+dlr_status dlr_batch_footprint(const dlr_problem* p, size_t* bytes) {
+    if (!bytes) return fail(DLR_ERR_ARG, "bytes is NULL");
+    g_last_error.clear();
+    const dlr_status v = validate(p);
+    if (v != DLR_OK) return v;
+    dlr_instance tmp;
+    init_fields(&tmp, p, nullptr);
+    *bytes = arena_bytes(&tmp);
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_create(size_t hbm_budget, void* hip_stream, dlr_batch* out) {
+    if (!out) return fail(DLR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    dlr_batch_s* B = new (std::nothrow) dlr_batch_s();
+    if (!B) return fail(DLR_ERR_OOM, "host allocation failed");
+    try {
+        B->main = static_cast<hipStream_t>(hip_stream);
+        if (hbm_budget == 0) {
+            size_t free_b = 0, total_b = 0;
+            hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+            hbm_budget = free_b > (1ull << 30) ? free_b - (1ull << 30) : 0;
+        }
+        B->budget = hbm_budget;
+        for (int k = 0; k < kBatchStreams; ++k) {
+            hipStream_t st = nullptr;
+            hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream");
+            B->pool.push_back(st);
+        }
+        hip_check(hipMalloc(&B->d_ticket, 4 * sizeof(unsigned)), "ticket");
+        hip_check(hipMemset(B->d_ticket, 0, 4 * sizeof(unsigned)), "ticket");
+        hip_check(hipEventCreateWithFlags(&B->ev_main, hipEventDisableTiming), "event");
+        batch_reserve(B, 64);
+    } catch (const std::exception& ex) {
+        dlr_batch_destroy(B);
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    *out = B;
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_admit(dlr_batch B, const dlr_problem* p, int32_t n_steps, int64_t* slot) {
+    if (!B || !slot) return fail(DLR_ERR_ARG, "batch or slot is NULL");
+    if (n_steps < 1) return fail(DLR_ERR_ARG, "n_steps must be >= 1");
+    size_t bytes = 0;
+    const dlr_status f = dlr_batch_footprint(p, &bytes);
+    if (f != DLR_OK) return f;
+    if (B->used + bytes > B->budget) return fail(DLR_ERR_OOM, "footprint exceeds the remaining batch budget");
+    const int64_t id = B->next_id;
+    dlr_handle h = nullptr;
+    const dlr_status c = dlr_create(p, B->pool[(size_t)(id % kBatchStreams)], &h);
+    if (c != DLR_OK) return c;
+    BatchSlot sl;
+    sl.id = id;
+    sl.I = h;
+    sl.bytes = bytes;
+    sl.remaining = n_steps;
+    if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+        dlr_destroy(h);
+        return fail(DLR_ERR_HIP, "event create");
+    }
+    B->slots.emplace(id, sl);
+    B->used += bytes;
+    ++B->next_id;
+    *slot = id;
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_advance(dlr_batch B) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    std::vector<BatchSlot*> act;
+    for (auto& kv : B->slots)
+        if (!kv.second.finished && kv.second.remaining > 0) act.push_back(&kv.second);
+    if (act.empty()) return DLR_OK;
+    try {
+        batch_reserve(B, act.size());
+        for (BatchSlot* sl : act) {
+            if (sl->I->fp32()) phase_begin<float>(sl->I); else phase_begin<double>(sl->I);
+            hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+        }
+        std::vector<BatchSlot*> pending = act;
+        while (!pending.empty()) {
+            for (BatchSlot* sl : pending) hip_check(hipStreamWaitEvent(B->main, sl->ev, 0), "wait");
+            batch_sweep<double>(B, pending);
+            batch_sweep<float>(B, pending);
+            hip_check(hipEventRecord(B->ev_main, B->main), "event");
+            for (BatchSlot* sl : pending) {
+                hip_check(hipStreamWaitEvent(sl->I->stream, B->ev_main, 0), "wait");
+                if (sl->I->fp32()) si_phi<float>(sl->I); else si_phi<double>(sl->I);
+                hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+            }
+            std::vector<BatchSlot*> next;
+            for (BatchSlot* sl : pending) {
+                hip_check(hipEventSynchronize(sl->ev), "sync");
+                const dlr_status st = si_check(sl->I);
+                if (st != DLR_OK) slot_fail(B, sl, st);
+                else if (!sl->I->si_conv) next.push_back(sl);
+            }
+            pending.swap(next);
+        }
+        for (BatchSlot* sl : act)
+            if (!sl->finished) {
+                if (sl->I->fp32()) phase_end<float>(sl->I); else phase_end<double>(sl->I);
+            }
+        for (BatchSlot* sl : act) {
+            if (sl->finished) continue;
+            const dlr_status st = step_finish(sl->I, false);
+            if (st != DLR_OK) {
+                slot_fail(B, sl, st);
+                continue;
+            }
+            if (--sl->remaining == 0) {
+                sl->finished = true;
+                B->done.push_back(sl->id);
+            }
+        }
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_poll(dlr_batch B, int64_t* done, int32_t cap, int32_t* n) {
+    if (!B || !n || (cap > 0 && !done) || cap < 0) return fail(DLR_ERR_ARG, "bad poll arguments");
+    int32_t k = 0;
+    while (k < cap && !B->done.empty()) {
+        done[k++] = B->done.front();
+        B->done.pop_front();
+    }
+    *n = k;
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_read(dlr_batch B, int64_t slot, double* E_r, double* T) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    BatchSlot* sl = find_slot(B, slot);
+    if (!sl) return fail(DLR_ERR_ARG, "no such slot");
+    if (sl->fail_status != DLR_OK) return fail(sl->fail_status, sl->fail_msg);
+    return dlr_read_fields(sl->I, E_r, T);
+}
+
+dlr_status dlr_batch_read_stats(dlr_batch B, int64_t slot, dlr_step_stats* out) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    BatchSlot* sl = find_slot(B, slot);
+    if (!sl) return fail(DLR_ERR_ARG, "no such slot");
+    return dlr_read_stats(sl->I, out);
+}
+
+dlr_status dlr_batch_release(dlr_batch B, int64_t slot) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    BatchSlot* sl = find_slot(B, slot);
+    if (!sl) return fail(DLR_ERR_ARG, "no such slot");
+    dlr_destroy(sl->I);
+    if (sl->ev) (void)hipEventDestroy(sl->ev);
+    B->used -= sl->bytes;
+    B->slots.erase(slot);
+    for (auto it = B->done.begin(); it != B->done.end(); ++it)
+        if (*it == slot) {
+            B->done.erase(it);
+            break;
+        }
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_usage(dlr_batch B, int32_t* active_slots, size_t* bytes_in_use) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    int32_t a = 0;
+    for (auto& kv : B->slots)
+        if (!kv.second.finished) ++a;
+    if (active_slots) *active_slots = a;
+    if (bytes_in_use) *bytes_in_use = B->used;
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_destroy(dlr_batch B) {
+    if (!B) return DLR_OK;
+    if (B->main || !B->pool.empty()) (void)hipDeviceSynchronize();
+    for (auto& kv : B->slots) {
+        dlr_destroy(kv.second.I);
+        if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
+    }
+    for (int g = 0; g < 2; ++g) {
+        if (B->d_table[g]) (void)hipFree(B->d_table[g]);
+        if (B->d_unit_end[g]) (void)hipFree(B->d_unit_end[g]);
+        if (B->h_table[g]) (void)hipHostFree(B->h_table[g]);
+        if (B->h_unit_end[g]) (void)hipHostFree(B->h_unit_end[g]);
+    }
+    if (B->d_ticket) (void)hipFree(B->d_ticket);
+    if (B->ev_main) (void)hipEventDestroy(B->ev_main);
+    for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
+    delete B;
     return DLR_OK;
 }
 

@@ -81,9 +81,11 @@ __host__ __device__ inline size_t padded_cell(long e, int ny) {
 __host__ __device__ inline size_t padded_plane(int nx, int ny) {
     return (((size_t)nx * (ny + 2 * kColGuard) + kColGuard) + 63) / 64 * 64;
 }
+// One instance's sweep: everything but the launch-level fields below is fixed for the life of
+// the instance, so the record is uploaded once and reused by every launch.
 template <typename TS>
 struct SweepArgs {
-    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of kSweepWaves x 64 columns
+    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of kSweepWaves x 64 columns; units = nsuper * nd
     size_t ldg;                            // diagonal plane stride (elements), diag_plane
     const TS* src0;      // [nd][ldg] fixed source q + psi0 / (c dt), each in its direction's orientation
     const TS* sig_t;     // [4][ldg] one copy per orientation
@@ -96,14 +98,25 @@ struct SweepArgs {
     double inv_hx, inv_hy;
     TS* edge;                        // [nd][nsuper][ny] outgoing x-face values of each superstrip
     unsigned long long* progress;    // [nd][nsuper] (launch << 32) | rows published
-    unsigned* ticket;                // [2] work ticket, retired workgroups
-    unsigned long long launch_id;
-    int grid_blocks;
     int* status;                     // kStatusSweepStall is raised if a wait exceeds spin_limit polls
     unsigned spin_limit;
 };
+
+// One persistent launch sweeps the units of several instances: table[k] describes instance k,
+// unit_end[k] = sum of total_units of instances 0..k.  Workgroups take units from one ticket in
+// order, so a unit only waits on lower tickets of its own instance (already running).
+struct SweepLaunch {
+    int ninst;
+    unsigned total_units;
+    const unsigned* unit_end;        // [ninst], device
+    unsigned* ticket;                // [2] work ticket, retired workgroups; zero before the launch, reset after
+    unsigned long long launch_id;    // unique per launch in the process (tags progress words)
+    int grid_blocks;
+};
 template <typename TS>
-void launch_sweep(hipStream_t s, const SweepArgs<TS>& a);
+void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L);
+// next process-wide sweep launch id
+unsigned long long next_sweep_launch_id();
 
 // ----------------------------------------------------------------------------- reductions
 // V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny).

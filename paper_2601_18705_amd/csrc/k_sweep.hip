@@ -29,6 +29,8 @@
 // smaller ticket, which is already running.
 #include "dlr_internal.h"
 
+#include <atomic>
+
 namespace dlr {
 
 namespace {
@@ -288,7 +290,8 @@ __device__ __forceinline__ void wait_vm_stores() {
 
 // Helper wavefront: incoming edge (global -> ring[0]) and outgoing edge (ring[kWaves] -> global).
 template <typename TS>
-__device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& sh, int S, int d, int lane) {
+__device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned long long launch_id, Shared<TS>& sh, int S,
+                                            int d, int lane) {
     const int nx = a.nx, ny = a.ny;
     const bool incoming = S > 0;
     const bool outgoing = ((S + 1) * kWaves) * 64 < nx;   // the next superstrip has columns
@@ -296,7 +299,7 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& 
     TS* edge_out = outgoing ? a.edge + ((size_t)d * a.nsuper + S) * ny : nullptr;
     unsigned long long* prog_in = incoming ? &a.progress[(size_t)d * a.nsuper + S - 1] : nullptr;
     unsigned long long* prog_out = outgoing ? &a.progress[(size_t)d * a.nsuper + S] : nullptr;
-    const unsigned long long tag = a.launch_id << 32;
+    const unsigned long long tag = launch_id << 32;
     int rin = incoming ? 0 : ny;    // rows copied into ring[0]
     int rout = outgoing ? 0 : ny;   // rows copied out of ring[kWaves]
     unsigned idle = 0;
@@ -304,7 +307,7 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& 
         bool moved = false;
         if (rin < ny) {
             const unsigned long long pv = __hip_atomic_load(prog_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int avail = (pv >> 32) == a.launch_id ? (int)(pv & 0xffffffffull) : 0;
+            int avail = (pv >> 32) == launch_id ? (int)(pv & 0xffffffffull) : 0;
             avail = min(avail, lds_load(&sh.cons[0]) + kRing);   // ring space
             avail = min(avail, rin + 64);
             if (avail > rin) {
@@ -350,35 +353,48 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, Shared<TS>& 
 }
 
 template <typename TS, int P>
-__global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(SweepArgs<TS> a) {
+__global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>* __restrict__ table, SweepLaunch L) {
     __shared__ Shared<TS> sh;
+    __shared__ int inst;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) sh.stall = 0;
     for (;;) {
-        if (threadIdx.x == 0) sh.task = atomicAdd(&a.ticket[0], 1u);
+        if (threadIdx.x == 0) {
+            sh.task = atomicAdd(&L.ticket[0], 1u);
+            sh.stall = 0;
+            // instance of the unit: first k with unit_end[k] > task (binary search)
+            int lo = 0, hi = L.ninst - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (L.unit_end[mid] > sh.task) hi = mid; else lo = mid + 1;
+            }
+            inst = lo;
+        }
         if (threadIdx.x <= kWaves) {
             sh.prod[threadIdx.x] = 0;
             sh.cons[threadIdx.x] = 0;
         }
         __syncthreads();
         const unsigned n = sh.task;
-        if (n >= (unsigned)a.total_units) break;
-        const int S = (int)(n / (unsigned)a.nd);
-        const int d = (int)(n % (unsigned)a.nd);
+        if (n >= L.total_units) break;
+        const int k = __builtin_amdgcn_readfirstlane(inst);
+        const SweepArgs<TS> a = table[k];
+        const unsigned local = n - (k > 0 ? L.unit_end[k - 1] : 0u);
+        const int S = (int)(local / (unsigned)a.nd);
+        const int d = (int)(local % (unsigned)a.nd);
         if (w < kWaves) {
             if ((S * kWaves + w) * 64 < a.nx) compute_wave<TS, P>(a, sh, S, d, w, lane);
         } else if ((S * kWaves) * 64 < a.nx) {
-            helper_wave<TS>(a, sh, S, d, lane);
+            helper_wave<TS>(a, L.launch_id, sh, S, d, lane);
         }
         __syncthreads();
+        if (threadIdx.x == 0 && sh.stall) atomicOr(a.status, (int)kStatusSweepStall);
     }
     if (threadIdx.x == 0) {
-        if (sh.stall) atomicOr(a.status, (int)kStatusSweepStall);
         // the last workgroup to retire resets the ticket for the next launch on the stream
-        const unsigned prev = atomicAdd(&a.ticket[1], 1u);
-        if (prev == (unsigned)a.grid_blocks - 1u) {
-            __hip_atomic_store(&a.ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = atomicAdd(&L.ticket[1], 1u);
+        if (prev == (unsigned)L.grid_blocks - 1u) {
+            __hip_atomic_store(&L.ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&L.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -386,11 +402,16 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(SweepArgs<TS> a) {
 }  // namespace
 
 template <typename TS>
-void launch_sweep(hipStream_t s, const SweepArgs<TS>& a) {
-    constexpr int P = sizeof(TS) == 4 ? 2 : 2;
-    hipLaunchKernelGGL((k_sweep<TS, P>), dim3(a.grid_blocks), dim3(64 * (kWaves + 1)), 0, s, a);
+void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L) {
+    constexpr int P = 2;
+    hipLaunchKernelGGL((k_sweep<TS, P>), dim3(L.grid_blocks), dim3(64 * (kWaves + 1)), 0, s, table, L);
 }
-template void launch_sweep<double>(hipStream_t, const SweepArgs<double>&);
-template void launch_sweep<float>(hipStream_t, const SweepArgs<float>&);
+template void launch_sweep<double>(hipStream_t, const SweepArgs<double>*, const SweepLaunch&);
+template void launch_sweep<float>(hipStream_t, const SweepArgs<float>*, const SweepLaunch&);
+
+unsigned long long next_sweep_launch_id() {
+    static std::atomic<unsigned long long> id{0};
+    return ++id;
+}
 
 }  // namespace dlr

@@ -21,7 +21,9 @@ STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
 EXPORTED = ["dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
-            "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_status_string", "dlr_last_error"]
+            "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
+            "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
+            "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_status_string", "dlr_last_error"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -72,12 +74,27 @@ def library():
         lib.dlr_read_stats.argtypes = [h, ctypes.POINTER(DlrStepStats)]
         lib.dlr_force_selection.argtypes = [h, _ip]
         lib.dlr_destroy.argtypes = [h]
+        sz = ctypes.c_size_t
+        i64 = ctypes.c_int64
+        lib.dlr_batch_footprint.argtypes = [ctypes.POINTER(DlrProblem), ctypes.POINTER(sz)]
+        lib.dlr_batch_create.argtypes = [sz, ctypes.c_void_p, ctypes.POINTER(h)]
+        lib.dlr_batch_admit.argtypes = [h, ctypes.POINTER(DlrProblem), ctypes.c_int32, ctypes.POINTER(i64)]
+        lib.dlr_batch_advance.argtypes = [h]
+        lib.dlr_batch_poll.argtypes = [h, ctypes.POINTER(i64), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        lib.dlr_batch_read.argtypes = [h, i64, _dp, _dp]
+        lib.dlr_batch_read_stats.argtypes = [h, i64, ctypes.POINTER(DlrStepStats)]
+        lib.dlr_batch_release.argtypes = [h, i64]
+        lib.dlr_batch_usage.argtypes = [h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)]
+        lib.dlr_batch_destroy.argtypes = [h]
         lib.dlr_status_string.argtypes = [ctypes.c_int]
         lib.dlr_status_string.restype = ctypes.c_char_p
         lib.dlr_last_error.argtypes = []
         lib.dlr_last_error.restype = ctypes.c_char_p
         for name in ("dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
-                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy"):
+                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy",
+                     "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
+                     "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
+                     "dlr_batch_usage", "dlr_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -99,33 +116,116 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
+def marshal_problem(problem):
+    """Problem dict -> (DlrProblem, arrays that must stay alive while it is used)."""
+    n = int(problem["nx"]) * int(problem["ny"])
+    keep = [_f64(problem["sigma_a"], n), _f64(problem["rho_cv"], n), _f64(problem["T_init"], n)]
+    qext = problem.get("q_ext")
+    keep.append(None if qext is None else _f64(qext, n))
+    p = DlrProblem()
+    p.abi_version = DLR_ABI_VERSION
+    p.nx, p.ny = int(problem["nx"]), int(problem["ny"])
+    p.x0, p.x1, p.y0, p.y1 = (float(problem[k]) for k in ("x0", "x1", "y0", "y1"))
+    p.n_polar, p.n_azim, p.rank = int(problem["n_polar"]), int(problem["n_azim"]), int(problem["rank"])
+    p.dt, p.c, p.a = float(problem["dt"]), float(problem["c"]), float(problem["a"])
+    p.sigma_a, p.rho_cv, p.T_init = (_ptr(a) for a in keep[:3])
+    p.q_ext = _ptr(keep[3])
+    for k in range(4):
+        p.bc[k] = int(problem["bc"][k])
+        p.T_b[k] = float(problem["T_b"][k])
+    p.precision = int(problem.get("precision", DLR_FP64))
+    p.si_tol = float(problem.get("si_tol", 1e-14))
+    p.si_max_iter = int(problem.get("si_max_iter", 10000))
+    p.deim_tie_tol = float(problem.get("deim_tie_tol", 1e-6))
+    return p, keep
+
+
+def footprint(problem):
+    """Device bytes the problem occupies once admitted to a batch."""
+    p, _keep = marshal_problem(problem)
+    out = ctypes.c_size_t()
+    _check(library().dlr_batch_footprint(ctypes.byref(p), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Batch:
+    """Independent problems resident on the device, advanced together (dlr_batch_*)."""
+
+    def __init__(self, hbm_budget=0, stream=None):
+        self._h = ctypes.c_void_p()
+        self._shape = {}
+        _check(library().dlr_batch_create(ctypes.c_size_t(int(hbm_budget)), ctypes.c_void_p(stream or 0),
+                                          ctypes.byref(self._h)))
+
+    def admit(self, problem, n_steps):
+        """Slot id, or None when the footprint does not fit (DLR_ERR_OOM: retry after a release)."""
+        p, _keep = marshal_problem(problem)
+        slot = ctypes.c_int64()
+        st = library().dlr_batch_admit(self._h, ctypes.byref(p), int(n_steps), ctypes.byref(slot))
+        if st == -2:
+            return None
+        _check(st)
+        self._shape[slot.value] = int(problem["nx"]) * int(problem["ny"])
+        return slot.value
+
+    def advance(self):
+        _check(library().dlr_batch_advance(self._h))
+
+    def poll(self, cap=4096):
+        ids = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        _check(library().dlr_batch_poll(self._h, ids, int(cap), ctypes.byref(n)))
+        return [ids[k] for k in range(n.value)]
+
+    def read(self, slot):
+        n = self._shape[slot]
+        E = np.empty(n)
+        T = np.empty(n)
+        _check(library().dlr_batch_read(self._h, ctypes.c_int64(slot), _ptr(E), _ptr(T)))
+        return E, T
+
+    def read_stats(self, slot):
+        s = DlrStepStats()
+        _check(library().dlr_batch_read_stats(self._h, ctypes.c_int64(slot), ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in DlrStepStats._fields_}
+
+    def release(self, slot):
+        _check(library().dlr_batch_release(self._h, ctypes.c_int64(slot)))
+        self._shape.pop(slot, None)
+
+    def usage(self):
+        a = ctypes.c_int32()
+        b = ctypes.c_size_t()
+        _check(library().dlr_batch_usage(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, int(b.value)
+
+    def close(self):
+        if self._h:
+            library().dlr_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Instance:
     """One problem resident on the device (dlr_create ... dlr_destroy)."""
 
     def __init__(self, problem, stream=None):
         lib = library()
-        n = int(problem["nx"]) * int(problem["ny"])
-        self.nx, self.ny, self.n = int(problem["nx"]), int(problem["ny"]), n
+        self.nx, self.ny, self.n = int(problem["nx"]), int(problem["ny"]), int(problem["nx"]) * int(problem["ny"])
         self.rank = int(problem["rank"])
         self.nq = int(problem["n_polar"]) * int(problem["n_azim"])
-        self._keep = [_f64(problem["sigma_a"], n), _f64(problem["rho_cv"], n), _f64(problem["T_init"], n)]
-        qext = problem.get("q_ext")
-        self._keep.append(None if qext is None else _f64(qext, n))
-        p = DlrProblem()
-        p.abi_version = DLR_ABI_VERSION
-        p.nx, p.ny = self.nx, self.ny
-        p.x0, p.x1, p.y0, p.y1 = (float(problem[k]) for k in ("x0", "x1", "y0", "y1"))
-        p.n_polar, p.n_azim, p.rank = int(problem["n_polar"]), int(problem["n_azim"]), self.rank
-        p.dt, p.c, p.a = float(problem["dt"]), float(problem["c"]), float(problem["a"])
-        p.sigma_a, p.rho_cv, p.T_init = (_ptr(a) for a in self._keep[:3])
-        p.q_ext = _ptr(self._keep[3])
-        for k in range(4):
-            p.bc[k] = int(problem["bc"][k])
-            p.T_b[k] = float(problem["T_b"][k])
-        p.precision = int(problem.get("precision", DLR_FP64))
-        p.si_tol = float(problem.get("si_tol", 1e-14))
-        p.si_max_iter = int(problem.get("si_max_iter", 10000))
-        p.deim_tie_tol = float(problem.get("deim_tie_tol", 1e-6))
+        p, self._keep = marshal_problem(problem)
         self._p = p
         self._h = ctypes.c_void_p()
         _check(lib.dlr_create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))

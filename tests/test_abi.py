@@ -60,3 +60,21 @@ def test_create_rejects_nonpositive_fields():
     with pytest.raises(dlrtrt.DlrError) as ei:
         dlrtrt.Instance(p)
     assert ei.value.status == -1
+
+
+def test_batch_footprint_grows_with_grid_and_rank():
+    from paper_2601_18705_amd import dlrtrt
+    small = problems.slab_beam(nx=32, n_polar=4, n_azim=8, rank=4)
+    big = problems.slab_beam(nx=64, n_polar=4, n_azim=8, rank=4)
+    wide = problems.slab_beam(nx=32, n_polar=4, n_azim=8, rank=16)
+    fs, fb, fw = (dlrtrt.footprint(p) for p in (small, big, wide))
+    assert 0 < fs < fb and fs < fw
+
+
+def test_batch_footprint_validates():
+    from paper_2601_18705_amd import dlrtrt
+    p = problems.slab_beam(nx=32, n_polar=4, n_azim=8, rank=4)
+    p["rank"] = 1000
+    with pytest.raises(dlrtrt.DlrError) as ei:
+        dlrtrt.footprint(p)
+    assert ei.value.status == -1
