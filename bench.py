@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--workload", default="random_medium")
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
+    ap.add_argument("--fp64-steps", type=int, default=10,
+                    help="steps of the FP64-sweep comparison leg at the same SI tolerance (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving leg (0 = skip); p50/p99 time-to-solution")
     ap.add_argument("--serve-max-s", type=float, default=60.0, help="wall-time cap of the serving leg")
@@ -238,6 +240,21 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
         "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
     }
+    if args.fp64_steps > 0 and not args.fp64:
+        print("[bench] FP64-sweep leg", file=sys.stderr, flush=True)
+        p64 = make_problem(args.workload)
+        p64["precision"], p64["si_tol"] = dlrtrt.DLR_FP64, p["si_tol"]
+        with dlrtrt.Instance(p64) as i64:
+            i64.step(2)
+            torch.cuda.synchronize()
+            t64 = time.perf_counter()
+            i64.step(args.fp64_steps)
+            torch.cuda.synchronize()
+            w64 = time.perf_counter() - t64
+            E64, T64 = i64.read_fields()
+        out["fp64_sweep_leg"] = {"dlr_steps_per_s": args.fp64_steps / w64, "steps": args.fp64_steps,
+                                 "si_tol": p64["si_tol"],
+                                 "fp32_speedup": (args.steps / wall) / (args.fp64_steps / w64)}
     if args.serve_requests > 0:
         print(f"[bench] serving leg: {args.serve_requests} requests", file=sys.stderr, flush=True)
         sv = serving_leg(args.serve_requests, args.serve_max_s, args.serve_budget_gib)

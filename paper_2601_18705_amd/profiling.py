@@ -1,0 +1,86 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
+
+Used to turn `rocprofv3 --kernel-trace --stats -f csv` and `rocprofv3 --pmc
+FETCH_SIZE` / `--pmc WRITE_SIZE` runs of bench.py into the short text and JSON
+records kept with the repository.  Reads CSV files only; runs nothing.
+
+    python -m paper_2601_18705_amd.profiling stats <kernel_stats.csv> <title> <command>
+    python -m paper_2601_18705_amd.profiling traffic <fetch counter_collection.csv>
+        <write counter_collection.csv> <calibration MiB> <sweep source> <out.json>
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import re
+import sys
+
+
+def short_name(name):
+    name = re.sub(r"dlr::\(anonymous namespace\)::", "", name)
+    name = re.sub(r"\(.*", "", name)
+    return name.replace("void ", "")
+
+
+def kernel_stats_md(path, title, command, note=""):
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# {title}", "", "Command (from the repository root on an MI355X, ROCm 7.2):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp", command, "```", ""]
+    if note:
+        out += [note, ""]
+    out += ["| kernel | calls | total (ms) | average (us) | min (us) | max (us) | share (%) |",
+            "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path, counter):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        vals.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def sweep_traffic(fetch_csv, write_csv, calib_mib, sweep_source, sweep_prefix="k_sweep"):
+    """HBM bytes per sweep launch.  Each counter (KiB per dispatch) is scaled by the factor that
+    makes it read the known size of the calibration kernel (an elementwise kernel that reads and
+    writes calib_mib MiB, the last 'elementwise' dispatch of the run)."""
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    calib = [k for k in fetch if "elementwise" in k]
+    if not calib:
+        raise SystemExit("no calibration kernel in the FETCH_SIZE run")
+    known_kib = calib_mib * 1024.0
+    f_scale = known_kib / fetch[calib[-1]][-1]
+    w_scale = known_kib / write[calib[-1]][-1] if calib[-1] in write else 1.0
+    sk = [k for k in fetch if k.startswith(sweep_prefix)]
+    f = [v for k in sk for v in fetch[k]]
+    w = [v for k in sk for v in write.get(k, [])]
+    fetch_b = sum(f) / len(f) * 1024.0 * f_scale
+    write_b = sum(w) / len(w) * 1024.0 * w_scale if w else 0.0
+    sha = hashlib.sha256(open(sweep_source, "rb").read()).hexdigest()[:16]
+    return {"sweep_source_sha": sha, "hbm_bytes_per_launch": fetch_b + write_b, "fetch_bytes_per_launch": fetch_b,
+            "write_bytes_per_launch": write_b, "fetch_scale": f_scale, "write_scale": w_scale,
+            "sweep_launches": len(f), "calibration_kernel": calib[-1], "calibration_mib": calib_mib}
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "stats":
+        sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else ""))
+    elif len(argv) == 6 and argv[0] == "traffic":
+        rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4])
+        with open(argv[5], "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
