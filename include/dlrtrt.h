@@ -56,8 +56,10 @@ enum { DLR_BC_VACUUM = 0, DLR_BC_INFLOW = 1, DLR_BC_REFLECT = 2 };
  * temperature update and all conservation sums are FP64 in every mode. */
 enum {
     DLR_FP64 = 0,                 /* sweeps and projections in FP64 */
-    DLR_FP32_SWEEP = 1,           /* sweeps and projections in FP32 (FP64 accumulation of sums) */
-    DLR_FP32_SWEEP_BF16_PROJ = 2  /* FP32 sweeps, BF16 projection operands, FP32 accumulation */
+    DLR_FP32_SWEEP = 1,           /* FP32 sweeps and scalar-flux sums; projections on FP32 matrix
+                                   * cores (FP32 accumulation per block, FP64 across blocks) */
+    DLR_FP32_SWEEP_BF16_PROJ = 2  /* FP32 sweeps; projections on BF16 matrix cores with each operand
+                                   * split as hi + lo (three products), FP32 accumulation per block */
 };
 
 /*

@@ -221,9 +221,8 @@ dlr_status validate(const dlr_problem* p) {
         if (p->bc[s] != DLR_BC_VACUUM && p->bc[s] != DLR_BC_INFLOW) return fail(DLR_ERR_ARG, "unknown bc");
         if (!(p->T_b[s] >= 0) || !std::isfinite(p->T_b[s])) return fail(DLR_ERR_ARG, "T_b must be >= 0");
     }
-    if (p->precision == DLR_FP32_SWEEP_BF16_PROJ)
-        return fail(DLR_ERR_UNSUPPORTED, "BF16 projections are not available in this build");
-    if (p->precision != DLR_FP64 && p->precision != DLR_FP32_SWEEP) return fail(DLR_ERR_ARG, "unknown precision");
+    if (p->precision != DLR_FP64 && p->precision != DLR_FP32_SWEEP && p->precision != DLR_FP32_SWEEP_BF16_PROJ)
+        return fail(DLR_ERR_ARG, "unknown precision");
     if (!(p->si_tol > 0) || p->si_max_iter < 1) return fail(DLR_ERR_ARG, "si_tol > 0 and si_max_iter >= 1");
     if (!(p->deim_tie_tol >= 0) || !(p->deim_tie_tol < 1)) return fail(DLR_ERR_ARG, "0 <= deim_tie_tol < 1");
     return DLR_OK;
@@ -393,7 +392,8 @@ void phase_end(dlr_instance* I) {
     dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
     // 6-7. projections on the new basis and the L-step for every ordinate
-    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj);
+    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj,
+                        I->prec == DLR_FP32_SWEEP_BF16_PROJ ? 16 : (I->fp32() ? 32 : 64));
     dlr::launch_project_finalize(s, r, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops);
     dlr::LstepArgs la{};
     la.nq = nq; la.r = r; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;

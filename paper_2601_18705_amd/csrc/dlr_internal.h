@@ -134,9 +134,11 @@ void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, doub
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X);
 
-// Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip)
+// Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use
+// FP64 MFMA operands (operand_bits 64), FP32 operands (32) or BF16 operands (16), the last two with
+// FP32 accumulation per block; the vector sums and the sum over blocks are FP64.
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double* partials, int nblocks);
+                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits);
 // raw[o] = area * sum over blocks of partials[b][o]
 void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw);
 // Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r]

@@ -38,6 +38,65 @@ __device__ __forceinline__ void store_tile(double* out, int r, int ti, int tj, d
     }
 }
 
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fv4 mfma4(float a, float b, fv4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Accumulator layout of v_mfma_f32_16x16x4: lane l, element v holds D[4*(l/16) + v][l%16].
+__device__ __forceinline__ void store_tile(double* out, int r, int ti, int tj, fv4 acc, double scale) {
+    const int lane = threadIdx.x & 63;
+    const int j = tj * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + 4 * (lane >> 4) + v;
+        if (i < r && j < r) out[i * r + j] = (double)acc[v] * scale;
+    }
+}
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short to_bf16(float x) {
+    unsigned u = __builtin_bit_cast(unsigned, x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(short h) {
+    return __builtin_bit_cast(float, (unsigned)(unsigned short)h << 16);
+}
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the pair carries about 16 mantissa bits
+struct bf4x2 {
+    bf4 hi, lo;
+};
+__device__ __forceinline__ bf4x2 split_bf16(float a, float b, float c, float d) {
+    const float v[4] = {a, b, c, d};
+    bf4x2 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const short h = to_bf16(v[j]);
+        o.hi[j] = h;
+        o.lo[j] = to_bf16(v[j] - from_bf16(h));
+    }
+    return o;
+}
+// v_mfma_f32_16x16x16_bf16: lane l supplies A[l%16][4*(l/16) + j] and B[4*(l/16) + j][l%16], j = 0..3;
+// the accumulator layout is that of the FP32 16x16x4 form (measured on gfx950).
+__device__ __forceinline__ fv4 mfma16(bf4 a, bf4 b, fv4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// A B with split operands: hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 rounding of the sum)
+__device__ __forceinline__ fv4 mfma16x3(const bf4x2& a, const bf4x2& b, fv4 c) {
+    c = mfma16(a.lo, b.hi, c);
+    c = mfma16(a.hi, b.lo, c);
+    return mfma16(a.hi, b.hi, c);
+}
+
+template <typename TO> struct AccOf;
+template <> struct AccOf<double> { typedef dv4 type; };
+template <> struct AccOf<float> { typedef fv4 type; };
+
 // ------------------------------------------------------------------------------------------------ Gram
 // partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) wt(e) V_j(e), wt = weight or 1.
 // The next chunk's global loads are staged in registers while the current chunk's MFMAs run.
@@ -127,7 +186,7 @@ struct ProjShape {
     static constexpr int NL = (RP * kPC + kThreads - 1) / kThreads;         // staged X(left) / X0 per thread
 };
 
-template <int RT>
+template <int RT, typename TO, bool BF16 = false>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r, const double* __restrict__ X,
                                                            const double* __restrict__ X0,
                                                            const double* __restrict__ sigma,
@@ -137,19 +196,22 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     using Sh = ProjShape<RT>;
     constexpr int RP = Sh::RP, PPW = Sh::PPW, KS = Sh::KS;
     constexpr int TPP = kThreads / RP;   // threads per basis column for the vectors
-    __shared__ double sX[RP * kPS];      // slot c+1 holds cell c0+c, slot 0 the cell before the chunk
-    __shared__ double sXl[RP * kPS];     // X at the left neighbour (e - ny)
-    __shared__ double sX0[RP * kPS];
+    typedef typename AccOf<TO>::type Acc;
+    __shared__ TO sX[RP * kPS];          // slot c+1 holds cell c0+c, slot 0 the cell before the chunk
+    __shared__ TO sXl[RP * kPS];         // X at the left neighbour (e - ny)
+    __shared__ TO sX0[RP * kPS];
+    constexpr bool kLowOp = sizeof(TO) < sizeof(double);
+    __shared__ double sXv[kLowOp ? RP * (kPC + 1) : 1];   // X in FP64 for the vector sums (low-precision operands)
     __shared__ double sSig[kPC], sSs[kPC], sQ[kPC];
     __shared__ int sFlag[kPC];           // bit0 left side, bit1 right, bit2 bottom, bit3 top
     __shared__ double red[5][kThreads];
     const long n = (long)nx * ny;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    dv4 acc[PPW][5];
+    Acc acc[PPW][5];
 #pragma unroll
     for (int pp = 0; pp < PPW; ++pp)
 #pragma unroll
-        for (int m = 0; m < 5; ++m) acc[pp][m] = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int m = 0; m < 5; ++m) acc[pp][m] = Acc{0, 0, 0, 0};
     const int pv = threadIdx.x % RP, cv = threadIdx.x / RP;
     double vq = 0.0, vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
     const long nch = (n + kPC - 1) / kPC;
@@ -195,7 +257,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
             const int idx = threadIdx.x + u * kThreads;
             if (idx < RP * (kPC + 1)) {
                 const int p = idx / (kPC + 1), c1 = idx - p * (kPC + 1);
-                sX[p * kPS + c1] = gX[u];
+                sX[p * kPS + c1] = (TO)gX[u];
+                if (kLowOp) sXv[idx] = gX[u];
             }
         }
 #pragma unroll
@@ -203,8 +266,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
             const int idx = threadIdx.x + u * kThreads;
             if (idx < RP * kPC) {
                 const int p = idx / kPC, c = idx % kPC;
-                sXl[p * kPS + c] = gL[u];
-                sX0[p * kPS + c] = g0[u];
+                sXl[p * kPS + c] = (TO)gL[u];
+                sX0[p * kPS + c] = (TO)g0[u];
             }
         }
         if (threadIdx.x < kPC) {
@@ -222,19 +285,58 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
         commit();
         __syncthreads();
         if (ch + gridDim.x < nch) stage(ch + gridDim.x);   // in flight during the MFMAs below
+        if constexpr (BF16) {
+            // sixteen cells per k-step; this lane's four consecutive cells c4 .. c4+3
+            for (int ks = (KS == 1 ? 0 : w); ks < kPC / 16; ks += KS) {
+                const int c4 = 16 * ks + 4 * (lane >> 4);
+                float sg[4], ss[4];
+                bool bottom[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sg[j] = (float)sSig[c4 + j];
+                    ss[j] = (float)sSs[c4 + j];
+                    bottom[j] = (sFlag[c4 + j] & 4) != 0;
+                }
+#pragma unroll
+                for (int pp = 0; pp < PPW; ++pp) {
+                    const int pr = (KS == 1) ? w + 4 * pp : 0;
+                    if (pr < Sh::NPAIR) {
+                        const int pa = (pr / RT) * 16 + (lane & 15), pb = (pr % RT) * 16 + (lane & 15);
+                        float ax[4], a0[4], bx[4], bl[4], bd[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            ax[j] = (float)sX[pa * kPS + c4 + j + 1];
+                            a0[j] = (float)sX0[pa * kPS + c4 + j];
+                            bx[j] = (float)sX[pb * kPS + c4 + j + 1];
+                            bl[j] = (float)sXl[pb * kPS + c4 + j];
+                            bd[j] = bottom[j] ? 0.0f : (float)sX[pb * kPS + c4 + j];
+                        }
+                        const bf4x2 Ax = split_bf16(ax[0], ax[1], ax[2], ax[3]);
+                        const bf4x2 A0 = split_bf16(a0[0], a0[1], a0[2], a0[3]);
+                        acc[pp][0] = mfma16x3(Ax, split_bf16(bl[0], bl[1], bl[2], bl[3]), acc[pp][0]);
+                        acc[pp][1] = mfma16x3(Ax, split_bf16(bd[0], bd[1], bd[2], bd[3]), acc[pp][1]);
+                        acc[pp][2] = mfma16x3(
+                            Ax, split_bf16(sg[0] * bx[0], sg[1] * bx[1], sg[2] * bx[2], sg[3] * bx[3]), acc[pp][2]);
+                        acc[pp][3] = mfma16x3(
+                            Ax, split_bf16(ss[0] * bx[0], ss[1] * bx[1], ss[2] * bx[2], ss[3] * bx[3]), acc[pp][3]);
+                        acc[pp][4] = mfma16x3(A0, split_bf16(bx[0], bx[1], bx[2], bx[3]), acc[pp][4]);
+                    }
+                }
+            }
+        } else
         for (int ks = (KS == 1 ? 0 : w); ks < kPC / 4; ks += KS) {
             const int c = 4 * ks + (lane >> 4);
             const bool bottom = (sFlag[c] & 4) != 0;   // no lower neighbour
-            const double sg = sSig[c], ss = sSs[c];
+            const TO sg = (TO)sSig[c], ss = (TO)sSs[c];
 #pragma unroll
             for (int pp = 0; pp < PPW; ++pp) {
                 const int pr = (KS == 1) ? w + 4 * pp : 0;
                 if (pr < Sh::NPAIR) {
                     const int pa = (pr / RT) * 16 + (lane & 15), pb = (pr % RT) * 16 + (lane & 15);
-                    const double ax = sX[pa * kPS + c + 1], a0 = sX0[pa * kPS + c];
-                    const double bx = sX[pb * kPS + c + 1];
-                    const double bl = sXl[pb * kPS + c];
-                    const double bd = bottom ? 0.0 : sX[pb * kPS + c];
+                    const TO ax = sX[pa * kPS + c + 1], a0 = sX0[pa * kPS + c];
+                    const TO bx = sX[pb * kPS + c + 1];
+                    const TO bl = sXl[pb * kPS + c];
+                    const TO bd = bottom ? (TO)0 : sX[pb * kPS + c];
                     acc[pp][0] = mfma4(ax, bl, acc[pp][0]);
                     acc[pp][1] = mfma4(ax, bd, acc[pp][1]);
                     acc[pp][2] = mfma4(ax, sg * bx, acc[pp][2]);
@@ -245,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
         }
         if (pv < r) {
             for (int c = cv; c < kPC; c += TPP) {
-                const double x = sX[pv * kPS + c + 1];
+                const double x = kLowOp ? sXv[pv * (kPC + 1) + c + 1] : (double)sX[pv * kPS + c + 1];
                 const int f = sFlag[c];
                 vq += sQ[c] * x;
                 if (f & 1) vl += x;
@@ -277,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
         if (w == 0) {
 #pragma unroll
             for (int m = 0; m < 5; ++m) {
-                dv4 t = acc[0][m];
+                Acc t = acc[0][m];
 #pragma unroll
                 for (int ww = 1; ww < 4; ++ww)
 #pragma unroll
@@ -353,17 +455,28 @@ template void launch_gram<double>(hipStream_t, long, int, const double*, size_t,
 template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, int, const double*, double, double*, int,
                                  double*);
 
-void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double* partials, int nblocks) {
+template <typename TO, bool BF16>
+void launch_project_t(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
+                      const double* sig_s, const double* q, double* partials, int nblocks) {
     const dim3 g(nblocks), b(kThreads);
     if (r <= 16)
-        hipLaunchKernelGGL((k_project_mfma<1>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<1, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_project_mfma<2>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<2, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
     else if (r <= 48)
-        hipLaunchKernelGGL((k_project_mfma<3>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<3, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
     else
-        hipLaunchKernelGGL((k_project_mfma<4>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<4, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+}
+
+void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
+                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits) {
+    if (operand_bits == 16)
+        launch_project_t<float, true>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
+    else if (operand_bits == 32)
+        launch_project_t<float, false>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
+    else
+        launch_project_t<double, false>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
 }
 
 void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw) {

@@ -166,3 +166,17 @@ def test_checkerboard_fp32_sweeps_within_1e4():
 def test_ragged_fp32():
     p = problems.random_medium(n=100, n_polar=4, n_azim=16, rank=10, dt=0.002, nsteps=5, seed=11)
     compare(p, 5, 1e-4, "random medium 100^2 fp32", FP32)
+
+
+BF16 = {"precision": 2, "si_tol": 1e-6}
+
+
+@pytest.mark.parametrize("name,factory,steps", [
+    ("slab_beam", lambda: problems.slab_beam(), 10),
+    ("checkerboard", lambda: problems.checkerboard(n=256, nsteps=20), 20),
+])
+def test_bf16_projections_within_1e4(name, factory, steps):
+    """BF16 projection operands split as hi + lo (three MFMAs per product, FP32 accumulation)
+    with FP32 sweeps: within 1e-4 of the FP64 oracle."""
+    worst, _ = compare(factory(), steps, 1e-4, f"{name} bf16 projections", BF16)
+    print(f"[parity] {name} bf16 projections: worst rel-L2 {worst:.3e}", flush=True)
