@@ -39,7 +39,7 @@ def _bad(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(rank=0), -1), (dict(rank=65), -1), (dict(rank=9), -1),          # rank > ordinates (8)
     (dict(n_azim=6), -1), (dict(dt=0.0), -1),
-    (dict(bc=[2, 0, 0, 0]), -7), (dict(precision=2), -7), (dict(precision=5), -1),
+    (dict(bc=[2, 0, 0, 0]), -7), (dict(precision=3), -1), (dict(precision=5), -1),
     (dict(si_max_iter=0), -1), (dict(deim_tie_tol=1.0), -1),
 ])
 def test_create_rejects_invalid_problems(kw, status):
