@@ -487,21 +487,12 @@ void download(void* dst, const void* src, size_t bytes) {
     hip_check(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "download");
 }
 
-// Mean intensity of the current factors, for E_r before the first step / after a load.
-void refresh_phi_host(dlr_instance* I) {
-    const size_t n = I->N, R = I->r, Q = I->nq;
-    std::vector<double> X(R * n), S(R * R), W(R * Q);
-    download(X.data(), I->X, X.size() * sizeof(double));
-    download(S.data(), I->S, S.size() * sizeof(double));
-    download(W.data(), I->W, W.size() * sizeof(double));
-    std::vector<double> beta(R, 0.0), cf(R, 0.0), phi(n, 0.0);
-    for (size_t k = 0; k < R; ++k)
-        for (size_t q = 0; q < Q; ++q) beta[k] += I->h_w[q] * W[k * Q + q];
-    for (size_t i = 0; i < R; ++i)
-        for (size_t j = 0; j < R; ++j) cf[i] += S[i * R + j] * beta[j];
-    for (size_t k = 0; k < R; ++k)
-        for (size_t e = 0; e < n; ++e) phi[e] += X[k * n + e] * cf[k];
-    upload(I->phi, phi.data(), n * sizeof(double));
+// Mean intensity of the current factors, for E_r before the first step / after a load: beta = W^T w,
+// coef = S beta, phi = X coef, on the device.
+void refresh_phi(dlr_instance* I) {
+    dlr::launch_wsum(I->stream, I->nq, I->r, I->W, I->w, I->S, I->beta, I->coef);
+    dlr::launch_phi_of_factors(I->stream, I->N, I->r, I->X, I->coef, I->phi);
+    hip_check(hipStreamSynchronize(I->stream), "sync");
 }
 
 // Problem fields, launch shapes and the quadrature of a new instance (no device work).
@@ -700,7 +691,7 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         upload(I->X, X.data(), X.size() * sizeof(double));
         upload(I->S, S.data(), S.size() * sizeof(double));
         upload(I->W, W.data(), W.size() * sizeof(double));
-        refresh_phi_host(I);
+        refresh_phi(I);
         I->s_is_usigma = true;   // S = diag(s, 0, ...)
         hip_check(hipDeviceSynchronize(), "sync");
     } catch (const std::exception& ex) {
@@ -849,7 +840,7 @@ dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, co
         upload(h->S, Si, R * R * sizeof(double));
         upload(h->W, W.data(), W.size() * sizeof(double));
         upload(h->T, to_cm(Ti, h->nx, h->ny).data(), n * sizeof(double));
-        refresh_phi_host(h);
+        refresh_phi(h);
         hip_check(hipDeviceSynchronize(), "sync");
         h->s_is_usigma = false;
         h->have_sel = false;

@@ -63,6 +63,9 @@ template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
                       const double* eta, TS* psi_cm, size_t ld);
 
+// phi = X coef, coef = S beta (launch_wsum)
+void launch_phi_of_factors(hipStream_t s, int n, int r, const double* X, const double* coef, double* phi);
+
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area,
                     double* T, double* phi, double* partials, int nblocks, unsigned* counter, double* out,

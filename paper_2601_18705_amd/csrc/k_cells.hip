@@ -284,7 +284,25 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
     }
 }
 
+// phi = X coef (the mean intensity of given factors: coef = S beta)
+__global__ __launch_bounds__(kBlock) void k_phi_of_factors(int n, int r, const double* __restrict__ X,
+                                                           const double* __restrict__ coef, double* __restrict__ phi) {
+    __shared__ double sc[kMaxRank];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) sc[i] = coef[i];
+    __syncthreads();
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        double ph = 0.0;
+        for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * sc[k];
+        phi[e] = ph;
+    }
+}
+
 }  // namespace
+
+void launch_phi_of_factors(hipStream_t s, int n, int r, const double* X, const double* coef, double* phi) {
+    hipLaunchKernelGGL(k_phi_of_factors, dim3(std::min((n + kBlock - 1) / kBlock, 4096)), dim3(kBlock), 0, s, n, r, X,
+                       coef, phi);
+}
 
 // ---------------------------------------------------------------------------------------------- launchers
 constexpr int kMaxTileBlocks = 1024;

@@ -180,3 +180,23 @@ def test_bf16_projections_within_1e4(name, factory, steps):
     with FP32 sweeps: within 1e-4 of the FP64 oracle."""
     worst, _ = compare(factory(), steps, 1e-4, f"{name} bf16 projections", BF16)
     print(f"[parity] {name} bf16 projections: worst rel-L2 {worst:.3e}", flush=True)
+
+
+def test_full_size_random_medium_first_step():
+    """The benchmark workload at its full size (1024^2, 32 x 64 ordinates, r = 32): one step
+    against the oracle, FP64 to 1e-10 and FP32 sweeps to 1e-4."""
+    p = problems.random_medium(nsteps=1)
+    compare(p, 1, 1e-10, "random medium 1024^2 fp64")
+    compare(p, 1, 1e-4, "random medium 1024^2 fp32", FP32)
+
+
+@pytest.mark.parametrize("rank", [48, 64])
+def test_largest_ranks(rank):
+    """Ranks that take the three- and four-tile MFMA paths (r = 64 is also full rank here)."""
+    p = problems.slab_beam(nx=24, n_polar=8, n_azim=8, rank=rank, nsteps=3)
+    compare(p, 3, 1e-10, f"slab 24^2 rank {rank} fp64")
+
+
+def test_single_cell_rank_one():
+    p = problems.slab_beam(nx=1, n_polar=1, n_azim=4, rank=1, nsteps=3)
+    compare(p, 3, 1e-10, "one cell, four ordinates, rank 1")
