@@ -103,6 +103,37 @@ def serving_leg(n_requests, max_s, budget_gib):
                       "checkerboard or log-normal medium"}
 
 
+def sn_leg(workload, precision, si_tol, steps, dlr_steps_per_s):
+    """Plain discrete ordinates on the same problem: every ordinate swept each source iteration."""
+    import torch
+    from paper_2601_18705_amd import dlrtrt
+    p = make_problem(workload)
+    p["precision"], p["si_tol"] = precision, si_tol
+    nq, N = p["n_polar"] * p["n_azim"], p["nx"] * p["ny"]
+    with dlrtrt.Instance(p, method="sn") as inst:
+        inst.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ca, sweep_ms, launches = 0, 0.0, 0
+        for _ in range(steps):
+            inst.step(1)
+            st = inst.read_stats()
+            ca += st["si_iters"] * N * nq
+            sweep_ms += st["sweep_ms"]
+            launches += st["si_iters"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    sb = 4 if precision != dlrtrt.DLR_FP64 else 8
+    # src0 read and psi write per ordinate; sigma_t and s_e once per orientation copy (4)
+    bytes_per_launch = N * nq * 2 * sb + 4 * N * 2 * sb
+    avg = sweep_ms / 1e3 / max(launches, 1)
+    return {"ordinates": nq, "steps": steps, "sn_steps_per_s": steps / wall,
+            "cell_angle_updates_per_s": ca / wall, "si_iterations_per_step": launches / steps,
+            "sweep_avg_launch_ms": avg * 1e3, "sweep_algorithmic_bytes_per_launch": bytes_per_launch,
+            "sweep_achieved_GBs": bytes_per_launch / avg / 1e9,
+            "dlr_speedup_steps_per_s": dlr_steps_per_s / (steps / wall)}
+
+
 def batch_run(count, steps):
     """The batched-instances workload: count independent problems admitted at once and
     advanced together for `steps` steps (FP32 sweeps, FP64 energy update)."""
@@ -141,6 +172,8 @@ def main():
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
     ap.add_argument("--fp64-steps", type=int, default=10,
                     help="steps of the FP64-sweep comparison leg at the same SI tolerance (0 = skip)")
+    ap.add_argument("--sn-steps", type=int, default=3,
+                    help="steps of the plain SN comparison leg over every ordinate (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving leg (0 = skip); p50/p99 time-to-solution")
     ap.add_argument("--serve-max-s", type=float, default=60.0, help="wall-time cap of the serving leg")
@@ -255,6 +288,10 @@ def main():
         out["fp64_sweep_leg"] = {"dlr_steps_per_s": args.fp64_steps / w64, "steps": args.fp64_steps,
                                  "si_tol": p64["si_tol"],
                                  "fp32_speedup": (args.steps / wall) / (args.fp64_steps / w64)}
+    if args.sn_steps > 0:
+        print("[bench] plain SN leg", file=sys.stderr, flush=True)
+        out["plain_sn_leg"] = sn_leg(args.workload, p["precision"], p["si_tol"], args.sn_steps,
+                                     args.steps / wall)
     if args.serve_requests > 0:
         print(f"[bench] serving leg: {args.serve_requests} requests", file=sys.stderr, flush=True)
         sv = serving_leg(args.serve_requests, args.serve_max_s, args.serve_budget_gib)

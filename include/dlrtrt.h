@@ -114,6 +114,19 @@ typedef struct {
  * (reflecting walls), DLR_ERR_OOM, DLR_ERR_HIP.  *out is NULL on error. */
 dlr_status dlr_create(const dlr_problem *prob, void *hip_stream, dlr_handle *out);
 
+/* Create a plain discrete-ordinates (SN) instance of the same problem: the
+ * full-rank method the DLR step approximates (Sec. 2: backward Euler with the
+ * linearised emission, source iteration on the scalar flux, every ordinate of
+ * the n_polar x n_azim quadrature swept each iteration, the intensity of all
+ * ordinates kept between steps).  rank and deim_tie_tol are ignored; precision
+ * selects FP64 or FP32 sweeps (modes 1 and 2 behave alike: there are no
+ * projections).  The handle takes dlr_step, dlr_sync, dlr_read_fields,
+ * dlr_read_stats (rank reports the number of ordinates) and dlr_destroy;
+ * dlr_read_factors, dlr_load_factors and dlr_force_selection return
+ * DLR_ERR_UNSUPPORTED.  Device memory holds two [ordinates][cells] arrays of
+ * the sweep precision.  Errors as dlr_create. */
+dlr_status dlr_sn_create(const dlr_problem *prob, void *hip_stream, dlr_handle *out);
+
 /* Advance n_steps >= 0 time steps (Algorithm 1).  Errors detected on the
  * device (non-convergence, non-finite values, rank breakdown) poison the
  * handle: this call and every later one except reads of the last good state

@@ -57,6 +57,7 @@ struct Arena {
 
 struct dlr_instance {
     // ---- problem (host copies)
+    bool sn = false;   // plain discrete ordinates (every ordinate swept, no factors)
     int nx = 0, ny = 0, N = 0, npol = 0, naz = 0, nq = 0, r = 0, prec = 0;
     double x0 = 0, x1 = 0, y0 = 0, y1 = 0, hx = 0, hy = 0, area = 0, dt = 0, c = 0, a = 0;
     double si_tol = 0, tie = 0;
@@ -112,6 +113,9 @@ struct dlr_instance {
     double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
     double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr;
     int* status = nullptr;
+    // plain SN only
+    double *q_diag = nullptr, *phio = nullptr;
+    int *orient = nullptr, *dirs = nullptr, *dir_off = nullptr;
     // pinned host mirrors
     double* h_norm = nullptr;
     int* h_status = nullptr;
@@ -121,8 +125,49 @@ struct dlr_instance {
 
     bool fp32() const { return prec != DLR_FP64; }
     size_t sweep_bytes() const { return fp32() ? sizeof(float) : sizeof(double); }
+    int nsweep() const { return sn ? nq : r; }   // directions of one sweep launch
+
+    // plain SN: all ordinates' psi and fixed source in the diagonal layout, q in 4 orientation copies
+    void carve_sn(Arena& A) {
+        const size_t n = (size_t)N, Q = (size_t)nq;
+        mu = A.take<double>(Q);
+        eta = A.take<double>(Q);
+        w = A.take<double>(Q);
+        orient = A.take<int>(Q);
+        dirs = A.take<int>(Q);
+        dir_off = A.take<int>(8);
+        inflow_x = A.take<double>(Q);
+        inflow_y = A.take<double>(Q);
+        sigma = A.take<double>(n);
+        rho_cv = A.take<double>(n);
+        q_ext = has_qext ? A.take<double>(n) : nullptr;
+        T = A.take<double>(n);
+        D = A.take<double>(n);
+        sig_s = A.take<double>(n);
+        q = A.take<double>(n);
+        q_diag = A.take<double>(4 * ldg);
+        sig_t = fp32() ? nullptr : A.take<double>(4 * ldg);
+        sig_t32 = fp32() ? A.take<float>(4 * ldg) : nullptr;
+        psi = A.take<char>(Q * ldg * sweep_bytes());
+        src0 = A.take<char>(Q * ldg * sweep_bytes());
+        s_e = A.take<char>(4 * ldg * sweep_bytes());
+        phio = A.take<double>(4 * ldg);
+        phi = A.take<double>(n);
+        phi2 = A.take<double>(n);
+        edge = A.take<char>(Q * (size_t)nsuper * ny * sweep_bytes());
+        progress = A.take<unsigned long long>(Q * (size_t)nsuper);
+        ticket = A.take<unsigned>(4);
+        sweep_rec = A.take<char>(sizeof(dlr::SweepArgs<double>));
+        unit_end = A.take<unsigned>(4);
+        partials = A.take<double>(partials_count);
+        norm_out = A.take<double>(4);
+        energy_out = A.take<double>(2);
+        counters = A.take<unsigned>(8);
+        status = A.take<int>(4);
+    }
 
     void carve(Arena& A) {
+        if (sn) return carve_sn(A);
         const size_t n = (size_t)N, R = (size_t)r, Q = (size_t)nq;
         mu = A.take<double>(Q);
         eta = A.take<double>(Q);
@@ -191,7 +236,7 @@ struct dlr_instance {
 
 namespace {
 
-dlr_status validate(const dlr_problem* p) {
+dlr_status validate(const dlr_problem* p, bool sn = false) {
     if (!p) return fail(DLR_ERR_ARG, "problem is NULL");
     if (p->abi_version != DLR_ABI_VERSION) return fail(DLR_ERR_ARG, "abi_version mismatch");
     if (p->nx < 1 || p->ny < 1) return fail(DLR_ERR_ARG, "nx, ny must be >= 1");
@@ -202,7 +247,7 @@ dlr_status validate(const dlr_problem* p) {
     const long long nq = (long long)p->n_polar * p->n_azim;
     if (nq > 16384) return fail(DLR_ERR_ARG, "at most 16384 ordinates");
     const long long ncell = (long long)p->nx * p->ny;
-    if (p->rank < 1 || p->rank > dlr::kMaxRank || p->rank > nq || p->rank > ncell)
+    if (!sn && (p->rank < 1 || p->rank > dlr::kMaxRank || p->rank > nq || p->rank > ncell))
         return fail(DLR_ERR_ARG, "rank must satisfy 1 <= rank <= min(64, ordinates, cells)");
     if (!(p->dt > 0) || !(p->c > 0) || !(p->a >= 0) || !std::isfinite(p->dt) || !std::isfinite(p->c) ||
         !std::isfinite(p->a))
@@ -224,7 +269,8 @@ dlr_status validate(const dlr_problem* p) {
     if (p->precision != DLR_FP64 && p->precision != DLR_FP32_SWEEP && p->precision != DLR_FP32_SWEEP_BF16_PROJ)
         return fail(DLR_ERR_ARG, "unknown precision");
     if (!(p->si_tol > 0) || p->si_max_iter < 1) return fail(DLR_ERR_ARG, "si_tol > 0 and si_max_iter >= 1");
-    if (!(p->deim_tie_tol >= 0) || !(p->deim_tie_tol < 1)) return fail(DLR_ERR_ARG, "0 <= deim_tie_tol < 1");
+    if (!sn && (!(p->deim_tie_tol >= 0) || !(p->deim_tie_tol < 1)))
+        return fail(DLR_ERR_ARG, "0 <= deim_tie_tol < 1");
     return DLR_OK;
 }
 
@@ -255,13 +301,14 @@ dlr_status check_device_status(dlr_instance* I) {
 template <typename TS>
 dlr::SweepArgs<TS> make_sweep_record(const dlr_instance* I) {
     dlr::SweepArgs<TS> sa{};
-    sa.nx = I->nx; sa.ny = I->ny; sa.nd = I->r; sa.nsuper = I->nsuper; sa.total_units = I->nsuper * I->r;
+    sa.nx = I->nx; sa.ny = I->ny; sa.nd = I->nsweep(); sa.nsuper = I->nsuper; sa.total_units = I->nsuper * sa.nd;
     sa.ldg = I->ldg;
     sa.src0 = static_cast<const TS*>(I->src0);
     sa.sig_t = I->fp32() ? reinterpret_cast<const TS*>(I->sig_t32) : reinterpret_cast<const TS*>(I->sig_t);
     sa.s_e = static_cast<const TS*>(I->s_e);
     sa.psi = static_cast<TS*>(I->psi);
-    sa.mu = I->sel_mu; sa.eta = I->sel_eta;
+    sa.mu = I->sn ? I->mu : I->sel_mu;
+    sa.eta = I->sn ? I->eta : I->sel_eta;
     sa.inflow_x = I->inflow_x; sa.inflow_y = I->inflow_y;
     sa.inv_hx = 1.0 / I->hx; sa.inv_hy = 1.0 / I->hy;
     sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress;
@@ -279,7 +326,7 @@ void upload_sweep_record(dlr_instance* I) {
         const dlr::SweepArgs<double> a = make_sweep_record<double>(I);
         std::memcpy(I->h_sweep_rec.data(), &a, sizeof(a));
     }
-    const unsigned units = (unsigned)(I->nsuper * I->r);
+    const unsigned units = (unsigned)(I->nsuper * I->nsweep());
     hip_check(hipMemcpy(I->sweep_rec, I->h_sweep_rec.data(), I->h_sweep_rec.size(), hipMemcpyHostToDevice), "record");
     hip_check(hipMemcpy(I->unit_end, &units, sizeof(units), hipMemcpyHostToDevice), "record");
 }
@@ -300,7 +347,7 @@ void phase_begin(dlr_instance* I) {
     hip_check(hipEventRecord(I->ev[0], s), "event");
     // 1. effective scattering and source
     dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
-                          I->q, I->sig_t, I->sig_t32, I->ldg);
+                          I->q, I->sig_t, I->sig_t32, I->ldg, nullptr);
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
@@ -327,11 +374,11 @@ template <typename TS>
 void sweep_alone(dlr_instance* I) {
     dlr::SweepLaunch L{};
     L.ninst = 1;
-    L.total_units = (unsigned)(I->nsuper * I->r);
+    L.total_units = (unsigned)(I->nsuper * I->nsweep());
     L.unit_end = I->unit_end;
     L.ticket = I->ticket;
     L.launch_id = dlr::next_sweep_launch_id();
-    L.grid_blocks = (int)std::min<unsigned>(L.total_units, 512u);
+    L.grid_blocks = (int)std::min<unsigned>(L.total_units, I->sn ? 1024u : 512u);
     hip_check(hipEventRecord(I->ev[2], I->stream), "event");
     dlr::launch_sweep<TS>(I->stream, reinterpret_cast<const dlr::SweepArgs<TS>*>(I->sweep_rec), L);
     hip_check(hipEventRecord(I->ev[3], I->stream), "event");
@@ -470,6 +517,63 @@ dlr_status step_once(dlr_instance* I) {
     return step_finish(I, true);
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// Plain SN step (the comparator): backward Euler with the same linearisation; the fixed source of every
+// ordinate is q + psi_prev / (c dt); source iteration on phi = sum_q w_q psi_q; T from the converged phi.
+template <typename TS>
+void sn_phi(dlr_instance* I, const double* phi_old, double* phi_new) {
+    dlr::launch_sn_phi<TS>(I->stream, I->nx, I->ny, I->ldg, I->dirs, I->dir_off, I->w, static_cast<const TS*>(I->psi),
+                           I->phio, I->sig_s, phi_old, phi_new, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
+                           I->counters + 0, I->norm_out);
+}
+
+template <typename TS>
+dlr_status sn_step_once(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    hip_check(hipEventRecord(I->ev[0], s), "event");
+    dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
+                          I->q, I->sig_t, I->sig_t32, I->ldg, I->q_diag);
+    dlr::launch_sn_source<TS>(s, I->nq, I->ldg, I->orient, I->q_diag, static_cast<const TS*>(I->psi),
+                              1.0 / (I->c * I->dt), static_cast<TS*>(I->src0));
+    sn_phi<TS>(I, I->phi2, I->phi);   // start: phi of the previous step's psi, and its s_e
+    I->phi_cur = I->phi;
+    I->phi_nxt = I->phi2;
+    I->si_it = 0;
+    I->si_conv = false;
+    I->sweep_ms_acc = 0.f;
+    while (!I->si_conv) {
+        sweep_alone<TS>(I);
+        sn_phi<TS>(I, I->phi_cur, I->phi_nxt);
+        std::swap(I->phi_cur, I->phi_nxt);
+        hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
+        hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+        I->sweep_ms_acc += ms;
+        const dlr_status st = si_check(I);
+        if (st != DLR_OK) return st;
+    }
+    dlr::launch_tupdate(s, I->N, 0, nullptr, nullptr, I->sigma, I->rho_cv, I->D, I->dt, I->a, I->c, I->area, I->T,
+                        I->phi, I->partials, I->nb_cells, I->counters + 1, I->energy_out, I->status);
+    hip_check(hipEventRecord(I->ev[1], s), "event");
+    const dlr_status st = check_device_status(I);
+    if (st != DLR_OK) return st;
+    double en = 0.0;
+    hip_check(hipMemcpy(&en, I->energy_out, sizeof(double), hipMemcpyDeviceToHost), "energy copy");
+    float step_ms = 0.f;
+    hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
+    I->stats.si_iters = I->si_it;
+    I->stats.energy = en;
+    I->stats.deim_min_margin = 0.0;
+    I->stats.sum_abs_cw_over_4pi = 1.0;
+    I->stats.sweep_ms = I->sweep_ms_acc;
+    I->stats.step_ms = step_ms;
+    ++I->steps_done;
+    I->stats.steps_done = I->steps_done;
+    return DLR_OK;
+}
+
 // row-major cells (e = j*nx + i, the C interface) <-> column-major cells (e = i*ny + j, device)
 std::vector<double> to_cm(const double* src, int nx, int ny) {
     std::vector<double> out((size_t)nx * ny);
@@ -496,9 +600,10 @@ void refresh_phi(dlr_instance* I) {
 }
 
 // Problem fields, launch shapes and the quadrature of a new instance (no device work).
-void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream) {
+void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool sn = false) {
+    I->sn = sn;
     I->nx = p->nx; I->ny = p->ny; I->N = p->nx * p->ny; I->npol = p->n_polar; I->naz = p->n_azim;
-    I->nq = p->n_polar * p->n_azim; I->r = p->rank; I->prec = p->precision;
+    I->nq = p->n_polar * p->n_azim; I->r = sn ? 0 : p->rank; I->prec = p->precision;
     I->x0 = p->x0; I->x1 = p->x1; I->y0 = p->y0; I->y1 = p->y1;
     I->hx = (p->x1 - p->x0) / p->nx; I->hy = (p->y1 - p->y0) / p->ny; I->area = I->hx * I->hy;
     I->dt = p->dt; I->c = p->c; I->a = p->a;
@@ -702,13 +807,86 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
     return DLR_OK;
 }
 
+dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
+    if (!out) return fail(DLR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    g_last_error.clear();
+    const dlr_status v = validate(p, true);
+    if (v != DLR_OK) return v;
+    dlr_instance* I = new (std::nothrow) dlr_instance();
+    if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
+    try {
+        init_fields(I, p, static_cast<hipStream_t>(hip_stream), true);
+        const size_t need = arena_bytes(I);
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        if (need + (64u << 20) > free_b) {
+            delete I;
+            return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
+        }
+        hipError_t e = hipMalloc(&I->arena.base, need);
+        if (e != hipSuccess) {
+            delete I;
+            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        I->arena.cap = need;
+        I->carve(I->arena);
+        hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
+        upload_sweep_record(I);
+        hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, sizeof(int), hipHostMallocDefault), "pinned");
+        for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
+        const size_t n = I->N, Q = I->nq;
+        // ordinates grouped by orientation, and their isotropic inflow values
+        std::vector<int> orient(Q), dirs, off(8, 0);
+        std::vector<double> inx(Q), iny(Q);
+        for (size_t k = 0; k < Q; ++k) {
+            orient[k] = dlr::orient_of(I->h_mu[k], I->h_eta[k]);
+            inx[k] = I->psib[I->h_mu[k] > 0.0 ? 0 : 1];
+            iny[k] = I->psib[I->h_eta[k] > 0.0 ? 2 : 3];
+        }
+        for (int o = 0; o < 4; ++o) {
+            off[o] = (int)dirs.size();
+            for (size_t k = 0; k < Q; ++k)
+                if (orient[k] == o) dirs.push_back((int)k);
+        }
+        off[4] = (int)dirs.size();
+        upload(I->mu, I->h_mu.data(), Q * sizeof(double));
+        upload(I->eta, I->h_eta.data(), Q * sizeof(double));
+        upload(I->w, I->h_w.data(), Q * sizeof(double));
+        upload(I->orient, orient.data(), Q * sizeof(int));
+        upload(I->dirs, dirs.data(), Q * sizeof(int));
+        upload(I->dir_off, off.data(), 8 * sizeof(int));
+        upload(I->inflow_x, inx.data(), Q * sizeof(double));
+        upload(I->inflow_y, iny.data(), Q * sizeof(double));
+        upload(I->sigma, to_cm(p->sigma_a, I->nx, I->ny).data(), n * sizeof(double));
+        upload(I->rho_cv, to_cm(p->rho_cv, I->nx, I->ny).data(), n * sizeof(double));
+        if (p->q_ext) upload(I->q_ext, to_cm(p->q_ext, I->nx, I->ny).data(), n * sizeof(double));
+        upload(I->T, to_cm(p->T_init, I->nx, I->ny).data(), n * sizeof(double));
+        // every ordinate starts at the isotropic equilibrium intensity B(T_init)
+        if (I->fp32())
+            dlr::launch_sn_init<float>(I->stream, I->nx, I->ny, I->nq, I->ldg, I->orient, I->T, I->a, I->c,
+                                       static_cast<float*>(I->psi), I->phi);
+        else
+            dlr::launch_sn_init<double>(I->stream, I->nx, I->ny, I->nq, I->ldg, I->orient, I->T, I->a, I->c,
+                                        static_cast<double*>(I->psi), I->phi);
+        hip_check(hipStreamSynchronize(I->stream), "sync");
+    } catch (const std::exception& ex) {
+        dlr_destroy(I);
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    *out = I;
+    return DLR_OK;
+}
+
 dlr_status dlr_step(dlr_handle h, int32_t n_steps) {
     if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
     if (n_steps < 0) return fail(DLR_ERR_ARG, "n_steps must be >= 0");
     if (h->poisoned) return fail(DLR_ERR_STATE, std::string("handle poisoned: ") + dlr_status_string(h->poison_code));
     try {
         for (int k = 0; k < n_steps; ++k) {
-            const dlr_status st = h->fp32() ? step_once<float>(h) : step_once<double>(h);
+            const dlr_status st = h->sn ? (h->fp32() ? sn_step_once<float>(h) : sn_step_once<double>(h))
+                                        : (h->fp32() ? step_once<float>(h) : step_once<double>(h));
             if (st != DLR_OK) return st;
         }
     } catch (const std::exception& ex) {
@@ -748,6 +926,7 @@ dlr_status dlr_read_fields(dlr_handle h, double* E_r, double* T) {
 
 dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, int32_t* selo) {
     if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (h->sn) return fail(DLR_ERR_UNSUPPORTED, "a plain SN handle has no factors");
     try {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const size_t n = h->N, R = h->r, Q = h->nq;
@@ -824,6 +1003,7 @@ dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, in
 
 dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, const double* Wi, const double* Ti) {
     if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (h->sn) return fail(DLR_ERR_UNSUPPORTED, "a plain SN handle has no factors");
     if (!Xi || !Si || !Wi || !Ti) return fail(DLR_ERR_ARG, "X, S, W and T are required");
     try {
         hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -860,12 +1040,13 @@ dlr_status dlr_read_stats(dlr_handle h, dlr_step_stats* out) {
     if (!h || !out) return fail(DLR_ERR_ARG, "NULL argument");
     *out = h->stats;
     out->steps_done = h->steps_done;
-    out->rank = h->r;
+    out->rank = h->nsweep();
     return DLR_OK;
 }
 
 dlr_status dlr_force_selection(dlr_handle h, const int32_t* selv) {
     if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (h->sn) return fail(DLR_ERR_UNSUPPORTED, "a plain SN handle has no angle selection");
     if (!selv) {
         h->force_pending = false;
         return DLR_OK;

@@ -46,7 +46,7 @@ __host__ __device__ inline size_t diag_pos(int nx, int ny, int o, int i, int j) 
 // The kernels that touch the diagonal layout walk tiles of 8 columns x 128 rows.
 void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t64, float* sig_t32, size_t ldg);
+                      double* sig_t64, float* sig_t32, size_t ldg, double* q_diag /* nullable: q, 4 copies */);
 
 template <typename TS>
 void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
@@ -62,6 +62,19 @@ void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg,
 template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
                       const double* eta, TS* psi_cm, size_t ld);
+
+// Plain discrete ordinates (the comparator): orient[d] = orientation of ordinate d; dirs/off list the
+// ordinates grouped by orientation; phio is [4][ldg] FP64 work space.
+template <typename TS>
+void launch_sn_source(hipStream_t s, int nq, size_t ldg, const int* orient, const double* q_diag, const TS* psi_old,
+                      double inv_cdt, TS* src0);
+template <typename TS>
+void launch_sn_init(hipStream_t s, int nx, int ny, int nq, size_t ldg, const int* orient, const double* T, double a,
+                    double c, TS* psi, double* phi);
+template <typename TS>
+void launch_sn_phi(hipStream_t s, int nx, int ny, size_t ldg, const int* dirs, const int* off, const double* w,
+                   const TS* psi, double* phio, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
+                   double* partials, int nblocks, unsigned* counter, double* out);
 
 // phi = X coef, coef = S beta (launch_wsum)
 void launch_phi_of_factors(hipStream_t s, int n, int r, const double* X, const double* coef, double* phi);

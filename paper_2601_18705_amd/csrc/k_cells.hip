@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_linearize(TileGrid g, const double* 
                                                       double dt, double a, double c, double* __restrict__ D,
                                                       double* __restrict__ sig_s, double* __restrict__ q,
                                                       double* __restrict__ sig_t64, float* __restrict__ sig_t32,
-                                                      size_t ldg) {
+                                                      size_t ldg, double* __restrict__ q_diag) {
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -95,13 +95,15 @@ __global__ __launch_bounds__(kBlock) void k_linearize(TileGrid g, const double* 
             const double d = C + kFourPi * dt * s * dB;
             D[e] = d;
             sig_s[e] = (kFourPi * dt * s * dB / d) * s;
-            q[e] = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
+            const double qe = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
+            q[e] = qe;
             const double st = s + 1.0 / (c * dt);
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
                 const size_t pe = (size_t)o * ldg + diag_pos(g.nx, g.ny, o, i, j);
                 if (sig_t64) sig_t64[pe] = st;
                 if (sig_t32) sig_t32[pe] = (float)st;
+                if (q_diag) q_diag[pe] = qe;
             }
         }
     }
@@ -263,7 +265,10 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
     bool bad = false;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         double ph = 0.0;
-        for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * sc[k];
+        if (X)
+            for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * sc[k];
+        else
+            ph = phi[e];   // plain SN: the converged scalar flux
         const double t0 = T[e];
         const double emis = a * c * t0 * t0 * t0 * t0;
         const double t = t0 + dt * sigma[e] * (ph - emis) / D[e];
@@ -284,6 +289,119 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
     }
 }
 
+// ---------------------------------------------------------------------------------------------- plain SN
+// Discrete ordinates without the low-rank factorisation (the comparator of the DLR step):
+// every ordinate is swept, phi = sum_q w_q psi_q, and psi of the previous step is the time
+// source.  Ordinates are listed grouped by orientation (dirs[off[o] .. off[o+1])), so the
+// directions of one orientation share a diagonal layout.
+
+// src0_d = q + psi_old_d / (c dt) over whole planes (padding positions compute padding)
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_sn_source(int nq, size_t ldg, const int* __restrict__ orient,
+                                                      const double* __restrict__ q_diag,
+                                                      const TS* __restrict__ psi_old, double inv_cdt,
+                                                      TS* __restrict__ src0) {
+    const size_t total = (size_t)nq * ldg;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t d = k / ldg, pos = k - d * ldg;
+        src0[k] = (TS)(q_diag[(size_t)orient[d] * ldg + pos] + (double)psi_old[k] * inv_cdt);
+    }
+}
+
+// psi_d = B(T) for every ordinate, phi = 4 pi B(T), s_e = sigma_s phi / (4 pi) (isotropic start)
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_sn_init(TileGrid g, int nq, size_t ldg, const int* __restrict__ orient,
+                                                    const double* __restrict__ T, double a, double c,
+                                                    TS* __restrict__ psi, double* __restrict__ phi) {
+    const long n = (long)g.nx * g.ny;
+    (void)n;
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            const double t = T[e];
+            const double B = a * c * t * t * t * t / kFourPi;
+            phi[e] = kFourPi * B;
+            size_t pos[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
+            for (int d = 0; d < nq; ++d) {
+                const int o = orient[d];
+                const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
+                psi[(size_t)d * ldg + pd] = (TS)B;
+            }
+        }
+    }
+}
+
+// phio[o][pos] = sum over the ordinates d of orientation o of w_d psi_d[pos]
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_sn_phi_partial(size_t ldg, const int* __restrict__ dirs,
+                                                           const int* __restrict__ off, const double* __restrict__ w,
+                                                           const TS* __restrict__ psi, double* __restrict__ phio) {
+    const int o = blockIdx.y;
+    const int d0 = off[o], d1 = off[o + 1];
+    for (size_t pos = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pos < ldg; pos += (size_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int k = d0; k < d1; ++k) {
+            const int d = dirs[k];
+            acc += w[d] * (double)psi[(size_t)d * ldg + pos];
+        }
+        phio[(size_t)o * ldg + pos] = acc;
+    }
+}
+
+// phi = sum_o phio[o] at the cell's position in each orientation, s_e, and the SI change norm
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_sn_phi_combine(TileGrid g, size_t ldg, const double* __restrict__ phio,
+                                                           const double* __restrict__ sig_s,
+                                                           const double* __restrict__ phi_old,
+                                                           double* __restrict__ phi_new, TS* __restrict__ s_e,
+                                                           double* __restrict__ partials, unsigned* counter,
+                                                           double* out) {
+    __shared__ double sh[kBlock];
+    double d2 = 0.0, p2 = 0.0;
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            size_t pos[4];
+            double ph = 0.0;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                pos[o] = diag_pos(g.nx, g.ny, o, i, j);
+                ph += phio[(size_t)o * ldg + pos[o]];
+            }
+            const double diff = ph - phi_old[e];
+            d2 += diff * diff;
+            p2 += ph * ph;
+            phi_new[e] = ph;
+            const TS se = (TS)(sig_s[e] * ph / kFourPi);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
+        }
+    }
+    d2 = block_sum(d2, sh);
+    p2 = block_sum(p2, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = d2;
+        partials[2 * blockIdx.x + 1] = p2;
+    }
+    if (retire_block(counter)) {
+        const double D2 = ordered_sum(partials, gridDim.x, 2, sh);
+        const double P2 = ordered_sum(partials + 1, gridDim.x, 2, sh);
+        if (threadIdx.x == 0) {
+            out[0] = D2;
+            out[1] = P2;
+            out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
+            *counter = 0u;
+        }
+    }
+}
+
 // phi = X coef (the mean intensity of given factors: coef = S beta)
 __global__ __launch_bounds__(kBlock) void k_phi_of_factors(int n, int r, const double* __restrict__ X,
                                                            const double* __restrict__ coef, double* __restrict__ phi) {
@@ -299,20 +417,57 @@ __global__ __launch_bounds__(kBlock) void k_phi_of_factors(int n, int r, const d
 
 }  // namespace
 
+constexpr int kMaxTileBlocks = 1024;
+
+template <typename TS>
+void launch_sn_source(hipStream_t s, int nq, size_t ldg, const int* orient, const double* q_diag, const TS* psi_old,
+                      double inv_cdt, TS* src0) {
+    const size_t total = (size_t)nq * ldg;
+    const unsigned blocks = (unsigned)std::min<size_t>((total + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL((k_sn_source<TS>), dim3(blocks), dim3(kBlock), 0, s, nq, ldg, orient, q_diag, psi_old, inv_cdt,
+                       src0);
+}
+template <typename TS>
+void launch_sn_init(hipStream_t s, int nx, int ny, int nq, size_t ldg, const int* orient, const double* T, double a,
+                    double c, TS* psi, double* phi) {
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL((k_sn_init<TS>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, nq, ldg,
+                       orient, T, a, c, psi, phi);
+}
+template <typename TS>
+void launch_sn_phi(hipStream_t s, int nx, int ny, size_t ldg, const int* dirs, const int* off, const double* w,
+                   const TS* psi, double* phio, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
+                   double* partials, int nblocks, unsigned* counter, double* out) {
+    const unsigned bx = (unsigned)std::min<size_t>((ldg + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL((k_sn_phi_partial<TS>), dim3(bx, 4), dim3(kBlock), 0, s, ldg, dirs, off, w, psi, phio);
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL((k_sn_phi_combine<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, ldg, phio, sig_s, phi_old,
+                       phi_new, s_e, partials, counter, out);
+}
+#define DLR_SN_INST(TS)                                                                                              \
+    template void launch_sn_source<TS>(hipStream_t, int, size_t, const int*, const double*, const TS*, double, TS*); \
+    template void launch_sn_init<TS>(hipStream_t, int, int, int, size_t, const int*, const double*, double, double,  \
+                                     TS*, double*);                                                                  \
+    template void launch_sn_phi<TS>(hipStream_t, int, int, size_t, const int*, const int*, const double*, const TS*, \
+                                    double*, const double*, const double*, double*, TS*, double*, int, unsigned*,     \
+                                    double*);
+DLR_SN_INST(float)
+DLR_SN_INST(double)
+#undef DLR_SN_INST
+
 void launch_phi_of_factors(hipStream_t s, int n, int r, const double* X, const double* coef, double* phi) {
     hipLaunchKernelGGL(k_phi_of_factors, dim3(std::min((n + kBlock - 1) / kBlock, 4096)), dim3(kBlock), 0, s, n, r, X,
                        coef, phi);
 }
 
 // ---------------------------------------------------------------------------------------------- launchers
-constexpr int kMaxTileBlocks = 1024;
 
 void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const double* rho_cv, const double* q_ext,
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
-                      double* sig_t64, float* sig_t32, size_t ldg) {
+                      double* sig_t64, float* sig_t32, size_t ldg, double* q_diag) {
     const TileGrid g = tile_grid(nx, ny);
     hipLaunchKernelGGL(k_linearize, dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, sigma,
-                       rho_cv, q_ext, T, dt, a, c, D, sig_s, q, sig_t64, sig_t32, ldg);
+                       rho_cv, q_ext, T, dt, a, c, D, sig_s, q, sig_t64, sig_t32, ldg, q_diag);
 }
 
 template <typename TS>

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_
                 -5: "DLR_ERR_NONFINITE", -6: "DLR_ERR_STATE", -7: "DLR_ERR_UNSUPPORTED", -8: "DLR_ERR_NUMERIC"}
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
-EXPORTED = ["dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
+EXPORTED = ["dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
             "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
             "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_status_string", "dlr_last_error"]
@@ -66,6 +66,7 @@ def library():
         lib = ctypes.CDLL(LIB_PATH)
         h = ctypes.c_void_p
         lib.dlr_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
+        lib.dlr_sn_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
         lib.dlr_step.argtypes = [h, ctypes.c_int32]
         lib.dlr_sync.argtypes = [h]
         lib.dlr_read_fields.argtypes = [h, _dp, _dp]
@@ -218,17 +219,30 @@ class Batch:
 
 
 class Instance:
-    """One problem resident on the device (dlr_create ... dlr_destroy)."""
+    """One problem resident on the device (dlr_create ... dlr_destroy).
 
-    def __init__(self, problem, stream=None):
+    method="dlr" steps the low-rank method; method="sn" creates a plain
+    discrete-ordinates instance of the same problem (dlr_sn_create), which has
+    no factors."""
+
+    def __init__(self, problem, stream=None, method="dlr"):
         lib = library()
         self.nx, self.ny, self.n = int(problem["nx"]), int(problem["ny"]), int(problem["nx"]) * int(problem["ny"])
-        self.rank = int(problem["rank"])
         self.nq = int(problem["n_polar"]) * int(problem["n_azim"])
+        self.method = method
+        if method == "sn":
+            self.rank = self.nq
+            problem = dict(problem, rank=1)
+            create = lib.dlr_sn_create
+        elif method == "dlr":
+            self.rank = int(problem["rank"])
+            create = lib.dlr_create
+        else:
+            raise ValueError(f"unknown method {method!r}")
         p, self._keep = marshal_problem(problem)
         self._p = p
         self._h = ctypes.c_void_p()
-        _check(lib.dlr_create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))
+        _check(create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))
 
     def step(self, n_steps=1):
         _check(library().dlr_step(self._h, int(n_steps)))

@@ -51,6 +51,19 @@ def test_create_rejects_invalid_problems(kw, status):
     assert ei.value.status == status
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_azim=6), -1), (dict(dt=0.0), -1), (dict(bc=[2, 0, 0, 0]), -7), (dict(precision=3), -1),
+    (dict(si_max_iter=0), -1), (dict(n_polar=200, n_azim=128), -1),
+])
+def test_sn_create_rejects_invalid_problems(kw, status):
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    p = _bad(**kw)
+    with pytest.raises(dlrtrt.DlrError) as ei:
+        dlrtrt.Instance(p, method="sn")
+    assert ei.value.status == status
+
+
 def test_create_rejects_nonpositive_fields():
     if not os.path.exists(dlrtrt.LIB_PATH):
         pytest.skip("libdlrtrt.so not built")
