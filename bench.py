@@ -217,6 +217,7 @@ def main():
     sweep_ms = 0.0
     launches = 0
     step_ms = 0.0
+    svd_sweeps = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         inst.step(1)
@@ -225,6 +226,7 @@ def main():
         sweep_ms += st["sweep_ms"]
         launches += st["si_iters"]
         step_ms += st["step_ms"]
+        svd_sweeps += st["svd_sweeps"]
         if k % 5 == 4:
             print(f"[bench] step {k + 1}/{args.steps} si {st['si_iters']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -266,6 +268,7 @@ def main():
         "sweep_cell_angle_updates_per_s": ca / (sweep_ms / 1e3),
         "si_iterations_per_step": launches / args.steps,
         "device_ms_per_step": step_ms / args.steps,
+        "svd_sweeps_per_step": svd_sweeps / args.steps,
         "latency_p50_p99_s": None,
         "serving": None,
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -106,6 +106,8 @@ typedef struct {
     double energy;                /* sum over cells of area * (rho c_v T + phi / c) */
     double sweep_ms;              /* device time in the sweep kernels of the last step */
     double step_ms;               /* device time of the whole last step */
+    int32_t svd_sweeps;           /* Jacobi sweeps of the last step's SVD of S (0 for plain SN) */
+    int32_t reserved;
 } dlr_step_stats;
 
 /* Create an instance: validates the problem, copies fields to the device and

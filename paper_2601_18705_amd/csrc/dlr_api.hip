@@ -193,6 +193,7 @@ struct dlr_instance {
         psi = A.take<char>(R * ldg * sweep_bytes());
         src0 = A.take<char>(R * ldg * sweep_bytes());
         s_e = A.take<char>(4 * ldg * sweep_bytes());
+        phio = A.take<double>(4 * ldg);
         psi_cm = A.take<char>(R * ld * sweep_bytes());
         phi = A.take<double>(n);
         phi2 = A.take<double>(n);
@@ -278,7 +279,8 @@ template <typename TS>
 dlr_status step_once(dlr_instance* I);
 
 dlr_status check_device_status(dlr_instance* I) {
-    hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, I->stream), "status copy");
+    hip_check(hipMemcpyAsync(I->h_status, I->status, 4 * sizeof(int), hipMemcpyDeviceToHost, I->stream),
+              "status copy");
     hip_check(hipStreamSynchronize(I->stream), "stream sync");
     const int st = *I->h_status;
     if (st == 0) return DLR_OK;
@@ -388,7 +390,7 @@ template <typename TS>
 void si_phi(dlr_instance* I) {
     hipStream_t s = I->stream;
     dlr::launch_phi<TS>(s, I->nx, I->ny, I->r, static_cast<const TS*>(I->psi), I->ldg, I->sel_mu, I->sel_eta, I->cw,
-                        I->sig_s, I->phi_cur, I->phi_nxt, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
+                        I->phio, I->sig_s, I->phi_cur, I->phi_nxt, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
                         I->counters + 0, I->norm_out);
     std::swap(I->phi_cur, I->phi_nxt);
     hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
@@ -490,6 +492,7 @@ dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     for (double v : cwv) sa_ += std::fabs(v);
     I->stats.sum_abs_cw_over_4pi = sa_ / dlr::kFourPi;
     I->stats.sweep_ms = timed_sweeps ? I->sweep_ms_acc : 0.f;
+    I->stats.svd_sweeps = I->h_status[2];   // written by the SVD kernel of this step
     I->stats.step_ms = step_ms;
     I->s_is_usigma = true;
     I->have_sel = true;
@@ -776,7 +779,7 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
-        hip_check(hipHostMalloc((void**)&I->h_status, sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
@@ -834,7 +837,7 @@ dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out
         hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
-        hip_check(hipHostMalloc((void**)&I->h_status, sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         const size_t n = I->N, Q = I->nq;
         // ordinates grouped by orientation, and their isotropic inflow values

@@ -27,6 +27,32 @@ constexpr double kFourPi = 4.0 * kPi;
 constexpr int kMaxRank = 64;
 constexpr int kSweepChunk = 32;   // rows published per edge-flag update in the sweep
 
+// Copy count doubles from global memory to LDS with eight independent loads in flight per
+// thread: the small dense kernels read data that the previous kernel has just written, often
+// from another XCD's L2, and a loop that waits for each load in turn pays that latency
+// count / blockDim times over.  Callers synchronise the block before reading dst.
+//
+// The loads are issued by every lane from a clamped (valid) address and masked afterwards:
+// "x = ok ? p[i] : 0" compiles to an exec-masked load whose result register the other lanes
+// then overwrite, which makes the wavefront wait for that load before issuing the next.  The
+// small dense kernels and the triangular multiply use the same form; in the streaming MFMA
+// staging loops the masked form measured faster and is kept there.
+__device__ inline void stage_lds(double* dst, const double* __restrict__ src, int count) {
+    for (int base = threadIdx.x; base < count; base += 8 * blockDim.x) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int o = base + u * blockDim.x;
+            v[u] = src[o < count ? o : count - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int o = base + u * blockDim.x;
+            if (o < count) dst[o] = v[u];
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------- diagonal sweep layout
 // A direction's orientation o has bit 0 set when mu <= 0 and bit 1 when eta <= 0.  In its swept
 // coordinates i' = i or nx-1-i, j' = j or ny-1-j the grid is cut into strips of 64 columns; the
@@ -55,8 +81,8 @@ void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const do
 
 template <typename TS>
 void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
-                const double* cw, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
-                double* partials, int nblocks, unsigned* counter, double* out);
+                const double* cw, double* phio /* [4][ldg] work */, const double* sig_s, const double* phi_old,
+                double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter, double* out);
 
 // Psi (diagonal layouts) -> padded-column planes [r][ld]
 template <typename TS>

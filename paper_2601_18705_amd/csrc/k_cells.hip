@@ -30,24 +30,36 @@ __device__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// Last-block-done reduction: each block stores its partial(s); the block that
-// retires last sums all partials in index order and resets the counter.
+// Last-block-done reduction: each block stores its partial(s) with store_partial; the
+// block that retires last sums all partials in index order and resets the counter.
+// The partials and the counter are agent-scope atomics: they are performed at the
+// device-coherent level, so no cache-wide fence is needed between the per-XCD L2s;
+// thread 0 waits until its partial stores have completed before it counts the block.
+__device__ __forceinline__ void store_partial(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_vm_stores() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
+}
 __device__ bool retire_block(unsigned* counter) {
     __shared__ bool last;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
+        wait_vm_stores();
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == gridDim.x - 1);
     }
     __syncthreads();
-    if (last) __threadfence();   // acquire: see every other block's partials (per-XCD L2s)
     return last;
+}
+__device__ void reset_counter(unsigned* counter) {
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ double ordered_sum(const double* p, int count, int stride, double* sh) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += p[(size_t)i * stride];
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        acc += __hip_atomic_load(p + (size_t)i * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return block_sum(acc, sh);
 }
 
@@ -163,64 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
 // ---------------------------------------------------------------------------------------------- phi
 // Scalar flux of the collocation system (Sec. 4.1): phi = beta^T What^{-1} Psi =
 // sum_d cw_d psi_d, its pseudo-scattering source, and the relative change
-// ||phi_new - phi_old||_2 / ||phi_new||_2 written to out[2] by the last block.
-template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_phi(TileGrid g, int r, const TS* __restrict__ psi, size_t ldg,
-                                                const double* __restrict__ mu, const double* __restrict__ eta,
-                                                const double* __restrict__ cw, const double* __restrict__ sig_s,
-                                                const double* __restrict__ phi_old, double* __restrict__ phi_new,
-                                                TS* __restrict__ s_e, double* __restrict__ partials,
-                                                unsigned* counter, double* out) {
-    __shared__ double sh[kBlock];
-    __shared__ double scw[kMaxRank];
-    __shared__ int so[kMaxRank];
-    for (int i = threadIdx.x; i < r; i += blockDim.x) {
-        scw[i] = cw[i];
-        so[i] = orient_of(mu[i], eta[i]);
-    }
-    __syncthreads();
-    double d2 = 0.0, p2 = 0.0;
-    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            int i, j;
-            if (!g.cell(b, kc, i, j)) continue;
-            const long e = (long)i * g.ny + j;
-            size_t pos[4];
-#pragma unroll
-            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
-            double ph = 0.0;
-            for (int d = 0; d < r; ++d) {
-                const int o = so[d];
-                const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
-                ph += scw[d] * (double)psi[(size_t)d * ldg + pd];
-            }
-            const double diff = ph - phi_old[e];
-            d2 += diff * diff;
-            p2 += ph * ph;
-            phi_new[e] = ph;
-            const TS se = (TS)(sig_s[e] * ph / kFourPi);
-#pragma unroll
-            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
-        }
-    }
-    d2 = block_sum(d2, sh);
-    p2 = block_sum(p2, sh);
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = d2;
-        partials[2 * blockIdx.x + 1] = p2;
-    }
-    if (retire_block(counter)) {
-        const double D2 = ordered_sum(partials, gridDim.x, 2, sh);
-        const double P2 = ordered_sum(partials + 1, gridDim.x, 2, sh);
-        if (threadIdx.x == 0) {
-            out[0] = D2;
-            out[1] = P2;
-            out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
-            *counter = 0u;
-        }
-    }
-}
+// ||phi_new - phi_old||_2 / ||phi_new||_2 written to out[2] by the last block:
+// k_phi_partial + k_phi_combine (with the plain SN kernels below).
 
 // ---------------------------------------------------------------------------------------------- Psi relayout
 template <typename TS>
@@ -279,12 +235,12 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
     }
     if (bad) atomicOr(status, (int)kStatusNonfinite);
     en = block_sum(en, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = en;
+    if (threadIdx.x == 0) store_partial(&partials[blockIdx.x], en);
     if (retire_block(counter)) {
         const double E = ordered_sum(partials, gridDim.x, 1, sh);
         if (threadIdx.x == 0) {
             out[0] = E * area;
-            *counter = 0u;
+            reset_counter(counter);
         }
     }
 }
@@ -335,26 +291,48 @@ __global__ __launch_bounds__(kBlock) void k_sn_init(TileGrid g, int nq, size_t l
     }
 }
 
-// phio[o][pos] = sum over the ordinates d of orientation o of w_d psi_d[pos]
+// Scalar flux in two passes.  The directions of one orientation share a diagonal layout, so
+// the first pass sums their weighted intensities position by position with contiguous
+// four-element loads: phio[o][pos] = sum over the directions d of orientation o of
+// w_d psi_d[pos].  Directions come as a list grouped by orientation (dirs, off) or, with
+// dirs = nullptr, as nd directions filtered by the orientation of (mu_d, eta_d).
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_sn_phi_partial(size_t ldg, const int* __restrict__ dirs,
-                                                           const int* __restrict__ off, const double* __restrict__ w,
-                                                           const TS* __restrict__ psi, double* __restrict__ phio) {
+__global__ __launch_bounds__(kBlock) void k_phi_partial(size_t ldg, int nd, const int* __restrict__ dirs,
+                                                        const int* __restrict__ off, const double* __restrict__ mu,
+                                                        const double* __restrict__ eta,
+                                                        const double* __restrict__ w, const TS* __restrict__ psi,
+                                                        double* __restrict__ phio) {
+    typedef TS tv4 __attribute__((ext_vector_type(4)));
     const int o = blockIdx.y;
-    const int d0 = off[o], d1 = off[o + 1];
-    for (size_t pos = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pos < ldg; pos += (size_t)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int k = d0; k < d1; ++k) {
-            const int d = dirs[k];
-            acc += w[d] * (double)psi[(size_t)d * ldg + pos];
+    const int k0 = dirs ? off[o] : 0, k1 = dirs ? off[o + 1] : nd;
+    const size_t nquad = ldg / 4;
+    for (size_t qd = (size_t)blockIdx.x * blockDim.x + threadIdx.x; qd < nquad; qd += (size_t)gridDim.x * blockDim.x) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            int d = k;
+            if (dirs) {
+                d = dirs[k];
+            } else if (orient_of(mu[d], eta[d]) != o) {
+                continue;
+            }
+            const double wd = w[d];
+            const tv4 v = *reinterpret_cast<const tv4*>(psi + (size_t)d * ldg + 4 * qd);
+            a0 += wd * (double)v.x;
+            a1 += wd * (double)v.y;
+            a2 += wd * (double)v.z;
+            a3 += wd * (double)v.w;
         }
-        phio[(size_t)o * ldg + pos] = acc;
+        double* dst = phio + (size_t)o * ldg + 4 * qd;
+        *reinterpret_cast<double2*>(dst) = make_double2(a0, a1);
+        *reinterpret_cast<double2*>(dst + 2) = make_double2(a2, a3);
     }
 }
 
-// phi = sum_o phio[o] at the cell's position in each orientation, s_e, and the SI change norm
+// Second pass: phi = sum_o phio[o] at the cell's position in each orientation, the four
+// copies of s_e = sigma_s phi / (4 pi), and the source-iteration change norm
+// (||phi_new - phi_old||^2, ||phi_new||^2 and their ratio, summed in block order).
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_sn_phi_combine(TileGrid g, size_t ldg, const double* __restrict__ phio,
+__global__ __launch_bounds__(kBlock) void k_phi_combine(TileGrid g, size_t ldg, const double* __restrict__ phio,
                                                            const double* __restrict__ sig_s,
                                                            const double* __restrict__ phi_old,
                                                            double* __restrict__ phi_new, TS* __restrict__ s_e,
@@ -387,8 +365,8 @@ __global__ __launch_bounds__(kBlock) void k_sn_phi_combine(TileGrid g, size_t ld
     d2 = block_sum(d2, sh);
     p2 = block_sum(p2, sh);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = d2;
-        partials[2 * blockIdx.x + 1] = p2;
+        store_partial(&partials[2 * blockIdx.x], d2);
+        store_partial(&partials[2 * blockIdx.x + 1], p2);
     }
     if (retire_block(counter)) {
         const double D2 = ordered_sum(partials, gridDim.x, 2, sh);
@@ -397,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_sn_phi_combine(TileGrid g, size_t ld
             out[0] = D2;
             out[1] = P2;
             out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
-            *counter = 0u;
+            reset_counter(counter);
         }
     }
 }
@@ -435,14 +413,23 @@ void launch_sn_init(hipStream_t s, int nx, int ny, int nq, size_t ldg, const int
                        orient, T, a, c, psi, phi);
 }
 template <typename TS>
+void launch_phi_two_pass(hipStream_t s, int nx, int ny, size_t ldg, int nd, const int* dirs, const int* off,
+                         const double* mu, const double* eta, const double* w, const TS* psi, double* phio,
+                         const double* sig_s, const double* phi_old, double* phi_new, TS* s_e, double* partials,
+                         int nblocks, unsigned* counter, double* out) {
+    const unsigned bx = (unsigned)std::min<size_t>((ldg / 4 + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL((k_phi_partial<TS>), dim3(bx, 4), dim3(kBlock), 0, s, ldg, nd, dirs, off, mu, eta, w, psi,
+                       phio);
+    const TileGrid g = tile_grid(nx, ny);
+    hipLaunchKernelGGL((k_phi_combine<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, ldg, phio, sig_s, phi_old, phi_new,
+                       s_e, partials, counter, out);
+}
+template <typename TS>
 void launch_sn_phi(hipStream_t s, int nx, int ny, size_t ldg, const int* dirs, const int* off, const double* w,
                    const TS* psi, double* phio, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
                    double* partials, int nblocks, unsigned* counter, double* out) {
-    const unsigned bx = (unsigned)std::min<size_t>((ldg + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL((k_sn_phi_partial<TS>), dim3(bx, 4), dim3(kBlock), 0, s, ldg, dirs, off, w, psi, phio);
-    const TileGrid g = tile_grid(nx, ny);
-    hipLaunchKernelGGL((k_sn_phi_combine<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, ldg, phio, sig_s, phi_old,
-                       phi_new, s_e, partials, counter, out);
+    launch_phi_two_pass<TS>(s, nx, ny, ldg, 0, dirs, off, nullptr, nullptr, w, psi, phio, sig_s, phi_old, phi_new, s_e,
+                            partials, nblocks, counter, out);
 }
 #define DLR_SN_INST(TS)                                                                                              \
     template void launch_sn_source<TS>(hipStream_t, int, size_t, const int*, const double*, const TS*, double, TS*); \
@@ -494,18 +481,17 @@ template void launch_psi0<float>(hipStream_t, int, int, int, const double*, cons
 
 template <typename TS>
 void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
-                const double* cw, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
+                const double* cw, double* phio, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
                 double* partials, int nblocks, unsigned* counter, double* out) {
-    const TileGrid g = tile_grid(nx, ny);
-    hipLaunchKernelGGL((k_phi<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, r, psi, ldg, mu, eta, cw, sig_s, phi_old,
-                       phi_new, s_e, partials, counter, out);
+    launch_phi_two_pass<TS>(s, nx, ny, ldg, r, nullptr, nullptr, mu, eta, cw, psi, phio, sig_s, phi_old, phi_new, s_e,
+                            partials, nblocks, counter, out);
 }
 template void launch_phi<double>(hipStream_t, int, int, int, const double*, size_t, const double*, const double*,
-                                 const double*, const double*, const double*, double*, double*, double*, int,
+                                 const double*, double*, const double*, const double*, double*, double*, double*, int,
                                  unsigned*, double*);
 template void launch_phi<float>(hipStream_t, int, int, int, const float*, size_t, const double*, const double*,
-                                const double*, const double*, const double*, double*, float*, double*, int, unsigned*,
-                                double*);
+                                const double*, double*, const double*, const double*, double*, float*, double*, int,
+                                unsigned*, double*);
 
 template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,

@@ -68,10 +68,12 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     double* __restrict__ U = a.work;
     if (tid == 0) bad = 0;
     for (int q = tid; q < nq; q += kDeimThreads) piv[q] = 0;
+#pragma unroll 8
     for (int i = tid; i < r * nq; i += kDeimThreads) U[i] = W[i];
     // beta_j = int W_j = sum_q w_q W_j(q): wavefront j % 16 sums column j in lane order
     for (int j = wv; j < r; j += kDeimWaves) {
         double acc = 0.0;
+#pragma unroll 8
         for (int q = lane; q < nq; q += 64) acc += a.w[q] * W[(size_t)j * nq + q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -128,9 +130,14 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     __syncthreads();
     // c = What^{-T} beta: solve M c = beta with M[i][j] = What[j][i] = W_i(Omega^(j))
     const int ld = r + 1;
+    __shared__ double sS[kMaxRank * kMaxRank];
+    __shared__ double Wh[kMaxRank * kMaxRank];   // Wh[i][j] = W_i(Omega^(sel j))
+    stage_lds(sS, a.S, r * r);
     for (int o = tid; o < r * r; o += kDeimThreads) {
         const int i = o / r, j = o % r;
-        M[i * ld + j] = W[(size_t)i * nq + sel[j]];
+        const double v = W[(size_t)i * nq + sel[j]];
+        M[i * ld + j] = v;
+        Wh[o] = v;
     }
     for (int i = tid; i < r; i += kDeimThreads) M[i * ld + r] = beta[i];
     __syncthreads();
@@ -171,14 +178,14 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         a.inflow_x[d] = a.psib[mu > 0.0 ? 0 : 1];
         a.inflow_y[d] = a.psib[eta > 0.0 ? 2 : 3];
         double s = 0.0;
-        for (int j = 0; j < r; ++j) s += a.S[i * r + j] * beta[j];
+        for (int j = 0; j < r; ++j) s += sS[i * r + j] * beta[j];
         a.a0[i] = s;
     }
     // C0[k][d] = sum_j S[k][j] W_j(Omega^(d))
     for (int o = tid; o < r * r; o += kDeimThreads) {
         const int k = o / r, d = o % r;
         double s = 0.0;
-        for (int j = 0; j < r; ++j) s += a.S[k * r + j] * W[(size_t)j * nq + sel[d]];
+        for (int j = 0; j < r; ++j) s += sS[k * r + j] * Wh[j * r + d];
         a.C0[o] = s;
     }
     if (tid == 0 && bad) atomicOr(a.status, a.forced ? (int)kStatusBadForcedSel : (int)kStatusSingularSolve);
@@ -186,35 +193,72 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
 
 // ---------------------------------------------------------------------------------------------- Gauss-Jordan
 // In-place Gauss-Jordan with partial pivoting on an r x ld augmented matrix in LDS
-// (first r columns = the matrix); afterwards columns r.. hold the solutions.
-__device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, int* pivrow, int* bad) {
+// (first r columns = the matrix); afterwards columns r.. hold the solutions.  Per pivot k:
+// wavefront 0 finds the pivot row (largest |A_ik|, i >= k, lowest index on ties); then the
+// new row k (the pivot row scaled by 1/pivot) goes to prow while the old row k moves to the
+// pivot row's place, and the factors of the other rows are read; then every other row is
+// updated and row k written.  Three barriers per pivot; r <= 64.
+__device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, double* prow, int* pivrow, double* pivval,
+                             int* bad) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int k = 0; k < r; ++k) {
-        if (tid == 0) {
-            int pr = k;
-            double best = fabs(Aug[k * ld + k]);
-            for (int i = k + 1; i < r; ++i)
-                if (fabs(Aug[i * ld + k]) > best) { best = fabs(Aug[i * ld + k]); pr = i; }
-            *pivrow = pr;
-            if (!(best > 0.0) || !isfinite(best)) *bad = 1;
+        if (tid < 64) {
+            const int i = k + tid;
+            double v = (i < r) ? fabs(Aug[i * ld + k]) : -1.0;
+            int idx = (i < r) ? i : 0x7fffffff;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(v, off);
+                const int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            }
+            if (tid == 0) {
+                const int p = (idx < r) ? idx : k;
+                *pivrow = p;
+                *pivval = Aug[p * ld + k];
+                if (!(v > 0.0) || !isfinite(v)) *bad = 1;
+            }
         }
         __syncthreads();
         const int pr = *pivrow;
-        if (pr != k)
-            for (int c = tid; c < ld; c += nt) {
-                const double t = Aug[k * ld + c];
-                Aug[k * ld + c] = Aug[pr * ld + c];
-                Aug[pr * ld + c] = t;
+        const double inv = 1.0 / *pivval;   // read before this phase moves the old row k
+        for (int c = tid; c < ld; c += nt) {
+            const double ak = Aug[k * ld + c], ap = Aug[pr * ld + c];
+            prow[c] = ap * inv;
+            if (pr != k) Aug[pr * ld + c] = ak;
+        }
+        for (int i = tid; i < r; i += nt)
+            fac[i] = (i == k) ? 0.0 : ((i == pr) ? Aug[k * ld + k] : Aug[i * ld + k]);
+        __syncthreads();
+        // rows by wavefront (i = wave + 4 a), columns by lane (c = lane + 64 b): no integer division
+        {
+            const int lane = tid & 63, wv = tid >> 6;
+            const int nw = nt >> 6;
+            double pv[3];   // ld <= 2 * 64 + 1 columns
+#pragma unroll
+            for (int b = 0; b < 3; ++b) pv[b] = prow[lane + 64 * b < ld ? lane + 64 * b : ld - 1];
+            for (int i0 = wv; i0 < r; i0 += 4 * nw) {
+                double x[12], f[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int i = i0 + a * nw;
+                    f[a] = fac[i < r ? i : r - 1];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int c = lane + 64 * b;
+                        x[a * 3 + b] = Aug[(i < r ? i : r - 1) * ld + (c < ld ? c : ld - 1)];
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int i = i0 + a * nw;
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int c = lane + 64 * b;
+                        if (i < r && c < ld) Aug[i * ld + c] = (i == k) ? pv[b] : x[a * 3 + b] - f[a] * pv[b];
+                    }
+                }
             }
-        __syncthreads();
-        const double inv = 1.0 / Aug[k * ld + k];
-        __syncthreads();
-        for (int c = tid; c < ld; c += nt) Aug[k * ld + c] *= inv;
-        for (int i = tid; i < r; i += nt) fac[i] = (i == k) ? 0.0 : Aug[i * ld + k];
-        __syncthreads();
-        for (int o = tid; o < r * ld; o += nt) {
-            const int i = o / ld, c = o % ld;
-            if (i != k) Aug[o] -= fac[i] * Aug[k * ld + c];
         }
         __syncthreads();
     }
@@ -226,6 +270,8 @@ constexpr int kLsThreads = 256;
 __global__ __launch_bounds__(kLsThreads) void k_lstep_solve(LstepArgs a) {
     extern __shared__ double dyn[];
     __shared__ double fac[kMaxRank];
+    __shared__ double prow[2 * kMaxRank + 1];
+    __shared__ double pivval;
     __shared__ int pivrow, bad;
     const int r = a.r, rr = r * r, q = blockIdx.x, tid = threadIdx.x;
     const int ld = 2 * r + 1;
@@ -240,24 +286,39 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_solve(LstepArgs a) {
     const int sx = mu > 0.0 ? 0 : 1, sy = eta > 0.0 ? 2 : 3;
     const double amu = fabs(mu), aeta = fabs(eta);
     if (tid == 0) bad = 0;
-    for (int o = tid; o < r * ld; o += kLsThreads) {
-        const int i = o / ld, c = o % ld;
-        double v;
-        if (c < r) {
-            v = amu * Ax[i * r + c] + aeta * Ay[i * r + c] + Mt[i * r + c];
-        } else if (c < 2 * r) {
-            v = (c - r == i) ? 1.0 : 0.0;
-        } else {
-            double lt = 0.0;   // old solution projected on the new basis: sum_j W0_j(q) G[j][i]
-            for (int j = 0; j < r; ++j) lt += a.W0[(size_t)j * a.nq + q] * G[j * r + i];
-            v = qX[i] + lt * a.inv_cdt + amu * a.psib[sx] * b[(sx - 0) * r + i] + aeta * a.psib[sy] * b[sy * r + i];
+    double* sG = dyn + (size_t)r * ld;   // r x r after the augmented matrix
+    __shared__ double sW0[kMaxRank];
+    stage_lds(sG, G, rr);
+    for (int j = tid; j < r; j += kLsThreads) sW0[j] = a.W0[(size_t)j * a.nq + q];
+    __syncthreads();
+    // rows by wavefront, columns by lane (ld <= 129)
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int kLsWaves = kLsThreads / 64;
+#pragma unroll 2
+    for (int i = wv; i < r; i += kLsWaves) {
+#pragma unroll
+        for (int bc = 0; bc < 3; ++bc) {
+            const int c = lane + 64 * bc;
+            if (c >= ld) continue;
+            double v;
+            if (c < r) {
+                v = amu * Ax[i * r + c] + aeta * Ay[i * r + c] + Mt[i * r + c];
+            } else if (c < 2 * r) {
+                v = (c - r == i) ? 1.0 : 0.0;
+            } else {
+                double lt = 0.0;   // old solution projected on the new basis: sum_j W0_j(q) G[j][i]
+                for (int j = 0; j < r; ++j) lt += sW0[j] * sG[j * r + i];
+                v = qX[i] + lt * a.inv_cdt + amu * a.psib[sx] * b[(sx - 0) * r + i] +
+                    aeta * a.psib[sy] * b[sy * r + i];
+            }
+            Aug[i * ld + c] = v;
         }
-        Aug[o] = v;
     }
     __syncthreads();
-    gauss_jordan(Aug, r, ld, fac, &pivrow, &bad);
+    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
     double* Bi = a.Binv + (size_t)q * rr;
-    for (int o = tid; o < rr; o += kLsThreads) Bi[o] = Aug[(o / r) * ld + r + (o % r)];
+    for (int i = wv; i < r; i += kLsWaves)
+        if (lane < r) Bi[i * r + lane] = Aug[i * ld + r + lane];
     for (int i = tid; i < r; i += kLsThreads) a.y[(size_t)q * r + i] = Aug[i * ld + 2 * r];
     if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
 }
@@ -269,10 +330,13 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_reduce(LstepArgs a) {
     const int q0 = blockIdx.x * per, q1 = min(a.nq, q0 + per);
     for (int o = threadIdx.x; o < tot; o += kLsThreads) {
         double acc = 0.0;
-        if (o < rr)
+        if (o < rr) {
+#pragma unroll 8
             for (int q = q0; q < q1; ++q) acc += a.w[q] * a.Binv[(size_t)q * rr + o];
-        else
+        } else {
+#pragma unroll 8
             for (int q = q0; q < q1; ++q) acc += a.w[q] * a.y[(size_t)q * r + (o - rr)];
+        }
         a.red_partials[(size_t)blockIdx.x * tot + o] = acc;
     }
 }
@@ -281,14 +345,19 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_reduce(LstepArgs a) {
 __global__ __launch_bounds__(kLsThreads) void k_lstep_schur(LstepArgs a) {
     extern __shared__ double dyn[];
     __shared__ double fac[kMaxRank];
+    __shared__ double prow[kMaxRank + 1];
+    __shared__ double pivval;
     __shared__ double Cb[kMaxRank * kMaxRank];
     __shared__ int pivrow, bad;
     const int r = a.r, rr = r * r, tot = rr + r, ld = r + 1, tid = threadIdx.x;
     const double* Ms = a.ops + 5 * rr;
     double* Aug = dyn;
     if (tid == 0) bad = 0;
+    __shared__ double sMs[kMaxRank * kMaxRank];
+    stage_lds(sMs, Ms, rr);
     for (int o = tid; o < tot; o += kLsThreads) {
         double acc = 0.0;
+#pragma unroll 8
         for (int b = 0; b < a.red_blocks; ++b) acc += a.red_partials[(size_t)b * tot + o];
         if (o < rr) Cb[o] = acc;
         else Aug[(o - rr) * ld + r] = acc;
@@ -297,14 +366,14 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_schur(LstepArgs a) {
     for (int o = tid; o < rr; o += kLsThreads) {
         const int i = o / r, j = o % r;
         double s = 0.0;
-        for (int k = 0; k < r; ++k) s += Cb[i * r + k] * Ms[k * r + j];
+        for (int k = 0; k < r; ++k) s += Cb[i * r + k] * sMs[k * r + j];
         Aug[i * ld + j] = ((i == j) ? 1.0 : 0.0) - s / kFourPi;
     }
     __syncthreads();
-    gauss_jordan(Aug, r, ld, fac, &pivrow, &bad);
+    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
     for (int i = tid; i < r; i += kLsThreads) {
         double s = 0.0;
-        for (int k = 0; k < r; ++k) s += Ms[i * r + k] * Aug[k * ld + r];
+        for (int k = 0; k < r; ++k) s += sMs[i * r + k] * Aug[k * ld + r];
         a.v[i] = s / kFourPi;
     }
     if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
@@ -318,6 +387,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_apply(LstepArgs a) {
     const int q = (int)(o / r), i = (int)(o % r);
     const double* Bi = a.Binv + (size_t)q * rr + (size_t)i * r;
     double s = a.y[(size_t)q * r + i];
+#pragma unroll 8
     for (int j = 0; j < r; ++j) s += Bi[j] * a.v[j];
     a.L[(size_t)i * a.nq + q] = s;
 }
@@ -330,10 +400,28 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_apply(LstepArgs a) {
 //
 // Round-robin (circle) schedule: in round t slot 0 holds column 0 and slot i >= 1
 // holds column 1 + (i - 1 + t) mod (re - 1); slots k and re-1-k form pair k.  The
-// pairs of a round are disjoint, so the eight lanes of pair k compute its rotation
+// pairs of a round are disjoint, so the sixteen lanes of pair k compute its rotation
 // from their own rows and apply it at once: one barrier per round.
-constexpr int kSvdThreads = 256;
-constexpr int kSvdLanes = 8;   // lanes per column pair; kSvdThreads / kSvdLanes >= kMaxRank / 2
+constexpr int kSvdLanes = 16;   // lanes per column pair: one DPP row
+constexpr int kSvdThreads = kSvdLanes * kMaxRank / 2;
+
+// v moved across the lanes of a DPP row (ctrl: quad_perm, row_half_mirror, row_mirror)
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// sum over the 16 lanes of a DPP row, in every lane: swap neighbours, swap pairs, then add the
+// mirrored half-row and the mirrored row
+__device__ inline double row16_sum(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm(1,0,3,2)
+    v += dpp_move<0x4E>(v);    // quad_perm(2,3,0,1)
+    v += dpp_move<0x141>(v);   // row_half_mirror
+    v += dpp_move<0x140>(v);   // row_mirror
+    return v;
+}
 
 __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __restrict__ Rin,
                                                      double* __restrict__ Vout, double* __restrict__ Sout,
@@ -344,10 +432,12 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
     __shared__ int order[kMaxRank];
     const int tid = threadIdx.x;
     const int rr = r * r;
+    // column-major: column c of S = R^T is row c of R, S[c * r + i] = R[c][i]; the lanes of a pair
+    // read consecutive rows of a column (no bank conflicts)
     for (int o = tid; o < rr; o += kSvdThreads) {
-        const int i = o / r, j = o % r;
-        S[j * r + i] = Rin[o];
-        V[o] = (i == j) ? 1.0 : 0.0;
+        const int c = o / r, i = o % r;
+        S[o] = Rin[o];
+        V[o] = (i == c) ? 1.0 : 0.0;
     }
     const double tol = fmax(1e-15, r * 2.3e-16);
     const int re = r + (r & 1);   // even number of slots; column r (if any) is a dummy
@@ -361,35 +451,54 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
         for (int round = 0; round < re - 1; ++round) {
             if (k < np) {
                 const int sa = k, sb = re - 1 - k;
-                const int p = (sa == 0) ? 0 : 1 + (sa - 1 + round) % (re - 1);
-                const int q = 1 + (sb - 1 + round) % (re - 1);
+                // (x + round) mod (re - 1) for 0 <= x, round < re - 1, without an integer division
+                int tp = sa - 1 + round, tq = sb - 1 + round;
+                if (tp >= re - 1) tp -= re - 1;
+                if (tq >= re - 1) tq -= re - 1;
+                const int p = (sa == 0) ? 0 : 1 + tp;
+                const int q = 1 + tq;
                 if (p < r && q < r) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = lane; i < r; i += kSvdLanes) {
-                        const double sp = S[i * r + p], sq = S[i * r + q];
-                        al += sp * sp;
-                        be += sq * sq;
-                        ga += sp * sq;
-                    }
+                    // the pair's rows of this lane (i = lane + 16 t), loaded once, clamped and masked
+                    double sp[4], sq[4], vp[4], vq[4];
 #pragma unroll
-                    for (int off = kSvdLanes / 2; off > 0; off >>= 1) {
-                        al += __shfl_xor(al, off, kSvdLanes);
-                        be += __shfl_xor(be, off, kSvdLanes);
-                        ga += __shfl_xor(ga, off, kSvdLanes);
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = lane + kSvdLanes * t;
+                        const int ic = i < r ? i : r - 1;
+                        sp[t] = S[p * r + ic];
+                        sq[t] = S[q * r + ic];
+                        vp[t] = V[p * r + ic];
+                        vq[t] = V[q * r + ic];
                     }
-                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const bool on = lane + kSvdLanes * t < r;
+                        const double x = on ? sp[t] : 0.0, y = on ? sq[t] : 0.0;
+                        al += x * x;
+                        be += y * y;
+                        ga += x * y;
+                    }
+                    al = row16_sum(al);
+                    be = row16_sum(be);
+                    ga = row16_sum(ga);
+                    if (ga != 0.0 && ga * ga > tol * tol * (al * be)) {
+                        // tan of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+                        // zeta = (be - al) / (2 ga), written without forming zeta
+                        const double d = be - al;
+                        const double sgn = (d * ga >= 0.0) ? 1.0 : -1.0;
+                        const double tt = sgn * (2.0 * fabs(ga)) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
                         const double c = 1.0 / sqrt(1.0 + tt * tt);
                         const double sn = c * tt;
                         rotated = 1;
-                        for (int i = lane; i < r; i += kSvdLanes) {
-                            const double sp = S[i * r + p], sq = S[i * r + q];
-                            S[i * r + p] = c * sp - sn * sq;
-                            S[i * r + q] = sn * sp + c * sq;
-                            const double vp = V[i * r + p], vq = V[i * r + q];
-                            V[i * r + p] = c * vp - sn * vq;
-                            V[i * r + q] = sn * vp + c * vq;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = lane + kSvdLanes * t;
+                            if (i < r) {
+                                S[p * r + i] = c * sp[t] - sn * sq[t];
+                                S[q * r + i] = sn * sp[t] + c * sq[t];
+                                V[p * r + i] = c * vp[t] - sn * vq[t];
+                                V[q * r + i] = sn * vp[t] + c * vq[t];
+                            }
                         }
                     }
                 }
@@ -399,9 +508,10 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
         converged = !__syncthreads_or(rotated);
     }
     if (tid == 0 && !converged) atomicOr(status, (int)kStatusSvdNoConv);
+    if (tid == 0) status[2] = sweep;   // diagnostic: sweeps taken
     for (int c = tid; c < r; c += kSvdThreads) {
         double sum = 0.0;
-        for (int i = 0; i < r; ++i) sum += S[i * r + c] * S[i * r + c];
+        for (int i = 0; i < r; ++i) sum += S[c * r + i] * S[c * r + i];
         nrm[c] = sqrt(sum);
     }
     __syncthreads();
@@ -418,11 +528,11 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
         int m = 0;
         double best = -1.0;
         for (int i = 0; i < r; ++i)
-            if (fabs(V[i * r + src]) > best) { best = fabs(V[i * r + src]); m = i; }
-        const double sg = (V[m * r + src] < 0.0) ? -1.0 : 1.0;
+            if (fabs(V[src * r + i]) > best) { best = fabs(V[src * r + i]); m = i; }
+        const double sg = (V[src * r + m] < 0.0) ? -1.0 : 1.0;
         for (int i = 0; i < r; ++i) {
-            Vout[i * r + c] = sg * V[i * r + src];
-            Sout[i * r + c] = sg * S[i * r + src];
+            Vout[i * r + c] = sg * V[src * r + i];
+            Sout[i * r + c] = sg * S[src * r + i];
         }
     }
 }
@@ -431,12 +541,13 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
 __global__ __launch_bounds__(256) void k_rmul(int n, int r, const double* __restrict__ V, const double* __restrict__ M,
                                               double* __restrict__ X) {
     __shared__ double sM[kMaxRank * kMaxRank];
-    for (int o = threadIdx.x; o < r * r; o += blockDim.x) sM[o] = M[o];
+    stage_lds(sM, M, r * r);
     __syncthreads();
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= (long)n * r) return;
     const int k = (int)(o / n), c = (int)(o % n);
     double s = 0.0;
+#pragma unroll 8
     for (int j = 0; j < r; ++j) s += V[(size_t)j * n + c] * sM[j * r + k];
     X[(size_t)k * n + c] = s;
 }
@@ -449,16 +560,20 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = wv; k < r; k += 16) {
         double acc = 0.0;
+#pragma unroll 8
         for (int q = lane; q < nq; q += 64) acc += w[q] * W[(size_t)k * nq + q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
         if (lane == 0) sb[k] = acc;
     }
     __syncthreads();
+    __shared__ double sS[kMaxRank * kMaxRank];
+    stage_lds(sS, S, r * r);
+    __syncthreads();
     for (int i = threadIdx.x; i < r; i += blockDim.x) {
         beta[i] = sb[i];
         double s = 0.0;
-        for (int j = 0; j < r; ++j) s += S[i * r + j] * sb[j];
+        for (int j = 0; j < r; ++j) s += sS[i * r + j] * sb[j];
         coef[i] = s;
     }
 }
@@ -471,7 +586,7 @@ void launch_deim(hipStream_t s, const DeimArgs& a) {
 
 void launch_lstep(hipStream_t s, const LstepArgs& a) {
     const int r = a.r;
-    const size_t solve_lds = (size_t)r * (2 * r + 1) * sizeof(double);
+    const size_t solve_lds = ((size_t)r * (2 * r + 1) + (size_t)r * r) * sizeof(double);
     const size_t schur_lds = (size_t)r * (r + 1) * sizeof(double);
     if (solve_lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)k_lstep_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds);

@@ -17,70 +17,82 @@ constexpr int kBlock = 256;
 // breakdown threshold (relative residual 1e-6 of a column against the previous
 // ones) flags status_code: the columns are too close to dependent for Cholesky QR
 // and the CGS2 fallback recomputes the factor.
-// The factorisation is right-looking with one barrier per column (row k of R' is
-// formed by the threads of row k's entries); R'^{-1} is formed column by column,
-// one wavefront per column, by back substitution in the wavefront's lanes.
-constexpr int kCholThreads = 1024;
+// One workgroup of four wavefronts, the matrix in LDS.  Per pivot k the threads of row k
+// form row k of R' and the trailing upper triangle gets the rank-one update, row i by
+// wavefront i mod 4 with the columns on the lanes (contiguous, conflict-free LDS accesses,
+// and only the live entries are touched), two barriers per pivot.  Wavefront 0 then forms
+// R'^{-1} row by row from the bottom, the lanes holding its columns.
+constexpr int kCholThreads = 256;
+static_assert(kMaxRank <= 64, "one lane per column");
 
 __global__ __launch_bounds__(kCholThreads) void k_chol(int r, const double* __restrict__ partials, int nblocks,
                                                        double* __restrict__ R, double* __restrict__ Rinv,
                                                        int* status, int status_code) {
     __shared__ double A[kMaxRank * kMaxRank];
-    __shared__ double Rp[kMaxRank * kMaxRank];
     __shared__ double Ri[kMaxRank * kMaxRank];
+    __shared__ double rowk[kMaxRank];
     __shared__ double sc[kMaxRank];
     __shared__ int bad;
-    const int rr = r * r;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, rr = r * r;
+    const int lane = tid & 63, wv = tid >> 6;
     if (tid == 0) bad = 0;
-    for (int o = tid; o < rr; o += kCholThreads) {
-        double g = 0.0;
-        for (int b = 0; b < nblocks; ++b) g += partials[(size_t)b * rr + o];
-        A[o] = g;
-        Rp[o] = 0.0;
-        Ri[o] = 0.0;
-    }
+    stage_lds(A, partials, rr);
     __syncthreads();
+    for (int b = 1; b < nblocks; ++b) {
+        stage_lds(Ri, partials + (size_t)b * rr, rr);
+        __syncthreads();
+        for (int o = tid; o < rr; o += kCholThreads) A[o] += Ri[o];
+        __syncthreads();
+    }
     for (int k = tid; k < r; k += kCholThreads) {
         const double gkk = A[k * r + k];
         if (!(gkk > 0.0) || !isfinite(gkk)) bad = 1;
         sc[k] = (gkk > 0.0) ? 1.0 / sqrt(gkk) : 0.0;
     }
     __syncthreads();
-    for (int o = tid; o < rr; o += kCholThreads) A[o] *= sc[o / r] * sc[o % r];
+    for (int i = wv; i < r; i += 4)
+        if (lane < r) {
+            A[i * r + lane] *= sc[i] * sc[lane];
+            Ri[i * r + lane] = 0.0;
+        }
     __syncthreads();
     for (int k = 0; k < r; ++k) {
-        // every thread reads the pivot; row k of R' and the trailing update of the upper triangle
-        // both read row k of A, which this iteration does not change
         const double piv = A[k * r + k];
         const double rkk = sqrt(fmax(piv, 1e-300));
         if (tid == 0 && !(piv > 1e-12)) bad = 1;
-        for (int o = tid; o < rr; o += kCholThreads) {
-            const int i = o / r, j = o % r;
-            if (i == k && j >= k) Rp[k * r + j] = (j == k) ? rkk : A[k * r + j] / rkk;
-            if (i > k && j > k && j >= i) A[o] -= (A[k * r + i] / rkk) * (A[k * r + j] / rkk);
+        // row k of R' (A keeps it: row k is not touched again)
+        if (tid >= k && tid < r) {
+            const double v = (tid == k) ? rkk : A[k * r + tid] / rkk;
+            rowk[tid] = v;
+            A[k * r + tid] = v;
         }
-        __syncthreads();   // only the upper triangle of A is read or updated
+        __syncthreads();
+        // trailing update of the upper triangle: A_ij -= R'_ki R'_kj, k < i <= j
+        if (lane < r) {
+            const double rj = rowk[lane];
+#pragma unroll 2
+            for (int i = k + 1 + wv; i < r; i += 4)
+                if (lane >= i) A[i * r + lane] -= rowk[i] * rj;
+        }
+        __syncthreads();
     }
-    // R'^{-1}: column j solved by wavefront j % 16 (lanes over rows, back substitution over i)
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int j = wv; j < r; j += kCholThreads / 64) {
-        for (int i = j; i >= 0; --i) {
-            // v_i = (delta_ij - sum_{m=i+1..j} R'_im v_m) / R'_ii, with v_m (m > i) already in Ri
+    // R'^{-1}, row i from rows i+1.. : Ri_ij = (delta_ij - sum_{i < m < r} R'_im Ri_mj) / R'_ii
+    // (Ri_mj = 0 for m > j, so the uniform bound adds exact zeros)
+    if (wv == 0 && lane < r) {
+        for (int i = r - 1; i >= 0; --i) {
             double part = 0.0;
-            for (int m = i + 1 + lane; m <= j; m += 64) part += Rp[i * r + m] * Ri[m * r + j];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            if (lane == 0) Ri[i * r + j] = (((i == j) ? 1.0 : 0.0) - part) / Rp[i * r + i];
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll 8
+            for (int m = i + 1; m < r; ++m) part += A[i * r + m] * Ri[m * r + lane];
+            if (lane >= i) Ri[i * r + lane] = (((i == lane) ? 1.0 : 0.0) - part) / A[i * r + i];
         }
     }
     __syncthreads();
-    for (int o = tid; o < rr; o += kCholThreads) {
-        const int i = o / r, j = o % r;
-        R[o] = (sc[j] > 0.0) ? Rp[o] / sc[j] : 0.0;
-        Rinv[o] = sc[i] * Ri[o];
-    }
+    for (int i = wv; i < r; i += 4)
+        if (lane < r) {
+            const int o = i * r + lane;
+            R[o] = (i <= lane && sc[lane] > 0.0) ? A[o] / sc[lane] : 0.0;
+            Rinv[o] = (i <= lane) ? sc[i] * Ri[o] : 0.0;
+        }
     if (tid == 0 && bad) atomicOr(status, status_code);
 }
 
@@ -96,7 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
     double v[RMAX];
     const size_t ve = pad_ny ? padded_cell(e, pad_ny) : (size_t)e;
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) v[j] = (j < r) ? (double)V[(size_t)j * ldv + ve] : 0.0;
+    for (int j = 0; j < RMAX; ++j) {
+        const double x = (double)V[(size_t)(j < r ? j : r - 1) * ldv + ve];
+        v[j] = (j < r) ? x : 0.0;
+    }
 #pragma unroll 4
     for (int k = 0; k < r; ++k) {
         double acc = 0.0;
@@ -113,12 +128,16 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
 __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __restrict__ raw, double hx, double hy,
                                                         double inv_cdt, const double* __restrict__ S0,
                                                         double* __restrict__ ops) {
+    __shared__ double sM4[kMaxRank * kMaxRank];
+    __shared__ double sS[kMaxRank * kMaxRank];
     const int rr = r * r;
+    stage_lds(sM4, raw + 4 * rr, rr);
+    stage_lds(sS, S0, rr);
+    __syncthreads();
     const double* M0 = raw;
     const double* M1 = raw + rr;
     const double* M2 = raw + 2 * rr;
     const double* M3 = raw + 3 * rr;
-    const double* M4 = raw + 4 * rr;
     const double* vec = raw + 5 * rr;
     for (int o = threadIdx.x; o < rr; o += blockDim.x) {
         const int i = o / r, j = o % r;
@@ -130,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
         ops[4 * rr + o] = M2[o] + id * inv_cdt;
         ops[5 * rr + o] = M3[o];
         double g = 0.0;
-        for (int m = 0; m < r; ++m) g += S0[m * r + i] * M4[m * r + j];
+        for (int m = 0; m < r; ++m) g += sS[m * r + i] * sM4[m * r + j];
         ops[6 * rr + o] = g;
     }
     for (int o = threadIdx.x; o < 5 * r; o += blockDim.x) {
@@ -164,10 +183,14 @@ template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, in
 
 __global__ __launch_bounds__(kBlock) void k_small_matmul(int r, const double* __restrict__ A,
                                                          const double* __restrict__ B, double* __restrict__ C) {
+    __shared__ double sA[kMaxRank * kMaxRank], sB[kMaxRank * kMaxRank];
+    stage_lds(sA, A, r * r);
+    stage_lds(sB, B, r * r);
+    __syncthreads();
     for (int o = threadIdx.x; o < r * r; o += blockDim.x) {
         const int i = o / r, j = o % r;
         double s = 0.0;
-        for (int k = 0; k < r; ++k) s += A[i * r + k] * B[k * r + j];
+        for (int k = 0; k < r; ++k) s += sA[i * r + k] * sB[k * r + j];
         C[o] = s;
     }
 }

@@ -44,7 +44,8 @@ class DlrStepStats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int64), ("si_iters", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("si_residual", ctypes.c_double), ("deim_min_margin", ctypes.c_double),
                 ("sum_abs_cw_over_4pi", ctypes.c_double), ("energy", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class DlrError(RuntimeError):
