@@ -95,6 +95,7 @@ struct dlr_instance {
     int *sel = nullptr, *forced = nullptr;
     double *cw = nullptr, *C0 = nullptr, *a0 = nullptr, *margins = nullptr, *sel_mu = nullptr, *sel_eta = nullptr;
     double *inflow_x = nullptr, *inflow_y = nullptr, *deim_work = nullptr;
+    unsigned* deim_count = nullptr;
     void* edge = nullptr;
     unsigned long long* progress = nullptr;
     unsigned* ticket = nullptr;
@@ -102,7 +103,7 @@ struct dlr_instance {
     unsigned* unit_end = nullptr;    // [1] sweep units of this instance
     std::vector<char> h_sweep_rec;   // host copy of the sweep record (SweepArgs of the instance's precision)
     int nsuper = 0;
-    size_t ld = 0;    // elements of one padded-column plane (Psi handed to the QR)
+    size_t ld = 0;    // elements of one compact cell plane of Psi handed to the QR (N rounded up to 64)
     size_t ldg = 0;   // elements of one diagonal sweep plane (psi, src0, and the 4 copies of sigma_t, s_e)
     double* partials = nullptr;
     size_t partials_count = 0;
@@ -207,7 +208,8 @@ struct dlr_instance {
         sel_eta = A.take<double>(R);
         inflow_x = A.take<double>(R);
         inflow_y = A.take<double>(R);
-        deim_work = A.take<double>(R * Q);
+        deim_work = A.take<double>(dlr::kDeimXchgDoubles);
+        deim_count = A.take<unsigned>(4);
         edge = A.take<char>(R * (size_t)nsuper * ny * sweep_bytes());
         progress = A.take<unsigned long long>(R * (size_t)nsuper);
         ticket = A.take<unsigned>(4);
@@ -292,6 +294,7 @@ dlr_status check_device_status(dlr_instance* I) {
     if (st & dlr::kStatusSingularSolve) m += " singular-solve";
     if (st & dlr::kStatusSvdNoConv) m += " svd-not-converged";
     if (st & dlr::kStatusSweepStall) m += " sweep-wait-stalled";
+    if (st & dlr::kStatusDeimStall) m += " deim-exchange-stalled";
     if (st & dlr::kStatusNoCompletion) m += " no-completion-vector";
     if (st & dlr::kStatusBadForcedSel) { m += " bad-forced-selection"; code = DLR_ERR_ARG; }
     I->poisoned = true;
@@ -354,7 +357,7 @@ void phase_begin(dlr_instance* I) {
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
     da.forced = I->force_pending ? I->forced : nullptr;
-    da.work = I->deim_work; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
+    da.xchg = I->deim_work; da.xcount = I->deim_count; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
     da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
     da.mu = I->mu; da.eta = I->eta;
     for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];
@@ -431,14 +434,14 @@ void phase_end(dlr_instance* I) {
     TS* psi_cm = static_cast<TS*>(I->psi_cm);
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
-    dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->ny, I->R1i, I->Xt);
-    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, 0, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, I->Xt);
+    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, 0, I->R2i, I->Xn);
+    dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
-    dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, I->ny, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
+    dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
     // 6-7. projections on the new basis and the L-step for every ordinate
     dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj,
@@ -453,14 +456,14 @@ void phase_end(dlr_instance* I) {
     dlr::launch_lstep(s, la);
     // 8. L = W S^T in the quadrature inner product: Cholesky QR twice, R = R2 R1; the CGS2 with
     // angular completion recomputes W and R on the device when a pivot flagged near-dependent columns
-    dlr::launch_gram<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_gram<double>(s, nq, r, I->L, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
-    dlr::launch_trmm<double>(s, nq, r, I->L, (size_t)nq, 0, I->R1i, I->Wt);
-    dlr::launch_gram<double>(s, nq, r, I->Wt, (size_t)nq, 0, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_trmm<double>(s, nq, r, I->L, (size_t)nq, I->R1i, I->Wt);
+    dlr::launch_gram<double>(s, nq, r, I->Wt, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
     dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
-    dlr::launch_trmm<double>(s, nq, r, I->Wt, (size_t)nq, 0, I->R2i, I->Wq);
+    dlr::launch_trmm<double>(s, nq, r, I->Wt, (size_t)nq, I->R2i, I->Wq);
     dlr::launch_small_matmul(s, r, I->R2, I->R1, I->Ra);
-    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, 0, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
+    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
                              I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
     dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
@@ -620,7 +623,7 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->has_qext = p->q_ext != nullptr;
     I->stream = stream;
     I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
-    I->ld = dlr::padded_plane(I->nx, I->ny);
+    I->ld = ((size_t)I->N + 63) / 64 * 64;   // compact column-major cell planes (e = i * ny + j)
     I->ldg = dlr::diag_plane(I->nx, I->ny);
     I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
     const size_t rr = (size_t)I->r * I->r;

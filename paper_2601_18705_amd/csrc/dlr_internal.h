@@ -8,8 +8,7 @@
 //   sweep planes             in the sweep precision (double or float), diagonal layout (below):
 //                            Psi, src0 [r][ldg] each in its own direction's orientation; sigma_t,
 //                            s_e [4][ldg], one copy per orientation
-//   Psi for the QR           [r][ld] "padded columns": cell (i, j) at i*ldc + kColGuard + j with
-//                            ldc = ny + 2 kColGuard (kColGuard spare rows above and below a column)
+//   Psi for the QR           [r][ld] compact cell planes (cell e = i*ny + j), ld = N rounded up to 64
 //   angular basis W, L       [r][nq] float64 (column k contiguous over ordinates)
 //   coupling S               [r][r] float64, row-major S[i*r + j]
 // The state is psi = X S W^T with X, W orthonormal; S is kept as a general
@@ -84,7 +83,7 @@ void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg,
                 const double* cw, double* phio /* [4][ldg] work */, const double* sig_s, const double* phi_old,
                 double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter, double* out);
 
-// Psi (diagonal layouts) -> padded-column planes [r][ld]
+// Psi (diagonal layouts) -> compact column-major cell planes [r][ld] (cell e = i * ny + j)
 template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
                       const double* eta, TS* psi_cm, size_t ld);
@@ -112,17 +111,6 @@ void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* 
 
 // ----------------------------------------------------------------------------- sweep
 constexpr int kSweepWaves = 2;     // compute wavefronts (64-column strips) per sweep workgroup
-constexpr int kColGuard = 16;      // spare rows above and below each column of a sweep plane
-
-// index of column-major cell e = i*ny + j in a padded-column sweep plane
-__host__ __device__ inline size_t padded_cell(long e, int ny) {
-    const long i = e / ny;
-    return (size_t)i * (ny + 2 * kColGuard) + kColGuard + (e - i * ny);
-}
-// elements of one padded sweep plane, plus a kColGuard-element trash slot, rounded to 64
-__host__ __device__ inline size_t padded_plane(int nx, int ny) {
-    return (((size_t)nx * (ny + 2 * kColGuard) + kColGuard) + 63) / 64 * 64;
-}
 // One instance's sweep: everything but the launch-level fields below is fixed for the life of
 // the instance, so the record is uploaded once and reused by every launch.
 template <typename TS>
@@ -161,11 +149,11 @@ void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& 
 unsigned long long next_sweep_launch_id();
 
 // ----------------------------------------------------------------------------- reductions
-// V planes are compact (pad_ny = 0) or padded-column sweep planes (pad_ny = ny).
+// V planes are compact [r][ldv] (cell e at V[k * ldv + e]).
 // G = scale * V^T diag(weight) V (r x r, row-major; weight nullable = 1), via per-block partials in
 // work [nblocks][r^2].
 template <typename TV>
-void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double scale,
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight, double scale,
                  double* work, int nblocks, double* G);
 // C = A B for r x r row-major matrices
 void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C);
@@ -174,7 +162,7 @@ void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B,
 void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,
                  int* status, int status_code);
 template <typename TV>
-void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X);
+void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X);
 
 // Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use
 // FP64 MFMA operands (operand_bits 64), FP32 operands (32) or BF16 operands (16), the last two with
@@ -188,6 +176,9 @@ void launch_project_finalize(hipStream_t s, int r, const double* partials, int n
                              double inv_cdt, const double* S0, double* ops);
 
 // ----------------------------------------------------------------------------- small dense FP64 work
+// DEIM exchange area: per column two exchanges among up to 64 workgroups (double-buffered),
+// and the workgroups' parts of beta
+constexpr size_t kDeimXchgDoubles = 2 * 64 + 2 * 64 * (2 + (size_t)kMaxRank) + 64 * (size_t)kMaxRank;
 struct DeimArgs {
     int nq, r;
     const double* W;       // [r][nq]
@@ -195,7 +186,8 @@ struct DeimArgs {
     const double* w;       // [nq]
     double tie_tol;
     const int* forced;     // [r] or nullptr
-    double* work;          // [r][nq] scratch
+    double* xchg;          // [kDeimXchgDoubles] exchange area among the workgroups
+    unsigned* xcount;      // [2] arrival / departure counters, zero between launches
     int* sel;              // [r]
     double* cw;            // [r]
     double* C0;            // [r][r]  C0[k*r + d] = sum_j S[k][j] W[j][sel_d]
@@ -237,7 +229,7 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 // comp_kind 0: spatial monomials on the nx x ny cell centres, 1: angular monomials in (mu, eta).
 // With flag != nullptr the kernel runs only if (*flag & flag_mask) and then clears those bits.
 template <typename TV>
-void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double wscalar,
+void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight, double wscalar,
                  int comp_kind,
                  int nx, int ny, const double* mu, const double* eta, double* Q, double* R, int* flag,
                  int flag_mask, int* status, int status_code);
@@ -258,6 +250,7 @@ enum DeviceStatus : int {
     kStatusSvdNoConv = 32,
     kStatusSweepStall = 64,
     kStatusNoCompletion = 128,
+    kStatusDeimStall = 256,
 };
 
 }  // namespace dlr

@@ -133,40 +133,46 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
                                                  double inv_cdt, const double* __restrict__ mu,
                                                  const double* __restrict__ eta, TS* __restrict__ src0, size_t ldg,
                                                  double* __restrict__ phi, TS* __restrict__ s_e) {
-    __shared__ double sC[RMAX * RMAX];
-    __shared__ double sa[RMAX];
-    __shared__ int so[RMAX];
-    for (int i = threadIdx.x; i < r * r; i += blockDim.x) sC[(i / r) * RMAX + (i % r)] = C0[i];
-    for (int i = threadIdx.x; i < r; i += blockDim.x) {
-        sa[i] = a0[i];
-        so[i] = orient_of(mu[i], eta[i]);
-    }
-    __syncthreads();
+    // C0, a0 and the orientations are uniform across the workgroup: they are read with scalar
+    // loads (through the scalar cache), which keeps the inner product off the LDS pipe
     const long n = (long)g.nx * g.ny;
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
         for (int kc = 0; kc < 4; ++kc) {
             int i, j;
             if (!g.cell(b, kc, i, j)) continue;
             const long e = (long)i * g.ny + j;
-            double x[RMAX];
-#pragma unroll
-            for (int k = 0; k < RMAX; ++k) x[k] = (k < r) ? X[(size_t)k * n + e] : 0.0;
+            // acc[d] = sum_k X_k(e) C0[k][d] in passes of 16 directions: a row of C0 is 16
+            // contiguous doubles (wide scalar loads into 32 SGPRs); X_k(e) is re-read from cache
+            constexpr int kPass = RMAX < 16 ? RMAX : 16;
             double ph = 0.0;
-#pragma unroll
-            for (int k = 0; k < RMAX; ++k)
-                if (k < r) ph += x[k] * sa[k];
+#pragma unroll 1
+            for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * a0[k];
             phi[e] = ph;
+            size_t pos[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
             const TS se = (TS)(sig_s[e] * ph / kFourPi);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + diag_pos(g.nx, g.ny, o, i, j)] = se;
+            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
             const double qe = q[e];
-#pragma unroll 4
-            for (int d = 0; d < r; ++d) {
-                double acc = 0.0;
+#pragma unroll 1
+            for (int d0 = 0; d0 < r; d0 += kPass) {
+                double acc[kPass];
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k)
-                    if (k < r) acc += x[k] * sC[k * RMAX + d];
-                src0[(size_t)d * ldg + diag_pos(g.nx, g.ny, so[d], i, j)] = (TS)(qe + acc * inv_cdt);
+                for (int d = 0; d < kPass; ++d) acc[d] = 0.0;
+#pragma unroll 1
+                for (int k = 0; k < r; ++k) {
+                    const double xk = X[(size_t)k * n + e];
+#pragma unroll
+                    for (int d = 0; d < kPass; ++d) acc[d] += xk * C0[k * r + (d0 + d < r ? d0 + d : r - 1)];
+                }
+#pragma unroll
+                for (int d = 0; d < kPass; ++d) {
+                    if (d0 + d >= r) break;
+                    const int o = orient_of(mu[d0 + d], eta[d0 + d]);
+                    const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
+                    src0[(size_t)(d0 + d) * ldg + pd] = (TS)(qe + acc[d] * inv_cdt);
+                }
             }
         }
     }
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const T
         for (int kc = 0; kc < 4; ++kc) {
             int i, j;
             if (!g.cell(b, kc, i, j)) continue;
-            const size_t pe = padded_cell((long)i * g.ny + j, g.ny);
+            const size_t pe = (size_t)i * g.ny + j;
             size_t pos[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);

@@ -17,179 +17,7 @@ namespace dlr {
 namespace {
 
 // ---------------------------------------------------------------------------------------------- block reductions
-constexpr int kDeimThreads = 1024;
-constexpr int kDeimWaves = kDeimThreads / 64;
 constexpr int kMaxOrdinates = 16384;
-
-// Reductions over the workgroup: wavefront shuffles, one slot per wavefront in LDS, one barrier;
-// every thread then combines the slots in wavefront order, so all threads hold the same result.
-__device__ double block_max1(double v, double* slots) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double m = slots[0];
-    for (int w = 1; w < kDeimWaves; ++w) m = fmax(m, slots[w]);
-    return m;
-}
-__device__ void block_minidx_max(int& p, double& v, int* islots, double* dslots) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        p = min(p, __shfl_xor(p, off));
-        v = fmax(v, __shfl_xor(v, off));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        islots[threadIdx.x >> 6] = p;
-        dslots[threadIdx.x >> 6] = v;
-    }
-    __syncthreads();
-    p = islots[0];
-    v = dslots[0];
-    for (int w = 1; w < kDeimWaves; ++w) {
-        p = min(p, islots[w]);
-        v = fmax(v, dslots[w]);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------- DEIM
-__global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
-    __shared__ double shd[kDeimThreads];
-    __shared__ int shi[kDeimThreads];
-    __shared__ double slotA[kDeimWaves], slotB[kDeimWaves];
-    __shared__ int islot[kDeimWaves];
-    __shared__ unsigned char piv[kMaxOrdinates];
-    __shared__ double beta[kMaxRank];
-    __shared__ double M[kMaxRank * (kMaxRank + 1)];
-    __shared__ int sel[kMaxRank];
-    __shared__ int bad;
-    const int nq = a.nq, r = a.r, tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
-    const double* __restrict__ W = a.W;
-    double* __restrict__ U = a.work;
-    if (tid == 0) bad = 0;
-    for (int q = tid; q < nq; q += kDeimThreads) piv[q] = 0;
-#pragma unroll 8
-    for (int i = tid; i < r * nq; i += kDeimThreads) U[i] = W[i];
-    // beta_j = int W_j = sum_q w_q W_j(q): wavefront j % 16 sums column j in lane order
-    for (int j = wv; j < r; j += kDeimWaves) {
-        double acc = 0.0;
-#pragma unroll 8
-        for (int q = lane; q < nq; q += 64) acc += a.w[q] * W[(size_t)j * nq + q];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) beta[j] = acc;
-    }
-    __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        const double* col = U + (size_t)j * nq;
-        double m = 0.0;
-        for (int q = tid; q < nq; q += kDeimThreads)
-            if (!piv[q]) m = fmax(m, fabs(col[q]));
-        m = block_max1(m, slotA);   // also orders the previous elimination before these reads
-        const double thr = (1.0 - a.tie_tol) * m;
-        int p = 0x7fffffff;
-        double second = 0.0;
-        for (int q = tid; q < nq; q += kDeimThreads) {
-            if (piv[q]) continue;
-            const double v = fabs(col[q]);
-            if (v >= thr) p = min(p, q);
-            else second = fmax(second, v);
-        }
-        block_minidx_max(p, second, islot, slotB);
-        if (a.forced) {
-            const int f = a.forced[j];
-            if (tid == 0 && (f < 0 || f >= nq || piv[f])) bad = 1;
-            p = (f >= 0 && f < nq) ? f : 0;
-        }
-        if (tid == 0) {
-            sel[j] = p;
-            a.margins[j] = (m > 0.0) ? (m - second) / m : 0.0;
-            if (!(m > 0.0)) bad = 1;
-        }
-        // the owner of row p marks it; every thread only tests the rows it owns
-        if (p % kDeimThreads == tid) piv[p] = 1;
-        // eliminate column j from the remaining rows, columns k > j, eight columns at a time so the
-        // loads of a batch are in flight together
-        const double pv = col[p];
-        for (int k0 = j + 1; k0 < r; k0 += 8) {
-            double up[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) up[b] = (k0 + b < r) ? U[(size_t)(k0 + b) * nq + p] : 0.0;
-            for (int q = tid; q < nq; q += kDeimThreads) {
-                if (piv[q]) continue;
-                const double l = col[q] / pv;
-                double x[8];
-#pragma unroll
-                for (int b = 0; b < 8; ++b) x[b] = (k0 + b < r) ? U[(size_t)(k0 + b) * nq + q] : 0.0;
-#pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    if (k0 + b < r) U[(size_t)(k0 + b) * nq + q] = x[b] - l * up[b];
-            }
-        }
-    }
-    __syncthreads();
-    // c = What^{-T} beta: solve M c = beta with M[i][j] = What[j][i] = W_i(Omega^(j))
-    const int ld = r + 1;
-    __shared__ double sS[kMaxRank * kMaxRank];
-    __shared__ double Wh[kMaxRank * kMaxRank];   // Wh[i][j] = W_i(Omega^(sel j))
-    stage_lds(sS, a.S, r * r);
-    for (int o = tid; o < r * r; o += kDeimThreads) {
-        const int i = o / r, j = o % r;
-        const double v = W[(size_t)i * nq + sel[j]];
-        M[i * ld + j] = v;
-        Wh[o] = v;
-    }
-    for (int i = tid; i < r; i += kDeimThreads) M[i * ld + r] = beta[i];
-    __syncthreads();
-    for (int k = 0; k < r; ++k) {
-        if (tid == 0) {
-            int pr = k;
-            double best = fabs(M[k * ld + k]);
-            for (int i = k + 1; i < r; ++i)
-                if (fabs(M[i * ld + k]) > best) { best = fabs(M[i * ld + k]); pr = i; }
-            shi[0] = pr;
-            if (!(best > 0.0)) bad = 1;
-        }
-        __syncthreads();
-        const int pr = shi[0];
-        if (pr != k)
-            for (int c = tid; c <= r; c += kDeimThreads) {
-                const double t = M[k * ld + c];
-                M[k * ld + c] = M[pr * ld + c];
-                M[pr * ld + c] = t;
-            }
-        __syncthreads();
-        const double inv = 1.0 / M[k * ld + k];
-        for (int i = tid; i < r; i += kDeimThreads) shd[i] = (i == k) ? 0.0 : M[i * ld + k] * inv;
-        __syncthreads();
-        for (int o = tid; o < r * ld; o += kDeimThreads) {
-            const int i = o / ld, c = o % ld;
-            if (i != k) M[o] -= shd[i] * M[k * ld + c];
-        }
-        __syncthreads();
-    }
-    for (int i = tid; i < r; i += kDeimThreads) {
-        const int d = i;
-        a.cw[i] = M[i * ld + r] / M[i * ld + i];
-        a.sel[d] = sel[d];
-        const double mu = a.mu[sel[d]], eta = a.eta[sel[d]];
-        a.sel_mu[d] = mu;
-        a.sel_eta[d] = eta;
-        a.inflow_x[d] = a.psib[mu > 0.0 ? 0 : 1];
-        a.inflow_y[d] = a.psib[eta > 0.0 ? 2 : 3];
-        double s = 0.0;
-        for (int j = 0; j < r; ++j) s += sS[i * r + j] * beta[j];
-        a.a0[i] = s;
-    }
-    // C0[k][d] = sum_j S[k][j] W_j(Omega^(d))
-    for (int o = tid; o < r * r; o += kDeimThreads) {
-        const int k = o / r, d = o % r;
-        double s = 0.0;
-        for (int j = 0; j < r; ++j) s += sS[k * r + j] * Wh[j * r + d];
-        a.C0[o] = s;
-    }
-    if (tid == 0 && bad) atomicOr(a.status, a.forced ? (int)kStatusBadForcedSel : (int)kStatusSingularSolve);
-}
 
 // ---------------------------------------------------------------------------------------------- Gauss-Jordan
 // In-place Gauss-Jordan with partial pivoting on an r x ld augmented matrix in LDS
@@ -262,6 +90,297 @@ __device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, double* pr
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------------------------- DEIM
+// Algorithm 1 step 2 (Sec. 4.2): the DEIM points of W are the pivots of Gaussian elimination
+// with partial pivoting on the rows of W (ordinates): for column j, the pivot is the
+// lowest-index row whose |value| is within the tie tolerance of the column maximum over the
+// rows not yet chosen (margin = relative gap to the largest value below that threshold), and
+// the column is eliminated from the remaining rows.  Then c solves What^T c = beta with
+// beta = W^T w, and C0 = S W[sel]^T, a0 = S beta.
+//
+// The rows are spread over ceil(nq / 256) workgroups, one row per thread, kept in registers.
+// Per column two exchanges among the workgroups: (1) each group's maximum, (2) each group's
+// lowest-index row at or above the threshold with its values, and its largest value below the
+// threshold.  Exchanged values are agent-scope atomics in a double-buffered area; a group
+// counts itself after its stores have completed and polls the count, bounded by a spin limit
+// (kStatusDeimStall) so that a stall cannot hang the device.  All groups reach the same
+// decisions from the same data; group 0 then solves for c and writes the outputs.
+constexpr int kDeimThreads = 256;
+constexpr int kDeimWaves = kDeimThreads / 64;
+constexpr int kDeimMaxGroups = kMaxOrdinates / kDeimThreads;
+constexpr size_t kXEx1 = 0;                                                        // [2][groups]
+constexpr size_t kXEx2 = kXEx1 + 2 * kDeimMaxGroups;                              // [2][groups][2 + kMaxRank]
+constexpr size_t kXBeta = kXEx2 + 2 * (size_t)kDeimMaxGroups * (2 + kMaxRank);    // [groups][kMaxRank]
+static_assert(kXBeta + (size_t)kDeimMaxGroups * kMaxRank <= kDeimXchgDoubles, "DEIM exchange area");
+constexpr unsigned kDeimSpinLimit = 1u << 20;
+
+__device__ __forceinline__ void xstore(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_vm_stores() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
+}
+// Every group arrives at exchange number `target / groups`: the stores of each wavefront have
+// completed, then thread 0 counts the group and polls until all groups have counted.  After one
+// wait has timed out the group stops polling (its results are flagged invalid anyway).
+__device__ void group_sync(unsigned* arrive, unsigned target, int* stall) {
+    wait_vm_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (!*stall && __hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++polls > kDeimSpinLimit) {
+                *stall = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+template <int RT>
+__global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
+    __shared__ double sv[kDeimWaves];
+    __shared__ int si[kDeimWaves];
+    __shared__ double sM, sSecond;
+    __shared__ int sP, sPw;
+    __shared__ double up[RT];
+    __shared__ double bw[kDeimWaves][RT];
+    __shared__ int bad, stall;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nq = a.nq, r = a.r;
+    const int q = g * kDeimThreads + tid;
+    const bool in = q < nq;
+    double* X = a.xchg;
+    if (tid == 0) {
+        bad = 0;
+        stall = 0;
+    }
+    // row q of W, and this group's part of beta = W^T w (wavefront sums, then wavefront order)
+    double u[RT];
+    const double wq = in ? a.w[q] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const double v = a.W[(size_t)(i < r ? i : r - 1) * nq + (in ? q : 0)];
+        u[i] = (in && i < r) ? v : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        double b = wq * u[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) b += __shfl_xor(b, off);
+        if (lane == 0) bw[wv][i] = b;
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += kDeimThreads) {
+        double b = 0.0;
+        for (int w = 0; w < kDeimWaves; ++w) b += bw[w][i];
+        xstore(&X[kXBeta + (size_t)g * kMaxRank + i], b);
+    }
+    bool pivoted = false;
+    unsigned nsync = 0;
+    for (int j = 0; j < r; ++j) {
+        double uj = 0.0;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) uj = (i == j) ? u[i] : uj;
+        const bool elig = in && !pivoted;
+        const double v = elig ? fabs(uj) : -1.0;
+        // (1) maximum over the rows not yet chosen
+        {
+            double m = v;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+            if (lane == 0) sv[wv] = m;
+            __syncthreads();
+            if (tid == 0) {
+                double mw = sv[0];
+                for (int w = 1; w < kDeimWaves; ++w) mw = fmax(mw, sv[w]);
+                xstore(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + g], mw);
+            }
+            group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
+            if (wv == 0) {
+                double mg = (lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) mg = fmax(mg, __shfl_xor(mg, off));
+                if (lane == 0) sM = fmax(mg, 0.0);
+            }
+            __syncthreads();
+        }
+        const double M = sM;
+        const double thr = (1.0 - a.tie_tol) * M;
+        // (2) lowest-index row at or above the threshold (or the forced row), largest value below
+        {
+            int pi = (elig && v >= thr) ? q : 0x7fffffff;
+            double sec = (elig && v < thr) ? v : 0.0;
+            if (a.forced) {
+                const int f = a.forced[j];
+                pi = (q == f) ? q : 0x7fffffff;
+                if (q == f && !elig) bad = 1;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                pi = min(pi, __shfl_xor(pi, off));
+                sec = fmax(sec, __shfl_xor(sec, off));
+            }
+            if (lane == 0) {
+                si[wv] = pi;
+                sv[wv] = sec;
+            }
+            __syncthreads();
+            int pw = si[0];
+            double sw = sv[0];
+            for (int w = 1; w < kDeimWaves; ++w) {
+                pw = min(pw, si[w]);
+                sw = fmax(sw, sv[w]);
+            }
+            double* slot = &X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + g) * (2 + kMaxRank)];
+            if (q == pw) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    if (i < r) xstore(&slot[2 + i], u[i]);
+            }
+            if (tid == 0) {
+                xstore(&slot[0], (double)pw);
+                xstore(&slot[1], sw);
+            }
+            group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
+            if (wv == 0) {
+                const double* sl = &X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + lane) * (2 + kMaxRank)];
+                double pg = (lane < G) ? xload(&sl[0]) : 2147483647.0;
+                double sg = (lane < G) ? xload(&sl[1]) : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    pg = fmin(pg, __shfl_xor(pg, off));
+                    sg = fmax(sg, __shfl_xor(sg, off));
+                }
+                if (lane == 0) {
+                    sP = (pg < 2147483647.0) ? (int)pg : -1;
+                    sSecond = sg;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = sP;
+        if (p < 0) {   // no row qualifies (an invalid forced index): flag and stop, consistently in all groups
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const int pg = p / kDeimThreads;
+        for (int i = tid; i < r; i += kDeimThreads)
+            up[i] = xload(&X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + pg) * (2 + kMaxRank) + 2 + i]);
+        if (tid == 0) {
+            if (g == 0) {
+                a.sel[j] = p;
+                a.margins[j] = (M > 0.0) ? (M - sSecond) / M : 0.0;
+            }
+            if (!(M > 0.0)) bad = 1;
+        }
+        __syncthreads();
+        // eliminate column j from the rows not yet chosen
+        if (q == p) pivoted = true;
+        if (in && !pivoted) {
+            const double l = uj / up[j];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                if (i > j && i < r) u[i] -= l * up[i];
+        }
+    }
+    // the last group to leave resets the counters for the next launch
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&a.xcount[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (unsigned)G - 1u) {
+            __hip_atomic_store(&a.xcount[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.xcount[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (stall) atomicOr(a.status, (int)kStatusDeimStall);
+        if (bad) atomicOr(a.status, a.forced ? (int)kStatusBadForcedSel : (int)kStatusSingularSolve);
+    }
+}
+
+// After the selection: beta (sum of the groups' parts in group order), What^T c = beta by
+// Gauss-Jordan with partial pivoting, and the per-direction outputs.  One workgroup.
+__global__ __launch_bounds__(kDeimThreads) void k_deim_tail(DeimArgs a, int groups) {
+    __shared__ double beta[kMaxRank];
+    __shared__ int sel[kMaxRank];
+    __shared__ double Aug[kMaxRank * (kMaxRank + 1)];
+    __shared__ double sS[kMaxRank * kMaxRank];
+    __shared__ double Wh[kMaxRank * kMaxRank];   // Wh[i][d] = W_i(Omega^(sel d))
+    __shared__ double fac[kMaxRank];
+    __shared__ double prow[kMaxRank + 1];
+    __shared__ double pivval;
+    __shared__ int pivrow, bad;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nq = a.nq, r = a.r;
+    const double* X = a.xchg;
+    if (tid == 0) bad = 0;
+    __shared__ double bparts[kDeimMaxGroups * kMaxRank];
+    __shared__ double smu[kMaxRank], seta[kMaxRank];
+    stage_lds(bparts, X + kXBeta, groups * kMaxRank);
+    stage_lds(sS, a.S, r * r);
+    for (int i = tid; i < r; i += kDeimThreads) {
+        const int sv = a.sel[i];
+        sel[i] = (sv >= 0 && sv < nq) ? sv : 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += kDeimThreads) {
+        double b = 0.0;
+        for (int w = 0; w < groups; ++w) b += bparts[w * kMaxRank + i];
+        beta[i] = b;
+        smu[i] = a.mu[sel[i]];
+        seta[i] = a.eta[sel[i]];
+    }
+    // What: the r x r gather, all loads of a thread issued before its stores
+    const int ld = r + 1;
+    for (int base = tid; base < r * r; base += 8 * kDeimThreads) {
+        double v[8];
+        int o8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int o = base + u * kDeimThreads;
+            const int oc = o < r * r ? o : r * r - 1;
+            const int i = oc / r, jj = oc - (oc / r) * r;
+            o8[u] = o;
+            v[u] = a.W[(size_t)i * nq + sel[jj]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (o8[u] < r * r) {
+                const int i = o8[u] / r, jj = o8[u] - (o8[u] / r) * r;
+                Aug[i * ld + jj] = v[u];
+                Wh[o8[u]] = v[u];
+            }
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += kDeimThreads) Aug[i * ld + r] = beta[i];
+    __syncthreads();
+    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
+    for (int i = tid; i < r; i += kDeimThreads) {
+        a.cw[i] = Aug[i * ld + r];
+        const double mu = smu[i], eta = seta[i];
+        a.sel_mu[i] = mu;
+        a.sel_eta[i] = eta;
+        a.inflow_x[i] = a.psib[mu > 0.0 ? 0 : 1];
+        a.inflow_y[i] = a.psib[eta > 0.0 ? 2 : 3];
+        double s = 0.0;
+        for (int jj = 0; jj < r; ++jj) s += sS[i * r + jj] * beta[jj];
+        a.a0[i] = s;
+    }
+    // C0[k][d] = sum_j S[k][j] W_j(Omega^(d))
+    for (int k = wv; k < r; k += kDeimWaves)
+        for (int d = lane; d < r; d += 64) {
+            double s = 0.0;
+            for (int jj = 0; jj < r; ++jj) s += sS[k * r + jj] * Wh[jj * r + d];
+            a.C0[k * r + d] = s;
+        }
+    if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
 }
 
 constexpr int kLsThreads = 256;
@@ -581,7 +700,16 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
 }  // namespace
 
 void launch_deim(hipStream_t s, const DeimArgs& a) {
-    hipLaunchKernelGGL(k_deim, dim3(1), dim3(kDeimThreads), 0, s, a);
+    const unsigned groups = (unsigned)((a.nq + kDeimThreads - 1) / kDeimThreads);
+    if (a.r <= 8)
+        hipLaunchKernelGGL((k_deim<8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    else if (a.r <= 16)
+        hipLaunchKernelGGL((k_deim<16>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    else if (a.r <= 32)
+        hipLaunchKernelGGL((k_deim<32>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_deim<64>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    hipLaunchKernelGGL(k_deim_tail, dim3(1), dim3(kDeimThreads), 0, s, a, (int)groups);
 }
 
 void launch_lstep(hipStream_t s, const LstepArgs& a) {

@@ -102,7 +102,7 @@ template <> struct AccOf<float> { typedef fv4 type; };
 // The next chunk's global loads are staged in registers while the current chunk's MFMAs run.
 template <typename TV, int RT>
 __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV* __restrict__ V, size_t ldv,
-                                                        int pad_ny, const double* __restrict__ weight, double scale,
+                                                        const double* __restrict__ weight, double scale,
                                                         double* __restrict__ partials) {
     constexpr int RP = 16 * RT, NT = RT * RT, TPW = (NT + 3) / 4;
     constexpr int NV = (RP * kPC + kThreads - 1) / kThreads;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV*
             const int idx = threadIdx.x + u * kThreads;
             const int p = idx / kPC, c = idx % kPC;
             const long e = c0 + c;
-            g[u] = (p < r && e < n) ? (double)V[(size_t)p * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)] : 0.0;
+            g[u] = (p < r && e < n) ? (double)V[(size_t)p * ldv + (size_t)e] : 0.0;
         }
         if (threadIdx.x < kPC) {
             const long e = c0 + threadIdx.x;
@@ -437,22 +437,22 @@ void sum_partials(hipStream_t s, int total, const double* partials, int nblocks,
 }  // namespace
 
 template <typename TV>
-void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight, double scale,
+void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight, double scale,
                  double* work, int nblocks, double* G) {
     const dim3 g(nblocks), b(kThreads);
     if (r <= 16)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 1>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 1>), g, b, 0, s, n, r, V, ldv, weight, scale, work);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 2>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 2>), g, b, 0, s, n, r, V, ldv, weight, scale, work);
     else if (r <= 48)
-        hipLaunchKernelGGL((k_gram_mfma<TV, 3>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 3>), g, b, 0, s, n, r, V, ldv, weight, scale, work);
     else
-        hipLaunchKernelGGL((k_gram_mfma<TV, 4>), g, b, 0, s, n, r, V, ldv, pad_ny, weight, scale, work);
+        hipLaunchKernelGGL((k_gram_mfma<TV, 4>), g, b, 0, s, n, r, V, ldv, weight, scale, work);
     sum_partials(s, r * r, work, nblocks, 1.0, G);
 }
-template void launch_gram<double>(hipStream_t, long, int, const double*, size_t, int, const double*, double, double*,
+template void launch_gram<double>(hipStream_t, long, int, const double*, size_t, const double*, double, double*,
                                   int, double*);
-template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, int, const double*, double, double*, int,
+template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, const double*, double, double*, int,
                                  double*);
 
 template <typename TO, bool BF16>

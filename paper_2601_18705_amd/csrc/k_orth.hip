@@ -128,7 +128,7 @@ __device__ void project_twice(const OrthCtx& c, int k, double* hs, double* hsum,
 }
 
 template <typename TV>
-__global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
+__global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* __restrict__ V, size_t ldv,
                                                        const double* __restrict__ weight, double wscalar,
                                                        int comp_kind, int nx, int ny, const double* __restrict__ mu,
                                                        const double* __restrict__ eta, double* __restrict__ Q,
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
     for (int k = 0; k < r; ++k) {
         double* v = Q + (size_t)k * n;
         for (long e = t; e < n; e += kOrthThreads)
-            v[e] = (double)V[(size_t)k * ldv + (pad_ny ? padded_cell(e, pad_ny) : (size_t)e)];
+            v[e] = (double)V[(size_t)k * ldv + (size_t)e];
         // attempt 0 is the column itself; later attempts are completion vectors
         for (int attempt = 0; attempt <= 100000; ++attempt) {
             double own, nrm;
@@ -202,15 +202,15 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
 }  // namespace
 
 template <typename TV>
-void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, int pad_ny, const double* weight,
+void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight,
                  double wscalar, int comp_kind, int nx, int ny, const double* mu, const double* eta, double* Q,
                  double* R, int* flag, int flag_mask, int* status, int status_code) {
-    hipLaunchKernelGGL((k_cgs2<TV>), dim3(1), dim3(kOrthThreads), 0, s, n, r, V, ldv, pad_ny, weight, wscalar,
+    hipLaunchKernelGGL((k_cgs2<TV>), dim3(1), dim3(kOrthThreads), 0, s, n, r, V, ldv, weight, wscalar,
                        comp_kind, nx, ny, mu, eta, Q, R, flag, flag_mask, status, status_code);
 }
-template void launch_cgs2<double>(hipStream_t, long, int, const double*, size_t, int, const double*, double, int, int,
+template void launch_cgs2<double>(hipStream_t, long, int, const double*, size_t, const double*, double, int, int,
                                   int, const double*, const double*, double*, double*, int*, int, int*, int);
-template void launch_cgs2<float>(hipStream_t, long, int, const float*, size_t, int, const double*, double, int, int,
+template void launch_cgs2<float>(hipStream_t, long, int, const float*, size_t, const double*, double, int, int,
                                  int, const double*, const double*, double*, double*, int*, int, int*, int);
 
 }  // namespace dlr

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int r, const double* __re
 
 // ---------------------------------------------------------------------------------------------- X = V Rinv
 template <typename TV, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restrict__ V, size_t ldv, int pad_ny,
+__global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restrict__ V, size_t ldv,
                                                  const double* __restrict__ Rinv, double* __restrict__ X) {
     __shared__ double sR[RMAX * RMAX];
     for (int o = threadIdx.x; o < r * r; o += kBlock) sR[(o / r) * RMAX + o % r] = Rinv[o];
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double v[RMAX];
-    const size_t ve = pad_ny ? padded_cell(e, pad_ny) : (size_t)e;
+    const size_t ve = (size_t)e;
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
         const double x = (double)V[(size_t)(j < r ? j : r - 1) * ldv + ve];
@@ -167,19 +167,19 @@ void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, doub
 }
 
 template <typename TV>
-void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, int pad_ny, const double* Rinv, double* X) {
+void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X) {
     dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
     if (r <= 8)
-        hipLaunchKernelGGL((k_trmm<TV, 8>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 8>), g, b, 0, s, n, r, V, ldv, Rinv, X);
     else if (r <= 16)
-        hipLaunchKernelGGL((k_trmm<TV, 16>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 16>), g, b, 0, s, n, r, V, ldv, Rinv, X);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_trmm<TV, 32>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 32>), g, b, 0, s, n, r, V, ldv, Rinv, X);
     else
-        hipLaunchKernelGGL((k_trmm<TV, 64>), g, b, 0, s, n, r, V, ldv, pad_ny, Rinv, X);
+        hipLaunchKernelGGL((k_trmm<TV, 64>), g, b, 0, s, n, r, V, ldv, Rinv, X);
 }
-template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, int, const double*, double*);
-template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, int, const double*, double*);
+template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, const double*, double*);
+template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, const double*, double*);
 
 __global__ __launch_bounds__(kBlock) void k_small_matmul(int r, const double* __restrict__ A,
                                                          const double* __restrict__ B, double* __restrict__ C) {
