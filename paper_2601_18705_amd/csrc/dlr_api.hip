@@ -626,6 +626,12 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->ld = ((size_t)I->N + 63) / 64 * 64;   // compact column-major cell planes (e = i * ny + j)
     I->ldg = dlr::diag_plane(I->nx, I->ny);
     I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
+    // chunk loop of the Gram kernel: four blocks per CU keep enough loads in flight (measured
+    // against two), but no more blocks than there are 64-cell chunks; the projection kernel's
+    // larger LDS footprint does better with two per CU
+    const int chunks = (int)std::min<long>(((long)I->N + 63) / 64, 1 << 20);
+    I->nb_gram = std::max(1, std::min(chunks, 1024));
+    I->nb_proj = std::max(1, std::min(chunks, 512));
     const size_t rr = (size_t)I->r * I->r;
     I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
                                   (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});

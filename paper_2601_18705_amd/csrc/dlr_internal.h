@@ -163,7 +163,6 @@ void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, doub
                  int* status, int status_code);
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X);
-
 // Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use
 // FP64 MFMA operands (operand_bits 64), FP32 operands (32) or BF16 operands (16), the last two with
 // FP32 accumulation per block; the vector sums and the sum over blocks are FP64.

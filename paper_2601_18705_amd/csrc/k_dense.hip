@@ -442,6 +442,99 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_solve(LstepArgs a) {
     if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
 }
 
+// Ranks up to 32: one wavefront per ordinate, lane c holding column c of [B_q | I] (2 RT <= 64
+// columns, rows in registers, padded to RT with the identity).  B_q = |mu| A_x + |eta| A_y + M_t is
+// the Galerkin projection, on the orthonormal basis X, of the upwind transport operator plus
+// sigma_t + 1/(c dt); its symmetric part is positive definite, so Gauss-Jordan elimination needs
+// no row exchanges (a zero or non-finite pivot still flags a singular solve).  Per pivot
+// k, lane k's column goes through a per-wavefront LDS buffer to all lanes.  Afterwards the lanes
+// of the identity part hold B_q^{-1} column by column; y_q = B_q^{-1} Q_q from an LDS copy.
+template <int RT>
+__global__ __launch_bounds__(256) void k_lstep_solve_wave(LstepArgs a) {
+    constexpr int kW = 4;   // wavefronts (ordinates) per block
+    __shared__ double colk[kW][RT];
+    __shared__ double Bs[kW][RT * (RT + 1)];
+    __shared__ double Qs[kW][RT];
+    __shared__ int bad;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = a.r, rr = r * r;
+    const int q = blockIdx.x * kW + wv;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (q < a.nq) {
+        const double mu = a.mu[q], eta = a.eta[q];
+        const double* Ax = a.ops + (mu > 0.0 ? 0 : 1) * rr;
+        const double* Ay = a.ops + (eta > 0.0 ? 2 : 3) * rr;
+        const double* Mt = a.ops + 4 * rr;
+        const double* G = a.ops + 6 * rr;
+        const double* qX = a.ops + 7 * rr;
+        const double* bv = qX + r;
+        const int sx = mu > 0.0 ? 0 : 1, sy = eta > 0.0 ? 2 : 3;
+        const double amu = fabs(mu), aeta = fabs(eta);
+        // column c of [B | I]: c < RT the matrix (identity outside r x r), c >= RT the identity
+        const bool matcol = lane < RT;
+        const int c = matcol ? lane : lane - RT;
+        const int cc = c < r ? c : r - 1;
+        double acol[RT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int ic = i < r ? i : r - 1;
+            const double v = amu * Ax[ic * r + cc] + aeta * Ay[ic * r + cc] + Mt[ic * r + cc];
+            acol[i] = (matcol && i < r && c < r) ? v : ((i == c) ? 1.0 : 0.0);
+        }
+        // right-hand side Q_q (lane i < r): qX + (old solution on the new basis) / (c dt) + inflow
+        if (lane < r) {
+            double lt = 0.0;   // sum_j W0_j(q) G[j][i]
+#pragma unroll 8
+            for (int j = 0; j < r; ++j) lt += a.W0[(size_t)j * a.nq + q] * G[j * r + lane];
+            Qs[wv][lane] = qX[lane] + lt * a.inv_cdt + amu * a.psib[sx] * bv[sx * r + lane] +
+                           aeta * a.psib[sy] * bv[sy * r + lane];
+        }
+        bool sing = false;
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            if (lane == k) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i) colk[wv][i] = acol[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double piv = colk[wv][k];
+            if (!(fabs(piv) > 0.0) || !isfinite(piv)) sing = true;
+            const double akk = acol[k] / piv;   // row k of the normalised pivot row
+            acol[k] = akk;
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                if (i != k) acol[i] -= colk[wv][i] * akk;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (sing && lane == 0) bad = 1;
+        // B_q^{-1}: lane RT + j holds column j
+        if (!matcol && c < r) {
+            double* Bi = a.Binv + (size_t)q * rr;
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                if (i < r) {
+                    Bi[i * r + c] = acol[i];
+                    Bs[wv][i * (RT + 1) + c] = acol[i];
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < r) {
+            double y = 0.0;
+            for (int j = 0; j < r; ++j) y += Bs[wv][lane * (RT + 1) + j] * Qs[wv][j];
+            a.y[(size_t)q * r + lane] = y;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
+}
+
 // partial sums over a contiguous range of ordinates of w_q B_q^{-1} and w_q y_q
 __global__ __launch_bounds__(kLsThreads) void k_lstep_reduce(LstepArgs a) {
     const int r = a.r, rr = r * r, tot = rr + r;
@@ -716,9 +809,19 @@ void launch_lstep(hipStream_t s, const LstepArgs& a) {
     const int r = a.r;
     const size_t solve_lds = ((size_t)r * (2 * r + 1) + (size_t)r * r) * sizeof(double);
     const size_t schur_lds = (size_t)r * (r + 1) * sizeof(double);
-    if (solve_lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)k_lstep_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds);
-    hipLaunchKernelGGL(k_lstep_solve, dim3(a.nq), dim3(kLsThreads), solve_lds, s, a);
+    const unsigned wave_blocks = (unsigned)((a.nq + 3) / 4);
+    if (r <= 8) {
+        hipLaunchKernelGGL((k_lstep_solve_wave<8>), dim3(wave_blocks), dim3(256), 0, s, a);
+    } else if (r <= 16) {
+        hipLaunchKernelGGL((k_lstep_solve_wave<16>), dim3(wave_blocks), dim3(256), 0, s, a);
+    } else if (r <= 32) {
+        hipLaunchKernelGGL((k_lstep_solve_wave<32>), dim3(wave_blocks), dim3(256), 0, s, a);
+    } else {
+        if (solve_lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_lstep_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)solve_lds);
+        hipLaunchKernelGGL(k_lstep_solve, dim3(a.nq), dim3(kLsThreads), solve_lds, s, a);
+    }
     hipLaunchKernelGGL(k_lstep_reduce, dim3(a.red_blocks), dim3(kLsThreads), 0, s, a);
     hipLaunchKernelGGL(k_lstep_schur, dim3(1), dim3(kLsThreads), schur_lds, s, a);
     const long tot = (long)a.nq * r;
