@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_linearize(TileGrid g, const double* 
 // written in direction d's diagonal layout.  Also the source-iteration start
 // phi = X0 S0 beta and s_e = sigma_s phi / (4 pi) (four orientation copies).
 template <typename TS, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double* __restrict__ X,
+__global__ __launch_bounds__(kBlock) void k_psi0_wide(TileGrid g, int r, const double* __restrict__ X,
                                                  const double* __restrict__ C0, const double* __restrict__ a0,
                                                  const double* __restrict__ q, const double* __restrict__ sig_s,
                                                  double inv_cdt, const double* __restrict__ mu,
@@ -165,6 +165,71 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
                     const double xk = X[(size_t)k * n + e];
 #pragma unroll
                     for (int d = 0; d < kPass; ++d) acc[d] += xk * C0[k * r + (d0 + d < r ? d0 + d : r - 1)];
+                }
+#pragma unroll
+                for (int d = 0; d < kPass; ++d) {
+                    if (d0 + d >= r) break;
+                    const int o = orient_of(mu[d0 + d], eta[d0 + d]);
+                    const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
+                    src0[(size_t)(d0 + d) * ldg + pd] = (TS)(qe + acc[d] * inv_cdt);
+                }
+            }
+        }
+    }
+}
+
+// Ranks up to 32: the r values X_k(e) of a cell are loaded together (all in flight) into the
+// thread's own LDS column, from which every pass of 16 directions (the first also forming the
+// scalar flux) reads them in a loop over k, a row of C0 per k by scalar loads.  X is read from
+// memory once.
+template <typename TS, int RMAX>
+__global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double* __restrict__ X,
+                                                 const double* __restrict__ C0, const double* __restrict__ a0,
+                                                 const double* __restrict__ q, const double* __restrict__ sig_s,
+                                                 double inv_cdt, const double* __restrict__ mu,
+                                                 const double* __restrict__ eta, TS* __restrict__ src0, size_t ldg,
+                                                 double* __restrict__ phi, TS* __restrict__ s_e) {
+    static_assert(RMAX <= 32, "64 KiB of LDS for the parked columns");
+    constexpr int kPass = RMAX < 16 ? RMAX : 16;
+    __shared__ double sx[RMAX * kBlock];   // sx[k * kBlock + thread]
+    const long n = (long)g.nx * g.ny;
+    double* mine = sx + threadIdx.x;
+    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+#pragma unroll 1
+        for (int kc = 0; kc < 4; ++kc) {
+            int i, j;
+            if (!g.cell(b, kc, i, j)) continue;
+            const long e = (long)i * g.ny + j;
+            {
+                double v[RMAX];   // all loads first (clamped rows), then the LDS stores
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) v[k] = X[(size_t)(k < r ? k : r - 1) * n + e];
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k)
+                    if (k < r) mine[k * kBlock] = v[k];
+            }
+            size_t pos[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
+            const double qe = q[e];
+            double ph = 0.0;
+#pragma unroll 1
+            for (int d0 = 0; d0 < r; d0 += kPass) {
+                double acc[kPass];
+#pragma unroll
+                for (int d = 0; d < kPass; ++d) acc[d] = 0.0;
+#pragma unroll 1
+                for (int k = 0; k < r; ++k) {
+                    const double xk = mine[k * kBlock];
+                    if (d0 == 0) ph += xk * a0[k];
+#pragma unroll
+                    for (int d = 0; d < kPass; ++d) acc[d] += xk * C0[k * r + (d0 + d < r ? d0 + d : r - 1)];
+                }
+                if (d0 == 0) {
+                    phi[e] = ph;
+                    const TS se = (TS)(sig_s[e] * ph / kFourPi);
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
                 }
 #pragma unroll
                 for (int d = 0; d < kPass; ++d) {
@@ -476,7 +541,8 @@ void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const do
     else if (r <= 32)
         hipLaunchKernelGGL((k_psi0<TS, 32>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
     else
-        hipLaunchKernelGGL((k_psi0<TS, 64>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
+        hipLaunchKernelGGL((k_psi0_wide<TS, 64>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg,
+                           phi, s_e);
 }
 template void launch_psi0<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
                                   const double*, const double*, double, const double*, const double*, double*, size_t,
