@@ -210,6 +210,54 @@ dlr_status dlr_batch_usage(dlr_batch b, int32_t *active_slots, size_t *bytes_in_
 /* Release every slot and free the batch.  NULL-safe. */
 dlr_status dlr_batch_destroy(dlr_batch b);
 
+/* ------------------------------------------------------------------------------------------
+ * Bilinear (Q1) DG sweep: the transport solve of the paper's spatial discretisation
+ * (Sec. 4.4, volume matrices G_j, face matrix F_d with central flux plus half the jump
+ * penalty -- which is the upwind flux --, mass matrices) with the degree-1 tensor element
+ * on each cell, 4 nodal values per cell and direction.  For every direction d and cell K it
+ * solves, cells in upwind order,
+ *   -int_K (Omega_d . grad v) psi + sum_{outflow faces} int (Omega_d . n) psi v + int_K sigma_t psi v
+ *     = int_K s v + sum_{inflow faces} int |Omega_d . n| psi_upwind v      for all bilinear v on K,
+ * psi_upwind being the neighbour's trace, or the inflow data on the domain boundary.
+ *
+ * Layouts (row-major, element type double for DLR_FP64, float for DLR_FP32_SWEEP):
+ *   cell e = j*nx + i, node a = ix + 2*iy at the cell corners (ix = 0 left, 1 right;
+ *   iy = 0 bottom, 1 top);
+ *   sigma_t  [ny*nx]          total opacity per cell (>= 0);
+ *   src      [n_dir][ny*nx][4] nodal values of the source (its bilinear interpolant enters
+ *                             as M s);
+ *   inflow_x [n_dir][ny][2]   row j's x-inflow face (left if mu > 0, else right), nodes iy;
+ *   inflow_y [n_dir][nx][2]   column i's y-inflow face (bottom if eta > 0, else top), nodes ix;
+ *   psi      [n_dir][ny*nx][4] output.
+ * Arrays are device pointers owned by the caller; src and psi must be aligned to 4
+ * elements, inflow arrays to 2.  Each call runs on the stream given at creation. */
+typedef struct dlr_q1_s *dlr_q1;
+
+/* Create a sweep operator for an nx x ny grid of hx x hy cells (nx, ny <= 2^20, nx * ny <=
+ * 2^28) and n_dir directions (host arrays mu, eta; finite, not both zero; copied).  precision: DLR_FP64 or
+ * DLR_FP32_SWEEP (all arithmetic in that type).  Device memory: the direction cosines and one
+ * [n_dir][ceil(nx/128)][ny][2] edge buffer.  Errors: DLR_ERR_ARG, DLR_ERR_OOM, DLR_ERR_HIP. */
+dlr_status dlr_q1_create(int32_t nx, int32_t ny, double hx, double hy, int32_t n_dir, const double *mu,
+                         const double *eta, int32_t precision, void *hip_stream, dlr_q1 *out);
+
+/* Queue one sweep of every direction (asynchronous).  A cell with sigma_t = 0 is fine; the
+ * local systems are nonsingular for any sigma_t >= 0.  Errors: DLR_ERR_ARG (NULL or
+ * misaligned array), DLR_ERR_HIP (launch), DLR_ERR_STATE (poisoned handle). */
+dlr_status dlr_q1_sweep(dlr_q1 h, const void *sigma_t, const void *src, const void *inflow_x,
+                        const void *inflow_y, void *psi);
+
+/* Wait for the queued sweeps and check the device status: a cross-workgroup wait that
+ * exceeded its spin limit returns DLR_ERR_HIP and poisons the handle. */
+dlr_status dlr_q1_sync(dlr_q1 h);
+
+/* Run reps >= 1 sweeps between two events on the handle's stream, synchronise, check the
+ * status as dlr_q1_sync, and return the mean device time of one sweep in milliseconds. */
+dlr_status dlr_q1_time(dlr_q1 h, const void *sigma_t, const void *src, const void *inflow_x,
+                       const void *inflow_y, void *psi, int32_t reps, double *ms_per_sweep);
+
+/* Free the operator (waits for its stream first).  NULL-safe. */
+dlr_status dlr_q1_destroy(dlr_q1 h);
+
 /* Static description of a status code. */
 const char *dlr_status_string(dlr_status s);
 

@@ -1286,4 +1286,195 @@ dlr_status dlr_batch_destroy(dlr_batch B) {
     return DLR_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------------------------
+// Bilinear (Q1) DG sweep operator
+
+}  // extern "C"
+
+struct dlr_q1_s {
+    int nx = 0, ny = 0, nd = 0, precision = 0, nsuper = 0, grid = 0;
+    double hx = 0, hy = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    double* mu = nullptr;
+    double* eta = nullptr;
+    void* edge = nullptr;
+    unsigned long long* progress = nullptr;
+    unsigned* ticket = nullptr;
+    int* status = nullptr;
+    int* h_status = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool poisoned = false;
+    size_t elem() const { return precision == DLR_FP64 ? sizeof(double) : sizeof(float); }
+};
+
+namespace {
+
+void q1_carve(dlr_q1_s* Q) {
+    const size_t nd = (size_t)Q->nd;
+    Q->mu = Q->arena.take<double>(nd);
+    Q->eta = Q->arena.take<double>(nd);
+    Q->progress = Q->arena.take<unsigned long long>(nd * Q->nsuper);
+    Q->ticket = Q->arena.take<unsigned>(2);
+    Q->status = Q->arena.take<int>(1);
+    const size_t ne = nd * Q->nsuper * (size_t)Q->ny * 2;
+    if (Q->precision == DLR_FP64)
+        Q->edge = Q->arena.take<double>(ne);
+    else
+        Q->edge = Q->arena.take<float>(ne);
+}
+
+template <typename TS>
+dlr::Q1Args<TS> q1_args(const dlr_q1_s* Q, const void* sig, const void* src, const void* inx, const void* iny,
+                        void* psi) {
+    dlr::Q1Args<TS> a{};
+    a.nx = Q->nx; a.ny = Q->ny; a.nd = Q->nd; a.nsuper = Q->nsuper;
+    a.total_units = (unsigned)(Q->nsuper * Q->nd);
+    a.grid_blocks = Q->grid;
+    a.hx = Q->hx; a.hy = Q->hy;
+    a.mu = Q->mu; a.eta = Q->eta;
+    a.sig = static_cast<const TS*>(sig);
+    a.src = static_cast<const TS*>(src);
+    a.inx = static_cast<const TS*>(inx);
+    a.iny = static_cast<const TS*>(iny);
+    a.psi = static_cast<TS*>(psi);
+    a.edge = static_cast<TS*>(Q->edge);
+    a.progress = Q->progress;
+    a.ticket = Q->ticket;
+    a.status = Q->status;
+    a.spin_limit = 1u << 20;
+    a.launch_id = dlr::next_sweep_launch_id();
+    return a;
+}
+
+dlr_status q1_launch(dlr_q1_s* Q, const void* sig, const void* src, const void* inx, const void* iny, void* psi) {
+    if (Q->poisoned) return fail(DLR_ERR_STATE, "Q1 sweep handle poisoned by an earlier device error");
+    if (!sig || !src || !inx || !iny || !psi) return fail(DLR_ERR_ARG, "NULL array");
+    const size_t el = Q->elem();
+    auto misaligned = [](const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; };
+    if (misaligned(sig, el) || misaligned(src, 4 * el) || misaligned(psi, 4 * el) || misaligned(inx, 2 * el) ||
+        misaligned(iny, 2 * el))
+        return fail(DLR_ERR_ARG, "misaligned array (src and psi need 4-element, inflow 2-element alignment)");
+    if (Q->precision == DLR_FP64)
+        dlr::launch_q1_sweep<double>(Q->stream, q1_args<double>(Q, sig, src, inx, iny, psi));
+    else
+        dlr::launch_q1_sweep<float>(Q->stream, q1_args<float>(Q, sig, src, inx, iny, psi));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DLR_ERR_HIP, std::string("Q1 sweep launch: ") + hipGetErrorString(e));
+    return DLR_OK;
+}
+
+dlr_status q1_check(dlr_q1_s* Q) {
+    hip_check(hipMemcpyAsync(Q->h_status, Q->status, sizeof(int), hipMemcpyDeviceToHost, Q->stream), "status copy");
+    hip_check(hipStreamSynchronize(Q->stream), "stream sync");
+    if (*Q->h_status == 0) return DLR_OK;
+    Q->poisoned = true;
+    return fail(DLR_ERR_HIP, "Q1 sweep: a hand-off wait exceeded its spin limit");
+}
+
+}  // namespace
+
+extern "C" {
+
+dlr_status dlr_q1_create(int32_t nx, int32_t ny, double hx, double hy, int32_t n_dir, const double* mu,
+                         const double* eta, int32_t precision, void* hip_stream, dlr_q1* out) {
+    if (!out) return fail(DLR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    g_last_error.clear();
+    if (nx < 1 || ny < 1 || nx > (1 << 20) || ny > (1 << 20) || (int64_t)nx * ny > (int64_t(1) << 28))
+        return fail(DLR_ERR_ARG, "need 1 <= nx, ny <= 2^20 and nx * ny <= 2^28");
+    if (!(hx > 0.0) || !(hy > 0.0) || !std::isfinite(hx) || !std::isfinite(hy))
+        return fail(DLR_ERR_ARG, "cell sizes must be positive and finite");
+    if (n_dir < 1 || !mu || !eta) return fail(DLR_ERR_ARG, "need n_dir >= 1 and direction arrays");
+    for (int d = 0; d < n_dir; ++d)
+        if (!std::isfinite(mu[d]) || !std::isfinite(eta[d]) || (mu[d] == 0.0 && eta[d] == 0.0))
+            return fail(DLR_ERR_ARG, "direction cosines must be finite and not both zero");
+    if (precision != DLR_FP64 && precision != DLR_FP32_SWEEP)
+        return fail(DLR_ERR_ARG, "precision must be DLR_FP64 or DLR_FP32_SWEEP");
+    dlr_q1_s* Q = new (std::nothrow) dlr_q1_s;
+    if (!Q) return fail(DLR_ERR_OOM, "host allocation");
+    Q->nx = nx; Q->ny = ny; Q->nd = n_dir; Q->precision = precision;
+    Q->hx = hx; Q->hy = hy;
+    Q->nsuper = (nx + 64 * dlr::kQ1Waves - 1) / (64 * dlr::kQ1Waves);
+    Q->grid = std::min(Q->nsuper * n_dir, 2048);
+    Q->stream = static_cast<hipStream_t>(hip_stream);
+    try {
+        q1_carve(Q);   // sizing pass
+        const size_t need = Q->arena.used;
+        Q->arena.used = 0;
+        hipError_t e = hipMalloc(&Q->arena.base, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            Q->arena.base = nullptr;
+            dlr_q1_destroy(Q);
+            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        Q->arena.cap = need;
+        q1_carve(Q);
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&Q->h_status), sizeof(int)), "host status");
+        for (auto& ev : Q->ev) hip_check(hipEventCreate(&ev), "event");
+        hip_check(hipMemsetAsync(Q->arena.base, 0, need, Q->stream), "clear");
+        hip_check(hipMemcpyAsync(Q->mu, mu, n_dir * sizeof(double), hipMemcpyHostToDevice, Q->stream), "mu");
+        hip_check(hipMemcpyAsync(Q->eta, eta, n_dir * sizeof(double), hipMemcpyHostToDevice, Q->stream), "eta");
+        hip_check(hipStreamSynchronize(Q->stream), "stream sync");
+    } catch (const HipError& ex) {
+        dlr_q1_destroy(Q);
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    *out = Q;
+    return DLR_OK;
+}
+
+dlr_status dlr_q1_sweep(dlr_q1 Q, const void* sigma_t, const void* src, const void* inflow_x, const void* inflow_y,
+                        void* psi) {
+    if (!Q) return fail(DLR_ERR_ARG, "NULL handle");
+    return q1_launch(Q, sigma_t, src, inflow_x, inflow_y, psi);
+}
+
+dlr_status dlr_q1_sync(dlr_q1 Q) {
+    if (!Q) return fail(DLR_ERR_ARG, "NULL handle");
+    if (Q->poisoned) return fail(DLR_ERR_STATE, "Q1 sweep handle poisoned by an earlier device error");
+    try {
+        return q1_check(Q);
+    } catch (const HipError& ex) {
+        Q->poisoned = true;
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+}
+
+dlr_status dlr_q1_time(dlr_q1 Q, const void* sigma_t, const void* src, const void* inflow_x, const void* inflow_y,
+                       void* psi, int32_t reps, double* ms_per_sweep) {
+    if (!Q) return fail(DLR_ERR_ARG, "NULL handle");
+    if (reps < 1 || !ms_per_sweep) return fail(DLR_ERR_ARG, "need reps >= 1 and an output");
+    try {
+        hip_check(hipEventRecord(Q->ev[0], Q->stream), "event");
+        for (int k = 0; k < reps; ++k) {
+            const dlr_status st = q1_launch(Q, sigma_t, src, inflow_x, inflow_y, psi);
+            if (st != DLR_OK) return st;
+        }
+        hip_check(hipEventRecord(Q->ev[1], Q->stream), "event");
+        const dlr_status st = q1_check(Q);
+        if (st != DLR_OK) return st;
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, Q->ev[0], Q->ev[1]), "elapsed");
+        *ms_per_sweep = (double)ms / reps;
+    } catch (const HipError& ex) {
+        Q->poisoned = true;
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    return DLR_OK;
+}
+
+dlr_status dlr_q1_destroy(dlr_q1 Q) {
+    if (!Q) return DLR_OK;
+    if (Q->arena.base) (void)hipStreamSynchronize(Q->stream);
+    for (auto& ev : Q->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (Q->h_status) (void)hipHostFree(Q->h_status);
+    if (Q->arena.base) (void)hipFree(Q->arena.base);
+    delete Q;
+    return DLR_OK;
+}
+
 }  // extern "C"

@@ -148,6 +148,33 @@ void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& 
 // next process-wide sweep launch id
 unsigned long long next_sweep_launch_id();
 
+// ----------------------------------------------------------------------------- bilinear DG sweep
+// Upwind sweep of the bilinear (Q1) DG discretisation (Sec. 4.4) for nd directions, natural
+// layouts: cell e = j*nx + i, local node a = ix + 2*iy (ix, iy = 0 on the left / bottom side).
+constexpr int kQ1Waves = 2;        // compute wavefronts (64-column strips) per Q1 workgroup
+template <typename TS>
+struct Q1Args {
+    int nx, ny, nd, nsuper;        // nsuper = superstrips of kQ1Waves x 64 columns
+    unsigned total_units;          // nsuper * nd
+    int grid_blocks;
+    double hx, hy;
+    const double* mu;              // [nd] direction cosines
+    const double* eta;             // [nd]
+    const TS* sig;                 // [ny*nx] sigma_t
+    const TS* src;                 // [nd][ny*nx][4] nodal source
+    const TS* inx;                 // [nd][ny][2] inflow on each row's x-inflow face, nodes iy = 0, 1
+    const TS* iny;                 // [nd][nx][2] inflow on each column's y-inflow face, nodes ix = 0, 1
+    TS* psi;                       // [nd][ny*nx][4]
+    TS* edge;                      // [nd][nsuper][ny][2] outgoing x-face values, sweep row order
+    unsigned long long* progress;  // [nd][nsuper] (launch << 32) | rows published
+    unsigned* ticket;              // [2] unit ticket, retired workgroups (zero between launches)
+    int* status;                   // kStatusSweepStall if a wait exceeds spin_limit polls
+    unsigned spin_limit;
+    unsigned long long launch_id;
+};
+template <typename TS>
+void launch_q1_sweep(hipStream_t s, const Q1Args<TS>& a);
+
 // ----------------------------------------------------------------------------- reductions
 // V planes are compact [r][ldv] (cell e at V[k * ldv + e]).
 // G = scale * V^T diag(weight) V (r x r, row-major; weight nullable = 1), via per-block partials in

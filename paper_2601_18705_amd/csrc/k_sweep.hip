@@ -28,6 +28,7 @@
 // (superstrip, direction) order, so a workgroup only waits on a unit with a
 // smaller ticket, which is already running.
 #include "dlr_internal.h"
+#include "wave_ops.h"
 
 #include <atomic>
 
@@ -72,18 +73,6 @@ __device__ __forceinline__ void store_chunk(TS* p, const TS (&v)[kC]) {
     }
 }
 
-// lane l receives lane l-1's value; lane 0 receives `first`
-__device__ __forceinline__ float shift_in(float first, float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, first),
-                                                                  __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double shift_in(double first, double v) {
-    const long long f = __builtin_bit_cast(long long, first), x = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(x & 0xffffffffll), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(x >> 32), 0x138, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
 __device__ __forceinline__ float step_value(float rhs, float sig, float axy, float ax, float ay, float left, float up) {
     const float num = fmaf(ax, left, fmaf(ay, up, rhs));
     return num * __builtin_amdgcn_rcpf(sig + axy);
@@ -102,22 +91,6 @@ struct Shared {
     int stall;
     unsigned task;
 };
-
-// Progress words of the LDS rings.  The LDS unit executes a wavefront's LDS instructions in
-// issue order, so a ring write followed by a progress store is seen in that order by any
-// wavefront that reads the progress word first and the ring afterwards; compiler barriers keep
-// the compiler from reordering them.  Relaxed atomics are used on purpose: a release or acquire
-// at workgroup scope would also wait for this wavefront's outstanding global loads (the
-// prefetched chunks), which is what the rings must not do.
-__device__ __forceinline__ int lds_load(int* p) {
-    const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    return v;
-}
-__device__ __forceinline__ void lds_store(int* p, int v) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 // Per-wavefront constant data of one strip.
 template <typename TS>
@@ -281,13 +254,8 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
 // L2-wide writeback / invalidate of a release or acquire at agent scope (both would also stall
 // every other wavefront sharing that L2).  The writer waits for its edge stores to complete
 // before it stores the progress word; the reader loads the edge values only after it has seen
-// that word.
-__device__ __forceinline__ void wait_vm_stores() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
+// that word (wait_vm_stores).
+//
 // Helper wavefront: incoming edge (global -> ring[0]) and outgoing edge (ring[kWaves] -> global).
 template <typename TS>
 __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned long long launch_id, Shared<TS>& sh, int S,

@@ -23,7 +23,8 @@ DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 EXPORTED = ["dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
             "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
-            "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_status_string", "dlr_last_error"]
+            "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
+            "dlr_q1_time", "dlr_q1_destroy", "dlr_status_string", "dlr_last_error"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -64,6 +65,13 @@ def library():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(the HIP library is the only implementation)")
+        # PyTorch ships its own HIP and HSA runtimes under the same sonames as the system
+        # ones.  Loaded first, they satisfy the library's dependencies, so the process holds
+        # one runtime; loaded after the library, they would be a second copy that finds no GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         h = ctypes.c_void_p
         lib.dlr_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
@@ -88,6 +96,13 @@ def library():
         lib.dlr_batch_release.argtypes = [h, i64]
         lib.dlr_batch_usage.argtypes = [h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)]
         lib.dlr_batch_destroy.argtypes = [h]
+        vp = ctypes.c_void_p
+        lib.dlr_q1_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                      _dp, _dp, ctypes.c_int32, vp, ctypes.POINTER(h)]
+        lib.dlr_q1_sweep.argtypes = [h, vp, vp, vp, vp, vp]
+        lib.dlr_q1_sync.argtypes = [h]
+        lib.dlr_q1_time.argtypes = [h, vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        lib.dlr_q1_destroy.argtypes = [h]
         lib.dlr_status_string.argtypes = [ctypes.c_int]
         lib.dlr_status_string.restype = ctypes.c_char_p
         lib.dlr_last_error.argtypes = []
@@ -96,7 +111,8 @@ def library():
                      "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
-                     "dlr_batch_usage", "dlr_batch_destroy"):
+                     "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
+                     "dlr_q1_time", "dlr_q1_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -287,6 +303,70 @@ class Instance:
     def close(self):
         if self._h:
             library().dlr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Q1Sweep:
+    """Bilinear (Q1) upwind DG sweep operator (dlr_q1_create ... dlr_q1_destroy).
+
+    Arrays are device tensors (torch, on the GPU, contiguous) of the operator's
+    precision: sigma_t [ny*nx], src [nd, ny*nx, 4], inflow_x [nd, ny, 2],
+    inflow_y [nd, nx, 2], psi [nd, ny*nx, 4]; cell e = j*nx + i, node
+    a = ix + 2*iy.  Every call runs on `stream` (a hipStream_t handle, None =
+    the null stream)."""
+
+    def __init__(self, nx, ny, hx, hy, mu, eta, precision=DLR_FP64, stream=None):
+        lib = library()
+        self.nx, self.ny = int(nx), int(ny)
+        mu_a = _f64(mu)
+        self.nd = mu_a.size
+        eta_a = _f64(eta, self.nd)
+        self.precision = int(precision)
+        self._h = ctypes.c_void_p()
+        _check(lib.dlr_q1_create(self.nx, self.ny, float(hx), float(hy), self.nd, _ptr(mu_a), _ptr(eta_a),
+                                 self.precision, ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))
+
+    def _ptrs(self, sigma_t, src, inflow_x, inflow_y, psi):
+        import torch
+        dt = torch.float64 if self.precision == DLR_FP64 else torch.float32
+        n = self.nx * self.ny
+        want = ((sigma_t, n), (src, self.nd * n * 4), (inflow_x, self.nd * self.ny * 2),
+                (inflow_y, self.nd * self.nx * 2), (psi, self.nd * n * 4))
+        out = []
+        for t, size in want:
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()
+                    and t.numel() == size):
+                raise ValueError(f"expected a contiguous {dt} GPU tensor of {size} elements")
+            out.append(ctypes.c_void_p(t.data_ptr()))
+        return out
+
+    def sweep(self, sigma_t, src, inflow_x, inflow_y, psi):
+        _check(library().dlr_q1_sweep(self._h, *self._ptrs(sigma_t, src, inflow_x, inflow_y, psi)))
+
+    def sync(self):
+        _check(library().dlr_q1_sync(self._h))
+
+    def time(self, sigma_t, src, inflow_x, inflow_y, psi, reps):
+        ms = ctypes.c_double()
+        _check(library().dlr_q1_time(self._h, *self._ptrs(sigma_t, src, inflow_x, inflow_y, psi), int(reps),
+                                     ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if self._h:
+            library().dlr_q1_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __enter__(self):

@@ -165,3 +165,33 @@ WORKLOADS = {
     "checkerboard": checkerboard,
     "random_medium": random_medium,
 }
+
+
+def q1_sweep_inputs(nx, ny, n_dir, seed, extent=(0.0, 1.0, 0.0, 1.0), sigma_shift=0.0, zero_cells=0.0,
+                    dtype=np.float64):
+    """Inputs of one bilinear (Q1) DG sweep over n_dir directions.
+
+    Directions: x and y cosines of points drawn uniformly on the unit sphere.
+    sigma_t: the log-normal random-medium opacity (s = 1.5, 16-cell correlation,
+    cropped from a square field of at least 32 x 32 cells) plus sigma_shift (1 / (c dt) of a time step),
+    with a fraction zero_cells of the cells set to exactly zero.  Nodal sources
+    [n_dir, ny*nx, 4] and inflow data ([n_dir, ny, 2] on the x-inflow faces,
+    [n_dir, nx, 2] on the y-inflow faces) uniform in [0, 1).  Cells e = j*nx + i,
+    nodes a = ix + 2*iy."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(-1.0, 1.0, n_dir)
+    az = rng.uniform(0.0, 2.0 * np.pi, n_dir)
+    st = np.sqrt(1.0 - z * z)
+    n = max(nx, ny, 32)
+    sig = lognormal_sigma(n, seed + 1).reshape(n, n)[:ny, :nx].ravel() + sigma_shift
+    if zero_cells > 0.0:
+        sig[rng.uniform(0.0, 1.0, sig.size) < zero_cells] = 0.0
+    return dict(
+        nx=int(nx), ny=int(ny),
+        hx=(extent[1] - extent[0]) / nx, hy=(extent[3] - extent[2]) / ny,
+        mu=st * np.cos(az), eta=st * np.sin(az),
+        sigma_t=sig.astype(dtype),
+        src=rng.uniform(0.0, 1.0, (n_dir, nx * ny, 4)).astype(dtype),
+        inflow_x=rng.uniform(0.0, 1.0, (n_dir, ny, 2)).astype(dtype),
+        inflow_y=rng.uniform(0.0, 1.0, (n_dir, nx, 2)).astype(dtype),
+    )

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "dlrtrt.h")).read()
-    return sorted(set(re.findall(r"\b(dlr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(dlr_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_and_binding_agree():
@@ -62,6 +62,22 @@ def test_sn_create_rejects_invalid_problems(kw, status):
     with pytest.raises(dlrtrt.DlrError) as ei:
         dlrtrt.Instance(p, method="sn")
     assert ei.value.status == status
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, 0.1, 0.1, [0.5], [0.5], 0), (4, 0, 0.1, 0.1, [0.5], [0.5], 0),
+    (1 << 15, 1 << 14, 0.1, 0.1, [0.5], [0.5], 0),                          # more than 2^28 cells
+    ((1 << 20) + 1, 1, 0.1, 0.1, [0.5], [0.5], 0),                          # a side above 2^20
+    (4, 4, 0.0, 0.1, [0.5], [0.5], 0), (4, 4, 0.1, float("inf"), [0.5], [0.5], 0),
+    (4, 4, 0.1, 0.1, [0.0], [0.0], 0), (4, 4, 0.1, 0.1, [float("nan")], [0.5], 0),
+    (4, 4, 0.1, 0.1, [0.5], [0.5], 2), (4, 4, 0.1, 0.1, [0.5], [0.5], 7),
+])
+def test_q1_create_rejects_invalid_arguments(args):
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    with pytest.raises(dlrtrt.DlrError) as ei:
+        dlrtrt.Q1Sweep(*args)
+    assert ei.value.status == -1
 
 
 def test_create_rejects_nonpositive_fields():
