@@ -28,20 +28,20 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "cell-angle sweep updates/s + DLR steps/s at 1024², r=32; p50/p99 solve latency"
 
 
-def sweep_source_hash():
-    with open(os.path.join(ROOT, "paper_2601_18705_amd", "csrc", "k_sweep.hip"), "rb") as f:
+def source_hash(name):
+    with open(os.path.join(ROOT, "paper_2601_18705_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload, bytes_per_launch):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    when it was taken on the current sweep kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sweep_counters_" + workload + ".json")
+def load_traffic(record, source="k_sweep.hip"):
+    """HBM bytes per launch from a committed rocprofv3 counter record (profiles/<record>.json),
+    when it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", record + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("sweep_source_sha") != sweep_source_hash():
+    if rec.get("sweep_source_sha") != source_hash(source):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -134,6 +134,41 @@ def sn_leg(workload, precision, si_tol, steps, dlr_steps_per_s):
             "dlr_speedup_steps_per_s": dlr_steps_per_s / (steps / wall)}
 
 
+def q1_leg(n, nd, reps):
+    """The bilinear (Q1) DG sweep operator on its own: n x n cells, nd directions, sigma_t of
+    the random medium plus 1/(c dt), FP32 and FP64, inputs resident in HBM."""
+    import numpy as np
+    import torch
+    from paper_2601_18705_amd import dlrtrt
+    from synth import problems
+    out = {"grid": f"{n}x{n}", "directions": nd,
+           "bytes_model": "per cell-direction: 4 source + 4 psi values; sigma_t once per cell"}
+    for name, prec, npdt in (("fp32", dlrtrt.DLR_FP32_SWEEP, np.float32), ("fp64", dlrtrt.DLR_FP64, np.float64)):
+        inp = problems.q1_sweep_inputs(n, n, nd, seed=3, sigma_shift=500.0, dtype=npdt)
+        dev = torch.device("cuda:0")
+        t = {k: torch.from_numpy(inp[k]).to(dev) for k in ("sigma_t", "src", "inflow_x", "inflow_y")}
+        psi = torch.empty_like(t["src"])
+        with dlrtrt.Q1Sweep(n, n, inp["hx"], inp["hy"], inp["mu"], inp["eta"], prec) as op:
+            op.time(t["sigma_t"], t["src"], t["inflow_x"], t["inflow_y"], psi, 2)
+            ms = op.time(t["sigma_t"], t["src"], t["inflow_x"], t["inflow_y"], psi, reps)
+        sb = np.dtype(npdt).itemsize
+        byts = nd * n * n * 8 * sb + n * n * sb
+        out[name] = {"ms_per_sweep": ms, "cell_direction_updates_per_s": nd * n * n / (ms * 1e-3),
+                     "algorithmic_bytes": byts, "achieved_GBs": byts / (ms * 1e-3) / 1e9,
+                     "frac_hbm_peak": byts / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                     "traffic": load_traffic(f"q1_counters_{n}x{n}_nd{nd}_{name}", "k_q1.hip")}
+        del t, psi
+    # the FP64 oracle on a bounded sample (one direction on 48 x 48 cells)
+    from oracle import q1_oracle
+    smp = problems.q1_sweep_inputs(48, 48, 1, seed=3, sigma_shift=500.0)
+    t0 = time.perf_counter()
+    q1_oracle.sweep(48, 48, smp["hx"], smp["hy"], smp["mu"], smp["eta"], smp["sigma_t"], smp["src"],
+                    smp["inflow_x"], smp["inflow_y"])
+    out["cpu_oracle"] = {"cell_direction_updates_per_s": 48 * 48 / (time.perf_counter() - t0), "cores": 1,
+                         "sample": "one direction on 48 x 48 cells (pure-Python cell loop, numpy 4x4 solves)"}
+    return out
+
+
 def batch_run(count, steps):
     """The batched-instances workload: count independent problems admitted at once and
     advanced together for `steps` steps (FP32 sweeps, FP64 energy update)."""
@@ -174,6 +209,8 @@ def main():
                     help="steps of the FP64-sweep comparison leg at the same SI tolerance (0 = skip)")
     ap.add_argument("--sn-steps", type=int, default=3,
                     help="steps of the plain SN comparison leg over every ordinate (0 = skip)")
+    ap.add_argument("--q1-reps", type=int, default=20,
+                    help="timed launches of the bilinear DG sweep leg, 1024^2 cells x 32 directions (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving leg (0 = skip); p50/p99 time-to-solution")
     ap.add_argument("--serve-max-s", type=float, default=60.0, help="wall-time cap of the serving leg")
@@ -238,7 +275,7 @@ def main():
     bytes_per_launch = N * r * 2 * sweep_bytes + N * 2 * sweep_bytes   # src0 read, psi write; sigma_t, s_e read
     avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic(p["name"] + ("_fp64" if args.fp64 else "_fp32"), bytes_per_launch)
+    traffic = load_traffic("sweep_counters_" + p["name"] + ("_fp64" if args.fp64 else "_fp32"))
 
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 4
@@ -295,6 +332,9 @@ def main():
         print("[bench] plain SN leg", file=sys.stderr, flush=True)
         out["plain_sn_leg"] = sn_leg(args.workload, p["precision"], p["si_tol"], args.sn_steps,
                                      args.steps / wall)
+    if args.q1_reps > 0:
+        print("[bench] bilinear DG sweep leg", file=sys.stderr, flush=True)
+        out["q1_sweep_leg"] = q1_leg(1024, 32, args.q1_reps)
     if args.serve_requests > 0:
         print(f"[bench] serving leg: {args.serve_requests} requests", file=sys.stderr, flush=True)
         sv = serving_leg(args.serve_requests, args.serve_max_s, args.serve_budget_gib)

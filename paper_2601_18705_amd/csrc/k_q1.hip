@@ -8,7 +8,7 @@
 // on the y-inflow face) the element matrices are tensor products of the 1D ones, and
 // after multiplying by the inverse 1D mass matrices the system becomes a Kronecker sum,
 //   (m (K (x) I) + e (I (x) K) + s I) psi = f,   K = [[3, 1], [-3, 1]],
-// with m = |mu| hy, e = |eta| hx, s = sigma_t hx hy scaled by 1 / (m + e), and
+// with m = |mu| hy, e = |eta| hx, s = sigma_t hx hy (all scaled by a common factor), and
 //   f = hx hy s_nodal + m [4, -2] (x) g_x + e g_y (x) [4, -2]
 // for the inflow traces g_x (two nodes of the x-inflow face) and g_y.  Eliminating the
 // ix' = 0 block leaves a 2 x 2 system alpha K + beta I for the outflow column; K
@@ -33,7 +33,7 @@
 // loading each lane's cell directly would cost one cache-line lookup per lane; instead the
 // cells of a chunk of kC steps (a diagonal band) move between HBM and LDS in runs of
 // consecutive cells of a row, and each step reads and writes its cell in LDS.  Band loads
-// run one (FP64) or two (FP32) chunks ahead in registers; cells outside the grid are read
+// run two chunks ahead in registers; cells outside the grid are read
 // at clamped addresses and never stored.
 #include "dlr_internal.h"
 #include "wave_ops.h"
@@ -44,10 +44,7 @@ namespace {
 
 constexpr int kW = kQ1Waves;   // compute wavefronts per workgroup
 constexpr int kC = 8;          // steps per chunk
-// chunks of band loads in flight per wavefront: two in FP32, one in FP64 (where a second
-// would not fit the register file)
-template <typename TS>
-constexpr int prefetch_depth() { return sizeof(TS) == 4 ? 2 : 1; }
+constexpr int kP = 2;          // chunks of band loads in flight per wavefront
 constexpr int kRing = 256;     // LDS ring length (rows)
 
 template <typename TS, int N>
@@ -78,10 +75,15 @@ struct Q1Shared {
     unsigned task;
 };
 
-// Per-direction constants, in units of m + e (see the header comment).
+// Per-direction constants.  The local system is scaled by 1 / (hx hy) in FP64 (so the
+// source enters unscaled) and by 1 / (|mu| hy + |eta| hx) in FP32, where it keeps the
+// determinants of fine meshes within single-precision range.
+template <typename TS>
+constexpr bool kUnitArea = sizeof(TS) == 8;
+
 template <typename TS>
 struct Dir {
-    TS m, e, H;                  // |mu| hy, |eta| hx, hx hy, each / (|mu| hy + |eta| hx)
+    TS m, e, H;                  // |mu| hy, |eta| hx, hx hy, each times the scale
     TS m4, m2n, e4, e2n;         // 4m, -2m, 4e, -2e: inflow weights of f
     TS m3, e3, e3n, e2;          // 3m, 3e, -3e, 2e
     TS ac, bc, d0c;              // alpha = ac + 2e s, beta = bc + s (4m + s), D0 = d0c + a (4e + a)
@@ -90,7 +92,7 @@ struct Dir {
 template <typename TS>
 __device__ __forceinline__ Dir<TS> make_dir(double mu, double eta, double hx, double hy) {
     const double mp = fabs(mu) * hy, ep = fabs(eta) * hx;
-    const double sc = 1.0 / (mp + ep);
+    const double sc = kUnitArea<TS> ? 1.0 / (hx * hy) : 1.0 / (mp + ep);
     const double m = mp * sc, e = ep * sc;
     Dir<TS> q;
     q.m = (TS)m;
@@ -130,13 +132,23 @@ struct CellCoef {
 
 template <typename TS>
 __device__ __forceinline__ CellCoef<TS> cell_coef(const Dir<TS>& q, TS sig) {
-    const TS s = sig * q.H;
+    const TS s = kUnitArea<TS> ? sig : sig * q.H;
     const TS a = q.m3 + s;
     const TS al = fma(q.e2, s, q.ac);
     const TS be = fma(s, q.m4 + s, q.bc);
     const TS t = al + al + be;
-    const TS r1 = rcp(fma(t, t, (al + al) * al));   // D1 = 2 alpha^2 + (2 alpha + beta)^2
-    const TS r0 = rcp(fma(a, q.e4 + a, q.d0c));     // D0 = 6e^2 + 4ea + a^2
+    const TS d1 = fma(t, t, (al + al) * al);   // D1 = 2 alpha^2 + (2 alpha + beta)^2
+    const TS d0 = fma(a, q.e4 + a, q.d0c);     // D0 = 6e^2 + 4ea + a^2
+    TS r1, r0;
+    if constexpr (kUnitArea<TS>) {
+        // one reciprocal for both: 1/D1 = D0 / (D0 D1), 1/D0 = D1 / (D0 D1)
+        const TS r = rcp(d0 * d1);
+        r1 = d0 * r;
+        r0 = d1 * r;
+    } else {
+        r1 = rcp(d1);
+        r0 = rcp(d0);
+    }
     CellCoef<TS> c;
     c.ga = a + q.e3;
     c.gb = a + q.e;
@@ -297,7 +309,8 @@ __device__ __forceinline__ void q1_compute(const Q1Args<TS>& a, Q1Shared<TS>& sh
             const int t = kC * m + k;
             const CellCoef<TS> c = cell_coef<TS>(q, gs[k]);
             const V4 sv = V4{xs[k][0], xs[k][1], ys[k][0], ys[k][1]};
-            const TS h00 = q.H * sv[A00], h10 = q.H * sv[A10], h01 = q.H * sv[A01], h11 = q.H * sv[A11];
+            const TS h00 = kUnitArea<TS> ? sv[A00] : q.H * sv[A00], h10 = kUnitArea<TS> ? sv[A10] : q.H * sv[A10];
+            const TS h01 = kUnitArea<TS> ? sv[A01] : q.H * sv[A01], h11 = kUnitArea<TS> ? sv[A11] : q.H * sv[A11];
             const TS f00p = fma(q.e4, top0, h00), f10p = fma(q.e4, top1, h10);
             const TS f01p = fma(q.e2n, top0, h01), f11p = fma(q.e2n, top1, h11);
             const TS gx0 = shift_in(ev[k][0], rgt0), gx1 = shift_in(ev[k][1], rgt1);
@@ -334,7 +347,6 @@ __device__ __forceinline__ void q1_compute(const Q1Args<TS>& a, Q1Shared<TS>& sh
 
     // Per chunk: stage its band (loaded two chunks ahead) into LDS, prefetch the band of the
     // chunk after next, run the steps, write psi back by row segments, publish the edge.
-    constexpr int kP = prefetch_depth<TS>();
     V4 bs[kP][kBandOps];
     TS bq[kP][kBandOps];
 #pragma unroll

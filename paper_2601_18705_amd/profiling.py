@@ -6,7 +6,10 @@ records kept with the repository.  Reads CSV files only; runs nothing.
 
     python -m paper_2601_18705_amd.profiling stats <kernel_stats.csv> <title> <command>
     python -m paper_2601_18705_amd.profiling traffic <fetch counter_collection.csv>
-        <write counter_collection.csv> <calibration MiB> <sweep source> <out.json>
+        <write counter_collection.csv> <calibration MiB> <kernel source> <out.json> [kernel name prefix]
+
+The kernel name prefix (default k_sweep, the degree-0 sweep) selects the dispatches
+averaged, e.g. "k_q1_sweep<double>" for the FP64 bilinear DG sweep.
 """
 from __future__ import annotations
 
@@ -53,13 +56,15 @@ def sweep_traffic(fetch_csv, write_csv, calib_mib, sweep_source, sweep_prefix="k
     writes calib_mib MiB, the last 'elementwise' dispatch of the run)."""
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
-    calib = [k for k in fetch if "elementwise" in k]
+    calib = [k for k in fetch if "elementwise" in k and "Mul" in k] or [k for k in fetch if "elementwise" in k]
     if not calib:
         raise SystemExit("no calibration kernel in the FETCH_SIZE run")
     known_kib = calib_mib * 1024.0
     f_scale = known_kib / fetch[calib[-1]][-1]
     w_scale = known_kib / write[calib[-1]][-1] if calib[-1] in write else 1.0
     sk = [k for k in fetch if k.startswith(sweep_prefix)]
+    if not sk:
+        raise SystemExit(f"no dispatch of {sweep_prefix} in the FETCH_SIZE run")
     f = [v for k in sk for v in fetch[k]]
     w = [v for k in sk for v in write.get(k, [])]
     fetch_b = sum(f) / len(f) * 1024.0 * f_scale
@@ -67,14 +72,15 @@ def sweep_traffic(fetch_csv, write_csv, calib_mib, sweep_source, sweep_prefix="k
     sha = hashlib.sha256(open(sweep_source, "rb").read()).hexdigest()[:16]
     return {"sweep_source_sha": sha, "hbm_bytes_per_launch": fetch_b + write_b, "fetch_bytes_per_launch": fetch_b,
             "write_bytes_per_launch": write_b, "fetch_scale": f_scale, "write_scale": w_scale,
-            "sweep_launches": len(f), "calibration_kernel": calib[-1], "calibration_mib": calib_mib}
+            "sweep_launches": len(f), "kernel": sweep_prefix, "calibration_kernel": calib[-1],
+            "calibration_mib": calib_mib}
 
 
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else ""))
-    elif len(argv) == 6 and argv[0] == "traffic":
-        rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4])
+    elif len(argv) in (6, 7) and argv[0] == "traffic":
+        rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4], *argv[6:7])
         with open(argv[5], "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
