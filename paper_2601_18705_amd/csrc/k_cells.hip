@@ -179,9 +179,10 @@ __global__ __launch_bounds__(kBlock) void k_psi0_wide(TileGrid g, int r, const d
 }
 
 // Ranks up to 32: the r values X_k(e) of a cell are loaded together (all in flight) into the
-// thread's own LDS column, from which every pass of 16 directions (the first also forming the
-// scalar flux) reads them in a loop over k, a row of C0 per k by scalar loads.  X is read from
-// memory once.
+// thread's own LDS column; C0 (zero-padded to RMAX x RMAX), a0 and the directions' orientations
+// are staged in LDS once per block.  Each pass of 16 directions (the first also forming the
+// scalar flux) loops over k, reading X_k from the column and the row segment of C0 as LDS
+// broadcasts.  X is read from memory once, src0 written once per direction.
 template <typename TS, int RMAX>
 __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double* __restrict__ X,
                                                  const double* __restrict__ C0, const double* __restrict__ a0,
@@ -192,6 +193,18 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
     static_assert(RMAX <= 32, "64 KiB of LDS for the parked columns");
     constexpr int kPass = RMAX < 16 ? RMAX : 16;
     __shared__ double sx[RMAX * kBlock];   // sx[k * kBlock + thread]
+    __shared__ double sC[RMAX * RMAX];     // sC[k * RMAX + d] = C0[k][d], zero outside r x r
+    __shared__ double sA[RMAX];
+    __shared__ int so[RMAX];
+    for (int o = threadIdx.x; o < RMAX * RMAX; o += kBlock) {
+        const int k = o / RMAX, d = o % RMAX;
+        sC[o] = (k < r && d < r) ? C0[k * r + d] : 0.0;
+    }
+    for (int k = threadIdx.x; k < RMAX; k += kBlock) {
+        sA[k] = k < r ? a0[k] : 0.0;
+        so[k] = k < r ? orient_of(mu[k], eta[k]) : 0;
+    }
+    __syncthreads();
     const long n = (long)g.nx * g.ny;
     double* mine = sx + threadIdx.x;
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
@@ -205,8 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) v[k] = X[(size_t)(k < r ? k : r - 1) * n + e];
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k)
-                    if (k < r) mine[k * kBlock] = v[k];
+                for (int k = 0; k < RMAX; ++k) mine[k * kBlock] = k < r ? v[k] : 0.0;
             }
             size_t pos[4];
 #pragma unroll
@@ -218,12 +230,12 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
                 double acc[kPass];
 #pragma unroll
                 for (int d = 0; d < kPass; ++d) acc[d] = 0.0;
-#pragma unroll 1
-                for (int k = 0; k < r; ++k) {
+#pragma unroll 4
+                for (int k = 0; k < RMAX; ++k) {
                     const double xk = mine[k * kBlock];
-                    if (d0 == 0) ph += xk * a0[k];
+                    if (d0 == 0) ph = fma(xk, sA[k], ph);
 #pragma unroll
-                    for (int d = 0; d < kPass; ++d) acc[d] += xk * C0[k * r + (d0 + d < r ? d0 + d : r - 1)];
+                    for (int d = 0; d < kPass; ++d) acc[d] = fma(xk, sC[k * RMAX + d0 + d], acc[d]);
                 }
                 if (d0 == 0) {
                     phi[e] = ph;
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
 #pragma unroll
                 for (int d = 0; d < kPass; ++d) {
                     if (d0 + d >= r) break;
-                    const int o = orient_of(mu[d0 + d], eta[d0 + d]);
+                    const int o = so[d0 + d];
                     const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
                     src0[(size_t)(d0 + d) * ldg + pd] = (TS)(qe + acc[d] * inv_cdt);
                 }
