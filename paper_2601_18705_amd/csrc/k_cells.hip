@@ -290,6 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const T
 // ---------------------------------------------------------------------------------------------- T update
 // Algorithm 1 step 9 with the mean intensity of the new factors phi = X (S beta):
 //   T = T0 + dt sigma (phi - a c T0^4) / D,  and energy sum area * (rho c_v T + phi / c).
+// RMAX >= r: the r values X_k(e) of a cell are loaded together (clamped rows, all in flight)
+template <int RMAX>
 __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* __restrict__ X,
                                                     const double* __restrict__ coef, const double* __restrict__ sigma,
                                                     const double* __restrict__ rho_cv, const double* __restrict__ D,
@@ -304,10 +306,16 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* 
     bool bad = false;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         double ph = 0.0;
-        if (X)
-            for (int k = 0; k < r; ++k) ph += X[(size_t)k * n + e] * sc[k];
-        else
+        if (X) {
+            double v[RMAX];
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) v[k] = X[(size_t)(k < r ? k : r - 1) * n + e];
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k)
+                if (k < r) ph = fma(v[k], sc[k], ph);
+        } else {
             ph = phi[e];   // plain SN: the converged scalar flux
+        }
         const double t0 = T[e];
         const double emis = a * c * t0 * t0 * t0 * t0;
         const double t = t0 + dt * sigma[e] * (ph - emis) / D[e];
@@ -592,8 +600,19 @@ template void launch_psi_to_cm<float>(hipStream_t, int, int, int, const float*, 
 void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
                     const double* rho_cv, const double* D, double dt, double a, double c, double area, double* T,
                     double* phi, double* partials, int nblocks, unsigned* counter, double* out, int* status) {
-    hipLaunchKernelGGL(k_tupdate, dim3(nblocks), dim3(kBlock), 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area,
-                       T, phi, partials, counter, out, status);
+    const dim3 g(nblocks), b(kBlock);
+    if (r <= 8)
+        hipLaunchKernelGGL(k_tupdate<8>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
+                           counter, out, status);
+    else if (r <= 16)
+        hipLaunchKernelGGL(k_tupdate<16>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
+                           counter, out, status);
+    else if (r <= 32)
+        hipLaunchKernelGGL(k_tupdate<32>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
+                           counter, out, status);
+    else
+        hipLaunchKernelGGL(k_tupdate<64>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
+                           counter, out, status);
 }
 
 }  // namespace dlr

@@ -182,8 +182,6 @@ struct ProjShape {
     static constexpr int NPAIR = RT * RT;
     static constexpr int KS = NPAIR >= 4 ? 1 : 4;                       // k-step split across wavefronts
     static constexpr int PPW = NPAIR >= 4 ? (NPAIR + 3) / 4 : 1;         // tile pairs per wavefront
-    static constexpr int NX = (RP * (kPC + 1) + kThreads - 1) / kThreads;   // staged X values per thread
-    static constexpr int NL = (RP * kPC + kThreads - 1) / kThreads;         // staged X(left) / X0 per thread
 };
 
 template <int RT, typename TO, bool BF16 = false>
@@ -206,7 +204,9 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     __shared__ int sFlag[kPC];           // bit0 left side, bit1 right, bit2 bottom, bit3 top
     __shared__ double red[5][kThreads];
     const long n = (long)nx * ny;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the & 3 tells the compiler the range of the wavefront index, so that the tile-pair guards
+    // below fold away and the MFMA accumulators stay put (no copies around each MFMA)
+    const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & 3;
     Acc acc[PPW][5];
 #pragma unroll
     for (int pp = 0; pp < PPW; ++pp)
@@ -216,59 +216,49 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     double vq = 0.0, vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
     const long nch = (n + kPC - 1) / kPC;
 
-    // register staging of one chunk
-    double gX[Sh::NX], gL[Sh::NL], g0[Sh::NL];
+    // register staging of one chunk: thread t holds cell c0 + (t & 63) of planes (t >> 6) + 4u,
+    // and threads t < RP the cell before the chunk (the lower neighbour of its first cell) of plane t
+    constexpr int NP = RP / 4;
+    const int sc = threadIdx.x & (kPC - 1), sp = threadIdx.x / kPC;
+    double gX[NP], gL[NP], g0[NP], gH = 0.0;
     double gs = 0.0, gss = 0.0, gq = 0.0;
     int gf = 0;
     auto stage = [&](long ch) {
         const long c0 = ch * kPC;
+        const long e = c0 + sc;
 #pragma unroll
-        for (int u = 0; u < Sh::NX; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            const int p = idx / (kPC + 1), c = idx - p * (kPC + 1) - 1;
-            const long e = c0 + c;
-            gX[u] = (p < r && e >= 0 && e < n) ? X[(size_t)p * n + e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < Sh::NL; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            const int p = idx / kPC, c = idx % kPC;
-            const long e = c0 + c;
+        for (int u = 0; u < NP; ++u) {
+            const int p = sp + 4 * u;
             const bool ok = p < r && e < n;
+            gX[u] = ok ? X[(size_t)p * n + e] : 0.0;
             gL[u] = (ok && e >= ny) ? X[(size_t)p * n + e - ny] : 0.0;
             g0[u] = ok ? X0[(size_t)p * n + e] : 0.0;
         }
+        if (threadIdx.x < RP) gH = (threadIdx.x < r && c0 > 0) ? X[(size_t)threadIdx.x * n + c0 - 1] : 0.0;
         if (threadIdx.x < kPC) {
-            const long e = c0 + threadIdx.x;
             gs = gss = gq = 0.0;
             gf = 0;
             if (e < n) {
                 gs = sigma[e];
                 gss = sig_s[e];
                 gq = q[e];
-                const long i = e / ny, j = e % ny;
+                const int ei = (int)e, i = ei / ny, j = ei - i * ny;   // cell counts stay below 2^31
                 gf = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
             }
         }
     };
     auto commit = [&]() {
 #pragma unroll
-        for (int u = 0; u < Sh::NX; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            if (idx < RP * (kPC + 1)) {
-                const int p = idx / (kPC + 1), c1 = idx - p * (kPC + 1);
-                sX[p * kPS + c1] = (TO)gX[u];
-                if (kLowOp) sXv[idx] = gX[u];
-            }
+        for (int u = 0; u < NP; ++u) {
+            const int p = sp + 4 * u;
+            sX[p * kPS + sc + 1] = (TO)gX[u];
+            if (kLowOp) sXv[p * (kPC + 1) + sc + 1] = gX[u];
+            sXl[p * kPS + sc] = (TO)gL[u];
+            sX0[p * kPS + sc] = (TO)g0[u];
         }
-#pragma unroll
-        for (int u = 0; u < Sh::NL; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            if (idx < RP * kPC) {
-                const int p = idx / kPC, c = idx % kPC;
-                sXl[p * kPS + c] = (TO)gL[u];
-                sX0[p * kPS + c] = (TO)g0[u];
-            }
+        if (threadIdx.x < RP) {
+            sX[threadIdx.x * kPS] = (TO)gH;
+            if (kLowOp) sXv[threadIdx.x * (kPC + 1)] = gH;
         }
         if (threadIdx.x < kPC) {
             sSig[threadIdx.x] = gs;
@@ -326,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
         } else
         for (int ks = (KS == 1 ? 0 : w); ks < kPC / 4; ks += KS) {
             const int c = 4 * ks + (lane >> 4);
-            const bool bottom = (sFlag[c] & 4) != 0;   // no lower neighbour
+            const TO keep = (sFlag[c] & 4) ? (TO)0 : (TO)1;   // 0 without a lower neighbour
             const TO sg = (TO)sSig[c], ss = (TO)sSs[c];
 #pragma unroll
             for (int pp = 0; pp < PPW; ++pp) {
@@ -336,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
                     const TO ax = sX[pa * kPS + c + 1], a0 = sX0[pa * kPS + c];
                     const TO bx = sX[pb * kPS + c + 1];
                     const TO bl = sXl[pb * kPS + c];
-                    const TO bd = bottom ? (TO)0 : sX[pb * kPS + c];
+                    const TO bd = keep * sX[pb * kPS + c];   // read unconditionally: no branch in the k-step
                     acc[pp][0] = mfma4(ax, bl, acc[pp][0]);
                     acc[pp][1] = mfma4(ax, bd, acc[pp][1]);
                     acc[pp][2] = mfma4(ax, sg * bx, acc[pp][2]);

@@ -112,13 +112,15 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
         const double x = (double)V[(size_t)(j < r ? j : r - 1) * ldv + ve];
         v[j] = (j < r) ? x : 0.0;
     }
-#pragma unroll 4
-    for (int k = 0; k < r; ++k) {
-        double acc = 0.0;
+    // k fully unrolled: the triangle j <= k is resolved at compile time (r (r+1)/2 multiply-adds)
 #pragma unroll
-        for (int j = 0; j < RMAX; ++j)
-            if (j <= k) acc += v[j] * sR[j * RMAX + k];
-        X[(size_t)k * n + e] = acc;
+    for (int k = 0; k < RMAX; ++k) {
+        if (k < r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j <= k; ++j) acc = fma(v[j], sR[j * RMAX + k], acc);
+            X[(size_t)k * n + e] = acc;
+        }
     }
 }
 
