@@ -435,10 +435,10 @@ void phase_end(dlr_instance* I) {
     // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
     dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, I->Xt);
     dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
+    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, I->R2i, I->Xn);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
     dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
@@ -457,10 +457,10 @@ void phase_end(dlr_instance* I) {
     // 8. L = W S^T in the quadrature inner product: Cholesky QR twice, R = R2 R1; the CGS2 with
     // angular completion recomputes W and R on the device when a pivot flagged near-dependent columns
     dlr::launch_gram<double>(s, nq, r, I->L, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, 1, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
     dlr::launch_trmm<double>(s, nq, r, I->L, (size_t)nq, I->R1i, I->Wt);
     dlr::launch_gram<double>(s, nq, r, I->Wt, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, 1, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
     dlr::launch_trmm<double>(s, nq, r, I->Wt, (size_t)nq, I->R2i, I->Wq);
     dlr::launch_small_matmul(s, r, I->R2, I->R1, I->Ra);
     dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,

@@ -184,10 +184,9 @@ void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, const do
                  double* work, int nblocks, double* G);
 // C = A B for r x r row-major matrices
 void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C);
-// Cholesky QR step: G (the sum of nblocks partial Gram matrices) -> R, Rinv; a pivot
-// too small for Cholesky QR sets status_code in *status
-void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv,
-                 int* status, int status_code);
+// Cholesky QR step: the Gram matrix G -> R, Rinv; a pivot too small for Cholesky QR sets
+// status_code in *status
+void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code);
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X);
 // Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use

@@ -12,88 +12,75 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------------------------- Cholesky
-// G = sum of partials (block order); column scaling s_k = 1/sqrt(G_kk); upper Cholesky
-// of s G s = R'^T R'; R = R' diag(1/s); Rinv = diag(s) R'^{-1}.  A pivot below the
-// breakdown threshold (relative residual 1e-6 of a column against the previous
-// ones) flags status_code: the columns are too close to dependent for Cholesky QR
-// and the CGS2 fallback recomputes the factor.
-// One workgroup of four wavefronts, the matrix in LDS.  Per pivot k the threads of row k
-// form row k of R' and the trailing upper triangle gets the rank-one update, row i by
-// wavefront i mod 4 with the columns on the lanes (contiguous, conflict-free LDS accesses,
-// and only the live entries are touched), two barriers per pivot.  Wavefront 0 then forms
-// R'^{-1} row by row from the bottom, the lanes holding its columns.
-constexpr int kCholThreads = 256;
-static_assert(kMaxRank <= 64, "one lane per column");
+// G (r x r, symmetric); column scaling s_k = 1/sqrt(G_kk); upper Cholesky of s G s = R'^T R';
+// R = R' diag(1/s); Rinv = diag(s) R'^{-1}.  A pivot below the breakdown threshold (relative
+// residual 1e-6 of a column against the previous ones) flags status_code: the columns are too
+// close to dependent for Cholesky QR and the CGS2 fallback recomputes the factor.
+// One wavefront, no barriers: lane j holds column j of the (symmetric) matrix in registers,
+// padded to RMAX x RMAX with the identity.  Per pivot k the lanes form their entry of row k of
+// R' and publish it in an LDS row, from which every lane reads R'_ki for its trailing entries
+// i > k (the wavefront's LDS accesses execute in order, so no barrier is needed).  The inverse
+// is formed row by row from the bottom the same way, lane j holding column j of R'^{-1}.
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
-__global__ __launch_bounds__(kCholThreads) void k_chol(int r, const double* __restrict__ partials, int nblocks,
-                                                       double* __restrict__ R, double* __restrict__ Rinv,
-                                                       int* status, int status_code) {
-    __shared__ double A[kMaxRank * kMaxRank];
-    __shared__ double Ri[kMaxRank * kMaxRank];
-    __shared__ double rowk[kMaxRank];
-    __shared__ double sc[kMaxRank];
-    __shared__ int bad;
-    const int tid = threadIdx.x, rr = r * r;
-    const int lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) bad = 0;
-    stage_lds(A, partials, rr);
-    __syncthreads();
-    for (int b = 1; b < nblocks; ++b) {
-        stage_lds(Ri, partials + (size_t)b * rr, rr);
-        __syncthreads();
-        for (int o = tid; o < rr; o += kCholThreads) A[o] += Ri[o];
-        __syncthreads();
+template <int RMAX>
+__global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G, double* __restrict__ R,
+                                             double* __restrict__ Rinv, int* status, int status_code) {
+    static_assert(RMAX <= 64, "one lane per column");
+    __shared__ double row[64];
+    __shared__ double scl[64];
+    const int j = threadIdx.x;
+    const bool col = j < r;
+    const int jc = col ? j : r - 1;
+    const double gjj = G[jc * r + jc];
+    bool bad = col && !(gjj > 0.0 && isfinite(gjj));
+    const double sj = col ? ((gjj > 0.0) ? 1.0 / sqrt(gjj) : 0.0) : 1.0;
+    scl[j] = sj;
+    double a[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+        const double g = G[(i < r ? i : r - 1) * r + jc];
+        a[i] = (i < r && col) ? scl[i] * g * sj : (i == j ? 1.0 : 0.0);
     }
-    for (int k = tid; k < r; k += kCholThreads) {
-        const double gkk = A[k * r + k];
-        if (!(gkk > 0.0) || !isfinite(gkk)) bad = 1;
-        sc[k] = (gkk > 0.0) ? 1.0 / sqrt(gkk) : 0.0;
-    }
-    __syncthreads();
-    for (int i = wv; i < r; i += 4)
-        if (lane < r) {
-            A[i * r + lane] *= sc[i] * sc[lane];
-            Ri[i * r + lane] = 0.0;
-        }
-    __syncthreads();
-    for (int k = 0; k < r; ++k) {
-        const double piv = A[k * r + k];
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);   // one pivot's LDS reads at a time (register pressure)
+        const double piv = lane_value(a[k], k);
+        if (k < r && !(piv > 1e-12)) bad = true;
         const double rkk = sqrt(fmax(piv, 1e-300));
-        if (tid == 0 && !(piv > 1e-12)) bad = 1;
-        // row k of R' (A keeps it: row k is not touched again)
-        if (tid >= k && tid < r) {
-            const double v = (tid == k) ? rkk : A[k * r + tid] / rkk;
-            rowk[tid] = v;
-            A[k * r + tid] = v;
-        }
-        __syncthreads();
-        // trailing update of the upper triangle: A_ij -= R'_ki R'_kj, k < i <= j
-        if (lane < r) {
-            const double rj = rowk[lane];
-#pragma unroll 2
-            for (int i = k + 1 + wv; i < r; i += 4)
-                if (lane >= i) A[i * r + lane] -= rowk[i] * rj;
-        }
-        __syncthreads();
+        const double rkj = (j > k) ? a[k] / rkk : (j == k ? rkk : 0.0);
+        a[k] = rkj;   // row k of R' (not touched again)
+        row[j] = rkj;
+#pragma unroll
+        for (int i = k + 1; i < RMAX; ++i) a[i] = fma(-row[i], rkj, a[i]);
     }
-    // R'^{-1}, row i from rows i+1.. : Ri_ij = (delta_ij - sum_{i < m < r} R'_im Ri_mj) / R'_ii
-    // (Ri_mj = 0 for m > j, so the uniform bound adds exact zeros)
-    if (wv == 0 && lane < r) {
-        for (int i = r - 1; i >= 0; --i) {
-            double part = 0.0;
-#pragma unroll 8
-            for (int m = i + 1; m < r; ++m) part += A[i * r + m] * Ri[m * r + lane];
-            if (lane >= i) Ri[i * r + lane] = (((i == lane) ? 1.0 : 0.0) - part) / A[i * r + i];
+    // R'^{-1}: Ri_ij = (delta_ij - sum_{i < m} R'_im Ri_mj) / R'_ii  (Ri_mj = 0 for m > j)
+    double ri[RMAX];
+#pragma unroll
+    for (int i = RMAX - 1; i >= 0; --i) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        row[j] = a[i];   // row i of R'
+        double part = 0.0;
+#pragma unroll
+        for (int m = i + 1; m < RMAX; ++m) part = fma(row[m], ri[m], part);
+        ri[i] = ((i == j ? 1.0 : 0.0) - part) / row[i];
+    }
+    if (col) {
+#pragma unroll
+        for (int i = 0; i < RMAX; ++i) {
+            if (i < r) {
+                R[i * r + j] = (i <= j && sj > 0.0) ? a[i] / sj : 0.0;
+                Rinv[i * r + j] = (i <= j) ? scl[i] * ri[i] : 0.0;
+            }
         }
     }
-    __syncthreads();
-    for (int i = wv; i < r; i += 4)
-        if (lane < r) {
-            const int o = i * r + lane;
-            R[o] = (i <= lane && sc[lane] > 0.0) ? A[o] / sc[lane] : 0.0;
-            Rinv[o] = (i <= lane) ? sc[i] * Ri[o] : 0.0;
-        }
-    if (tid == 0 && bad) atomicOr(status, status_code);
+    const unsigned long long anybad = __ballot(bad);
+    if (j == 0 && anybad) atomicOr(status, status_code);
 }
 
 // ---------------------------------------------------------------------------------------------- X = V Rinv
@@ -163,9 +150,15 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
 
 }  // namespace
 
-void launch_chol(hipStream_t s, int r, const double* partials, int nblocks, double* R, double* Rinv, int* status,
-                 int status_code) {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), 0, s, r, partials, nblocks, R, Rinv, status, status_code);
+void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code) {
+    if (r <= 8)
+        hipLaunchKernelGGL(k_chol<8>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+    else if (r <= 16)
+        hipLaunchKernelGGL(k_chol<16>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+    else if (r <= 32)
+        hipLaunchKernelGGL(k_chol<32>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+    else
+        hipLaunchKernelGGL(k_chol<64>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
 }
 
 template <typename TV>
