@@ -92,6 +92,77 @@ __device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, double* pr
     }
 }
 
+// The same solve on one wavefront without barriers, for systems of a single workgroup's
+// critical path: lane i holds row i of the augmented system in registers, the pivot of
+// column k is the largest remaining |A_ik| (ties to the lowest row) found by a wavefront
+// reduction, the pivot row is broadcast through prow (the wavefront's LDS accesses execute in
+// order), and column k is eliminated from every other row.  The solution overwrites the
+// right-hand-side column (x_k in row k).  Called by the whole workgroup; wavefront 0 works.
+template <int RMAX>
+__device__ __forceinline__ void gauss_jordan_wave_impl(double* Aug, int r, int ld, double* prow, int* bad) {
+    const int i = threadIdx.x;
+    const bool live = i < r;
+    const int ic = live ? i : r - 1;
+    double a[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+        const double v = Aug[ic * ld + (c < r ? c : r - 1)];
+        a[c] = (live && c < r) ? v : 0.0;
+    }
+    double b = live ? Aug[ic * ld + r] : 0.0;
+    bool used = !live, isbad = false;
+    int mypiv = -1;
+    double mydiag = 1.0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        if (k < r) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // one pivot's LDS traffic at a time
+            double v = used ? -1.0 : fabs(a[k]);
+            int idx = i;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(v, off);
+                const int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            const int p = __builtin_amdgcn_readfirstlane(idx);
+            if (!(v > 0.0) || !isfinite(v)) isbad = true;
+            if (i == p) {
+#pragma unroll
+                for (int c = k; c < RMAX; ++c) prow[c] = a[c];
+                prow[RMAX] = b;
+                used = true;
+                mypiv = k;
+                mydiag = a[k];
+            }
+            const double f = (i == p) ? 0.0 : a[k] / prow[k];
+#pragma unroll
+            for (int c = k + 1; c < RMAX; ++c) a[c] = fma(-f, prow[c], a[c]);
+            b = fma(-f, prow[RMAX], b);
+        }
+    }
+    if (mypiv >= 0) Aug[mypiv * ld + r] = b / mydiag;
+    if (__ballot(isbad) != 0ull && i == 0) *bad = 1;
+}
+
+__device__ __forceinline__ void gauss_jordan_wave(double* Aug, int r, int ld, double* prow, int* bad) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        if (r <= 8)
+            gauss_jordan_wave_impl<8>(Aug, r, ld, prow, bad);
+        else if (r <= 16)
+            gauss_jordan_wave_impl<16>(Aug, r, ld, prow, bad);
+        else if (r <= 32)
+            gauss_jordan_wave_impl<32>(Aug, r, ld, prow, bad);
+        else
+            gauss_jordan_wave_impl<64>(Aug, r, ld, prow, bad);
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------------------------- DEIM
 // Algorithm 1 step 2 (Sec. 4.2): the DEIM points of W are the pivots of Gaussian elimination
 // with partial pivoting on the rows of W (ordinates): for column j, the pivot is the
@@ -360,8 +431,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim_tail(DeimArgs a, int grou
     }
     __syncthreads();
     for (int i = tid; i < r; i += kDeimThreads) Aug[i * ld + r] = beta[i];
-    __syncthreads();
-    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
+    gauss_jordan_wave(Aug, r, ld, prow, &bad);
     for (int i = tid; i < r; i += kDeimThreads) {
         a.cw[i] = Aug[i * ld + r];
         const double mu = smu[i], eta = seta[i];
@@ -582,7 +652,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_schur(LstepArgs a) {
         Aug[i * ld + j] = ((i == j) ? 1.0 : 0.0) - s / kFourPi;
     }
     __syncthreads();
-    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
+    gauss_jordan_wave(Aug, r, ld, prow, &bad);
     for (int i = tid; i < r; i += kLsThreads) {
         double s = 0.0;
         for (int k = 0; k < r; ++k) s += sMs[i * r + k] * Aug[k * ld + r];
