@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
 
 template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L) {
-    constexpr int P = 2;
+    constexpr int P = 4;
     hipLaunchKernelGGL((k_sweep<TS, P>), dim3(L.grid_blocks), dim3(64 * (kWaves + 1)), 0, s, table, L);
 }
 template void launch_sweep<double>(hipStream_t, const SweepArgs<double>*, const SweepLaunch&);
