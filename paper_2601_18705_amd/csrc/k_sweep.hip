@@ -163,6 +163,10 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
     for (int p = 0; p < P; ++p) issue_loads<TS>(s, p, bs[p], bq[p], be[p]);
     TS mine = s.by;
 
+    // Progress words only grow, so a stale copy is conservative: a wavefront polls the LDS word
+    // only when the copy it last read does not cover what it needs.
+    int known_prod = 0;   // rows published into ring[w], as last read
+    int known_cons = 0;   // rows consumed from ring[out_ring], as last read
     auto left_values = [&](int m, TS (&edgev)[kC]) {
         const int r0 = kC * m;
         if (!from_ring || r0 >= ny) {
@@ -171,12 +175,16 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
             return;
         }
         const int need = min(r0 + kC, ny);
-        unsigned polls = 0;
-        while (lds_load(&sh.prod[w]) < need) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > a.spin_limit) {
-                sh.stall = 1;
-                break;
+        if (known_prod < need) {   // poll only when the last word read does not cover this chunk
+            unsigned polls = 0;
+            for (;;) {
+                known_prod = lds_load(&sh.prod[w]);
+                if (known_prod >= need) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++polls > a.spin_limit) {
+                    sh.stall = 1;
+                    break;
+                }
             }
         }
 #pragma unroll
@@ -187,12 +195,16 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
         if (!has_next) return;
         const int r0 = kC * m;
         const int newest = r0 + kC - 64;   // newest row written by lane 63 in this chunk
-        unsigned polls = 0;
-        while (newest - lds_load(&sh.cons[out_ring]) >= kRing) {   // back-pressure
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > a.spin_limit) {
-                sh.stall = 1;
-                break;
+        if (newest - known_cons >= kRing) {   // back-pressure, re-read only when the ring may be full
+            unsigned polls = 0;
+            for (;;) {
+                known_cons = lds_load(&sh.cons[out_ring]);
+                if (newest - known_cons < kRing) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++polls > a.spin_limit) {
+                    sh.stall = 1;
+                    break;
+                }
             }
         }
         if (lane == 63) {
