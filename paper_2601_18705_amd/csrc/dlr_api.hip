@@ -357,7 +357,7 @@ void phase_begin(dlr_instance* I) {
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
     da.forced = I->force_pending ? I->forced : nullptr;
-    da.xchg = I->deim_work; da.xcount = I->deim_count; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
+    da.xchg = I->deim_work; da.xcount = I->deim_count; da.launch_seq = dlr::next_sweep_launch_id(); da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
     da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
     da.mu = I->mu; da.eta = I->eta;
     for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];

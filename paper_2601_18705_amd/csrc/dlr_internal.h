@@ -203,7 +203,8 @@ void launch_project_finalize(hipStream_t s, int r, const double* partials, int n
 // ----------------------------------------------------------------------------- small dense FP64 work
 // DEIM exchange area: per column two exchanges among up to 64 workgroups (double-buffered),
 // and the workgroups' parts of beta
-constexpr size_t kDeimXchgDoubles = 2 * 64 + 2 * 64 * (2 + (size_t)kMaxRank) + 64 * (size_t)kMaxRank;
+constexpr size_t kDeimXchgDoubles =
+    2 * 64 + 2 * 64 * (2 + (size_t)kMaxRank) + 64 * (size_t)kMaxRank + 2 * 64 * (3 + (size_t)kMaxRank);
 struct DeimArgs {
     int nq, r;
     const double* W;       // [r][nq]
@@ -213,6 +214,7 @@ struct DeimArgs {
     const int* forced;     // [r] or nullptr
     double* xchg;          // [kDeimXchgDoubles] exchange area among the workgroups
     unsigned* xcount;      // [2] arrival / departure counters, zero between launches
+    unsigned long long launch_seq;   // unique per launch (>= 1): tags the exchanged words
     int* sel;              // [r]
     double* cw;            // [r]
     double* C0;            // [r][r]  C0[k*r + d] = sum_j S[k][j] W[j][sel_d]

@@ -172,9 +172,15 @@ __device__ __forceinline__ void gauss_jordan_wave(double* Aug, int r, int ld, do
 // beta = W^T w, and C0 = S W[sel]^T, a0 = S beta.
 //
 // The rows are spread over ceil(nq / 256) workgroups, one row per thread, kept in registers.
-// Per column two exchanges among the workgroups: (1) each group's maximum, (2) each group's
-// lowest-index row at or above the threshold with its values, and its largest value below the
-// threshold.  Exchanged values are agent-scope atomics in a double-buffered area; a group
+// Per column one exchange among the workgroups: each group publishes its maximum m_g, its
+// lowest-index row at or above its own threshold (1 - tol) m_g with that row's values, and its
+// largest value below that threshold.  The group(s) holding the global maximum M have the
+// global threshold, so the pivot is the lowest of their candidates, and every other group lies
+// entirely below the threshold -- unless some m_g lies in [(1 - tol) M, M), a near-tie across
+// groups.  All groups see the same published values and detect that case alike; it falls back
+// to a second exchange of each group's lowest-index row at or above the global threshold.  A
+// forced selection (the parity replay) always takes the two-exchange path: (1) each group's
+// maximum, (2) the rows at or above the global threshold.  Exchanged values are agent-scope atomics in a double-buffered area; a group
 // counts itself after its stores have completed and polls the count, bounded by a spin limit
 // (kStatusDeimStall) so that a stall cannot hang the device.  All groups reach the same
 // decisions from the same data; group 0 then solves for c and writes the outputs.
@@ -184,7 +190,8 @@ constexpr int kDeimMaxGroups = kMaxOrdinates / kDeimThreads;
 constexpr size_t kXEx1 = 0;                                                        // [2][groups]
 constexpr size_t kXEx2 = kXEx1 + 2 * kDeimMaxGroups;                              // [2][groups][2 + kMaxRank]
 constexpr size_t kXBeta = kXEx2 + 2 * (size_t)kDeimMaxGroups * (2 + kMaxRank);    // [groups][kMaxRank]
-static_assert(kXBeta + (size_t)kDeimMaxGroups * kMaxRank <= kDeimXchgDoubles, "DEIM exchange area");
+constexpr size_t kXExM = kXBeta + (size_t)kDeimMaxGroups * kMaxRank;              // [2][groups][3 + kMaxRank]
+static_assert(kXExM + 2 * (size_t)kDeimMaxGroups * (3 + kMaxRank) <= kDeimXchgDoubles, "DEIM exchange area");
 constexpr unsigned kDeimSpinLimit = 1u << 20;
 
 __device__ __forceinline__ void xstore(double* p, double v) {
@@ -218,10 +225,11 @@ __device__ void group_sync(unsigned* arrive, unsigned target, int* stall) {
 
 template <int RT>
 __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
-    __shared__ double sv[kDeimWaves];
+    __shared__ double sv[kDeimWaves], sv2[kDeimWaves];
     __shared__ int si[kDeimWaves];
     __shared__ double sM, sSecond;
-    __shared__ int sP, sPw;
+    __shared__ int sP, sFallback;
+    __shared__ size_t sSrc;   // offset of the pivot row's values in the exchange area
     __shared__ double up[RT];
     __shared__ double bw[kDeimWaves][RT];
     __shared__ int bad, stall;
@@ -263,31 +271,9 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         for (int i = 0; i < RT; ++i) uj = (i == j) ? u[i] : uj;
         const bool elig = in && !pivoted;
         const double v = elig ? fabs(uj) : -1.0;
-        // (1) maximum over the rows not yet chosen
-        {
-            double m = v;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-            if (lane == 0) sv[wv] = m;
-            __syncthreads();
-            if (tid == 0) {
-                double mw = sv[0];
-                for (int w = 1; w < kDeimWaves; ++w) mw = fmax(mw, sv[w]);
-                xstore(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + g], mw);
-            }
-            group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
-            if (wv == 0) {
-                double mg = (lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) mg = fmax(mg, __shfl_xor(mg, off));
-                if (lane == 0) sM = fmax(mg, 0.0);
-            }
-            __syncthreads();
-        }
-        const double M = sM;
-        const double thr = (1.0 - a.tie_tol) * M;
-        // (2) lowest-index row at or above the threshold (or the forced row), largest value below
-        {
+        // the two-exchange step (2): lowest-index row at or above thr (or the forced row) with its
+        // values, largest value below thr; sets sP, sSecond, and sSrc to the pivot row's values
+        auto exchange_above = [&](double thr) {
             int pi = (elig && v >= thr) ? q : 0x7fffffff;
             double sec = (elig && v < thr) ? v : 0.0;
             if (a.forced) {
@@ -302,14 +288,14 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             }
             if (lane == 0) {
                 si[wv] = pi;
-                sv[wv] = sec;
+                sv2[wv] = sec;
             }
             __syncthreads();
             int pw = si[0];
-            double sw = sv[0];
+            double sw = sv2[0];
             for (int w = 1; w < kDeimWaves; ++w) {
                 pw = min(pw, si[w]);
-                sw = fmax(sw, sv[w]);
+                sw = fmax(sw, sv2[w]);
             }
             double* slot = &X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + g) * (2 + kMaxRank)];
             if (q == pw) {
@@ -334,18 +320,129 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                 if (lane == 0) {
                     sP = (pg < 2147483647.0) ? (int)pg : -1;
                     sSecond = sg;
+                    sSrc = (pg < 2147483647.0)
+                               ? kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + (int)pg / kDeimThreads) * (2 + kMaxRank) + 2
+                               : 0;
                 }
             }
             __syncthreads();
+        };
+        // this group's maximum over the rows not yet chosen
+        double m = v;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if (lane == 0) sv[wv] = m;
+        __syncthreads();
+        double mw = sv[0];
+        for (int w = 1; w < kDeimWaves; ++w) mw = fmax(mw, sv[w]);
+        if (!a.forced) {
+            // one exchange: m_g, the lowest-index row at or above (1 - tol) m_g with its values,
+            // and the largest value below that threshold
+            const double thl = (1.0 - a.tie_tol) * mw;
+            int pi = (elig && v >= thl) ? q : 0x7fffffff;
+            double sec = (elig && v < thl) ? v : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                pi = min(pi, __shfl_xor(pi, off));
+                sec = fmax(sec, __shfl_xor(sec, off));
+            }
+            if (lane == 0) {
+                si[wv] = pi;
+                sv2[wv] = sec;
+            }
+            __syncthreads();
+            int pw = si[0];
+            double sw = sv2[0];
+            for (int w = 1; w < kDeimWaves; ++w) {
+                pw = min(pw, si[w]);
+                sw = fmax(sw, sv2[w]);
+            }
+            // The candidate word, stored last (after the group's other stores have completed),
+            // carries the launch and the column: tag * 2^15 + index (index 2^14 = none).  Readers
+            // poll it instead of a shared arrival counter.  A group cannot reach column j + 2 (and
+            // overwrite this slot) before every group has published column j + 1, i.e. finished
+            // reading column j.
+            const double tag = (double)(((a.launch_seq & 0xffffffffull) << 6) | (unsigned long long)j);
+            double* slot = &X[kXExM + ((size_t)(j & 1) * kDeimMaxGroups + g) * (3 + kMaxRank)];
+            if (q == pw) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    if (i < r) xstore(&slot[3 + i], u[i]);
+            }
+            if (tid == 0) {
+                xstore(&slot[0], mw);
+                xstore(&slot[1], sw);
+            }
+            wait_vm_stores();
+            __syncthreads();
+            if (tid == 0) xstore(&slot[2], tag * 32768.0 + (double)(pw < nq ? pw : 16384));
+            if (wv == 0) {
+                const double* sl = &X[kXExM + ((size_t)(j & 1) * kDeimMaxGroups + lane) * (3 + kMaxRank)];
+                double word = 0.0;
+                bool seen = lane >= G;
+                unsigned polls = 0;
+                for (;;) {
+                    if (!seen) {
+                        word = xload(&sl[2]);
+                        seen = floor(word / 32768.0) == tag;
+                    }
+                    if (__all(seen)) break;
+                    if (stall || ++polls > kDeimSpinLimit) {
+                        stall = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                const double mg = (lane < G) ? xload(&sl[0]) : -1.0;
+                const double sg = (lane < G) ? xload(&sl[1]) : 0.0;
+                const double ci = word - tag * 32768.0;
+                const double cg = (lane < G && ci < 16384.0) ? ci : 2147483647.0;
+                double Mx = mg;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) Mx = fmax(Mx, __shfl_xor(Mx, off));
+                const double Mpos = fmax(Mx, 0.0);
+                const double thr = (1.0 - a.tie_tol) * Mpos;
+                const bool band = lane < G && mg >= thr && mg < Mx;
+                double cand = (lane < G && mg == Mx) ? cg : 2147483647.0;
+                double scnd = (lane < G) ? ((mg < thr) ? fmax(mg, 0.0) : ((mg == Mx) ? sg : 0.0)) : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    cand = fmin(cand, __shfl_xor(cand, off));
+                    scnd = fmax(scnd, __shfl_xor(scnd, off));
+                }
+                const bool fallback = __ballot(band) != 0ull;
+                if (lane == 0) {
+                    sM = Mpos;
+                    sFallback = fallback ? 1 : 0;
+                    sP = (cand < 2147483647.0) ? (int)cand : -1;
+                    sSecond = scnd;
+                    sSrc = (cand < 2147483647.0)
+                               ? kXExM + ((size_t)(j & 1) * kDeimMaxGroups + (int)cand / kDeimThreads) * (3 + kMaxRank) + 3
+                               : 0;
+                }
+            }
+            __syncthreads();
+            if (sFallback) exchange_above((1.0 - a.tie_tol) * sM);
+        } else {
+            // (1) the maximum over the rows not yet chosen, (2) the rows at or above the threshold
+            if (tid == 0) xstore(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + g], mw);
+            group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
+            if (wv == 0) {
+                double mg = (lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) mg = fmax(mg, __shfl_xor(mg, off));
+                if (lane == 0) sM = fmax(mg, 0.0);
+            }
+            __syncthreads();
+            exchange_above((1.0 - a.tie_tol) * sM);
         }
+        const double M = sM;
         const int p = sP;
         if (p < 0) {   // no row qualifies (an invalid forced index): flag and stop, consistently in all groups
             if (tid == 0) bad = 1;
             break;
         }
-        const int pg = p / kDeimThreads;
-        for (int i = tid; i < r; i += kDeimThreads)
-            up[i] = xload(&X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + pg) * (2 + kMaxRank) + 2 + i]);
+        for (int i = tid; i < r; i += kDeimThreads) up[i] = xload(&X[sSrc + i]);
         if (tid == 0) {
             if (g == 0) {
                 a.sel[j] = p;
