@@ -87,7 +87,7 @@ struct dlr_instance {
     double *sigma = nullptr, *rho_cv = nullptr, *q_ext = nullptr, *T = nullptr;
     double *D = nullptr, *sig_s = nullptr, *q = nullptr, *sig_t = nullptr;
     float* sig_t32 = nullptr;
-    double *X = nullptr, *Xn = nullptr, *Xt = nullptr;
+    double *X = nullptr, *Xn = nullptr;
     double *S = nullptr, *Sn = nullptr;
     double *W = nullptr, *Wt = nullptr, *Wq = nullptr, *L = nullptr;
     void *psi = nullptr, *src0 = nullptr, *s_e = nullptr, *psi_cm = nullptr;
@@ -184,7 +184,6 @@ struct dlr_instance {
         sig_t32 = fp32() ? A.take<float>(4 * ldg) : nullptr;
         X = A.take<double>(R * n);
         Xn = A.take<double>(R * n);
-        Xt = A.take<double>(R * n);
         S = A.take<double>(R * R);
         Sn = A.take<double>(R * R);
         W = A.take<double>(R * Q);
@@ -432,14 +431,18 @@ void phase_end(dlr_instance* I) {
     const double cdt = I->c * I->dt;
     TS* psi = static_cast<TS*>(I->psi);
     TS* psi_cm = static_cast<TS*>(I->psi_cm);
-    // 5. X from the swept columns: Cholesky QR, twice (column-scaled), in the cell-area inner product
+    // 5. X from the swept columns: Cholesky QR (column-scaled) in the cell-area inner product; the
+    // second pass re-orthonormalises in place unless the first already left the Gram matrix within
+    // tol of the identity (1e-11 with FP64 sweeps, 1e-8 with FP32 sweeps: X then differs from the
+    // exact orthonormal factor by less than that)
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
     dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, I->Xt);
-    dlr::launch_gram<double>(s, N, r, I->Xt, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<double>(s, N, r, I->Xt, (size_t)N, I->R2i, I->Xn);
+    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, I->Xn);
+    dlr::launch_gram<double>(s, N, r, I->Xn, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3,
+                     I->fp32() ? 1e-8 : 1e-11);
+    dlr::launch_trmm_inplace(s, N, r, I->Xn, I->R2i, I->status + 3);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
     dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);

@@ -185,8 +185,12 @@ void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, const do
 // C = A B for r x r row-major matrices
 void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C);
 // Cholesky QR step: the Gram matrix G -> R, Rinv; a pivot too small for Cholesky QR sets
-// status_code in *status
-void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code);
+// status_code in *status.  With near_identity, also writes 1 there when max |G - I| < identity_tol
+// (the basis is already orthonormal to that tolerance), else 0.
+void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code,
+                 int* near_identity = nullptr, double identity_tol = 0.0);
+// X = X Rinv in place for n x r column-major X; nothing when *skip is set
+void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip);
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X);
 // Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use

@@ -30,7 +30,8 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 
 template <int RMAX>
 __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G, double* __restrict__ R,
-                                             double* __restrict__ Rinv, int* status, int status_code) {
+                                             double* __restrict__ Rinv, int* status, int status_code,
+                                             int* near_identity, double identity_tol) {
     static_assert(RMAX <= 64, "one lane per column");
     __shared__ double row[64];
     __shared__ double scl[64];
@@ -42,10 +43,18 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
     const double sj = col ? ((gjj > 0.0) ? 1.0 / sqrt(gjj) : 0.0) : 1.0;
     scl[j] = sj;
     double a[RMAX];
+    double dev = 0.0;   // max |G_ij - delta_ij| of this column
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) {
         const double g = G[(i < r ? i : r - 1) * r + jc];
         a[i] = (i < r && col) ? scl[i] * g * sj : (i == j ? 1.0 : 0.0);
+        if (i < r && col) dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
+    }
+    if (near_identity) {
+        // the Gram matrix of an already orthonormal basis: the second Cholesky QR pass may be skipped
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
+        if (j == 0) *near_identity = (dev < identity_tol) ? 1 : 0;
     }
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
@@ -111,6 +120,34 @@ __global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restr
     }
 }
 
+// X = X Rinv in place (no aliasing qualifiers: every thread loads its cell's row before it stores),
+// skipped when *skip is set
+template <int RMAX>
+__global__ __launch_bounds__(kBlock) void k_trmm_inplace(int n, int r, double* X, const double* __restrict__ Rinv,
+                                                         const int* __restrict__ skip) {
+    if (*skip) return;
+    __shared__ double sR[RMAX * RMAX];
+    for (int o = threadIdx.x; o < r * r; o += kBlock) sR[(o / r) * RMAX + o % r] = Rinv[o];
+    __syncthreads();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double v[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        const double x = X[(size_t)(j < r ? j : r - 1) * n + e];
+        v[j] = (j < r) ? x : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        if (k < r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j <= k; ++j) acc = fma(v[j], sR[j * RMAX + k], acc);
+            X[(size_t)k * n + e] = acc;
+        }
+    }
+}
+
 // ops layout: Axp, Axm, Ayp, Aym, Mt, Ms, G (r x r each), qX[r], b[4][r]
 //   A_x^+ = <X, D_x^+ X> = (I - M0)/hx   (X orthonormal), A_x^- = (I - M0^T)/hx, same for y;
 //   M_t = <X, sigma X> + I/(c dt);  G = S0^T P with P_ik = <X0_i, X_k> (old solution onto new X)
@@ -150,15 +187,32 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
 
 }  // namespace
 
-void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code) {
+void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code,
+                 int* near_identity, double identity_tol) {
     if (r <= 8)
-        hipLaunchKernelGGL(k_chol<8>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+        hipLaunchKernelGGL(k_chol<8>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
+                           identity_tol);
     else if (r <= 16)
-        hipLaunchKernelGGL(k_chol<16>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+        hipLaunchKernelGGL(k_chol<16>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
+                           identity_tol);
     else if (r <= 32)
-        hipLaunchKernelGGL(k_chol<32>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+        hipLaunchKernelGGL(k_chol<32>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
+                           identity_tol);
     else
-        hipLaunchKernelGGL(k_chol<64>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code);
+        hipLaunchKernelGGL(k_chol<64>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
+                           identity_tol);
+}
+
+void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip) {
+    dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
+    if (r <= 8)
+        hipLaunchKernelGGL((k_trmm_inplace<8>), g, b, 0, s, n, r, X, Rinv, skip);
+    else if (r <= 16)
+        hipLaunchKernelGGL((k_trmm_inplace<16>), g, b, 0, s, n, r, X, Rinv, skip);
+    else if (r <= 32)
+        hipLaunchKernelGGL((k_trmm_inplace<32>), g, b, 0, s, n, r, X, Rinv, skip);
+    else
+        hipLaunchKernelGGL((k_trmm_inplace<64>), g, b, 0, s, n, r, X, Rinv, skip);
 }
 
 template <typename TV>
