@@ -45,13 +45,19 @@ struct Vec4 {
     typedef TS type __attribute__((ext_vector_type(4), aligned(sizeof(TS))));
 };
 
+// The plane pointers come from the sweep record in memory, so the compiler cannot see that they
+// point to global memory and would emit flat accesses -- which also count against the LDS wait
+// counter, making every wait on a ring row wait for all prefetched chunks as well.  The chunk
+// loads and stores therefore go through global-address-space pointers.
+#define DLR_GLOBAL __attribute__((address_space(1)))
+
 // Chunk m of a lane: diagonal groups 4m..4m+3 at p + g*256 elements, four values each.
 template <typename TS>
 __device__ __forceinline__ void load_chunk(const TS* p, TS (&v)[kC]) {
     typedef typename Vec4<TS>::type V;
 #pragma unroll
     for (int c = 0; c < kC / 4; ++c) {
-        const V x = *reinterpret_cast<const V*>(p + (size_t)c * 256);
+        const V x = *(const DLR_GLOBAL V*)(p + (size_t)c * 256);
         v[4 * c + 0] = x[0];
         v[4 * c + 1] = x[1];
         v[4 * c + 2] = x[2];
@@ -69,7 +75,7 @@ __device__ __forceinline__ void store_chunk(TS* p, const TS (&v)[kC]) {
         x[1] = v[4 * c + 1];
         x[2] = v[4 * c + 2];
         x[3] = v[4 * c + 3];
-        *reinterpret_cast<V*>(p + (size_t)c * 256) = x;
+        *(DLR_GLOBAL V*)(p + (size_t)c * 256) = x;
     }
 }
 
@@ -275,10 +281,14 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned lon
     const int nx = a.nx, ny = a.ny;
     const bool incoming = S > 0;
     const bool outgoing = ((S + 1) * kWaves) * 64 < nx;   // the next superstrip has columns
-    const TS* edge_in = incoming ? a.edge + ((size_t)d * a.nsuper + (S - 1)) * ny : nullptr;
-    TS* edge_out = outgoing ? a.edge + ((size_t)d * a.nsuper + S) * ny : nullptr;
-    unsigned long long* prog_in = incoming ? &a.progress[(size_t)d * a.nsuper + S - 1] : nullptr;
-    unsigned long long* prog_out = outgoing ? &a.progress[(size_t)d * a.nsuper + S] : nullptr;
+    // (global address space, as the chunk pointers: no flat accesses on the LDS wait counter)
+    const DLR_GLOBAL TS* edge_in =
+        incoming ? (const DLR_GLOBAL TS*)(a.edge + ((size_t)d * a.nsuper + (S - 1)) * ny) : nullptr;
+    DLR_GLOBAL TS* edge_out = outgoing ? (DLR_GLOBAL TS*)(a.edge + ((size_t)d * a.nsuper + S) * ny) : nullptr;
+    DLR_GLOBAL unsigned long long* prog_in =
+        incoming ? (DLR_GLOBAL unsigned long long*)&a.progress[(size_t)d * a.nsuper + S - 1] : nullptr;
+    DLR_GLOBAL unsigned long long* prog_out =
+        outgoing ? (DLR_GLOBAL unsigned long long*)&a.progress[(size_t)d * a.nsuper + S] : nullptr;
     const unsigned long long tag = launch_id << 32;
     int rin = incoming ? 0 : ny;    // rows copied into ring[0]
     int rout = outgoing ? 0 : ny;   // rows copied out of ring[kWaves]
