@@ -262,26 +262,86 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
 // k_phi_partial + k_phi_combine (with the plain SN kernels below).
 
 // ---------------------------------------------------------------------------------------------- Psi relayout
-template <typename TS>
+// Psi (four diagonal layouts) -> compact cell planes.  A thread owns column i and the four rows j0..j0+3.
+// In a direction's layout those rows are the consecutive diagonal positions t = a..a+3 (in reverse order
+// when the orientation flips j), which lie in the aligned groups floor(a/4) and floor(a/4) + 1 of the
+// column's lane: both are loaded as vectors and the four values picked by a & 3.  DU directions are
+// loaded before any is stored; positions of rows beyond ny are clamped into the layout and not stored.
+__device__ inline void load_quad(const float* p, float (&v)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+}
+__device__ inline void load_quad(const double* p, double (&v)[4]) {
+    const double2 x = *reinterpret_cast<const double2*>(p), y = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = x.x, v[1] = x.y, v[2] = y.x, v[3] = y.y;
+}
+__device__ inline void store_quad(float* p, const float (&v)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void store_quad(double* p, const double (&v)[4]) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+template <typename TS, int DU>
 __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const TS* __restrict__ psi, size_t ldg,
                                                       const double* __restrict__ mu, const double* __restrict__ eta,
                                                       TS* __restrict__ psi_cm, size_t ld) {
     __shared__ int so[kMaxRank];
     for (int i = threadIdx.x; i < r; i += blockDim.x) so[i] = orient_of(mu[i], eta[i]);
     __syncthreads();
+    const int G = diag_groups(g.ny);
+    const bool vec = (g.ny & 3) == 0;   // 16-byte aligned row quads in the compact planes
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+        const int tx = b / g.nty, ty = b % g.nty;
+        // a wavefront covers the tile's 8 columns x 32 rows: its loads touch few, mostly whole,
+        // lines of the diagonal layouts and its stores write whole 128-byte column segments
+        const int i = tx * kTileCols + (threadIdx.x & 7);
+        const int j0 = ty * kTileRows + (threadIdx.x >> 3) * 4;
+        if (i >= g.nx || j0 >= g.ny) continue;
+        size_t cb[4];   // element offset of group 0 of the column's lane, per orientation
+        int sa[4];      // first diagonal position a of the four rows, per orientation
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            int i, j;
-            if (!g.cell(b, kc, i, j)) continue;
-            const size_t pe = (size_t)i * g.ny + j;
-            size_t pos[4];
+        for (int o = 0; o < 4; ++o) {
+            const int ip = (o & 1) ? g.nx - 1 - i : i, l = ip & 63;
+            cb[o] = ((size_t)(ip >> 6) * G * 64 + l) * 4;
+            sa[o] = ((o & 2) ? g.ny - 4 - j0 : j0) + l;
+        }
+        TS* out = psi_cm + (size_t)i * g.ny + j0;
+        for (int d0 = 0; d0 < r; d0 += DU) {
+            TS lo[DU][4], hi[DU][4];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
-            for (int d = 0; d < r; ++d) {
+            for (int u = 0; u < DU; ++u) {
+                const int d = min(d0 + u, r - 1);
                 const int o = so[d];
-                const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
-                psi_cm[(size_t)d * ld + pe] = psi[(size_t)d * ldg + pd];
+                const size_t c = o == 0 ? cb[0] : o == 1 ? cb[1] : o == 2 ? cb[2] : cb[3];
+                const int a = o == 0 ? sa[0] : o == 1 ? sa[1] : o == 2 ? sa[2] : sa[3];
+                const TS* p = psi + (size_t)d * ldg + c;
+                load_quad(p + (size_t)max(a >> 2, 0) * 256, lo[u]);
+                load_quad(p + (size_t)min((a >> 2) + 1, G - 1) * 256, hi[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < DU; ++u) {
+                const int d = d0 + u;
+                if (d >= r) break;
+                const int o = so[d];
+                const int s = (o == 0 ? sa[0] : o == 1 ? sa[1] : o == 2 ? sa[2] : sa[3]) & 3;
+                TS w[8] = {lo[u][0], lo[u][1], lo[u][2], lo[u][3], hi[u][0], hi[u][1], hi[u][2], hi[u][3]};
+#pragma unroll
+                for (int k = 0; k < 7; ++k) w[k] = (s & 1) ? w[k + 1] : w[k];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) w[k] = (s & 2) ? w[k + 2] : w[k];
+                TS v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = (o & 2) ? w[3 - k] : w[k];
+                TS* q = out + (size_t)d * ld;
+                if (vec) {
+                    store_quad(q, v);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (j0 + k < g.ny) q[k] = v[k];
+                }
             }
         }
     }
@@ -589,7 +649,7 @@ template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,
                       const double* eta, TS* psi_cm, size_t ld) {
     const TileGrid g = tile_grid(nx, ny);
-    hipLaunchKernelGGL((k_psi_to_cm<TS>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, r, psi,
+    hipLaunchKernelGGL((k_psi_to_cm<TS, sizeof(TS) == 4 ? 8 : 4>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), dim3(kBlock), 0, s, g, r, psi,
                        ldg, mu, eta, psi_cm, ld);
 }
 template void launch_psi_to_cm<double>(hipStream_t, int, int, int, const double*, size_t, const double*,

@@ -68,6 +68,7 @@ def test_slab_beam_fp64_matches_oracle():
     (130, 20, 2, 8, 12),     # three strips (two full + ragged), rank 12
     (7, 64, 3, 4, 1),        # single partial strip, rank one
     (64, 64, 4, 12, 16),     # exactly one full strip
+    (33, 29, 4, 8, 20),      # rank between the 16- and 32-direction blocks, ragged 16-cell tile
 ])
 def test_ragged_shapes_fp64(nx, ny, npol, naz, rank):
     p = problems.slab_beam(nx=nx, n_polar=npol, n_azim=naz, rank=rank, nsteps=4)
