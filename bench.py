@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="random_medium")
-    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed for the CPU baseline (0 = skip; 4 take about 10 s)")
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
     ap.add_argument("--fp64-steps", type=int, default=10,
                     help="steps of the FP64-sweep comparison leg at the same SI tolerance (0 = skip)")

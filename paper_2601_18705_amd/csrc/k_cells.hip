@@ -178,78 +178,152 @@ __global__ __launch_bounds__(kBlock) void k_psi0_wide(TileGrid g, int r, const d
     }
 }
 
-// Ranks up to 32: the r values X_k(e) of a cell are loaded together (all in flight) into the
-// thread's own LDS column; C0 (zero-padded to RMAX x RMAX), a0 and the directions' orientations
-// are staged in LDS once per block.  Each pass of 16 directions (the first also forming the
-// scalar flux) loops over k, reading X_k from the column and the row segment of C0 as LDS
-// broadcasts.  X is read from memory once, src0 written once per direction.
-template <typename TS, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double* __restrict__ X,
-                                                 const double* __restrict__ C0, const double* __restrict__ a0,
-                                                 const double* __restrict__ q, const double* __restrict__ sig_s,
-                                                 double inv_cdt, const double* __restrict__ mu,
-                                                 const double* __restrict__ eta, TS* __restrict__ src0, size_t ldg,
-                                                 double* __restrict__ phi, TS* __restrict__ s_e) {
-    static_assert(RMAX <= 32, "64 KiB of LDS for the parked columns");
-    constexpr int kPass = RMAX < 16 ? RMAX : 16;
-    __shared__ double sx[RMAX * kBlock];   // sx[k * kBlock + thread]
-    __shared__ double sC[RMAX * RMAX];     // sC[k * RMAX + d] = C0[k][d], zero outside r x r
-    __shared__ double sA[RMAX];
+// Four consecutive values as one vector access (16-byte aligned).
+__device__ inline void load_quad(const float* p, float (&v)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+}
+__device__ inline void load_quad(const double* p, double (&v)[4]) {
+    const double2 x = *reinterpret_cast<const double2*>(p), y = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = x.x, v[1] = x.y, v[2] = y.x, v[3] = y.y;
+}
+__device__ inline void store_quad(float* p, const float (&v)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void store_quad(double* p, const double (&v)[4]) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+// Ranks up to 32 on the matrix cores, in workgroup tiles of 8 columns x RT rows.
+// MFMA phase: per 16-cell piece of one column the wavefront forms D = C0^T X^T (blocks of 16 directions
+// x 16 cells) with v_mfma_f64_16x16x4.  C0^T (zero-padded to RMAX x RMAX) stays in registers for the
+// launch; X is read straight from memory as the B operand (four k rows of 16 consecutive cells per
+// instruction, rows past r clamped to a valid row that meets a zero of C0).  Lane l supplies A[l%16][l/16]
+// and B[l/16][l%16], and its accumulator element v is D[4 v + l/16][l%16].  The src0 values and
+// sigma_s phi / (4 pi) go to LDS (one row per direction plus one); phi = X a0 is summed over the lane's k
+// rows and across the four lane rows and written directly.
+// Store phase: in a direction's diagonal layout the tile's column holds RT consecutive positions t, which
+// touch RT/4 + 1 aligned groups of four; a thread writes one group of one column (a 16-byte store, or
+// single values in the groups cut by the tile's top and bottom rows), so eight consecutive threads fill a
+// whole 128-byte line.  The s_e row is written the same way into each of the four orientation copies.
+template <typename TS, int RMAX, int RT>
+__global__ __launch_bounds__(kBlock) void k_psi0_mfma(int nx, int ny, int r, const double* __restrict__ X,
+                                                      const double* __restrict__ C0, const double* __restrict__ a0,
+                                                      const double* __restrict__ q, const double* __restrict__ sig_s,
+                                                      double inv_cdt, const double* __restrict__ mu,
+                                                      const double* __restrict__ eta, TS* __restrict__ src0,
+                                                      size_t ldg, double* __restrict__ phi, TS* __restrict__ s_e) {
+    static_assert(RMAX % 16 == 0 && RMAX <= 32 && RT % 16 == 0, "16-direction blocks, 16-cell pieces");
+    constexpr int NB = RMAX / 16, KS = RMAX / 4;
+    constexpr int NP = 8 * RT / 16;                     // 16-cell pieces per tile
+    constexpr int SD = 8 * RT + 32 / (int)sizeof(TS);   // LDS row stride: two-way bank access in both phases
+    constexpr int NG = RT / 4 + 1;                      // aligned groups one column's RT positions touch
+    static_assert(NP % 8 == 0, "pieces in pairs per wavefront");
+    __shared__ TS sD[(RMAX + 1) * SD];
     __shared__ int so[RMAX];
-    for (int o = threadIdx.x; o < RMAX * RMAX; o += kBlock) {
-        const int k = o / RMAX, d = o % RMAX;
-        sC[o] = (k < r && d < r) ? C0[k * r + d] : 0.0;
-    }
-    for (int k = threadIdx.x; k < RMAX; k += kBlock) {
-        sA[k] = k < r ? a0[k] : 0.0;
-        so[k] = k < r ? orient_of(mu[k], eta[k]) : 0;
-    }
-    __syncthreads();
-    const long n = (long)g.nx * g.ny;
-    double* mine = sx + threadIdx.x;
-    for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
-#pragma unroll 1
-        for (int kc = 0; kc < 4; ++kc) {
-            int i, j;
-            if (!g.cell(b, kc, i, j)) continue;
-            const long e = (long)i * g.ny + j;
-            {
-                double v[RMAX];   // all loads first (clamped rows), then the LDS stores
+    const int lane = threadIdx.x & 63, c = lane & 15, kr = lane >> 4, w = threadIdx.x >> 6;
+    double A[NB][KS], al[KS];
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k) v[k] = X[(size_t)(k < r ? k : r - 1) * n + e];
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + kr;
+        al[ks] = k < r ? a0[k] : 0.0;
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k) mine[k * kBlock] = k < r ? v[k] : 0.0;
+        for (int nb = 0; nb < NB; ++nb) {
+            const int d = 16 * nb + c;
+            A[nb][ks] = (k < r && d < r) ? C0[k * r + d] : 0.0;
+        }
+    }
+    for (int k = threadIdx.x; k < RMAX; k += kBlock) so[k] = k < r ? orient_of(mu[k], eta[k]) : 0;
+    const int nty = (ny + RT - 1) / RT, ntiles = ((nx + 7) / 8) * nty;
+    const long n = (long)nx * ny;
+    const int G = diag_groups(ny);
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const int i0 = (b / nty) * 8, j0 = (b % nty) * RT;
+        __syncthreads();   // the previous tile's rows are stored (and so[] is set)
+        // pairs of pieces (m0, m0 + 4), m0 = w, w + 8, ...: the next pair's X is loaded before the
+        // current pair's products
+        double xb[2][KS];
+        auto load_pair = [&](int m0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int m = m0 + 4 * u, col = m / (RT / 16), row = (m % (RT / 16)) * 16 + c;
+                const long e = (long)min(i0 + col, nx - 1) * ny + min(j0 + row, ny - 1);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) xb[u][ks] = X[(size_t)min(4 * ks + kr, r - 1) * n + e];
             }
-            size_t pos[4];
-#pragma unroll
-            for (int o = 0; o < 4; ++o) pos[o] = diag_pos(g.nx, g.ny, o, i, j);
-            const double qe = q[e];
-            double ph = 0.0;
+        };
+        load_pair(w);
 #pragma unroll 1
-            for (int d0 = 0; d0 < r; d0 += kPass) {
-                double acc[kPass];
+        for (int m0 = w; m0 < NP; m0 += 8) {
+            double xc[2][KS];
 #pragma unroll
-                for (int d = 0; d < kPass; ++d) acc[d] = 0.0;
-#pragma unroll 4
-                for (int k = 0; k < RMAX; ++k) {
-                    const double xk = mine[k * kBlock];
-                    if (d0 == 0) ph = fma(xk, sA[k], ph);
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int d = 0; d < kPass; ++d) acc[d] = fma(xk, sC[k * RMAX + d0 + d], acc[d]);
+                for (int ks = 0; ks < KS; ++ks) xc[u][ks] = xb[u][ks];
+            if (m0 + 8 < NP) load_pair(m0 + 8);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int m = m0 + 4 * u, col = m / (RT / 16), row = (m % (RT / 16)) * 16 + c;
+                const bool live = i0 + col < nx && j0 + row < ny;
+                const long e = (long)min(i0 + col, nx - 1) * ny + min(j0 + row, ny - 1);
+                const int loc = col * RT + row;
+                dv4 acc[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = dv4{0.0, 0.0, 0.0, 0.0};
+                double ph = 0.0;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[nb][ks], xc[u][ks], acc[nb], 0, 0, 0);
+                    ph = fma(xc[u][ks], al[ks], ph);
                 }
-                if (d0 == 0) {
-                    phi[e] = ph;
-                    const TS se = (TS)(sig_s[e] * ph / kFourPi);
+                ph += __shfl_xor(ph, 16);
+                ph += __shfl_xor(ph, 32);
+                if (live && kr == 0) phi[e] = ph;
+                const double qe = q[e];
 #pragma unroll
-                    for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
-                }
+                for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                for (int d = 0; d < kPass; ++d) {
-                    if (d0 + d >= r) break;
-                    const int o = so[d0 + d];
-                    const size_t pd = o == 0 ? pos[0] : o == 1 ? pos[1] : o == 2 ? pos[2] : pos[3];
-                    src0[(size_t)(d0 + d) * ldg + pd] = (TS)(qe + acc[d] * inv_cdt);
-                }
+                    for (int v = 0; v < 4; ++v)
+                        sD[(16 * nb + 4 * v + kr) * SD + loc] = (TS)(qe + acc[nb][v] * inv_cdt);
+                if (kr == 0) sD[RMAX * SD + loc] = (TS)(sig_s[e] * ph / kFourPi);
+            }
+        }
+        __syncthreads();
+        const int jmax = min(j0 + RT, ny) - 1;   // last row of the tile inside the grid
+#pragma unroll 2
+        for (int task = threadIdx.x; task < (r + 4) * NG * 8; task += kBlock) {
+            const int cc = task & 7, gi = (task >> 3) % NG, dd = (task >> 3) / NG;
+            const int i = i0 + cc;
+            if (i >= nx) continue;
+            const int o = dd < r ? so[dd] : dd - r;
+            const TS* sv = sD + (dd < r ? dd : RMAX) * SD + cc * RT;
+            TS* plane = dd < r ? src0 + (size_t)dd * ldg : s_e + (size_t)(dd - r) * ldg;
+            const int ip = (o & 1) ? nx - 1 - i : i, l = ip & 63;
+            const int tlo = ((o & 2) ? ny - 1 - jmax : j0) + l;   // first position of the column's rows
+            const int gg = (tlo >> 2) + gi;
+            TS v[4];
+            int nok = 0, okm = 0;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int jp = 4 * gg + s4 - l, j = (o & 2) ? ny - 1 - jp : jp;
+                const bool ok = j >= j0 && j <= jmax;
+                v[s4] = sv[ok ? j - j0 : 0];
+                nok += ok;
+                okm |= (int)ok << s4;
+            }
+            if (nok == 0) continue;
+            TS* p = plane + (((size_t)(ip >> 6) * G + gg) * 64 + l) * 4;
+            if (nok == 4) {
+                store_quad(p, v);
+            } else {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    if (okm >> s4 & 1) p[s4] = v[s4];
             }
         }
     }
@@ -267,22 +341,6 @@ __global__ __launch_bounds__(kBlock) void k_psi0(TileGrid g, int r, const double
 // when the orientation flips j), which lie in the aligned groups floor(a/4) and floor(a/4) + 1 of the
 // column's lane: both are loaded as vectors and the four values picked by a & 3.  DU directions are
 // loaded before any is stored; positions of rows beyond ny are clamped into the layout and not stored.
-__device__ inline void load_quad(const float* p, float (&v)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
-}
-__device__ inline void load_quad(const double* p, double (&v)[4]) {
-    const double2 x = *reinterpret_cast<const double2*>(p), y = *reinterpret_cast<const double2*>(p + 2);
-    v[0] = x.x, v[1] = x.y, v[2] = y.x, v[3] = y.y;
-}
-__device__ inline void store_quad(float* p, const float (&v)[4]) {
-    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ inline void store_quad(double* p, const double (&v)[4]) {
-    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
-}
-
 template <typename TS, int DU>
 __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const TS* __restrict__ psi, size_t ldg,
                                                       const double* __restrict__ mu, const double* __restrict__ eta,
@@ -612,17 +670,20 @@ template <typename TS>
 void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
                  const double* q, const double* sig_s, double inv_cdt, const double* mu, const double* eta,
                  TS* src0, size_t ldg, double* phi, TS* s_e) {
-    const TileGrid g = tile_grid(nx, ny);
-    dim3 gr(std::min(g.ntx * g.nty, kMaxTileBlocks)), b(kBlock);
-    if (r <= 8)
-        hipLaunchKernelGGL((k_psi0<TS, 8>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
-    else if (r <= 16)
-        hipLaunchKernelGGL((k_psi0<TS, 16>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
-    else if (r <= 32)
-        hipLaunchKernelGGL((k_psi0<TS, 32>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
-    else
-        hipLaunchKernelGGL((k_psi0_wide<TS, 64>), gr, b, 0, s, g, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta, src0, ldg,
-                           phi, s_e);
+    constexpr int RT = sizeof(TS) == 4 ? 64 : 32;
+    const int tiles = ((nx + 7) / 8) * ((ny + RT - 1) / RT);
+    const dim3 b(kBlock), gm(std::min(tiles, 4096));
+    if (r <= 16) {
+        hipLaunchKernelGGL((k_psi0_mfma<TS, 16, RT>), gm, b, 0, s, nx, ny, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta,
+                           src0, ldg, phi, s_e);
+    } else if (r <= 32) {
+        hipLaunchKernelGGL((k_psi0_mfma<TS, 32, RT>), gm, b, 0, s, nx, ny, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta,
+                           src0, ldg, phi, s_e);
+    } else {
+        const TileGrid g = tile_grid(nx, ny);
+        hipLaunchKernelGGL((k_psi0_wide<TS, 64>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), b, 0, s, g, r, X, C0,
+                           a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
+    }
 }
 template void launch_psi0<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
                                   const double*, const double*, double, const double*, const double*, double*, size_t,

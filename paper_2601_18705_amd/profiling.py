@@ -4,7 +4,8 @@ Used to turn `rocprofv3 --kernel-trace --stats -f csv` and `rocprofv3 --pmc
 FETCH_SIZE` / `--pmc WRITE_SIZE` runs of bench.py into the short text and JSON
 records kept with the repository.  Reads CSV files only; runs nothing.
 
-    python -m paper_2601_18705_amd.profiling stats <kernel_stats.csv> <title> <command>
+    python -m paper_2601_18705_amd.profiling stats <kernel_stats.csv> <title> <command> [note]
+        [comma-separated kernel name prefixes to leave out]
     python -m paper_2601_18705_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> <calibration MiB> <kernel source> <out.json> [kernel name prefix]
 
@@ -26,8 +27,11 @@ def short_name(name):
     return name.replace("void ", "")
 
 
-def kernel_stats_md(path, title, command, note=""):
-    rows = list(csv.DictReader(open(path)))
+def kernel_stats_md(path, title, command, note="", exclude=()):
+    """Markdown table of a kernel-statistics CSV; kernels whose short name starts with one of the
+    exclude prefixes are dropped and the shares recomputed over the rest."""
+    rows = [r for r in csv.DictReader(open(path)) if not short_name(r["Name"]).startswith(tuple(exclude))]
+    total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
     out = [f"# {title}", "", "Command (from the repository root on an MI355X, ROCm 7.2):", "", "```",
            "cd /tmp && export TMPDIR=/tmp", command, "```", ""]
     if note:
@@ -37,7 +41,7 @@ def kernel_stats_md(path, title, command, note=""):
     for r in rows:
         out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
-                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {100.0 * float(r['TotalDurationNs']) / total:.1f} |")
     return "\n".join(out) + "\n"
 
 
@@ -78,7 +82,8 @@ def sweep_traffic(fetch_csv, write_csv, calib_mib, sweep_source, sweep_prefix="k
 
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
-        sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else ""))
+        sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else "",
+                                         argv[5].split(",") if len(argv) > 5 else ()))
     elif len(argv) in (6, 7) and argv[0] == "traffic":
         rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4], *argv[6:7])
         with open(argv[5], "w") as fh:
