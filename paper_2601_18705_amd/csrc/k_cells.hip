@@ -178,21 +178,24 @@ __global__ __launch_bounds__(kBlock) void k_psi0_wide(TileGrid g, int r, const d
     }
 }
 
-// Four consecutive values as one vector access (16-byte aligned).
+// Four consecutive values as vector accesses (16-byte aligned), on the compiler's native vector types
+// (the field-wise HIP vector structs can be split into narrower memory instructions).
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
 __device__ inline void load_quad(const float* p, float (&v)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+    const fv4 x = *reinterpret_cast<const fv4*>(p);
+    v[0] = x[0], v[1] = x[1], v[2] = x[2], v[3] = x[3];
 }
 __device__ inline void load_quad(const double* p, double (&v)[4]) {
-    const double2 x = *reinterpret_cast<const double2*>(p), y = *reinterpret_cast<const double2*>(p + 2);
-    v[0] = x.x, v[1] = x.y, v[2] = y.x, v[3] = y.y;
+    const dv2 x = *reinterpret_cast<const dv2*>(p), y = *reinterpret_cast<const dv2*>(p + 2);
+    v[0] = x[0], v[1] = x[1], v[2] = y[0], v[3] = y[1];
 }
 __device__ inline void store_quad(float* p, const float (&v)[4]) {
-    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<fv4*>(p) = fv4{v[0], v[1], v[2], v[3]};
 }
 __device__ inline void store_quad(double* p, const double (&v)[4]) {
-    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+    *reinterpret_cast<dv2*>(p) = dv2{v[0], v[1]};
+    *reinterpret_cast<dv2*>(p + 2) = dv2{v[2], v[3]};
 }
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
@@ -357,14 +360,6 @@ __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const T
         const int i = tx * kTileCols + (threadIdx.x & 7);
         const int j0 = ty * kTileRows + (threadIdx.x >> 3) * 4;
         if (i >= g.nx || j0 >= g.ny) continue;
-        size_t cb[4];   // element offset of group 0 of the column's lane, per orientation
-        int sa[4];      // first diagonal position a of the four rows, per orientation
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const int ip = (o & 1) ? g.nx - 1 - i : i, l = ip & 63;
-            cb[o] = ((size_t)(ip >> 6) * G * 64 + l) * 4;
-            sa[o] = ((o & 2) ? g.ny - 4 - j0 : j0) + l;
-        }
         TS* out = psi_cm + (size_t)i * g.ny + j0;
         for (int d0 = 0; d0 < r; d0 += DU) {
             TS lo[DU][4], hi[DU][4];
@@ -372,33 +367,41 @@ __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const T
             for (int u = 0; u < DU; ++u) {
                 const int d = min(d0 + u, r - 1);
                 const int o = so[d];
-                const size_t c = o == 0 ? cb[0] : o == 1 ? cb[1] : o == 2 ? cb[2] : cb[3];
-                const int a = o == 0 ? sa[0] : o == 1 ? sa[1] : o == 2 ? sa[2] : sa[3];
-                const TS* p = psi + (size_t)d * ldg + c;
+                // the column's lane l in direction d's layout, and the first position a of the rows
+                // (arithmetic on the orientation bits: indexed per-thread tables end up in LDS)
+                const int ip = (o & 1) ? g.nx - 1 - i : i, l = ip & 63;
+                const int a = ((o & 2) ? g.ny - 4 - j0 : j0) + l;
+                const TS* p = psi + (size_t)d * ldg + ((size_t)(ip >> 6) * G * 64 + l) * 4;
                 load_quad(p + (size_t)max(a >> 2, 0) * 256, lo[u]);
                 load_quad(p + (size_t)min((a >> 2) + 1, G - 1) * 256, hi[u]);
             }
 #pragma unroll
             for (int u = 0; u < DU; ++u) {
                 const int d = d0 + u;
-                if (d >= r) break;
-                const int o = so[d];
-                const int s = (o == 0 ? sa[0] : o == 1 ? sa[1] : o == 2 ? sa[2] : sa[3]) & 3;
-                TS w[8] = {lo[u][0], lo[u][1], lo[u][2], lo[u][3], hi[u][0], hi[u][1], hi[u][2], hi[u][3]};
+                if (d < r) {   // a guard, not a break: the loop must unroll (lo, hi stay in registers)
+                    const int o = so[d];
+                    const int l = ((o & 1) ? g.nx - 1 - i : i) & 63;
+                    const int s = (((o & 2) ? g.ny - 4 - j0 : j0) + l) & 3;
+                    // positions a & 3 .. (a & 3) + 3 of the two groups, selected on named values (an
+                    // indexed array here is turned into address selects and placed in LDS)
+                    const bool s1 = s & 1, s2 = s & 2;
+                    TS a0 = s1 ? lo[u][1] : lo[u][0], a1 = s1 ? lo[u][2] : lo[u][1];
+                    TS a2 = s1 ? lo[u][3] : lo[u][2], a3 = s1 ? hi[u][0] : lo[u][3];
+                    const TS a4 = s1 ? hi[u][1] : hi[u][0], a5 = s1 ? hi[u][2] : hi[u][1];
+                    a0 = s2 ? a2 : a0;
+                    a1 = s2 ? a3 : a1;
+                    a2 = s2 ? a4 : a2;
+                    a3 = s2 ? a5 : a3;
+                    const bool rev = o & 2;
+                    TS v[4] = {rev ? a3 : a0, rev ? a2 : a1, rev ? a1 : a2, rev ? a0 : a3};
+                    TS* q = out + (size_t)d * ld;
+                    if (vec) {
+                        store_quad(q, v);
+                    } else {
 #pragma unroll
-                for (int k = 0; k < 7; ++k) w[k] = (s & 1) ? w[k + 1] : w[k];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) w[k] = (s & 2) ? w[k + 2] : w[k];
-                TS v[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[k] = (o & 2) ? w[3 - k] : w[k];
-                TS* q = out + (size_t)d * ld;
-                if (vec) {
-                    store_quad(q, v);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (j0 + k < g.ny) q[k] = v[k];
+                        for (int k = 0; k < 4; ++k)
+                            if (j0 + k < g.ny) q[k] = v[k];
+                    }
                 }
             }
         }

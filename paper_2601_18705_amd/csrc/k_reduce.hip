@@ -93,59 +93,81 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
 }
 
 // ---------------------------------------------------------------------------------------------- X = V Rinv
-template <typename TV, int RMAX>
-__global__ __launch_bounds__(kBlock) void k_trmm(int n, int r, const TV* __restrict__ V, size_t ldv,
-                                                 const double* __restrict__ Rinv, double* __restrict__ X) {
-    __shared__ double sR[RMAX * RMAX];
-    for (int o = threadIdx.x; o < r * r; o += kBlock) sR[(o / r) * RMAX + o % r] = Rinv[o];
-    __syncthreads();
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double v[RMAX];
-    const size_t ve = (size_t)e;
+// X = V Rinv with Rinv upper triangular, on the matrix cores.  Per 16-cell tile a wavefront forms
+// D = Rinv^T V^T (blocks of 16 output planes x 16 cells) with v_mfma_f64_16x16x4: Rinv^T stays in
+// registers for the launch, V is read straight from memory as the B operand (four planes of 16
+// consecutive cells per instruction; planes past r are clamped to a valid one that meets a zero of Rinv),
+// and output block mb only takes the k-steps j <= 16 mb + 15 of the triangle.  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; its accumulator element v is D[4 v + l/16][l%16], so a store writes
+// 16 consecutive cells of four planes.  V may be X (in place): a wavefront loads all rows of its tiles
+// before it stores any, and the tiles of different wavefronts are disjoint.  Nothing is done when skip
+// is given and set.
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+template <typename TV, int RMAX, int T>
+__global__ __launch_bounds__(kBlock) void k_trmm_mfma(int n, int r, const TV* V, size_t ldv,
+                                                      const double* __restrict__ Rinv, double* X,
+                                                      const int* __restrict__ skip) {
+    static_assert(RMAX % 16 == 0, "16-plane blocks");
+    if (skip && *skip) return;
+    constexpr int NB = RMAX / 16, KS = RMAX / 4;
+    const int lane = threadIdx.x & 63, c = lane & 15, kr = lane >> 4;
+    double A[NB][KS];
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) {
-        const double x = (double)V[(size_t)(j < r ? j : r - 1) * ldv + ve];
-        v[j] = (j < r) ? x : 0.0;
-    }
-    // k fully unrolled: the triangle j <= k is resolved at compile time (r (r+1)/2 multiply-adds)
+    for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-        if (k < r) {
-            double acc = 0.0;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int j = 4 * ks + kr, k = 16 * mb + c;
+            A[mb][ks] = (ks <= 4 * mb + 3 && j <= k && k < r) ? Rinv[j * r + k] : 0.0;
+        }
+    const long tiles = ((long)n + 15) / 16;
+    const long wave = ((long)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const long nwaves = (long)gridDim.x * (kBlock / 64);
+    for (long t0 = wave * T; t0 < tiles; t0 += nwaves * T) {
+        double xb[T][KS];
+        long e[T];
 #pragma unroll
-            for (int j = 0; j <= k; ++j) acc = fma(v[j], sR[j * RMAX + k], acc);
-            X[(size_t)k * n + e] = acc;
+        for (int u = 0; u < T; ++u) {
+            e[u] = min((t0 + u) * 16 + c, (long)n - 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) xb[u][ks] = (double)V[(size_t)min(4 * ks + kr, r - 1) * ldv + e[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            dv4 acc[NB];
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) {
+                acc[mb] = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    if (ks <= 4 * mb + 3)
+                        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[mb][ks], xb[u][ks], acc[mb], 0, 0, 0);
+            }
+            if ((t0 + u) * 16 + c < n) {
+#pragma unroll
+                for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int k = 16 * mb + 4 * v + kr;
+                        if (k < r) X[(size_t)k * n + e[u]] = acc[mb][v];
+                    }
+            }
         }
     }
 }
 
-// X = X Rinv in place (no aliasing qualifiers: every thread loads its cell's row before it stores),
-// skipped when *skip is set
-template <int RMAX>
-__global__ __launch_bounds__(kBlock) void k_trmm_inplace(int n, int r, double* X, const double* __restrict__ Rinv,
-                                                         const int* __restrict__ skip) {
-    if (*skip) return;
-    __shared__ double sR[RMAX * RMAX];
-    for (int o = threadIdx.x; o < r * r; o += kBlock) sR[(o / r) * RMAX + o % r] = Rinv[o];
-    __syncthreads();
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double v[RMAX];
-#pragma unroll
-    for (int j = 0; j < RMAX; ++j) {
-        const double x = X[(size_t)(j < r ? j : r - 1) * n + e];
-        v[j] = (j < r) ? x : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-        if (k < r) {
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j <= k; ++j) acc = fma(v[j], sR[j * RMAX + k], acc);
-            X[(size_t)k * n + e] = acc;
-        }
-    }
+template <typename TV>
+void launch_trmm_any(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X,
+                     const int* skip) {
+    const long tiles = ((long)n + 15) / 16;
+    const dim3 b(kBlock);
+    auto grid = [&](int t) { return dim3((unsigned)std::min<long>((tiles + 4 * t - 1) / (4 * t), 2048)); };
+    if (r <= 16)
+        hipLaunchKernelGGL((k_trmm_mfma<TV, 16, 2>), grid(2), b, 0, s, n, r, V, ldv, Rinv, X, skip);
+    else if (r <= 32)
+        hipLaunchKernelGGL((k_trmm_mfma<TV, 32, 2>), grid(2), b, 0, s, n, r, V, ldv, Rinv, X, skip);
+    else
+        hipLaunchKernelGGL((k_trmm_mfma<TV, 64, 1>), grid(1), b, 0, s, n, r, V, ldv, Rinv, X, skip);
 }
 
 // ops layout: Axp, Axm, Ayp, Aym, Mt, Ms, G (r x r each), qX[r], b[4][r]
@@ -204,28 +226,12 @@ void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv,
 }
 
 void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip) {
-    dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
-    if (r <= 8)
-        hipLaunchKernelGGL((k_trmm_inplace<8>), g, b, 0, s, n, r, X, Rinv, skip);
-    else if (r <= 16)
-        hipLaunchKernelGGL((k_trmm_inplace<16>), g, b, 0, s, n, r, X, Rinv, skip);
-    else if (r <= 32)
-        hipLaunchKernelGGL((k_trmm_inplace<32>), g, b, 0, s, n, r, X, Rinv, skip);
-    else
-        hipLaunchKernelGGL((k_trmm_inplace<64>), g, b, 0, s, n, r, X, Rinv, skip);
+    launch_trmm_any<double>(s, n, r, X, (size_t)n, Rinv, X, skip);
 }
 
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X) {
-    dim3 g((n + kBlock - 1) / kBlock), b(kBlock);
-    if (r <= 8)
-        hipLaunchKernelGGL((k_trmm<TV, 8>), g, b, 0, s, n, r, V, ldv, Rinv, X);
-    else if (r <= 16)
-        hipLaunchKernelGGL((k_trmm<TV, 16>), g, b, 0, s, n, r, V, ldv, Rinv, X);
-    else if (r <= 32)
-        hipLaunchKernelGGL((k_trmm<TV, 32>), g, b, 0, s, n, r, V, ldv, Rinv, X);
-    else
-        hipLaunchKernelGGL((k_trmm<TV, 64>), g, b, 0, s, n, r, V, ldv, Rinv, X);
+    launch_trmm_any<TV>(s, n, r, V, ldv, Rinv, X, nullptr);
 }
 template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, const double*, double*);
 template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, const double*, double*);
