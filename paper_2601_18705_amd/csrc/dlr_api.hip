@@ -629,11 +629,13 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->ld = ((size_t)I->N + 63) / 64 * 64;   // compact column-major cell planes (e = i * ny + j)
     I->ldg = dlr::diag_plane(I->nx, I->ny);
     I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);
-    // chunk loop of the Gram kernel: four blocks per CU keep enough loads in flight (measured
-    // against two), but no more blocks than there are 64-cell chunks; the projection kernel's
-    // larger LDS footprint does better with two per CU
+    // Gram kernel: wavefronts take 32-cell passes; two blocks per CU keep all wavefronts resident at
+    // once (a second, partly filled round of wavefronts cost a third of the time) and no block is
+    // launched without a pass.  The projection kernel walks 64-cell chunks, two blocks per CU.
     const int chunks = (int)std::min<long>(((long)I->N + 63) / 64, 1 << 20);
-    I->nb_gram = std::max(1, std::min(chunks, 1024));
+    const long passes = ((long)I->N + 31) / 32;
+    I->nb_gram = (int)std::max<long>(1, std::min<long>((passes + 3) / 4, 512));
+    I->nb_gram_ang = std::max(1, std::min((((int)I->nq + 31) / 32 + 3) / 4, 32));
     I->nb_proj = std::max(1, std::min(chunks, 512));
     const size_t rr = (size_t)I->r * I->r;
     I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),

@@ -17,6 +17,7 @@ namespace dlr {
 namespace {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;   // four wavefronts
 constexpr int kPC = 64;         // cells per chunk = 16 k-steps of 4 cells
@@ -98,68 +99,103 @@ template <> struct AccOf<double> { typedef dv4 type; };
 template <> struct AccOf<float> { typedef fv4 type; };
 
 // ------------------------------------------------------------------------------------------------ Gram
-// partial_b[i*r + j] = scale * sum over the chunks of block b of V_i(e) wt(e) V_j(e), wt = weight or 1.
-// The next chunk's global loads are staged in registers while the current chunk's MFMAs run.
+// partial_b[i*r + j] = scale * sum over the cells of block b of V_i(e) wt(e) V_j(e), wt = weight or 1.
+// Operands come straight from memory, no LDS: a wavefront takes passes of 32 cells, and in a pass lane l
+// holds cells 8 (l/16) .. 8 (l/16) + 7 of plane 16 tb + l%16 for each 16-plane block tb (one 32- or
+// 64-byte load per block).  k-step s (0..7) of v_mfma_f64_16x16x4 pairs cell 8 (l/16) + s of the A and B
+// operands, so the eight k-steps cover the pass's 32 cells (the sum over cells is order-free).  Only the
+// tiles ti <= tj are formed (the matrix is symmetric; the mirror is written at the end).  Planes past r are
+// clamped to a valid one (their rows and columns are not stored), cells past n are zero.  The four
+// wavefronts' sums are added through LDS in wavefront order, so every result is bitwise reproducible.
 template <typename TV, int RT>
 __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV* __restrict__ V, size_t ldv,
                                                         const double* __restrict__ weight, double scale,
                                                         double* __restrict__ partials) {
-    constexpr int RP = 16 * RT, NT = RT * RT, TPW = (NT + 3) / 4;
-    constexpr int NV = (RP * kPC + kThreads - 1) / kThreads;
-    __shared__ double sV[RP * kPS];
-    __shared__ double sW[kPC];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    dv4 acc[TPW];
+    constexpr int NT = RT * (RT + 1) / 2;
+    __shared__ double sacc[NT * 4 * 64];
+    const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & 3, p = lane & 15, g = lane >> 4;
+    dv4 acc[NT];
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) acc[s] = dv4{0.0, 0.0, 0.0, 0.0};
-    const long nch = (n + kPC - 1) / kPC;
-    double g[NV];
-    double gw = 1.0;
-    auto stage = [&](long ch) {
-        const long c0 = ch * kPC;
+    for (int t = 0; t < NT; ++t) acc[t] = dv4{0.0, 0.0, 0.0, 0.0};
+    size_t base[RT];
 #pragma unroll
-        for (int u = 0; u < NV; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            const int p = idx / kPC, c = idx % kPC;
-            const long e = c0 + c;
-            g[u] = (p < r && e < n) ? (double)V[(size_t)p * ldv + (size_t)e] : 0.0;
-        }
-        if (threadIdx.x < kPC) {
-            const long e = c0 + threadIdx.x;
-            gw = (weight && e < n) ? weight[e] : 1.0;
-        }
-    };
-    long ch = blockIdx.x;
-    if (ch < nch) stage(ch);
-    for (; ch < nch; ch += gridDim.x) {
-        __syncthreads();
+    for (int tb = 0; tb < RT; ++tb) base[tb] = (size_t)min(16 * tb + p, r - 1) * ldv;
+    // 8 consecutive cells as two or four 16-byte loads: planes and their leading dimension are aligned
+    const bool vec = (ldv % 8 == 0) && ((reinterpret_cast<uintptr_t>(V) & 63) == 0);
+    const long passes = (n + 31) / 32;
+    const long stride = (long)gridDim.x * 4;
+    double cur[RT][8], wt[8];
+    auto load = [&](long ps) {
+        const long c0 = ps * 32 + 8 * g;
+        if (vec && c0 + 8 <= n) {
 #pragma unroll
-        for (int u = 0; u < NV; ++u) {
-            const int idx = threadIdx.x + u * kThreads;
-            if (idx < RP * kPC) sV[(idx / kPC) * kPS + idx % kPC] = g[u];
-        }
-        if (threadIdx.x < kPC) sW[threadIdx.x] = gw;
-        __syncthreads();
-        if (ch + gridDim.x < nch) stage(ch + gridDim.x);
-        for (int ks = 0; ks < kPC / 4; ++ks) {
-            const int c = 4 * ks + (lane >> 4);
-            const double wc = sW[c];
+            for (int tb = 0; tb < RT; ++tb) {
+                const TV* q = V + base[tb] + c0;
+                if constexpr (sizeof(TV) == 4) {
+                    const fv4 x = *reinterpret_cast<const fv4*>(q), y = *reinterpret_cast<const fv4*>(q + 4);
 #pragma unroll
-            for (int s = 0; s < TPW; ++s) {
-                const int t = w + 4 * s;
-                if (t < NT) {
-                    const int ti = t / RT, tj = t % RT;
-                    acc[s] = mfma4(sV[(ti * 16 + (lane & 15)) * kPS + c],
-                                   wc * sV[(tj * 16 + (lane & 15)) * kPS + c], acc[s]);
+                    for (int k = 0; k < 4; ++k) cur[tb][k] = x[k], cur[tb][4 + k] = y[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; k += 2) {
+                        const dv2 x = *reinterpret_cast<const dv2*>(q + k);
+                        cur[tb][k] = x[0], cur[tb][k + 1] = x[1];
+                    }
                 }
             }
+        } else {
+#pragma unroll
+            for (int tb = 0; tb < RT; ++tb)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) cur[tb][k] = c0 + k < n ? (double)V[base[tb] + c0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wt[k] = (weight && c0 + k < n) ? weight[c0 + k] : 1.0;
+    };
+    long ps = blockIdx.x * 4 + w;
+    if (ps < passes) load(ps);
+    for (; ps < passes; ps += stride) {
+        double v[RT][8], vw[RT][8];
+#pragma unroll
+        for (int tb = 0; tb < RT; ++tb)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[tb][k] = cur[tb][k], vw[tb][k] = cur[tb][k] * wt[k];
+        if (ps + stride < passes) load(ps + stride);   // in flight during the products below
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int t = 0;
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                for (int tj = ti; tj < RT; ++tj, ++t) acc[t] = mfma4(v[ti][k], vw[tj][k], acc[t]);
         }
     }
-    double* out = partials + (size_t)blockIdx.x * r * r;
+    // wavefront 0 writes its sums, wavefronts 1..3 add theirs in order, then the block's partial is stored
+#pragma unroll 1
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww) {
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-        const int t = w + 4 * s;
-        if (t < NT) store_tile(out, r, t / RT, t % RT, acc[s], scale);
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    double& dst = sacc[(t * 4 + e) * 64 + lane];
+                    dst = (ww == 0 ? 0.0 : dst) + acc[t][e];
+                }
+        }
+        __syncthreads();
+    }
+    double* out = partials + (size_t)blockIdx.x * r * r;
+    for (int o = threadIdx.x; o < NT * 4 * 64; o += kThreads) {
+        const int t = o / 256, e = (o / 64) % 4, l = o % 64;
+        int ti = 0, tj = 0, tt = t;
+        while (tt >= RT - ti) tt -= RT - ti, ++ti;
+        tj = ti + tt;
+        const int i = ti * 16 + 4 * e + (l >> 4), j = tj * 16 + (l & 15);   // D[4 e + l/16][l%16]
+        if (i < r && j < r) {
+            const double val = sacc[o] * scale;
+            out[i * r + j] = val;
+            if (ti != tj) out[j * r + i] = val;
+        }
     }
 }
 
