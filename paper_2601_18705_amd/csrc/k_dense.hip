@@ -11,6 +11,7 @@
 //    Cbar = sum w_q B_q^{-1}, zeta = sum w_q B_q^{-1} Q_q, and L_q = B_q^{-1} (M_s Lbar / 4 pi + Q_q);
 //  * a one-sided (Hestenes) Jacobi SVD of the r x r coupling matrix.
 #include "dlr_internal.h"
+#include "wave_ops.h"
 
 namespace dlr {
 
@@ -94,8 +95,8 @@ __device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, double* pr
 
 // The same solve on one wavefront without barriers, for systems of a single workgroup's
 // critical path: lane i holds row i of the augmented system in registers, the pivot of
-// column k is the largest remaining |A_ik| (ties to the lowest row) found by a wavefront
-// reduction, the pivot row is broadcast through prow (the wavefront's LDS accesses execute in
+// column k is the largest remaining |A_ik| (ties to the lowest row) found by a DPP wavefront
+// maximum and a ballot, the pivot row is broadcast through prow (the wavefront's LDS accesses execute in
 // order), and column k is eliminated from every other row.  The solution overwrites the
 // right-hand-side column (x_k in row k).  Called by the whole workgroup; wavefront 0 works.
 template <int RMAX>
@@ -117,18 +118,11 @@ __device__ __forceinline__ void gauss_jordan_wave_impl(double* Aug, int r, int l
     for (int k = 0; k < RMAX; ++k) {
         if (k < r) {
             __atomic_signal_fence(__ATOMIC_SEQ_CST);   // one pivot's LDS traffic at a time
-            double v = used ? -1.0 : fabs(a[k]);
-            int idx = i;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(v, off);
-                const int oi = __shfl_xor(idx, off);
-                if (ov > v || (ov == v && oi < idx)) {
-                    v = ov;
-                    idx = oi;
-                }
-            }
-            const int p = __builtin_amdgcn_readfirstlane(idx);
+            const double mine = used ? -1.0 : fabs(a[k]);
+            const double v = wave_max(mine);
+            // the lowest row holding the maximum (the lowest free row when no value compares equal)
+            const unsigned long long hit = __ballot(mine == v);
+            const int p = hit ? __builtin_ctzll(hit) : __builtin_ctzll(__ballot(!used));
             if (!(v > 0.0) || !isfinite(v)) isbad = true;
             if (i == p) {
 #pragma unroll
@@ -281,11 +275,8 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                 pi = (q == f) ? q : 0x7fffffff;
                 if (q == f && !elig) bad = 1;
             }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                pi = min(pi, __shfl_xor(pi, off));
-                sec = fmax(sec, __shfl_xor(sec, off));
-            }
+            pi = wave_min(pi);
+            sec = wave_max(sec);
             if (lane == 0) {
                 si[wv] = pi;
                 sv2[wv] = sec;
@@ -312,11 +303,8 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                 const double* sl = &X[kXEx2 + ((size_t)(j & 1) * kDeimMaxGroups + lane) * (2 + kMaxRank)];
                 double pg = (lane < G) ? xload(&sl[0]) : 2147483647.0;
                 double sg = (lane < G) ? xload(&sl[1]) : 0.0;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    pg = fmin(pg, __shfl_xor(pg, off));
-                    sg = fmax(sg, __shfl_xor(sg, off));
-                }
+                pg = wave_min(pg);
+                sg = wave_max(sg);
                 if (lane == 0) {
                     sP = (pg < 2147483647.0) ? (int)pg : -1;
                     sSecond = sg;
@@ -328,9 +316,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             __syncthreads();
         };
         // this group's maximum over the rows not yet chosen
-        double m = v;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        const double m = wave_max(v);
         if (lane == 0) sv[wv] = m;
         __syncthreads();
         double mw = sv[0];
@@ -341,11 +327,8 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             const double thl = (1.0 - a.tie_tol) * mw;
             int pi = (elig && v >= thl) ? q : 0x7fffffff;
             double sec = (elig && v < thl) ? v : 0.0;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                pi = min(pi, __shfl_xor(pi, off));
-                sec = fmax(sec, __shfl_xor(sec, off));
-            }
+            pi = wave_min(pi);
+            sec = wave_max(sec);
             if (lane == 0) {
                 si[wv] = pi;
                 sv2[wv] = sec;
@@ -397,19 +380,14 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                 const double sg = (lane < G) ? xload(&sl[1]) : 0.0;
                 const double ci = word - tag * 32768.0;
                 const double cg = (lane < G && ci < 16384.0) ? ci : 2147483647.0;
-                double Mx = mg;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) Mx = fmax(Mx, __shfl_xor(Mx, off));
+                const double Mx = wave_max(mg);
                 const double Mpos = fmax(Mx, 0.0);
                 const double thr = (1.0 - a.tie_tol) * Mpos;
                 const bool band = lane < G && mg >= thr && mg < Mx;
                 double cand = (lane < G && mg == Mx) ? cg : 2147483647.0;
                 double scnd = (lane < G) ? ((mg < thr) ? fmax(mg, 0.0) : ((mg == Mx) ? sg : 0.0)) : 0.0;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    cand = fmin(cand, __shfl_xor(cand, off));
-                    scnd = fmax(scnd, __shfl_xor(scnd, off));
-                }
+                cand = wave_min(cand);
+                scnd = wave_max(scnd);
                 const bool fallback = __ballot(band) != 0ull;
                 if (lane == 0) {
                     sM = Mpos;
@@ -428,9 +406,8 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             if (tid == 0) xstore(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + g], mw);
             group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
             if (wv == 0) {
-                double mg = (lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) mg = fmax(mg, __shfl_xor(mg, off));
+                const double mg =
+                    wave_max((lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0);
                 if (lane == 0) sM = fmax(mg, 0.0);
             }
             __syncthreads();

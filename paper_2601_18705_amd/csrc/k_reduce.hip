@@ -17,10 +17,13 @@ constexpr int kBlock = 256;
 // residual 1e-6 of a column against the previous ones) flags status_code: the columns are too
 // close to dependent for Cholesky QR and the CGS2 fallback recomputes the factor.
 // One wavefront, no barriers: lane j holds column j of the (symmetric) matrix in registers,
-// padded to RMAX x RMAX with the identity.  Per pivot k the lanes form their entry of row k of
-// R' and publish it in an LDS row, from which every lane reads R'_ki for its trailing entries
-// i > k (the wavefront's LDS accesses execute in order, so no barrier is needed).  The inverse
-// is formed row by row from the bottom the same way, lane j holding column j of R'^{-1}.
+// padded to RMAX x RMAX with the identity, and column j of an identity block B.  Pivot k divides
+// row k by r_kk = sqrt(pivot) (one reciprocal, then products) and subtracts R'_ki times it from
+// each row i > k, in both blocks.  After the last pivot the first block is R' and the second is
+// E with E A = R', i.e. E = R'^{-T}: lane j holds row j of R'^{-1}, so no separate inversion is
+// needed; row k of both is final after pivot k and stored then.  The row values R'_ki reach the
+// lanes through an LDS row (the wavefront's LDS accesses execute in order, so no barrier is
+// needed); the entries of row k + 1, which the next pivot needs at once, come through lane reads.
 __device__ __forceinline__ double lane_value(double v, int l) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
@@ -41,13 +44,15 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
     const double gjj = G[jc * r + jc];
     bool bad = col && !(gjj > 0.0 && isfinite(gjj));
     const double sj = col ? ((gjj > 0.0) ? 1.0 / sqrt(gjj) : 0.0) : 1.0;
+    const double unscale = (col && gjj > 0.0) ? sqrt(gjj) : 0.0;   // 1 / s_j (R = R' diag(1/s))
     scl[j] = sj;
-    double a[RMAX];
+    double a[RMAX], bm[RMAX];
     double dev = 0.0;   // max |G_ij - delta_ij| of this column
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) {
         const double g = G[(i < r ? i : r - 1) * r + jc];
         a[i] = (i < r && col) ? scl[i] * g * sj : (i == j ? 1.0 : 0.0);
+        bm[i] = (i == j) ? 1.0 : 0.0;
         if (i < r && col) dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
     }
     if (near_identity) {
@@ -56,36 +61,32 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
         for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
         if (j == 0) *near_identity = (dev < identity_tol) ? 1 : 0;
     }
+    double piv = lane_value(a[0], 0);
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
         __atomic_signal_fence(__ATOMIC_SEQ_CST);   // one pivot's LDS reads at a time (register pressure)
-        const double piv = lane_value(a[k], k);
         if (k < r && !(piv > 1e-12)) bad = true;
         const double rkk = sqrt(fmax(piv, 1e-300));
-        const double rkj = (j > k) ? a[k] / rkk : (j == k ? rkk : 0.0);
-        a[k] = rkj;   // row k of R' (not touched again)
+        const double inv = 1.0 / rkk;
+        const double rkj = (j > k) ? a[k] * inv : (j == k ? rkk : 0.0);
+        const double bk = bm[k] * inv;
+        // row k of R' and entry k of row j of R'^{-1} are final: stored now, their registers freed
+        if (col && k < r) {
+            R[k * r + j] = (k <= j) ? rkj * unscale : 0.0;
+            Rinv[j * r + k] = (k >= j) ? sj * bk : 0.0;
+        }
         row[j] = rkj;
+        if (k + 1 < RMAX) {
+            const double x = lane_value(rkj, k + 1);   // R'_{k,k+1}
+            a[k + 1] = fma(-x, rkj, a[k + 1]);
+            bm[k + 1] = fma(-x, bk, bm[k + 1]);
+            piv = lane_value(a[k + 1], k + 1);
+        }
 #pragma unroll
-        for (int i = k + 1; i < RMAX; ++i) a[i] = fma(-row[i], rkj, a[i]);
-    }
-    // R'^{-1}: Ri_ij = (delta_ij - sum_{i < m} R'_im Ri_mj) / R'_ii  (Ri_mj = 0 for m > j)
-    double ri[RMAX];
-#pragma unroll
-    for (int i = RMAX - 1; i >= 0; --i) {
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        row[j] = a[i];   // row i of R'
-        double part = 0.0;
-#pragma unroll
-        for (int m = i + 1; m < RMAX; ++m) part = fma(row[m], ri[m], part);
-        ri[i] = ((i == j ? 1.0 : 0.0) - part) / row[i];
-    }
-    if (col) {
-#pragma unroll
-        for (int i = 0; i < RMAX; ++i) {
-            if (i < r) {
-                R[i * r + j] = (i <= j && sj > 0.0) ? a[i] / sj : 0.0;
-                Rinv[i * r + j] = (i <= j) ? scl[i] * ri[i] : 0.0;
-            }
+        for (int i = k + 2; i < RMAX; ++i) {
+            const double x = row[i];   // R'_{k,i}
+            a[i] = fma(-x, rkj, a[i]);
+            bm[i] = fma(-x, bk, bm[i]);
         }
     }
     const unsigned long long anybad = __ballot(bad);
