@@ -55,6 +55,9 @@ struct Arena {
 
 }  // namespace
 
+constexpr int kPinnedNorm = 4;                                     // SI norm words
+constexpr int kPinnedDoubles = kPinnedNorm + 1 + 2 * dlr::kMaxRank;   // + energy, margins, weights
+
 struct dlr_instance {
     // ---- problem (host copies)
     bool sn = false;   // plain discrete ordinates (every ordinate swept, no factors)
@@ -118,7 +121,7 @@ struct dlr_instance {
     double *q_diag = nullptr, *phio = nullptr;
     int *orient = nullptr, *dirs = nullptr, *dir_off = nullptr;
     // pinned host mirrors
-    double* h_norm = nullptr;
+    double* h_norm = nullptr;   // pinned: SI norms [0, kPinnedNorm), then energy, margins[r], cw[r]
     int* h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch shapes
@@ -481,14 +484,16 @@ void phase_end(dlr_instance* I) {
 
 dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     const int r = I->r;
+    // energy, DEIM margins and weights into pinned memory behind the step; the status check's copy
+    // and stream synchronisation complete them (one host round trip per step instead of four)
+    double* hf = I->h_norm + kPinnedNorm;
+    hip_check(hipMemcpyAsync(hf, I->energy_out, sizeof(double), hipMemcpyDeviceToHost, I->stream), "energy copy");
+    hip_check(hipMemcpyAsync(hf + 1, I->margins, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "margin copy");
+    hip_check(hipMemcpyAsync(hf + 1 + r, I->cw, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "cw copy");
     const dlr_status st = check_device_status(I);
     if (st != DLR_OK) return st;
-    double en = 0.0;
-    hip_check(hipMemcpy(&en, I->energy_out, sizeof(double), hipMemcpyDeviceToHost), "energy copy");
-    std::vector<double> marg(r);
-    hip_check(hipMemcpy(marg.data(), I->margins, r * sizeof(double), hipMemcpyDeviceToHost), "margin copy");
-    std::vector<double> cwv(r);
-    hip_check(hipMemcpy(cwv.data(), I->cw, r * sizeof(double), hipMemcpyDeviceToHost), "cw copy");
+    const double en = hf[0];
+    const std::vector<double> marg(hf + 1, hf + 1 + r), cwv(hf + 1 + r, hf + 1 + 2 * r);
     float step_ms = 0.f;
     hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
     I->stats.si_iters = I->si_it;
@@ -566,10 +571,11 @@ dlr_status sn_step_once(dlr_instance* I) {
     dlr::launch_tupdate(s, I->N, 0, nullptr, nullptr, I->sigma, I->rho_cv, I->D, I->dt, I->a, I->c, I->area, I->T,
                         I->phi, I->partials, I->nb_cells, I->counters + 1, I->energy_out, I->status);
     hip_check(hipEventRecord(I->ev[1], s), "event");
-    const dlr_status st = check_device_status(I);
+    double* hf = I->h_norm + kPinnedNorm;
+    hip_check(hipMemcpyAsync(hf, I->energy_out, sizeof(double), hipMemcpyDeviceToHost, s), "energy copy");
+    const dlr_status st = check_device_status(I);   // its synchronisation completes the copy above
     if (st != DLR_OK) return st;
-    double en = 0.0;
-    hip_check(hipMemcpy(&en, I->energy_out, sizeof(double), hipMemcpyDeviceToHost), "energy copy");
+    const double en = hf[0];
     float step_ms = 0.f;
     hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
     I->stats.si_iters = I->si_it;
@@ -792,7 +798,7 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         I->carve(I->arena);
         hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
-        hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         const size_t n = I->N;
@@ -850,7 +856,7 @@ dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out
         I->carve(I->arena);
         hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
-        hip_check(hipHostMalloc((void**)&I->h_norm, 4 * sizeof(double), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         const size_t n = I->N, Q = I->nq;
