@@ -525,8 +525,7 @@ dlr_status step_once(dlr_instance* I) {
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
     }
-    const dlr_status ds = check_device_status(I);   // DEIM status before using its output further
-    if (ds != DLR_OK) return ds;
+    // the DEIM status was checked with the last source iteration's status word (copied after it)
     phase_end<TS>(I);
     return step_finish(I, true);
 }

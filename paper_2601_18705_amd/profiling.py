@@ -9,6 +9,9 @@ records kept with the repository.  Reads CSV files only; runs nothing.
     python -m paper_2601_18705_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> <calibration MiB> <kernel source> <out.json> [kernel name prefix]
 
+    python -m paper_2601_18705_amd.profiling traffic-table <fetch counter_collection.csv>
+        <write counter_collection.csv> <calibration MiB> <title> <command>...
+
 The kernel name prefix (default k_sweep, the degree-0 sweep) selects the dispatches
 averaged, e.g. "k_q1_sweep<double>" for the FP64 bilinear DG sweep.
 """
@@ -80,10 +83,40 @@ def sweep_traffic(fetch_csv, write_csv, calib_mib, sweep_source, sweep_prefix="k
             "calibration_mib": calib_mib}
 
 
+def traffic_table_md(fetch_csv, write_csv, calib_mib, title, commands, min_mb=20.0):
+    """Markdown table of HBM bytes per dispatch for every kernel of two counter runs (FETCH_SIZE and
+    WRITE_SIZE), each scaled by the calibration kernel's factor as in sweep_traffic; kernels that
+    move less than min_mb per dispatch are left out."""
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    calib = [k for k in fetch if "elementwise" in k and "Mul" in k] or [k for k in fetch if "elementwise" in k]
+    if not calib:
+        raise SystemExit("no calibration kernel in the FETCH_SIZE run")
+    known_kib = calib_mib * 1024.0
+    f_scale = known_kib / fetch[calib[-1]][-1]
+    w_scale = known_kib / write[calib[-1]][-1] if calib[-1] in write else 1.0
+    out = [f"# {title}", "", "Commands (from the repository root on an MI355X, ROCm 7.2):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp", *commands, "```", "",
+           f"Counters scaled by the factors that make them read the {calib_mib:g} MiB of `{calib[-1][:60]}`: "
+           f"FETCH_SIZE x {f_scale:.2f}, WRITE_SIZE x {w_scale:.2f}.  Averages over the dispatches of each kernel.", "",
+           "| kernel | dispatches | read (MB) | written (MB) |", "|---|---:|---:|---:|"]
+    for k, fv in fetch.items():
+        if k in calib:
+            continue
+        f = sum(fv) / len(fv) * 1024.0 * f_scale / 1e6
+        wv = write.get(k, [])
+        w = sum(wv) / len(wv) * 1024.0 * w_scale / 1e6 if wv else 0.0
+        if f + w >= min_mb:
+            out.append(f"| `{k}` | {len(fv)} | {f:.1f} | {w:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else "",
                                          argv[5].split(",") if len(argv) > 5 else ()))
+    elif len(argv) >= 6 and argv[0] == "traffic-table":
+        sys.stdout.write(traffic_table_md(argv[1], argv[2], float(argv[3]), argv[4], argv[5:]))
     elif len(argv) in (6, 7) and argv[0] == "traffic":
         rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4], *argv[6:7])
         with open(argv[5], "w") as fh:
