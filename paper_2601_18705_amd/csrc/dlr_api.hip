@@ -642,6 +642,9 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->nb_gram = (int)std::max<long>(1, std::min<long>((passes + 3) / 4, 512));
     I->nb_gram_ang = std::max(1, std::min((((int)I->nq + 31) / 32 + 3) / 4, 32));
     I->nb_proj = std::max(1, std::min(chunks, 512));
+    // temperature update: about four blocks per CU keep enough of the r plane loads in flight
+    // (one block per CU left the kernel latency-bound)
+    I->nb_cells = (int)std::max<long>(1, std::min<long>(((long)I->N + 255) / 256, 1024));
     const size_t rr = (size_t)I->r * I->r;
     I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
                                   (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});
