@@ -843,7 +843,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
                         const double d = be - al;
                         const double sgn = (d * ga >= 0.0) ? 1.0 : -1.0;
                         const double tt = sgn * (2.0 * fabs(ga)) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt);
+                        const double c = rsqrt(1.0 + tt * tt);
                         const double sn = c * tt;
                         rotated = 1;
 #pragma unroll
