@@ -236,9 +236,9 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     __shared__ TO sX0[RP * kPS];
     constexpr bool kLowOp = sizeof(TO) < sizeof(double);
     __shared__ double sXv[kLowOp ? RP * (kPC + 1) : 1];   // X in FP64 for the vector sums (low-precision operands)
-    __shared__ double sSig[kPC], sSs[kPC], sQ[kPC];
+    __shared__ double sSig[kPC], sSs[kPC];
     __shared__ int sFlag[kPC];           // bit0 left side, bit1 right, bit2 bottom, bit3 top
-    __shared__ double red[5][kThreads];
+    __shared__ double red[4][kThreads];
     const long n = (long)nx * ny;
     // the & 3 tells the compiler the range of the wavefront index, so that the tile-pair guards
     // below fold away and the MFMA accumulators stay put (no copies around each MFMA)
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
 #pragma unroll
         for (int m = 0; m < 5; ++m) acc[pp][m] = Acc{0, 0, 0, 0};
     const int pv = threadIdx.x % RP, cv = threadIdx.x / RP;
-    double vq = 0.0, vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
+    double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
     const long nch = (n + kPC - 1) / kPC;
 
     // register staging of one chunk: thread t holds cell c0 + (t & 63) of planes (t >> 6) + 4u,
@@ -257,7 +257,13 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
     constexpr int NP = RP / 4;
     const int sc = threadIdx.x & (kPC - 1), sp = threadIdx.x / kPC;
     double gX[NP], gL[NP], g0[NP], gH = 0.0;
-    double gs = 0.0, gss = 0.0, gq = 0.0;
+    double gs = 0.0, gss = 0.0, gq = 0.0;   // gq: q at this thread's staged cell (every thread)
+    // sum_e q(e) X_p(e) for this thread's staged planes p = sp + 4u, accumulated in registers as the
+    // chunks are committed (summed over the wavefront's cells at the end)
+    double vqr[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) vqr[u] = 0.0;
+    bool edge = false, edge_cur = false;   // the staged / committed chunk holds cells on the grid boundary
     int gf = 0;
     auto stage = [&](long ch) {
         const long c0 = ch * kPC;
@@ -271,13 +277,15 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
             g0[u] = ok ? X0[(size_t)p * n + e] : 0.0;
         }
         if (threadIdx.x < RP) gH = (threadIdx.x < r && c0 > 0) ? X[(size_t)threadIdx.x * n + c0 - 1] : 0.0;
+        gq = e < n ? q[e] : 0.0;
+        const long jlo = c0 % ny;   // first column position of the chunk (it may run into the next column)
+        edge = c0 < ny || c0 + kPC > n - ny || jlo == 0 || jlo + kPC >= ny;
         if (threadIdx.x < kPC) {
-            gs = gss = gq = 0.0;
+            gs = gss = 0.0;
             gf = 0;
             if (e < n) {
                 gs = sigma[e];
                 gss = sig_s[e];
-                gq = q[e];
                 const int ei = (int)e, i = ei / ny, j = ei - i * ny;   // cell counts stay below 2^31
                 gf = (i == 0 ? 1 : 0) | (i == nx - 1 ? 2 : 0) | (j == 0 ? 4 : 0) | (j == ny - 1 ? 8 : 0);
             }
@@ -288,18 +296,19 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
         for (int u = 0; u < NP; ++u) {
             const int p = sp + 4 * u;
             sX[p * kPS + sc + 1] = (TO)gX[u];
-            if (kLowOp) sXv[p * (kPC + 1) + sc + 1] = gX[u];
+            if (kLowOp && edge) sXv[p * (kPC + 1) + sc + 1] = gX[u];
+            vqr[u] = fma(gq, gX[u], vqr[u]);
             sXl[p * kPS + sc] = (TO)gL[u];
             sX0[p * kPS + sc] = (TO)g0[u];
         }
         if (threadIdx.x < RP) {
             sX[threadIdx.x * kPS] = (TO)gH;
-            if (kLowOp) sXv[threadIdx.x * (kPC + 1)] = gH;
+            if (kLowOp && edge) sXv[threadIdx.x * (kPC + 1)] = gH;
         }
+        edge_cur = edge;
         if (threadIdx.x < kPC) {
             sSig[threadIdx.x] = gs;
             sSs[threadIdx.x] = gss;
-            sQ[threadIdx.x] = gq;
             sFlag[threadIdx.x] = gf;
         }
     };
@@ -371,11 +380,11 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
                 }
             }
         }
-        if (pv < r) {
+        if (edge_cur && pv < r) {   // sums over the boundary sides: only chunks that hold such cells
             for (int c = cv; c < kPC; c += TPP) {
-                const double x = kLowOp ? sXv[pv * (kPC + 1) + c + 1] : (double)sX[pv * kPS + c + 1];
                 const int f = sFlag[c];
-                vq += sQ[c] * x;
+                if (f == 0) continue;
+                const double x = kLowOp ? sXv[pv * (kPC + 1) + c + 1] : (double)sX[pv * kPS + c + 1];
                 if (f & 1) vl += x;
                 if (f & 2) vr += x;
                 if (f & 4) vb += x;
@@ -414,18 +423,27 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
             }
         }
     }
+    // v0: each wavefront's staged planes p = sp + 4u, summed over its 64 cells in butterfly order
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        double t = vqr[u];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const int p = sp + 4 * u;
+        if (lane == 0 && p < r) out[5 * rr + p] = t;
+    }
+    // v1..v4: the boundary sides
     __syncthreads();
-    red[0][threadIdx.x] = vq;
-    red[1][threadIdx.x] = vl;
-    red[2][threadIdx.x] = vr;
-    red[3][threadIdx.x] = vb;
-    red[4][threadIdx.x] = vt;
+    red[0][threadIdx.x] = vl;
+    red[1][threadIdx.x] = vr;
+    red[2][threadIdx.x] = vb;
+    red[3][threadIdx.x] = vt;
     __syncthreads();
-    for (int o = threadIdx.x; o < 5 * r; o += kThreads) {
+    for (int o = threadIdx.x; o < 4 * r; o += kThreads) {
         const int kind = o / r, p = o % r;
         double acc_v = 0.0;
         for (int k = 0; k < TPP; ++k) acc_v += red[kind][p + k * RP];
-        out[5 * rr + o] = acc_v;
+        out[5 * rr + r + o] = acc_v;
     }
 }
 
