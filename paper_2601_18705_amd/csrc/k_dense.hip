@@ -914,13 +914,27 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
                                                double* __restrict__ beta, double* __restrict__ coef) {
     __shared__ double sb[kMaxRank];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = wv; k < r; k += 16) {
-        double acc = 0.0;
+    // columns k and k + 16 of a wavefront are summed together (twice the loads in flight); each keeps
+    // its own lane order and butterfly
+    for (int k = wv; k < r; k += 32) {
+        const int k2 = k + 16;
+        const bool two = k2 < r;
+        double acc = 0.0, acc2 = 0.0;
 #pragma unroll 8
-        for (int q = lane; q < nq; q += 64) acc += w[q] * W[(size_t)k * nq + q];
+        for (int q = lane; q < nq; q += 64) {
+            const double wq = w[q];
+            acc += wq * W[(size_t)k * nq + q];
+            if (two) acc2 += wq * W[(size_t)k2 * nq + q];
+        }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) sb[k] = acc;
+        for (int off = 32; off > 0; off >>= 1) {
+            acc += __shfl_xor(acc, off);
+            acc2 += __shfl_xor(acc2, off);
+        }
+        if (lane == 0) {
+            sb[k] = acc;
+            if (two) sb[k2] = acc2;
+        }
     }
     __syncthreads();
     __shared__ double sS[kMaxRank * kMaxRank];
