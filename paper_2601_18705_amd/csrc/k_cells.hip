@@ -210,8 +210,9 @@ typedef double dv4 __attribute__((ext_vector_type(4)));
 // rows and across the four lane rows and written directly.
 // Store phase: in a direction's diagonal layout the tile's column holds RT consecutive positions t, which
 // touch RT/4 + 1 aligned groups of four; a thread writes one group of one column (a 16-byte store, or
-// single values in the groups cut by the tile's top and bottom rows), so eight consecutive threads fill a
-// whole 128-byte line.  The s_e row is written the same way into each of the four orientation copies.
+// single values in the groups cut by the tile's top and bottom rows), so eight consecutive threads cover
+// whole 128-byte lines (one in FP32, two in FP64).  The s_e row is written the same way into each of the
+// four orientation copies.
 template <typename TS, int RMAX, int RT>
 __global__ __launch_bounds__(kBlock) void k_psi0_mfma(int nx, int ny, int r, const double* __restrict__ X,
                                                       const double* __restrict__ C0, const double* __restrict__ a0,
