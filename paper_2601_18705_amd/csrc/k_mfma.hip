@@ -458,6 +458,7 @@ __global__ __launch_bounds__(1024) void k_sum_partials(int total, const double* 
     double a0 = 0.0, a1 = 0.0;
     if (o < total) {
         int b = sl;
+#pragma unroll 8   // same order of additions; the loads of eight iterations in flight together
         for (; b + 16 < nblocks; b += 32) {
             a0 += partials[(size_t)b * total + o];
             a1 += partials[(size_t)(b + 16) * total + o];
