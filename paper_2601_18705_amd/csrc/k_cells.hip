@@ -95,19 +95,34 @@ __global__ __launch_bounds__(kBlock) void k_linearize(TileGrid g, const double* 
                                                       double* __restrict__ sig_t64, float* __restrict__ sig_t32,
                                                       size_t ldg, double* __restrict__ q_diag) {
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+        // the loads of the thread's four cells first (cells outside the grid read cell (0, 0)), then
+        // the arithmetic and stores of the cells inside
+        bool ok[4];
+        int ci[4], cj[4];
+        double tv[4], sv[4], cv[4], qx[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            int i, j;
-            if (!g.cell(b, k, i, j)) continue;
+            ok[k] = g.cell(b, k, ci[k], cj[k]);
+            if (!ok[k]) ci[k] = cj[k] = 0;
+            const long e = (long)ci[k] * g.ny + cj[k];
+            tv[k] = T[e];
+            sv[k] = sigma[e];
+            cv[k] = rho_cv[e];
+            qx[k] = q_ext ? q_ext[e] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok[k]) continue;
+            const int i = ci[k], j = cj[k];
             const long e = (long)i * g.ny + j;
-            const double t = T[e], s = sigma[e], C = rho_cv[e];
+            const double t = tv[k], s = sv[k], C = cv[k];
             const double t3 = t * t * t;
             const double B0 = a * c * t3 * t / kFourPi;
             const double dB = a * c * t3 / kPi;
             const double d = C + kFourPi * dt * s * dB;
             D[e] = d;
             sig_s[e] = (kFourPi * dt * s * dB / d) * s;
-            const double qe = s * B0 * C / d + (q_ext ? q_ext[e] / kFourPi : 0.0);
+            const double qe = s * B0 * C / d + (q_ext ? qx[k] / kFourPi : 0.0);
             q[e] = qe;
             const double st = s + 1.0 / (c * dt);
 #pragma unroll
@@ -517,17 +532,28 @@ __global__ __launch_bounds__(kBlock) void k_phi_partial(size_t ldg, int nd, cons
                                                         double* __restrict__ phio) {
     typedef TS tv4 __attribute__((ext_vector_type(4)));
     const int o = blockIdx.y;
-    const int k0 = dirs ? off[o] : 0, k1 = dirs ? off[o + 1] : nd;
+    // without a list, the block first lists the directions of orientation o in order (nd <= 64: the
+    // selected directions of a rank-r factorisation), so the loop below has no per-direction branch
+    // and unrolls with several loads in flight
+    __shared__ int sdir[64];
+    __shared__ int sndir;
+    if (!dirs) {
+        if (threadIdx.x < 64) {
+            const int d = threadIdx.x;
+            const bool m = d < nd && orient_of(mu[d], eta[d]) == o;
+            const unsigned long long mask = __ballot(m);
+            if (m) sdir[__popcll(mask & ((1ull << d) - 1ull))] = d;
+            if (d == 0) sndir = __popcll(mask);
+        }
+        __syncthreads();
+    }
+    const int k0 = dirs ? off[o] : 0, cnt = dirs ? off[o + 1] - off[o] : sndir;
     const size_t nquad = ldg / 4;
     for (size_t qd = (size_t)blockIdx.x * blockDim.x + threadIdx.x; qd < nquad; qd += (size_t)gridDim.x * blockDim.x) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int k = k0; k < k1; ++k) {
-            int d = k;
-            if (dirs) {
-                d = dirs[k];
-            } else if (orient_of(mu[d], eta[d]) != o) {
-                continue;
-            }
+#pragma unroll 8
+        for (int k = 0; k < cnt; ++k) {
+            const int d = dirs ? dirs[k0 + k] : sdir[k];
             const double wd = w[d];
             const tv4 v = *reinterpret_cast<const tv4*>(psi + (size_t)d * ldg + 4 * qd);
             a0 += wd * (double)v.x;
@@ -554,25 +580,39 @@ __global__ __launch_bounds__(kBlock) void k_phi_combine(TileGrid g, size_t ldg, 
     __shared__ double sh[kBlock];
     double d2 = 0.0, p2 = 0.0;
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
+        // the loads of the thread's four cells first (cells outside the grid read cell (0, 0)), so
+        // they are in flight together; then the sums and stores of the cells inside
+        bool ok[4];
+        long e[4];
+        size_t pos[4][4];
+        double po[4][4], pold[4], ss[4];
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
             int i, j;
-            if (!g.cell(b, kc, i, j)) continue;
-            const long e = (long)i * g.ny + j;
-            size_t pos[4];
-            double ph = 0.0;
+            ok[kc] = g.cell(b, kc, i, j);
+            if (!ok[kc]) i = j = 0;
+            e[kc] = (long)i * g.ny + j;
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                pos[o] = diag_pos(g.nx, g.ny, o, i, j);
-                ph += phio[(size_t)o * ldg + pos[o]];
+                pos[kc][o] = diag_pos(g.nx, g.ny, o, i, j);
+                po[kc][o] = phio[(size_t)o * ldg + pos[kc][o]];
             }
-            const double diff = ph - phi_old[e];
+            pold[kc] = phi_old[e[kc]];
+            ss[kc] = sig_s[e[kc]];
+        }
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            if (!ok[kc]) continue;
+            double ph = 0.0;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) ph += po[kc][o];
+            const double diff = ph - pold[kc];
             d2 += diff * diff;
             p2 += ph * ph;
-            phi_new[e] = ph;
-            const TS se = (TS)(sig_s[e] * ph / kFourPi);
+            phi_new[e[kc]] = ph;
+            const TS se = (TS)(ss[kc] * ph / kFourPi);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[o]] = se;
+            for (int o = 0; o < 4; ++o) s_e[(size_t)o * ldg + pos[kc][o]] = se;
         }
     }
     d2 = block_sum(d2, sh);
