@@ -221,8 +221,8 @@ def main():
                     help="after the timed run, run a plain elementwise kernel over a buffer of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in the design notes, not implemented)"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 "
+                                   "(the step is not sharded across GPUs)"}))
         sys.exit(2)
 
     import torch

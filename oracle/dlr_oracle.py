@@ -14,8 +14,7 @@ the upwind sweep (``sweep.c``), a forward substitution in plain C loops.
 Library primitives used as steps: Gauss-Legendre nodes, small dense solves and
 inverses, matrix products, and the SVD of the r x r coupling matrix.
 
-Readings of the paper where it is silent, garbled or inconsistent (each one is
-listed with its reason in the design notes):
+Readings of the paper where it is silent, garbled or inconsistent:
   * B(T) = a c T^4 / (4 pi) (per steradian), so 4 pi B' = 4 a c T^3.
   * Effective source (Newton linearisation of backward Euler for T): the source
     is sigma B(T0) rho c_v / D with D = rho c_v + 4 pi dt sigma B'(T0); the
