@@ -209,6 +209,65 @@ def total_energy(p, grid, T, phi):
     return float(grid.area * np.sum(p["rho_cv"] * T + phi / p["c"]))
 
 
+def source_power(p, grid):
+    """Sum over cells of area * q_ext (q_ext is the angle-integrated external source)."""
+    return float(grid.area * np.sum(p["q_ext"]))
+
+
+def boundary_flows(p, grid, quad, side_psi):
+    """Radiation power entering and leaving through the sides of the domain.
+
+    side_psi(side) -> [nq, m]: the intensity of every ordinate on the m cells
+    along that side (row order on the left and right, column order on the
+    bottom and top).  Summing the degree-0 upwind equations over cells and
+    ordinates (weights w_q, cell area) telescopes each row and column of the
+    transport term to its two end faces, so a face contributes
+    w_q |Omega_q . n| psi_face times its length (h_y on the left and right
+    sides, h_x on the bottom and top).  Leaving: the wall cell's own value
+    (the upwind trace) for ordinates with Omega . n > 0.  Entering: the inflow
+    value -- B(T_b) on an INFLOW side, 0 on a VACUUM side, the mirrored
+    ordinate's wall value on a REFLECT side.  With these,
+      E_tot(new) - E_tot(old) = dt (source_power + inflow - outflow)
+    holds exactly for plain SN and full-rank DLR (time-discrete balance of the
+    temperature update and the transport equation of Sec. 2).
+
+    Returns (inflow, outflow)."""
+    face = {SIDE_LEFT: grid.hy, SIDE_RIGHT: grid.hy, SIDE_BOTTOM: grid.hx, SIDE_TOP: grid.hx}
+    inflow = 0.0
+    outflow = 0.0
+    for side in range(4):
+        vals = side_psi(side)
+        if side in (SIDE_LEFT, SIDE_RIGHT):
+            cosn = quad.mu if side == SIDE_RIGHT else -quad.mu     # Omega . n, outward normal
+            mirror = quad.refl_x
+        else:
+            cosn = quad.eta if side == SIDE_TOP else -quad.eta
+            mirror = quad.refl_y
+        for qi in range(quad.n):
+            if cosn[qi] > 0.0:
+                outflow += quad.w[qi] * cosn[qi] * face[side] * float(np.sum(vals[qi]))
+            else:
+                kind = p["bc"][side]
+                if kind == BC_INFLOW:
+                    psib = planck(p["T_b"][side], p["a"], p["c"])
+                    inflow += quad.w[qi] * (-cosn[qi]) * face[side] * psib * vals.shape[1]
+                elif kind == BC_REFLECT:
+                    inflow += quad.w[qi] * (-cosn[qi]) * face[side] * float(np.sum(vals[mirror[qi]]))
+    return inflow, outflow
+
+
+def side_cells(grid, side):
+    """Cell indices (e = j nx + i) along one side, in row or column order."""
+    e = np.arange(grid.ncell).reshape(grid.ny, grid.nx)
+    if side == SIDE_LEFT:
+        return e[:, 0]
+    if side == SIDE_RIGHT:
+        return e[:, -1]
+    if side == SIDE_BOTTOM:
+        return e[0, :]
+    return e[-1, :]
+
+
 # =========================================================================== sweep + inflow
 
 def sweep(grid, mu, eta, sigma_t, rhs, inx, iny):
@@ -321,7 +380,9 @@ def sn_step(p, quad, st, tol=None, max_iter=None):
         if it >= max_iter:
             raise RuntimeError("plain SN source iteration did not converge")
     T = temperature_update(p, st.T, lin, phi)
-    return SNState(T, psi, phi), {"si_iters": it}
+    inflow, outflow = boundary_flows(p, grid, quad, lambda side: psi[:, side_cells(grid, side)])
+    return SNState(T, psi, phi), {"si_iters": it, "inflow": inflow, "outflow": outflow,
+                                  "energy": total_energy(p, grid, T, phi)}
 
 
 # =========================================================================== DLR helpers
@@ -393,17 +454,22 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
     return Qt.T, R
 
 
-def deim(W, tie_tol):
+def deim(W, tie_tol, edges=False):
     """Greedy DEIM interpolation points on the angular basis (Sec. 4.2).
 
     Point j maximises |R_j| where R_j is W_j minus its interpolant by
     W_1..W_{j-1} at the points already chosen.  Near ties (within tie_tol of
     the maximum) go to the smallest ordinate index.  Returns the point indices
-    and, per pick, the relative margin to the best non-tied competitor.
+    and, per pick, the relative margin to the best non-tied competitor.  With
+    edges=True it also returns, per pick, how far the decision is from
+    changing: the smallest distance of any |R_q| / max |R| from the tie
+    threshold 1 - tie_tol (a perturbation of R smaller than that, relative to
+    max |R|, cannot change the pick).
     """
     n, r = W.shape
     sel = []
     margins = []
+    edge = []
     for j in range(r):
         if j == 0:
             R = W[:, 0].copy()
@@ -416,7 +482,11 @@ def deim(W, tie_tol):
         pj = int(np.nonzero(tied)[0].min())
         rest = a[~tied]
         margins.append(float((m - rest.max()) / m) if rest.size else 1.0)
+        others = np.delete(a, int(np.argmax(a)))
+        edge.append(float(np.min(np.abs(others / m - (1.0 - tie_tol)))) if others.size else 1.0)
         sel.append(pj)
+    if edges:
+        return np.array(sel, dtype=np.int64), np.array(margins), np.array(edge)
     return np.array(sel, dtype=np.int64), np.array(margins)
 
 
@@ -497,9 +567,9 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
 
     # 2. DEIM angle selection on W0
     if forced_sel is None:
-        sel, margins = deim(W0, p["deim_tie_tol"])
+        sel, margins, edges = deim(W0, p["deim_tie_tol"], edges=True)
     else:
-        sel, margins = np.asarray(forced_sel, dtype=np.int64), np.zeros(r)
+        sel, margins, edges = np.asarray(forced_sel, dtype=np.int64), np.zeros(r), np.zeros(r)
     What = W0[sel, :]                    # What[i, j] = W_j(Omega^(i))
     beta = W0.T @ quad.w                 # beta_j = int W_j
     cw = np.linalg.solve(What.T, beta)   # phi = beta^T What^{-1} Psi = cw . Psi
@@ -557,7 +627,10 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
     new = DLRState(X, S, W, T0)
     phi_new = mean_intensity(quad, new)
     new.T = temperature_update(p, T0, lin, phi_new)
-    stats = {"si_iters": it, "sel": sel, "margins": margins, "sigma": sig, "cw": cw,
+    G = S @ W.T                          # psi on any set of cells = X[cells] G
+    inflow, outflow = boundary_flows(p, grid, quad, lambda side: (X[side_cells(grid, side)] @ G).T)
+    stats = {"si_iters": it, "sel": sel, "margins": margins, "deim_edge": edges, "sigma": sig, "cw": cw,
+             "inflow": inflow, "outflow": outflow, "energy": total_energy(p, grid, new.T, phi_new),
              "phi": phi_new, "sum_abs_cw_over_4pi": float(np.abs(cw).sum() / FOUR_PI),
              "Psi": Psi, "Psi0": Psi0, "X_pre": X_pre, "L": L, "lin": lin, "Lt0": Lt0}
     return new, stats

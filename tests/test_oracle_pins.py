@@ -283,40 +283,87 @@ def test_energy_conserved_reflecting_sn_and_full_rank_dlr():
     assert sn.T.max() < 0.99   # something actually moved
 
 
-def _boundary_tally(p, grid, quad, psi):
-    """Net energy rate entering through the boundary: inflow minus outflow,
-    sum over faces of w |Omega.n| psi_face * face length."""
-    a, c = p["a"], p["c"]
-    f = psi.reshape(quad.n, grid.ny, grid.nx)
-    net = 0.0
-    for qi in range(quad.n):
-        mu, eta, w = quad.mu[qi], quad.eta[qi], quad.w[qi]
-        # x faces
-        out_x = f[qi, :, -1] if mu > 0 else f[qi, :, 0]
-        in_side = O.SIDE_LEFT if mu > 0 else O.SIDE_RIGHT
-        in_x = O.planck(p["T_b"][in_side], a, c) if p["bc"][in_side] == O.BC_INFLOW else 0.0
-        net += w * abs(mu) * grid.hy * (grid.ny * in_x - out_x.sum())
-        out_y = f[qi, -1, :] if eta > 0 else f[qi, 0, :]
-        in_side = O.SIDE_BOTTOM if eta > 0 else O.SIDE_TOP
-        in_y = O.planck(p["T_b"][in_side], a, c) if p["bc"][in_side] == O.BC_INFLOW else 0.0
-        net += w * abs(eta) * grid.hx * (grid.nx * in_y - out_y.sum())
-    return net
-
-
-def test_energy_balance_with_inflow_vacuum_and_source():
-    """E_new - E_old = dt (boundary inflow - outflow + int q_ext) for plain SN."""
+def _open_problem():
     p = _hetero(bc=[O.BC_INFLOW, O.BC_VACUUM, O.BC_INFLOW, O.BC_VACUUM])
     p["T_b"] = [1.0, 0.0, 0.5, 0.0]
     p["q_ext"] = np.linspace(0.0, 2.0, p["nx"] * p["ny"])
+    return p
+
+
+def test_energy_balance_with_inflow_vacuum_and_source():
+    """E_new - E_old = dt (boundary inflow - outflow + int q_ext) for plain SN, with the
+    oracle's boundary tally (inflow and outflow from the end-of-step intensity)."""
+    p = _open_problem()
     quad = O.quadrature(p["n_polar"], p["n_azim"])
     grid = O.grid_of(p)
     st = O.sn_initial_state(p, quad)
     for _ in range(3):
         E0 = O.total_energy(p, grid, st.T, st.phi)
-        st, _ = O.sn_step(p, quad, st)
+        st, stats = O.sn_step(p, quad, st)
         E1 = O.total_energy(p, grid, st.T, st.phi)
-        dE = p["dt"] * (_boundary_tally(p, grid, quad, st.psi) + grid.area * p["q_ext"].sum())
+        assert abs(stats["energy"] - E1) <= 1e-15 * E1
+        assert stats["inflow"] > 0 and stats["outflow"] > 0
+        dE = p["dt"] * (stats["inflow"] - stats["outflow"] + O.source_power(p, grid))
         assert abs((E1 - E0) - dE) < 1e-12 * E1
+
+
+def test_energy_balance_full_rank_dlr_from_factors():
+    """The same balance for full-rank DLR, the outflow evaluated from the new factors
+    X S W^T on the wall cells; both flows equal plain SN's."""
+    p = _open_problem()
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    grid = O.grid_of(p)
+    dl = O.dlr_initial_state(p, quad)
+    sn = O.sn_initial_state(p, quad)
+    E0 = O.total_energy(p, grid, dl.T, O.mean_intensity(quad, dl))
+    for _ in range(3):
+        dl, stats = O.dlr_step(p, quad, dl)
+        sn, sst = O.sn_step(p, quad, sn)
+        E1 = stats["energy"]
+        dE = p["dt"] * (stats["inflow"] - stats["outflow"] + O.source_power(p, grid))
+        assert abs((E1 - E0) - dE) < 1e-11 * E1
+        assert abs(stats["inflow"] - sst["inflow"]) < 1e-12 * sst["inflow"]
+        assert abs(stats["outflow"] - sst["outflow"]) < 1e-10 * sst["outflow"]
+        E0 = E1
+
+
+def test_boundary_flows_single_side_closed_form():
+    """One inflow side: the inflow is psi_b x side length x sum of w |mu| over the entering
+    ordinates (half of sum_q w_q |mu_q| by the quadrature's mirror symmetry), and a field that
+    is zero on every wall cell has no outflow; a uniform field psi = 1 leaves through each side
+    at length x sum over exiting ordinates of w |Omega . n|."""
+    p = _hetero(nx=6, ny=3, bc=[O.BC_VACUUM] * 4)
+    p["bc"][O.SIDE_LEFT] = O.BC_INFLOW
+    p["T_b"] = [0.7, 0, 0, 0]
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    grid = O.grid_of(p)
+    psib = O.planck(0.7, p["a"], p["c"])
+    zero = O.boundary_flows(p, grid, quad, lambda side: np.zeros((quad.n, O.side_cells(grid, side).size)))
+    height = grid.y1 - grid.y0
+    assert abs(zero[0] - psib * height * 0.5 * np.sum(quad.w * np.abs(quad.mu))) < 1e-14
+    assert zero[1] == 0.0
+    one = O.boundary_flows(p, grid, quad, lambda side: np.ones((quad.n, O.side_cells(grid, side).size)))
+    width = grid.x1 - grid.x0
+    expect = 2 * height * 0.5 * np.sum(quad.w * np.abs(quad.mu)) + 2 * width * 0.5 * np.sum(quad.w * np.abs(quad.eta))
+    assert abs(one[1] - expect) < 1e-13 * expect
+
+
+def test_reflecting_walls_have_no_net_flow():
+    p = _hetero()
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    st = O.sn_initial_state(p, quad)
+    for _ in range(2):
+        st, stats = O.sn_step(p, quad, st)
+        assert abs(stats["inflow"] - stats["outflow"]) < 1e-12 * stats["outflow"]
+
+
+def test_deim_decision_edge():
+    """The decision edge is the smallest distance of |R_q| / max |R| from the tie threshold."""
+    W = np.array([[0.5], [1.0], [0.2], [0.999_999_5]])
+    sel, margins, edge = O.deim(W, 1e-6, edges=True)
+    assert sel[0] == 1 and abs(edge[0] - 0.5e-6) < 1e-15
+    sel, margins, edge = O.deim(np.array([[0.5], [1.0], [0.2], [0.9]]), 1e-6, edges=True)
+    assert abs(edge[0] - (1.0 - 1e-6 - 0.9)) < 1e-15 and abs(margins[0] - 0.1) < 1e-15
 
 
 # ============================================================================ (d) full rank == plain SN
