@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define DLR_ABI_VERSION 1
+#define DLR_ABI_VERSION 2
 
 typedef enum {
     DLR_OK = 0,
@@ -47,7 +47,10 @@ typedef enum {
     DLR_ERR_NONFINITE = -5,      /* NaN/Inf in the mean intensity or temperature */
     DLR_ERR_STATE = -6,          /* handle poisoned by an earlier device error */
     DLR_ERR_UNSUPPORTED = -7,    /* option not available on the GPU path */
-    DLR_ERR_NUMERIC = -8         /* numerically rank-deficient factor (QR breakdown) */
+    DLR_ERR_NUMERIC = -8,        /* numerical breakdown: rank-deficient factor with no completion
+                                  * vector, singular L-step system, SVD without convergence */
+    DLR_ERR_TIMEOUT = -9         /* a bounded wait between workgroups on the device (sweep hand-off,
+                                  * DEIM exchange) exceeded its spin limit; the handle is poisoned */
 } dlr_status;
 
 enum { DLR_BC_VACUUM = 0, DLR_BC_INFLOW = 1, DLR_BC_REFLECT = 2 };
@@ -95,6 +98,22 @@ typedef struct {
 
 typedef struct dlr_instance *dlr_handle;
 
+/* Device memory of the library.  By default instances, batch slots and tables, and Q1
+ * operators take their device memory from hipMalloc and return it with hipFree.  A caller
+ * that owns device memory (for example PyTorch's caching allocator) can route every later
+ * allocation through its own pair of functions:
+ *   alloc(bytes, stream, user): a device pointer aligned to at least 256 bytes, or NULL (the
+ *     creating call then fails with DLR_ERR_OOM); stream is the hipStream_t the memory will be
+ *     used on (NULL = the default stream);
+ *   release(ptr, stream, user): takes it back; the library calls it only after every piece of
+ *     work it queued on that memory has completed.
+ * An allocation is always released through the pair that made it, so the hook may be replaced
+ * at any time; alloc = release = NULL restores hipMalloc / hipFree.  The setting is
+ * process-wide and must not race with calls that create or destroy objects.
+ * Errors: DLR_ERR_ARG when exactly one of alloc, release is NULL. */
+dlr_status dlr_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *user),
+                             void (*release)(void *ptr, void *stream, void *user), void *user);
+
 /* Per-step diagnostics of the most recent step (FP64). */
 typedef struct {
     int64_t steps_done;           /* steps completed since create / load */
@@ -108,6 +127,15 @@ typedef struct {
     double step_ms;               /* device time of the whole last step */
     int32_t svd_sweeps;           /* Jacobi sweeps of the last step's SVD of S (0 for plain SN) */
     int32_t reserved;
+    /* Energy balance of the step (Sec. 2 time-discrete balance, Algorithm 1 step 9).  Powers
+     * through the sides of the domain: each face contributes w_q |Omega_q . n| psi times its
+     * length, the leaving part from the end-of-step intensity of the wall cell (for DLR the
+     * new factors X S W^T), the entering part from the isotropic inflow B(T_b).  For plain
+     * SN and full-rank DLR, energy(n+1) - energy(n) = dt (source + inflow - outflow) up to the
+     * source-iteration tolerance; at reduced rank the difference is the method's own drift. */
+    double inflow;                /* power entering through DLR_BC_INFLOW sides */
+    double outflow;               /* power leaving through all sides */
+    double source;                /* sum over cells of area * q_ext */
 } dlr_step_stats;
 
 /* Create an instance: validates the problem, copies fields to the device and
@@ -247,7 +275,7 @@ dlr_status dlr_q1_sweep(dlr_q1 h, const void *sigma_t, const void *src, const vo
                         const void *inflow_y, void *psi);
 
 /* Wait for the queued sweeps and check the device status: a cross-workgroup wait that
- * exceeded its spin limit returns DLR_ERR_HIP and poisons the handle. */
+ * exceeded its spin limit returns DLR_ERR_TIMEOUT and poisons the handle. */
 dlr_status dlr_q1_sync(dlr_q1 h);
 
 /* Run reps >= 1 sweeps between two events on the handle's stream, synchronise, check the

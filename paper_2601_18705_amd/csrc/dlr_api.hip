@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -35,10 +36,79 @@ void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device memory: hipMalloc / hipFree, or the caller's pair from dlr_set_allocator.  Every
+// allocation keeps the pair (and the stream) it was made with, so it goes back the same way.
+struct AllocHook {
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*release)(void*, void*, void*) = nullptr;
+    void* user = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocHook g_hook;
+
+struct DevMem {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    AllocHook hook;
+    bool user_owned() const { return hook.alloc != nullptr; }
+};
+
+// false: out of memory (nothing allocated)
+bool dev_alloc(DevMem& m, size_t bytes, hipStream_t stream) {
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        m.hook = g_hook;
+    }
+    m.bytes = bytes;
+    m.stream = stream;
+    if (m.hook.alloc) {
+        m.ptr = m.hook.alloc(bytes, stream, m.hook.user);
+        if (m.ptr && (reinterpret_cast<uintptr_t>(m.ptr) & 255) != 0)
+            throw std::runtime_error("allocator hook returned memory not aligned to 256 bytes");
+        return m.ptr != nullptr;
+    }
+    const hipError_t e = hipMalloc(&m.ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        m.ptr = nullptr;
+        return false;
+    }
+    return true;
+}
+
+// The caller has made sure that no queued work still uses the memory.
+void dev_free(DevMem& m) {
+    if (!m.ptr) return;
+    if (m.hook.release)
+        m.hook.release(m.ptr, m.stream, m.hook.user);
+    else
+        (void)hipFree(m.ptr);
+    m.ptr = nullptr;
+}
+
+bool hook_installed() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_hook.alloc != nullptr;
+}
+
 // One device allocation carved into 256-byte aligned pieces.
 struct Arena {
     char* base = nullptr;
     size_t used = 0, cap = 0;
+    DevMem mem;
+    // false: out of memory
+    bool allocate(size_t bytes, hipStream_t stream) {
+        if (!dev_alloc(mem, bytes, stream)) return false;
+        base = static_cast<char*>(mem.ptr);
+        cap = bytes;
+        used = 0;
+        return true;
+    }
+    void release() {
+        dev_free(mem);
+        base = nullptr;
+    }
     template <typename T>
     T* take(size_t count) {
         const size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
@@ -56,7 +126,7 @@ struct Arena {
 }  // namespace
 
 constexpr int kPinnedNorm = 4;                                     // SI norm words
-constexpr int kPinnedDoubles = kPinnedNorm + 1 + 2 * dlr::kMaxRank;   // + energy, margins, weights
+constexpr int kPinnedDoubles = kPinnedNorm + 2 + 2 * dlr::kMaxRank;   // + energy, outflow, margins, weights
 
 struct dlr_instance {
     // ---- problem (host copies)
@@ -67,6 +137,7 @@ struct dlr_instance {
     int si_max_iter = 0;
     int bc[4] = {0, 0, 0, 0};
     double Tb[4] = {0, 0, 0, 0}, psib[4] = {0, 0, 0, 0};
+    double inflow_power = 0, source_power = 0;   // constant terms of the energy balance
     bool has_qext = false;
     hipStream_t stream = nullptr;
     std::vector<double> h_mu, h_eta, h_w;
@@ -115,7 +186,7 @@ struct dlr_instance {
     unsigned* counters = nullptr;
     double *Gm = nullptr, *Ra = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr;
     double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
-    double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr;
+    double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr, *gside = nullptr;
     int* status = nullptr;
     // plain SN only
     double *q_diag = nullptr, *phio = nullptr;
@@ -235,6 +306,7 @@ struct dlr_instance {
         Vsvd = A.take<double>(R * R);
         beta = A.take<double>(R);
         coef = A.take<double>(R);
+        gside = A.take<double>(4 * R);
         status = A.take<int>(4);
     }
 };
@@ -295,8 +367,8 @@ dlr_status check_device_status(dlr_instance* I) {
     if (st & dlr::kStatusQrBreakdownW) m += " angular-QR-breakdown";
     if (st & dlr::kStatusSingularSolve) m += " singular-solve";
     if (st & dlr::kStatusSvdNoConv) m += " svd-not-converged";
-    if (st & dlr::kStatusSweepStall) m += " sweep-wait-stalled";
-    if (st & dlr::kStatusDeimStall) m += " deim-exchange-stalled";
+    if (st & dlr::kStatusSweepStall) { m += " sweep-wait-stalled"; code = DLR_ERR_TIMEOUT; }
+    if (st & dlr::kStatusDeimStall) { m += " deim-exchange-stalled"; code = DLR_ERR_TIMEOUT; }
     if (st & dlr::kStatusNoCompletion) m += " no-completion-vector";
     if (st & dlr::kStatusBadForcedSel) { m += " bad-forced-selection"; code = DLR_ERR_ARG; }
     I->poisoned = true;
@@ -336,6 +408,17 @@ void upload_sweep_record(dlr_instance* I) {
     const unsigned units = (unsigned)(I->nsuper * I->nsweep());
     hip_check(hipMemcpy(I->sweep_rec, I->h_sweep_rec.data(), I->h_sweep_rec.size(), hipMemcpyHostToDevice), "record");
     hip_check(hipMemcpy(I->unit_end, &units, sizeof(units), hipMemcpyHostToDevice), "record");
+}
+
+dlr::TupdateArgs tupdate_args(dlr_instance* I, const double* X, const double* gside) {
+    dlr::TupdateArgs A{};
+    A.nx = I->nx; A.ny = I->ny; A.r = X ? I->r : 0;
+    A.X = X; A.coef = I->coef; A.gside = gside;
+    A.sigma = I->sigma; A.rho_cv = I->rho_cv; A.D = I->D;
+    A.dt = I->dt; A.a = I->a; A.c = I->c; A.area = I->area; A.hx = I->hx; A.hy = I->hy;
+    A.T = I->T; A.phi = I->phi;
+    A.partials = I->partials; A.counter = I->counters + 1; A.out = I->energy_out; A.status = I->status;
+    return A;
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -473,10 +556,9 @@ void phase_end(dlr_instance* I) {
                              I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
     dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
-    dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef);
-    // 9. temperature update with the mean intensity of the new factors
-    dlr::launch_tupdate(s, N, r, I->Xn, I->coef, I->sigma, I->rho_cv, I->D, I->dt, I->a, I->c, I->area, I->T, I->phi,
-                        I->partials, I->nb_cells, I->counters + 1, I->energy_out, I->status);
+    dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef, I->mu, I->eta, I->gside);
+    // 9. temperature update with the mean intensity of the new factors, energy sum and outflow
+    dlr::launch_tupdate(s, tupdate_args(I, I->Xn, I->gside), I->nb_cells);
     std::swap(I->X, I->Xn);
     std::swap(I->S, I->Sn);
     hip_check(hipEventRecord(I->ev[1], s), "event");
@@ -487,13 +569,16 @@ dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     // energy, DEIM margins and weights into pinned memory behind the step; the status check's copy
     // and stream synchronisation complete them (one host round trip per step instead of four)
     double* hf = I->h_norm + kPinnedNorm;
-    hip_check(hipMemcpyAsync(hf, I->energy_out, sizeof(double), hipMemcpyDeviceToHost, I->stream), "energy copy");
-    hip_check(hipMemcpyAsync(hf + 1, I->margins, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "margin copy");
-    hip_check(hipMemcpyAsync(hf + 1 + r, I->cw, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "cw copy");
+    hip_check(hipMemcpyAsync(hf, I->energy_out, 2 * sizeof(double), hipMemcpyDeviceToHost, I->stream), "energy copy");
+    hip_check(hipMemcpyAsync(hf + 2, I->margins, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "margin copy");
+    hip_check(hipMemcpyAsync(hf + 2 + r, I->cw, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "cw copy");
     const dlr_status st = check_device_status(I);
     if (st != DLR_OK) return st;
     const double en = hf[0];
-    const std::vector<double> marg(hf + 1, hf + 1 + r), cwv(hf + 1 + r, hf + 1 + 2 * r);
+    I->stats.outflow = hf[1];
+    I->stats.inflow = I->inflow_power;
+    I->stats.source = I->source_power;
+    const std::vector<double> marg(hf + 2, hf + 2 + r), cwv(hf + 2 + r, hf + 2 + 2 * r);
     float step_ms = 0.f;
     hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
     I->stats.si_iters = I->si_it;
@@ -567,14 +652,24 @@ dlr_status sn_step_once(dlr_instance* I) {
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
     }
-    dlr::launch_tupdate(s, I->N, 0, nullptr, nullptr, I->sigma, I->rho_cv, I->D, I->dt, I->a, I->c, I->area, I->T,
-                        I->phi, I->partials, I->nb_cells, I->counters + 1, I->energy_out, I->status);
+    dlr::launch_tupdate(s, tupdate_args(I, nullptr, nullptr), I->nb_cells);
+    if (I->fp32())
+        dlr::launch_sn_outflow<float>(s, I->nx, I->ny, I->nq, I->ldg, I->mu, I->eta, I->w,
+                                      static_cast<const float*>(I->psi), I->hx, I->hy, I->partials, 1024,
+                                      I->counters + 2, I->energy_out);
+    else
+        dlr::launch_sn_outflow<double>(s, I->nx, I->ny, I->nq, I->ldg, I->mu, I->eta, I->w,
+                                       static_cast<const double*>(I->psi), I->hx, I->hy, I->partials, 1024,
+                                       I->counters + 2, I->energy_out);
     hip_check(hipEventRecord(I->ev[1], s), "event");
     double* hf = I->h_norm + kPinnedNorm;
-    hip_check(hipMemcpyAsync(hf, I->energy_out, sizeof(double), hipMemcpyDeviceToHost, s), "energy copy");
+    hip_check(hipMemcpyAsync(hf, I->energy_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "energy copy");
     const dlr_status st = check_device_status(I);   // its synchronisation completes the copy above
     if (st != DLR_OK) return st;
     const double en = hf[0];
+    I->stats.outflow = hf[1];
+    I->stats.inflow = I->inflow_power;
+    I->stats.source = I->source_power;
     float step_ms = 0.f;
     hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
     I->stats.si_iters = I->si_it;
@@ -647,8 +742,21 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->nb_cells = (int)std::max<long>(1, std::min<long>(((long)I->N + 255) / 256, 1024));
     const size_t rr = (size_t)I->r * I->r;
     I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
-                                  (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2});
+                                  (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2, (size_t)(sn ? 1024 : 0)});
     dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
+    // constant terms of the energy balance: the inflow power (each inflow face takes
+    // w_q |Omega_q . n| B(T_b) for every entering ordinate, times its length) and the source power
+    I->inflow_power = 0.0;
+    for (size_t q = 0; q < I->h_mu.size(); ++q) {
+        const double m = I->h_mu[q], e = I->h_eta[q], wq = I->h_w[q];
+        const int sx = m > 0.0 ? 0 : 1, sy = e > 0.0 ? 2 : 3;   // side the ordinate enters through
+        I->inflow_power += wq * std::fabs(m) * I->psib[sx] * (I->ny * I->hy);
+        I->inflow_power += wq * std::fabs(e) * I->psib[sy] * (I->nx * I->hx);
+    }
+    I->source_power = 0.0;
+    if (p->q_ext)
+        for (long e = 0; e < (long)I->N; ++e) I->source_power += p->q_ext[e];
+    I->source_power *= I->area;
 }
 
 // Device bytes of an instance's arena.
@@ -656,6 +764,21 @@ size_t arena_bytes(dlr_instance* I) {
     Arena sizing;
     I->carve(sizing);
     return sizing.used;
+}
+
+// The instance's arena (hipMalloc or the allocator hook), carved and cleared on its stream.
+dlr_status allocate_instance(dlr_instance* I) {
+    const size_t need = arena_bytes(I);
+    if (!hook_installed()) {
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        if (need + (64u << 20) > free_b) return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
+    }
+    if (!I->arena.allocate(need, I->stream)) return fail(DLR_ERR_OOM, "device allocation of the instance failed");
+    I->carve(I->arena);
+    hip_check(hipMemsetAsync(I->arena.base, 0, I->arena.cap, I->stream), "clear");
+    hip_check(hipStreamSynchronize(I->stream), "sync");
+    return DLR_OK;
 }
 
 }  // namespace
@@ -687,6 +810,7 @@ struct dlr_batch_s {
     char* h_table[2] = {nullptr, nullptr};
     unsigned* h_unit_end[2] = {nullptr, nullptr};
     unsigned* d_ticket = nullptr;
+    DevMem table_mem[2], unit_end_mem[2], ticket_mem;   // device memory behind the three above
     hipEvent_t ev_main = nullptr;
 };
 
@@ -700,13 +824,21 @@ void batch_reserve(dlr_batch_s* B, size_t entries) {
     if (entries <= B->cap) return;
     size_t cap = std::max<size_t>(64, B->cap);
     while (cap < entries) cap *= 2;
+    hip_check(hipStreamSynchronize(B->main), "sync");   // earlier launches may still read the tables
     for (int g = 0; g < 2; ++g) {
-        if (B->d_table[g]) (void)hipFree(B->d_table[g]);
-        if (B->d_unit_end[g]) (void)hipFree(B->d_unit_end[g]);
+        dev_free(B->table_mem[g]);
+        dev_free(B->unit_end_mem[g]);
+        B->d_table[g] = nullptr;
+        B->d_unit_end[g] = nullptr;
         if (B->h_table[g]) (void)hipHostFree(B->h_table[g]);
         if (B->h_unit_end[g]) (void)hipHostFree(B->h_unit_end[g]);
-        hip_check(hipMalloc(&B->d_table[g], cap * kRecBytes), "batch table");
-        hip_check(hipMalloc(&B->d_unit_end[g], cap * sizeof(unsigned)), "batch table");
+        B->h_table[g] = nullptr;
+        B->h_unit_end[g] = nullptr;
+        if (!dev_alloc(B->table_mem[g], cap * kRecBytes, B->main) ||
+            !dev_alloc(B->unit_end_mem[g], cap * sizeof(unsigned), B->main))
+            throw HipError("batch table: device allocation failed");
+        B->d_table[g] = static_cast<char*>(B->table_mem[g].ptr);
+        B->d_unit_end[g] = static_cast<unsigned*>(B->unit_end_mem[g].ptr);
         hip_check(hipHostMalloc((void**)&B->h_table[g], cap * kRecBytes, hipHostMallocDefault), "batch table");
         hip_check(hipHostMalloc((void**)&B->h_unit_end[g], cap * sizeof(unsigned), hipHostMallocDefault),
                   "batch table");
@@ -757,6 +889,16 @@ BatchSlot* find_slot(dlr_batch_s* B, int64_t id) {
 
 extern "C" {
 
+dlr_status dlr_set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*, void*), void* user) {
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(DLR_ERR_ARG, "alloc and release must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_hook.alloc = alloc;
+    g_hook.release = release;
+    g_hook.user = alloc ? user : nullptr;
+    return DLR_OK;
+}
+
 const char* dlr_status_string(dlr_status s) {
     switch (s) {
         case DLR_OK: return "ok";
@@ -768,6 +910,7 @@ const char* dlr_status_string(dlr_status s) {
         case DLR_ERR_STATE: return "handle poisoned by an earlier error";
         case DLR_ERR_UNSUPPORTED: return "unsupported option";
         case DLR_ERR_NUMERIC: return "numerical breakdown";
+        case DLR_ERR_TIMEOUT: return "device wait exceeded its spin limit";
     }
     return "unknown status";
 }
@@ -784,21 +927,11 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
     if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
     try {
         init_fields(I, p, static_cast<hipStream_t>(hip_stream));
-        const size_t need = arena_bytes(I);
-        size_t free_b = 0, total_b = 0;
-        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-        if (need + (64u << 20) > free_b) {
+        const dlr_status am = allocate_instance(I);
+        if (am != DLR_OK) {
             delete I;
-            return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
+            return am;
         }
-        hipError_t e = hipMalloc(&I->arena.base, need);
-        if (e != hipSuccess) {
-            delete I;
-            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        I->arena.cap = need;
-        I->carve(I->arena);
-        hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
@@ -842,21 +975,11 @@ dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out
     if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
     try {
         init_fields(I, p, static_cast<hipStream_t>(hip_stream), true);
-        const size_t need = arena_bytes(I);
-        size_t free_b = 0, total_b = 0;
-        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-        if (need + (64u << 20) > free_b) {
+        const dlr_status am = allocate_instance(I);
+        if (am != DLR_OK) {
             delete I;
-            return fail(DLR_ERR_OOM, "instance does not fit in free device memory");
+            return am;
         }
-        hipError_t e = hipMalloc(&I->arena.base, need);
-        if (e != hipSuccess) {
-            delete I;
-            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        I->arena.cap = need;
-        I->carve(I->arena);
-        hip_check(hipMemset(I->arena.base, 0, I->arena.cap), "memset");
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
@@ -1097,7 +1220,7 @@ dlr_status dlr_destroy(dlr_handle h) {
         if (ev) (void)hipEventDestroy(ev);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     if (h->h_status) (void)hipHostFree(h->h_status);
-    if (h->arena.base) (void)hipFree(h->arena.base);
+    h->arena.release();
     delete h;
     return DLR_OK;
 }
@@ -1134,8 +1257,10 @@ dlr_status dlr_batch_create(size_t hbm_budget, void* hip_stream, dlr_batch* out)
             hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream");
             B->pool.push_back(st);
         }
-        hip_check(hipMalloc(&B->d_ticket, 4 * sizeof(unsigned)), "ticket");
-        hip_check(hipMemset(B->d_ticket, 0, 4 * sizeof(unsigned)), "ticket");
+        if (!dev_alloc(B->ticket_mem, 256, B->main)) throw HipError("ticket: device allocation failed");
+        B->d_ticket = static_cast<unsigned*>(B->ticket_mem.ptr);
+        hip_check(hipMemsetAsync(B->d_ticket, 0, 4 * sizeof(unsigned), B->main), "ticket");
+        hip_check(hipStreamSynchronize(B->main), "sync");
         hip_check(hipEventCreateWithFlags(&B->ev_main, hipEventDisableTiming), "event");
         batch_reserve(B, 64);
     } catch (const std::exception& ex) {
@@ -1287,12 +1412,12 @@ dlr_status dlr_batch_destroy(dlr_batch B) {
         if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
     }
     for (int g = 0; g < 2; ++g) {
-        if (B->d_table[g]) (void)hipFree(B->d_table[g]);
-        if (B->d_unit_end[g]) (void)hipFree(B->d_unit_end[g]);
+        dev_free(B->table_mem[g]);
+        dev_free(B->unit_end_mem[g]);
         if (B->h_table[g]) (void)hipHostFree(B->h_table[g]);
         if (B->h_unit_end[g]) (void)hipHostFree(B->h_unit_end[g]);
     }
-    if (B->d_ticket) (void)hipFree(B->d_ticket);
+    dev_free(B->ticket_mem);
     if (B->ev_main) (void)hipEventDestroy(B->ev_main);
     for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
     delete B;
@@ -1383,7 +1508,7 @@ dlr_status q1_check(dlr_q1_s* Q) {
     hip_check(hipStreamSynchronize(Q->stream), "stream sync");
     if (*Q->h_status == 0) return DLR_OK;
     Q->poisoned = true;
-    return fail(DLR_ERR_HIP, "Q1 sweep: a hand-off wait exceeded its spin limit");
+    return fail(DLR_ERR_TIMEOUT, "Q1 sweep: a hand-off wait exceeded its spin limit");
 }
 
 }  // namespace
@@ -1416,14 +1541,10 @@ dlr_status dlr_q1_create(int32_t nx, int32_t ny, double hx, double hy, int32_t n
         q1_carve(Q);   // sizing pass
         const size_t need = Q->arena.used;
         Q->arena.used = 0;
-        hipError_t e = hipMalloc(&Q->arena.base, need);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            Q->arena.base = nullptr;
+        if (!Q->arena.allocate(need, Q->stream)) {
             dlr_q1_destroy(Q);
-            return fail(DLR_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            return fail(DLR_ERR_OOM, "device allocation of the Q1 operator failed");
         }
-        Q->arena.cap = need;
         q1_carve(Q);
         hip_check(hipHostMalloc(reinterpret_cast<void**>(&Q->h_status), sizeof(int)), "host status");
         for (auto& ev : Q->ev) hip_check(hipEventCreate(&ev), "event");
@@ -1485,7 +1606,7 @@ dlr_status dlr_q1_destroy(dlr_q1 Q) {
     for (auto& ev : Q->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (Q->h_status) (void)hipHostFree(Q->h_status);
-    if (Q->arena.base) (void)hipFree(Q->arena.base);
+    Q->arena.release();
     delete Q;
     return DLR_OK;
 }

@@ -104,10 +104,26 @@ void launch_sn_phi(hipStream_t s, int nx, int ny, size_t ldg, const int* dirs, c
 // phi = X coef, coef = S beta (launch_wsum)
 void launch_phi_of_factors(hipStream_t s, int n, int r, const double* X, const double* coef, double* phi);
 
-void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
-                    const double* rho_cv, const double* D, double dt, double a, double c, double area,
-                    double* T, double* phi, double* partials, int nblocks, unsigned* counter, double* out,
-                    int* status);
+// Temperature update (Algorithm 1 step 9) with the energy sum and, for DLR, the outflow tally.
+struct TupdateArgs {
+    int nx, ny, r;                  // r = 0 and X = nullptr: plain SN (phi holds the converged flux)
+    const double* X;                // [r][N] column-major cells e = i * ny + j
+    const double* coef;             // [r] S beta
+    const double* gside;            // [4][r] side vectors of the outflow tally (launch_wsum), or nullptr
+    const double *sigma, *rho_cv, *D;
+    double dt, a, c, area, hx, hy;
+    double *T, *phi;
+    double* partials;               // [2 * nblocks]
+    unsigned* counter;              // zero between launches
+    double* out;                    // out[0] = energy, out[1] = outflow (when gside is set)
+    int* status;
+};
+void launch_tupdate(hipStream_t s, const TupdateArgs& A, int nblocks);
+// plain SN: out[1] = outflow tally from every ordinate's psi (diagonal planes of their orientations)
+template <typename TS>
+void launch_sn_outflow(hipStream_t s, int nx, int ny, int nq, size_t ldg, const double* mu, const double* eta,
+                       const double* w, const TS* psi, double hx, double hy, double* partials, int nblocks,
+                       unsigned* counter, double* out);
 
 // ----------------------------------------------------------------------------- sweep
 constexpr int kSweepWaves = 2;     // compute wavefronts (64-column strips) per sweep workgroup
@@ -266,9 +282,11 @@ void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const do
                  int flag_mask, int* status, int status_code);
 // X[k][c] = sum_j V[j][c] M[j][k] for a [r][n] column-major V (general r x r right multiply)
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X);
-// beta[k] = sum_q w_q W[k][q];  coef = S beta
+// beta[k] = sum_q w_q W[k][q];  coef = S beta.  With mu, eta and gside set, also the side vectors
+// of the outflow tally: gside[s][i] = sum_j S[i][j] sum_{q leaving through side s} w_q |Omega_q . n_s| W[j][q]
+// (sides 0 left, 1 right, 2 bottom, 3 top).
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
-                 double* coef);
+                 double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr);
 
 // status words written by kernels
 enum DeviceStatus : int {

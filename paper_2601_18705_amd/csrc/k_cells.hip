@@ -427,47 +427,107 @@ __global__ __launch_bounds__(kBlock) void k_psi_to_cm(TileGrid g, int r, const T
 // ---------------------------------------------------------------------------------------------- T update
 // Algorithm 1 step 9 with the mean intensity of the new factors phi = X (S beta):
 //   T = T0 + dt sigma (phi - a c T0^4) / D,  and energy sum area * (rho c_v T + phi / c).
+// With the side vectors gside[s] = S (sum over the ordinates leaving through side s of
+// w_q |Omega_q . n| W_q), the intensity leaving a wall cell e through side s, summed over
+// ordinates, is X(e) . gside[s]; times the face length this is the cell's share of the
+// outflow tally of the time-discrete energy balance.
 // RMAX >= r: the r values X_k(e) of a cell are loaded together (clamped rows, all in flight)
 template <int RMAX>
-__global__ __launch_bounds__(kBlock) void k_tupdate(int n, int r, const double* __restrict__ X,
-                                                    const double* __restrict__ coef, const double* __restrict__ sigma,
-                                                    const double* __restrict__ rho_cv, const double* __restrict__ D,
-                                                    double dt, double a, double c, double area, double* __restrict__ T,
-                                                    double* __restrict__ phi, double* __restrict__ partials,
-                                                    unsigned* counter, double* out, int* status) {
+__global__ __launch_bounds__(kBlock) void k_tupdate(TupdateArgs A) {
     __shared__ double sh[kBlock];
     __shared__ double sc[kMaxRank];
-    for (int i = threadIdx.x; i < r; i += blockDim.x) sc[i] = coef[i];
+    __shared__ double sg[4][kMaxRank];
+    const int n = A.nx * A.ny, r = A.r;
+    for (int i = threadIdx.x; i < r; i += blockDim.x) sc[i] = A.coef[i];
+    if (A.gside)
+        for (int i = threadIdx.x; i < 4 * r; i += blockDim.x) sg[i / r][i % r] = A.gside[i];
     __syncthreads();
-    double en = 0.0;
+    double en = 0.0, ob = 0.0;
     bool bad = false;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         double ph = 0.0;
-        if (X) {
-            double v[RMAX];
+        double v[RMAX];
+        if (A.X) {
 #pragma unroll
-            for (int k = 0; k < RMAX; ++k) v[k] = X[(size_t)(k < r ? k : r - 1) * n + e];
+            for (int k = 0; k < RMAX; ++k) v[k] = A.X[(size_t)(k < r ? k : r - 1) * n + e];
 #pragma unroll
             for (int k = 0; k < RMAX; ++k)
                 if (k < r) ph = fma(v[k], sc[k], ph);
         } else {
-            ph = phi[e];   // plain SN: the converged scalar flux
+            ph = A.phi[e];   // plain SN: the converged scalar flux
         }
-        const double t0 = T[e];
-        const double emis = a * c * t0 * t0 * t0 * t0;
-        const double t = t0 + dt * sigma[e] * (ph - emis) / D[e];
-        T[e] = t;
-        phi[e] = ph;
-        en += rho_cv[e] * t + ph / c;
+        const double t0 = A.T[e];
+        const double emis = A.a * A.c * t0 * t0 * t0 * t0;
+        const double t = t0 + A.dt * A.sigma[e] * (ph - emis) / A.D[e];
+        A.T[e] = t;
+        A.phi[e] = ph;
+        en += A.rho_cv[e] * t + ph / A.c;
         bad |= !(isfinite(ph) && isfinite(t));
+        if (A.X && A.gside) {
+            // column-major cells: e = i * ny + j
+            const unsigned ci = (unsigned)e / (unsigned)A.ny, cj = (unsigned)e - ci * (unsigned)A.ny;
+            const bool on[4] = {ci == 0u, ci == (unsigned)A.nx - 1u, cj == 0u, cj == (unsigned)A.ny - 1u};
+            if (on[0] || on[1] || on[2] || on[3]) {
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    if (!on[sd]) continue;
+                    double o = 0.0;
+#pragma unroll
+                    for (int k = 0; k < RMAX; ++k)
+                        if (k < r) o = fma(v[k], sg[sd][k], o);
+                    ob = fma(sd < 2 ? A.hy : A.hx, o, ob);
+                }
+            }
+        }
     }
-    if (bad) atomicOr(status, (int)kStatusNonfinite);
+    if (bad) atomicOr(A.status, (int)kStatusNonfinite);
     en = block_sum(en, sh);
-    if (threadIdx.x == 0) store_partial(&partials[blockIdx.x], en);
-    if (retire_block(counter)) {
-        const double E = ordered_sum(partials, gridDim.x, 1, sh);
+    ob = block_sum(ob, sh);
+    if (threadIdx.x == 0) {
+        store_partial(&A.partials[2 * blockIdx.x], en);
+        store_partial(&A.partials[2 * blockIdx.x + 1], ob);
+    }
+    if (retire_block(A.counter)) {
+        const double E = ordered_sum(A.partials, gridDim.x, 2, sh);
+        const double O = ordered_sum(A.partials + 1, gridDim.x, 2, sh);
         if (threadIdx.x == 0) {
-            out[0] = E * area;
+            A.out[0] = E * A.area;
+            if (A.gside) A.out[1] = O;
+            reset_counter(A.counter);
+        }
+    }
+}
+
+// Outflow tally of plain SN from every ordinate's intensity: in its sweep coordinates an
+// ordinate leaves through the last column i' = nx - 1 (x faces, length hy) and the last row
+// j' = ny - 1 (y faces, length hx).  Each block takes ordinates d = block, block + grid, ...;
+// out[1] = sum over d of w_d (|mu_d| hy sum_j' psi(nx-1, j') + |eta_d| hx sum_i' psi(i', ny-1)).
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_sn_outflow(int nx, int ny, int nq, size_t ldg,
+                                                       const double* __restrict__ mu, const double* __restrict__ eta,
+                                                       const double* __restrict__ w, const TS* __restrict__ psi,
+                                                       double hx, double hy, double* __restrict__ partials,
+                                                       unsigned* counter, double* out) {
+    __shared__ double sh[kBlock];
+    const int ndg = diag_groups(ny);
+    auto at = [&](const TS* p, int ip, int jp) {
+        const int l = ip & 63, t = jp + l;
+        return (double)p[((size_t)((ip >> 6) * ndg + (t >> 2)) * 64 + l) * 4 + (t & 3)];
+    };
+    double acc = 0.0;
+    for (int d = blockIdx.x; d < nq; d += gridDim.x) {
+        const TS* p = psi + (size_t)d * ldg;
+        double sx = 0.0, sy = 0.0;
+        for (int jp = threadIdx.x; jp < ny; jp += blockDim.x) sx += at(p, nx - 1, jp);
+        for (int ip = threadIdx.x; ip < nx; ip += blockDim.x) sy += at(p, ip, ny - 1);
+        acc += w[d] * (fabs(mu[d]) * hy * sx + fabs(eta[d]) * hx * sy);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) store_partial(&partials[blockIdx.x], acc);
+    if (retire_block(counter)) {
+        const double O = ordered_sum(partials, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            out[1] = O;
             reset_counter(counter);
         }
     }
@@ -762,22 +822,30 @@ template void launch_psi_to_cm<double>(hipStream_t, int, int, int, const double*
 template void launch_psi_to_cm<float>(hipStream_t, int, int, int, const float*, size_t, const double*, const double*,
                                       float*, size_t);
 
-void launch_tupdate(hipStream_t s, int n, int r, const double* X, const double* coef, const double* sigma,
-                    const double* rho_cv, const double* D, double dt, double a, double c, double area, double* T,
-                    double* phi, double* partials, int nblocks, unsigned* counter, double* out, int* status) {
+void launch_tupdate(hipStream_t s, const TupdateArgs& A, int nblocks) {
     const dim3 g(nblocks), b(kBlock);
-    if (r <= 8)
-        hipLaunchKernelGGL(k_tupdate<8>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
-                           counter, out, status);
-    else if (r <= 16)
-        hipLaunchKernelGGL(k_tupdate<16>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
-                           counter, out, status);
-    else if (r <= 32)
-        hipLaunchKernelGGL(k_tupdate<32>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
-                           counter, out, status);
+    if (A.r <= 8)
+        hipLaunchKernelGGL(k_tupdate<8>, g, b, 0, s, A);
+    else if (A.r <= 16)
+        hipLaunchKernelGGL(k_tupdate<16>, g, b, 0, s, A);
+    else if (A.r <= 32)
+        hipLaunchKernelGGL(k_tupdate<32>, g, b, 0, s, A);
     else
-        hipLaunchKernelGGL(k_tupdate<64>, g, b, 0, s, n, r, X, coef, sigma, rho_cv, D, dt, a, c, area, T, phi, partials,
-                           counter, out, status);
+        hipLaunchKernelGGL(k_tupdate<64>, g, b, 0, s, A);
 }
+
+template <typename TS>
+void launch_sn_outflow(hipStream_t s, int nx, int ny, int nq, size_t ldg, const double* mu, const double* eta,
+                       const double* w, const TS* psi, double hx, double hy, double* partials, int nblocks,
+                       unsigned* counter, double* out) {
+    hipLaunchKernelGGL(k_sn_outflow<TS>, dim3(std::max(1, std::min(nblocks, nq))), dim3(kBlock), 0, s, nx, ny, nq,
+                       ldg, mu, eta, w, psi, hx, hy, partials, counter, out);
+}
+template void launch_sn_outflow<double>(hipStream_t, int, int, int, size_t, const double*, const double*,
+                                        const double*, const double*, double, double, double*, int, unsigned*,
+                                        double*);
+template void launch_sn_outflow<float>(hipStream_t, int, int, int, size_t, const double*, const double*,
+                                       const double*, const float*, double, double, double*, int, unsigned*,
+                                       double*);
 
 }  // namespace dlr

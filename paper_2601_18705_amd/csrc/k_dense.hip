@@ -911,29 +911,63 @@ __global__ __launch_bounds__(256) void k_rmul(int n, int r, const double* __rest
 // beta_k = sum_q w_q W_k(q), coef = S beta; wavefront k sums column k (fixed lane order)
 __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __restrict__ W,
                                                const double* __restrict__ w, const double* __restrict__ S,
-                                               double* __restrict__ beta, double* __restrict__ coef) {
+                                               double* __restrict__ beta, double* __restrict__ coef,
+                                               const double* __restrict__ mu, const double* __restrict__ eta,
+                                               double* __restrict__ gside) {
     __shared__ double sb[kMaxRank];
+    __shared__ double sgs[4][kMaxRank];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool sides = gside != nullptr;
     // columns k and k + 16 of a wavefront are summed together (twice the loads in flight); each keeps
-    // its own lane order and butterfly
+    // its own lane order and butterfly.  With the side vectors, the ordinate's weight times its
+    // exit cosine goes to the side it leaves through (left mu < 0, right mu > 0, bottom eta < 0,
+    // top eta > 0).
     for (int k = wv; k < r; k += 32) {
         const int k2 = k + 16;
         const bool two = k2 < r;
         double acc = 0.0, acc2 = 0.0;
+        double g[4] = {0.0, 0.0, 0.0, 0.0}, g2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
         for (int q = lane; q < nq; q += 64) {
             const double wq = w[q];
-            acc += wq * W[(size_t)k * nq + q];
-            if (two) acc2 += wq * W[(size_t)k2 * nq + q];
+            const double x = W[(size_t)k * nq + q];
+            const double x2 = two ? W[(size_t)k2 * nq + q] : 0.0;
+            acc += wq * x;
+            if (two) acc2 += wq * x2;
+            if (sides) {
+                const double m = mu[q], e = eta[q];
+                const double fx = wq * fabs(m), fy = wq * fabs(e);
+                const int sx = m > 0.0 ? 1 : 0, sy = e > 0.0 ? 3 : 2;
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const double f = sd == sx ? fx : (sd == sy ? fy : 0.0);
+                    g[sd] += f * x;
+                    g2[sd] += f * x2;
+                }
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             acc += __shfl_xor(acc, off);
             acc2 += __shfl_xor(acc2, off);
         }
+        if (sides) {
+#pragma unroll
+            for (int sd = 0; sd < 4; ++sd)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    g[sd] += __shfl_xor(g[sd], off);
+                    g2[sd] += __shfl_xor(g2[sd], off);
+                }
+        }
         if (lane == 0) {
             sb[k] = acc;
             if (two) sb[k2] = acc2;
+            if (sides)
+                for (int sd = 0; sd < 4; ++sd) {
+                    sgs[sd][k] = g[sd];
+                    if (two) sgs[sd][k2] = g2[sd];
+                }
         }
     }
     __syncthreads();
@@ -946,6 +980,13 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
         for (int j = 0; j < r; ++j) s += sS[i * r + j] * sb[j];
         coef[i] = s;
     }
+    if (sides)
+        for (int t = threadIdx.x; t < 4 * r; t += blockDim.x) {
+            const int sd = t / r, i = t - sd * r;
+            double s = 0.0;
+            for (int j = 0; j < r; ++j) s += sS[i * r + j] * sgs[sd][j];
+            gside[t] = s;
+        }
 }
 
 }  // namespace
@@ -995,8 +1036,8 @@ void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, 
 }
 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
-                 double* coef) {
-    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef);
+                 double* coef, const double* mu, const double* eta, double* gside) {
+    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef, mu, eta, gside);
 }
 
 }  // namespace dlr

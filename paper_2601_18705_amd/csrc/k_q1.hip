@@ -402,7 +402,7 @@ __device__ __forceinline__ void q1_helper(const Q1Args<TS>& a, Q1Shared<TS>& sh,
             int avail = ny;
             if (from_edge) {
                 const unsigned long long pv = __hip_atomic_load(prog_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                avail = (pv >> 32) == a.launch_id ? (int)(pv & 0xffffffffull) : 0;
+                avail = (pv >> 32) == (a.launch_id & 0xffffffffull) ? (int)(pv & 0xffffffffull) : 0;
             }
             avail = min(avail, lds_load(&sh.cons[0]) + kRing);   // ring space
             avail = min(avail, rin + 64);

@@ -297,7 +297,7 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned lon
         bool moved = false;
         if (rin < ny) {
             const unsigned long long pv = __hip_atomic_load(prog_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int avail = (pv >> 32) == launch_id ? (int)(pv & 0xffffffffull) : 0;
+            int avail = (pv >> 32) == (launch_id & 0xffffffffull) ? (int)(pv & 0xffffffffull) : 0;
             avail = min(avail, lds_load(&sh.cons[0]) + kRing);   // ring space
             avail = min(avail, rin + 64);
             if (avail > rin) {

@@ -14,13 +14,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdlrtrt.so")
 
-DLR_ABI_VERSION = 1
+DLR_ABI_VERSION = 2
 DLR_OK = 0
 STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_HIP", -4: "DLR_ERR_NOT_CONVERGED",
-                -5: "DLR_ERR_NONFINITE", -6: "DLR_ERR_STATE", -7: "DLR_ERR_UNSUPPORTED", -8: "DLR_ERR_NUMERIC"}
+                -5: "DLR_ERR_NONFINITE", -6: "DLR_ERR_STATE", -7: "DLR_ERR_UNSUPPORTED", -8: "DLR_ERR_NUMERIC",
+                -9: "DLR_ERR_TIMEOUT"}
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
-EXPORTED = ["dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
+EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
             "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
             "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
@@ -46,7 +47,15 @@ class DlrStepStats(ctypes.Structure):
                 ("si_residual", ctypes.c_double), ("deim_min_margin", ctypes.c_double),
                 ("sum_abs_cw_over_4pi", ctypes.c_double), ("energy", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
-                ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("inflow", ctypes.c_double), ("outflow", ctypes.c_double), ("source", ctypes.c_double)]
+
+
+# dlr_set_allocator callbacks: alloc(bytes, stream, user) -> device pointer or NULL,
+# release(ptr, stream, user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None   # keeps the installed callbacks alive
 
 
 class DlrError(RuntimeError):
@@ -103,11 +112,12 @@ def library():
         lib.dlr_q1_sync.argtypes = [h]
         lib.dlr_q1_time.argtypes = [h, vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         lib.dlr_q1_destroy.argtypes = [h]
+        lib.dlr_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, ctypes.c_void_p]
         lib.dlr_status_string.argtypes = [ctypes.c_int]
         lib.dlr_status_string.restype = ctypes.c_char_p
         lib.dlr_last_error.argtypes = []
         lib.dlr_last_error.restype = ctypes.c_char_p
-        for name in ("dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
+        for name in ("dlr_set_allocator", "dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
                      "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
@@ -116,6 +126,40 @@ def library():
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def set_allocator(alloc=None, release=None):
+    """dlr_set_allocator with Python callables alloc(nbytes, stream) -> int device pointer (0 on
+    failure) and release(ptr, stream); both None restores hipMalloc / hipFree."""
+    global _allocator_refs
+    lib = library()
+    if alloc is None and release is None:
+        _check(lib.dlr_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        _allocator_refs = None
+        return
+
+    def _a(nbytes, stream, _user):
+        return int(alloc(int(nbytes), stream or 0)) or None
+
+    def _r(ptr, stream, _user):
+        release(int(ptr), stream or 0)
+
+    refs = (ALLOC_FN(_a), RELEASE_FN(_r))
+    _check(lib.dlr_set_allocator(refs[0], refs[1], None))
+    _allocator_refs = refs
+
+
+def torch_allocator():
+    """(alloc, release) callables backed by PyTorch's caching allocator on the current device."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def release(ptr, _stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, release
 
 
 def _check(status):

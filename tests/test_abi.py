@@ -107,3 +107,13 @@ def test_batch_footprint_validates():
     with pytest.raises(dlrtrt.DlrError) as ei:
         dlrtrt.footprint(p)
     assert ei.value.status == -1
+
+
+def test_set_allocator_needs_both_functions_or_neither():
+    if not os.path.exists(dlrtrt.LIB_PATH):
+        pytest.skip("libdlrtrt.so not built")
+    lib = dlrtrt.library()
+    keep = dlrtrt.ALLOC_FN(lambda n, s, u: None)
+    assert lib.dlr_set_allocator(keep, dlrtrt.RELEASE_FN(), None) == -1
+    assert lib.dlr_set_allocator(dlrtrt.ALLOC_FN(), dlrtrt.RELEASE_FN(), None) == 0
+    assert lib.dlr_status_string(-9).decode() == "device wait exceeded its spin limit"

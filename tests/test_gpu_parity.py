@@ -1,9 +1,14 @@
 """GPU parity of the HIP path against the FP64 CPU oracle (same seeded inputs).
 
-FP64 mode: relative L2 error of E_r = phi / c and of T at most 1e-10 at every
-step.  The DEIM picks are compared first; when they agree the run is checked
-free-running, otherwise the GPU is re-run with the oracle's picks forced
-(replay) and checked there, and the divergence is reported.
+FP64 mode: relative L2 and max-norm error of E_r = phi / c and of T, and the
+per-cell relative error of T, at most 1e-10 at every step; the device's energy
+sum, boundary outflow and inflow agree with the oracle's to the same tolerance.
+The DEIM picks are compared first.  When they agree the run is checked
+free-running.  When they differ at a step whose oracle decision edge (distance of
+a residual from the tie threshold) is above the near-tie level of the precision,
+the test fails: the GPU picked wrongly.  Otherwise (a real near-tie) the GPU is
+re-run with the oracle's picks forced (replay), checked there, and the
+divergence is reported.
 """
 import numpy as np
 import pytest
@@ -11,15 +16,24 @@ import pytest
 from oracle import dlr_oracle as O
 from synth import problems
 
+from _parity import NEAR_TIE, balance_residual, check_balance, check_fields, rel
+
 pytestmark = pytest.mark.gpu
 
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+_ORACLE_CACHE = {}
 
 
-def gpu_run(p, nsteps, forced=None):
+def oracle_run(p, nsteps, key=None):
+    """The oracle's per-step records (cached by key, for problems shared between tests)."""
+    if key is not None and key in _ORACLE_CACHE and len(_ORACLE_CACHE[key]) >= nsteps:
+        return _ORACLE_CACHE[key][:nsteps]
+    _, ref = O.run_dlr(p, nsteps=nsteps)
+    if key is not None:
+        _ORACLE_CACHE[key] = ref
+    return ref
+
+
+def gpu_run(p, nsteps, forced=None, prev=None):
     from paper_2601_18705_amd import dlrtrt
     out = []
     with dlrtrt.Instance(p) as inst:
@@ -33,29 +47,36 @@ def gpu_run(p, nsteps, forced=None):
     return out
 
 
-def compare(p, nsteps, tol, label, gpu_overrides=None):
+def compare(p, nsteps, tol, label, gpu_overrides=None, ref=None):
     """Oracle on p (FP64, its own SI tolerance); GPU on p updated with gpu_overrides."""
     pg = dict(p, **(gpu_overrides or {}))
+    prec = int(pg.get("precision", 0))
     print(f"[parity] {label}: {p['nx']}x{p['ny']} q{p['n_polar']}x{p['n_azim']} r{p['rank']} "
-          f"prec{pg['precision']} steps{nsteps}", flush=True)
-    _, ref = O.run_dlr(p, nsteps=nsteps)
+          f"prec{prec} steps{nsteps}", flush=True)
+    if ref is None:
+        ref = oracle_run(p, nsteps)
     g = gpu_run(pg, nsteps)
     same = all(np.array_equal(np.asarray(a["sel"]), np.asarray(b["sel"])) for a, b in zip(g, ref))
     if not same:
         first = next(n for n, (a, b) in enumerate(zip(g, ref)) if not np.array_equal(a["sel"], b["sel"]))
-        print(f"[parity] {label}: DEIM picks diverge at step {first} (oracle margins "
-              f"{np.round(ref[first]['margins'], 8)}); replaying the oracle's picks", flush=True)
+        edge = float(np.min(ref[first]["deim_edge"]))
+        assert edge <= NEAR_TIE[prec], (
+            f"{label}: DEIM picks differ at step {first} although the oracle's decision edge "
+            f"{edge:.3e} is above the near-tie level {NEAR_TIE[prec]:g}: "
+            f"gpu {g[first]['sel'].tolist()} oracle {ref[first]['sel'].tolist()}")
+        print(f"[parity] {label}: near-tie at step {first} (decision edge {edge:.3e}); "
+              f"replaying the oracle's picks", flush=True)
         free = g
         g = gpu_run(pg, nsteps, forced=[h["sel"] for h in ref])
         fe = max(max(rel(a["E_r"], b["E_r"]), rel(a["T"], b["T"])) for a, b in zip(free, ref))
-        print(f"[parity] {label}: free-running worst rel-L2 {fe:.3e} (reported, not asserted)", flush=True)
+        print(f"[parity] {label}: free-running worst rel-L2 {fe:.3e} after the near-tie (reported)", flush=True)
     worst = 0.0
     for n, (a, b) in enumerate(zip(g, ref)):
-        eE, eT = rel(a["E_r"], b["E_r"]), rel(a["T"], b["T"])
-        worst = max(worst, eE, eT)
-        assert eE <= tol and eT <= tol, f"{label} step {n}: rel E_r {eE:.3e}, T {eT:.3e}"
+        worst = max(worst, check_fields(a["E_r"], a["T"], b, tol, f"{label} step {n}"))
+        check_balance(a["stats"], b, tol, f"{label} step {n}")
         assert a["stats"]["si_iters"] >= 1
-    print(f"[parity] {label}: worst rel-L2 {worst:.3e} (free-running={same})", flush=True)
+    print(f"[parity] {label}: worst error {worst:.3e} (free-running={same}); "
+          f"SI iterations {[a['stats']['si_iters'] for a in g]}", flush=True)
     return worst, same
 
 
@@ -90,12 +111,19 @@ def test_checkerboard_fp64_first_steps():
 
 
 def test_full_rank_gpu_equals_plain_sn():
-    """r = N_Omega: the GPU DLR step reproduces the oracle's plain SN step."""
+    """r = N_Omega: the GPU DLR step reproduces the oracle's plain SN step, and its own
+    statistics close the energy balance E(n+1) - E(n) = dt (source + inflow - outflow)."""
     p = problems.slab_beam(nx=32, n_polar=4, n_azim=8, rank=32, nsteps=5)
+    p["q_ext"] = np.linspace(0.0, 1.0, p["nx"] * p["ny"])
+    p["bc"] = [1, 0, 1, 0]
+    p["T_b"] = [1.0, 0.0, 0.6, 0.0]
     _, sn = O.run_sn(p, nsteps=5)
     g = gpu_run(p, 5)
-    for a, b in zip(g, sn):
-        assert rel(a["E_r"], b["E_r"]) < 1e-10 and rel(a["T"], b["T"]) < 1e-10
+    for n, (a, b) in enumerate(zip(g, sn)):
+        check_fields(a["E_r"], a["T"], b, 1e-10, f"full rank step {n}")
+        check_balance(a["stats"], b, 1e-10, f"full rank step {n}")
+        if n > 0:
+            assert balance_residual(g[n - 1]["stats"]["energy"], a["stats"], p["dt"]) < 1e-12
 
 
 def test_runs_are_bitwise_reproducible():
@@ -183,19 +211,49 @@ def test_bf16_projections_within_1e4(name, factory, steps):
     print(f"[parity] {name} bf16 projections: worst rel-L2 {worst:.3e}", flush=True)
 
 
-def test_full_size_random_medium_first_step():
-    """The benchmark workload at its full size (1024^2, 32 x 64 ordinates, r = 32): one step
-    against the oracle, FP64 to 1e-10 and FP32 sweeps to 1e-4."""
-    p = problems.random_medium(nsteps=1)
-    compare(p, 1, 1e-10, "random medium 1024^2 fp64")
-    compare(p, 1, 1e-4, "random medium 1024^2 fp32", FP32)
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("label,over,tol", [("fp64", None, 1e-10), ("fp32", FP32, 1e-4)])
+def test_full_size_random_medium_five_steps(label, over, tol):
+    """The benchmark workload at its full size (1024^2, 32 x 64 ordinates, r = 32): five
+    free-running steps against the oracle, FP64 to 1e-10 and FP32 sweeps to 1e-4."""
+    p = problems.random_medium(nsteps=5)
+    ref = oracle_run(p, 5, key="random_medium_1024")
+    compare(p, 5, tol, f"random medium 1024^2 {label}", over, ref=ref)
+
+
+def random_medium_cut(n=256, nsteps=100):
+    """The lower-left n x n cells of the 1024^2 benchmark medium (same cells, same opacity
+    field, domain [0, n/1024]^2, left inflow): 100 steps reach the heated regime, where
+    the source iteration needs several sweeps per step."""
+    full = problems.random_medium(n=1024, nsteps=nsteps)
+    p = problems.random_medium(n=n, nsteps=nsteps)
+    p["sigma_a"] = full["sigma_a"].reshape(1024, 1024)[:n, :n].ravel().copy()
+    p["x1"] = p["y1"] = n / 1024.0
+    p["name"] = f"random_medium_cut_{n}x{n}_q32x64_r32_seed3"
+    return p
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("label,over,tol", [("fp64", None, 1e-10), ("fp32", FP32, 1e-4)])
+def test_random_medium_cut_100_steps(label, over, tol):
+    """256^2 cut of the benchmark medium, 2048 ordinates, r = 32, 100 steps (t = 0.2)."""
+    p = random_medium_cut()
+    ref = oracle_run(p, 100, key="random_medium_cut_256")
+    print(f"[parity] cut 256^2: oracle SI iterations {[h['si_iters'] for h in ref[::10]]} (every 10th step)",
+          flush=True)
+    assert max(h["si_iters"] for h in ref) >= 5
+    compare(p, 100, tol, f"random medium cut 256^2 {label}", over, ref=ref)
 
 
 @pytest.mark.parametrize("rank", [48, 64])
-def test_largest_ranks(rank):
-    """Ranks that take the three- and four-tile MFMA paths (r = 64 is also full rank here)."""
+@pytest.mark.parametrize("label,over,tol", [("fp64", None, 1e-10), ("fp32", FP32, 1e-4),
+                                            ("bf16", {"precision": 2, "si_tol": 1e-6}, 1e-4)])
+def test_largest_ranks(rank, label, over, tol):
+    """Ranks that take the three- and four-tile MFMA paths (r = 64 is also full rank here),
+    in every precision mode."""
     p = problems.slab_beam(nx=24, n_polar=8, n_azim=8, rank=rank, nsteps=3)
-    compare(p, 3, 1e-10, f"slab 24^2 rank {rank} fp64")
+    ref = oracle_run(p, 3, key=f"slab24_r{rank}")
+    compare(p, 3, tol, f"slab 24^2 rank {rank} {label}", over, ref=ref)
 
 
 def test_single_cell_rank_one():
