@@ -4,11 +4,13 @@ FP64 mode: relative L2 and max-norm error of E_r = phi / c and of T, and the
 per-cell relative error of T, at most 1e-10 at every step; the device's energy
 sum, boundary outflow and inflow agree with the oracle's to the same tolerance.
 The DEIM picks are compared first.  When they agree the run is checked
-free-running.  When they differ at a step whose oracle decision edge (distance of
-a residual from the tie threshold) is above the near-tie level of the precision,
-the test fails: the GPU picked wrongly.  Otherwise (a real near-tie) the GPU is
-re-run with the oracle's picks forced (replay), checked there, and the
-divergence is reported.
+free-running.  When the first differing pick has an oracle decision edge
+(distance of a residual from the tie threshold) above what the precision can
+perturb -- the near-tie level, or the uncertainty of an angular basis whose
+singular values of the previous step are nearly degenerate, so that the SVD fixes
+its columns only up to rotations among them -- the test fails: the GPU picked
+wrongly.  Otherwise the GPU is re-run with the oracle's picks forced (replay),
+checked there, and the divergence is reported.
 """
 import numpy as np
 import pytest
@@ -16,7 +18,7 @@ import pytest
 from oracle import dlr_oracle as O
 from synth import problems
 
-from _parity import NEAR_TIE, balance_residual, check_balance, check_fields, rel
+from _parity import balance_residual, check_balance, check_fields, divergence_allowed, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +49,12 @@ def gpu_run(p, nsteps, forced=None, prev=None):
     return out
 
 
+# Per-cell relative temperature error allowed with split-BF16 projection operands: the split
+# keeps about 16 bits of each operand, and a cold cell's temperature change carries the
+# absolute error of phi, which is set by the hot region; relative L2 and max-norm stay at 1e-4.
+BF16_CELL_TOL = 1e-3
+
+
 def compare(p, nsteps, tol, label, gpu_overrides=None, ref=None):
     """Oracle on p (FP64, its own SI tolerance); GPU on p updated with gpu_overrides."""
     pg = dict(p, **(gpu_overrides or {}))
@@ -59,20 +67,22 @@ def compare(p, nsteps, tol, label, gpu_overrides=None, ref=None):
     same = all(np.array_equal(np.asarray(a["sel"]), np.asarray(b["sel"])) for a, b in zip(g, ref))
     if not same:
         first = next(n for n, (a, b) in enumerate(zip(g, ref)) if not np.array_equal(a["sel"], b["sel"]))
-        edge = float(np.min(ref[first]["deim_edge"]))
-        assert edge <= NEAR_TIE[prec], (
-            f"{label}: DEIM picks differ at step {first} although the oracle's decision edge "
-            f"{edge:.3e} is above the near-tie level {NEAR_TIE[prec]:g}: "
+        j = int(np.flatnonzero(np.asarray(g[first]["sel"]) != np.asarray(ref[first]["sel"]))[0])
+        ok, edge, limit = divergence_allowed(ref, first, j, prec)
+        assert ok, (
+            f"{label}: DEIM pick {j} differs at step {first} although the oracle's decision edge "
+            f"{edge:.3e} is above the allowed {limit:.3e}: "
             f"gpu {g[first]['sel'].tolist()} oracle {ref[first]['sel'].tolist()}")
-        print(f"[parity] {label}: near-tie at step {first} (decision edge {edge:.3e}); "
-              f"replaying the oracle's picks", flush=True)
+        print(f"[parity] {label}: pick {j} differs at step {first} (decision edge {edge:.3e}, "
+              f"allowed {limit:.3e}); replaying the oracle's picks", flush=True)
         free = g
         g = gpu_run(pg, nsteps, forced=[h["sel"] for h in ref])
         fe = max(max(rel(a["E_r"], b["E_r"]), rel(a["T"], b["T"])) for a, b in zip(free, ref))
         print(f"[parity] {label}: free-running worst rel-L2 {fe:.3e} after the near-tie (reported)", flush=True)
     worst = 0.0
     for n, (a, b) in enumerate(zip(g, ref)):
-        worst = max(worst, check_fields(a["E_r"], a["T"], b, tol, f"{label} step {n}"))
+        worst = max(worst, check_fields(a["E_r"], a["T"], b, tol, f"{label} step {n}",
+                                        cell_tol=BF16_CELL_TOL if prec == 2 else None))
         check_balance(a["stats"], b, tol, f"{label} step {n}")
         assert a["stats"]["si_iters"] >= 1
     print(f"[parity] {label}: worst error {worst:.3e} (free-running={same}); "
