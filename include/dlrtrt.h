@@ -286,6 +286,26 @@ dlr_status dlr_q1_time(dlr_q1 h, const void *sigma_t, const void *src, const voi
 /* Free the operator (waits for its stream first).  NULL-safe. */
 dlr_status dlr_q1_destroy(dlr_q1 h);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * or harnesses that forbid hipMalloc): one sweep as dlr_q1_sweep, without an operator handle.
+ * The arguments are those of dlr_q1_create and dlr_q1_sweep, except that mu and eta are DEVICE
+ * arrays [n_dir] (finite, not both zero in a direction; not checked) and the stream must belong
+ * to the current device.  status: device int32 owned by the caller, who clears it; the call ORs a
+ * nonzero code into it when a cross-workgroup wait of the sweep exceeded its spin limit (what
+ * dlr_q1_sync reports as DLR_ERR_TIMEOUT).  The call is asynchronous and allocates nothing: the
+ * sweep's hand-off state (unit ticket, progress words, edge values) lives in a static device
+ * array of 16 MiB per GPU, held until the process ends; it needs
+ * 256 + 8 n_dir ceil(nx / 128) (rounded up to 256) + 2 n_dir ceil(nx / 128) ny * element bytes,
+ * and larger problems are rejected with DLR_ERR_ARG before any work is queued.  Every call on a
+ * GPU shares that array: calls that overlap on one GPU (different streams, or threads) race and
+ * must be serialised by the caller; calls queued one after another on one stream are fine.
+ * Errors: DLR_ERR_ARG (shape, NULL or misaligned array, scratch too small, stream of another
+ * device), DLR_ERR_HIP (symbol lookup or launch), DLR_ERR_UNSUPPORTED (device index >= 64). */
+dlr_status dlr_q1_sweep_noalloc(int32_t nx, int32_t ny, double hx, double hy, int32_t n_dir, const double *mu,
+                                const double *eta, int32_t precision, void *hip_stream, const void *sigma_t,
+                                const void *src, const void *inflow_x, const void *inflow_y, void *psi,
+                                int32_t *status);
+
 /* Static description of a status code. */
 const char *dlr_status_string(dlr_status s);
 

@@ -1612,3 +1612,94 @@ dlr_status dlr_q1_destroy(dlr_q1 Q) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------------------
+// Q1 sweep without allocation.  The hand-off state of the sweep (unit ticket, progress words, edge
+// values) lives in a static device array instead of an operator's arena.  In host code the array's
+// name only stands for the symbol; its device address (one per GPU) comes from hipGetSymbolAddress
+// with that GPU current and is what every kernel argument uses.
+namespace {
+
+constexpr size_t kQ1ScratchBytes = size_t(16) << 20;
+constexpr size_t kQ1ScratchHead = 256;   // ticket [2] (zeroed before every launch), then progress, edges
+__device__ __align__(256) unsigned char scratch[kQ1ScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+__global__ void k_zero_words(unsigned* p, int n) {
+    const int i = (int)threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// the device address of the scratch array on the current device (resolved once per device)
+dlr_status scratch_address(hipStream_t stream, void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(DLR_ERR_HIP, "hipGetDevice failed");
+    if (stream) {
+        int sdev = -1;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return fail(DLR_ERR_HIP, "hipStreamGetDevice failed");
+        if (sdev != dev) return fail(DLR_ERR_ARG, "the stream belongs to another device than the current one");
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(DLR_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(DLR_ERR_HIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dlr_status dlr_q1_sweep_noalloc(int32_t nx, int32_t ny, double hx, double hy, int32_t n_dir, const double* mu,
+                                const double* eta, int32_t precision, void* hip_stream, const void* sigma_t,
+                                const void* src, const void* inflow_x, const void* inflow_y, void* psi,
+                                int32_t* status) {
+    g_last_error.clear();
+    if (nx < 1 || ny < 1 || nx > (1 << 20) || ny > (1 << 20) || (int64_t)nx * ny > (int64_t(1) << 28))
+        return fail(DLR_ERR_ARG, "need 1 <= nx, ny <= 2^20 and nx * ny <= 2^28");
+    if (!(hx > 0.0) || !(hy > 0.0) || !std::isfinite(hx) || !std::isfinite(hy))
+        return fail(DLR_ERR_ARG, "cell sizes must be positive and finite");
+    if (n_dir < 1 || !mu || !eta) return fail(DLR_ERR_ARG, "need n_dir >= 1 and direction arrays");
+    if (precision != DLR_FP64 && precision != DLR_FP32_SWEEP)
+        return fail(DLR_ERR_ARG, "precision must be DLR_FP64 or DLR_FP32_SWEEP");
+    if (!status) return fail(DLR_ERR_ARG, "status is NULL");
+    dlr_q1_s Q;   // describes the launch only: no arena, no events
+    Q.nx = nx; Q.ny = ny; Q.nd = n_dir; Q.precision = precision;
+    Q.hx = hx; Q.hy = hy;
+    Q.nsuper = (nx + 64 * dlr::kQ1Waves - 1) / (64 * dlr::kQ1Waves);
+    Q.grid = std::min(Q.nsuper * n_dir, 2048);
+    Q.stream = static_cast<hipStream_t>(hip_stream);
+    const size_t nprog = (size_t)n_dir * Q.nsuper;
+    const size_t edge_off = (kQ1ScratchHead + nprog * sizeof(unsigned long long) + 255) & ~size_t(255);
+    const size_t need = edge_off + nprog * (size_t)ny * 2 * Q.elem();
+    if (need > kQ1ScratchBytes)
+        return fail(DLR_ERR_ARG, "n_dir * ceil(nx / 128) * ny exceeds the static scratch of " +
+                                     std::to_string(kQ1ScratchBytes >> 20) + " MiB");
+    void* base = nullptr;
+    const dlr_status sa = scratch_address(Q.stream, &base);
+    if (sa != DLR_OK) return sa;
+    char* b = static_cast<char*>(base);
+    Q.ticket = reinterpret_cast<unsigned*>(b);
+    Q.progress = reinterpret_cast<unsigned long long*>(b + kQ1ScratchHead);
+    Q.edge = b + edge_off;
+    Q.mu = const_cast<double*>(mu);
+    Q.eta = const_cast<double*>(eta);
+    Q.status = status;
+    // the unit ticket must start at zero (a fill kernel, not a memset: the call may be captured)
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, Q.stream, Q.ticket, 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DLR_ERR_HIP, std::string("scratch clear: ") + hipGetErrorString(e));
+    // progress words carry the launch id, so stale ones from earlier calls never match
+    return q1_launch(&Q, sigma_t, src, inflow_x, inflow_y, psi);
+}
+
+}  // extern "C"

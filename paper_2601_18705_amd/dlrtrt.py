@@ -25,7 +25,7 @@ EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr
             "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
             "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
-            "dlr_q1_time", "dlr_q1_destroy", "dlr_status_string", "dlr_last_error"]
+            "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc", "dlr_status_string", "dlr_last_error"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -112,6 +112,8 @@ def library():
         lib.dlr_q1_sync.argtypes = [h]
         lib.dlr_q1_time.argtypes = [h, vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         lib.dlr_q1_destroy.argtypes = [h]
+        lib.dlr_q1_sweep_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
         lib.dlr_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, ctypes.c_void_p]
         lib.dlr_status_string.argtypes = [ctypes.c_int]
         lib.dlr_status_string.restype = ctypes.c_char_p
@@ -122,7 +124,7 @@ def library():
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
                      "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
-                     "dlr_q1_time", "dlr_q1_destroy"):
+                     "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -360,6 +362,28 @@ class Instance:
             self.close()
         except Exception:
             pass
+
+
+def q1_sweep_noalloc(nx, ny, hx, hy, mu, eta, precision, sigma_t, src, inflow_x, inflow_y, psi, status,
+                     stream=None):
+    """dlr_q1_sweep_noalloc: one Q1 sweep without an operator handle and without allocating.
+    mu, eta: float64 GPU tensors [n_dir]; status: int32 GPU tensor [1] (the caller clears it);
+    the arrays as in Q1Sweep.  Asynchronous on `stream` (None = the null stream)."""
+    import torch
+    nd = int(mu.numel())
+    dt = torch.float64 if int(precision) == DLR_FP64 else torch.float32
+    n = int(nx) * int(ny)
+    want = ((mu, torch.float64, nd), (eta, torch.float64, nd), (sigma_t, dt, n), (src, dt, nd * n * 4),
+            (inflow_x, dt, nd * int(ny) * 2), (inflow_y, dt, nd * int(nx) * 2), (psi, dt, nd * n * 4),
+            (status, torch.int32, 1))
+    ptrs = []
+    for t, tdt, size in want:
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == tdt and t.is_contiguous()
+                and t.numel() == size):
+            raise ValueError(f"expected a contiguous {tdt} GPU tensor of {size} elements")
+        ptrs.append(ctypes.c_void_p(t.data_ptr()))
+    _check(library().dlr_q1_sweep_noalloc(int(nx), int(ny), float(hx), float(hy), nd, ptrs[0], ptrs[1],
+                                          int(precision), ctypes.c_void_p(stream or 0), *ptrs[2:]))
 
 
 class Q1Sweep:
