@@ -59,13 +59,31 @@ def make_problem(name):
     return p
 
 
-def cpu_baseline(p, steps, warm=0):
-    """The FP64 oracle on the host: `steps` DLR steps from the cold start
-    (initial factors not timed), single thread (BLAS pinned to one thread)."""
+def host_info():
+    """Host CPU model and logical core count (the oracle's baseline is timed on these)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(p, steps, threads=1):
+    """The FP64 oracle on the host: `steps` DLR steps from the cold start (initial factors
+    not timed).  threads = 1 pins BLAS to one thread; threads = None lets it use every core
+    the process may run on (the oracle's C sweep itself is single-threaded)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import dlr_oracle as O
-    with threadpool_limits(limits=1):
+    cores = threads if threads is not None else (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                                                 else os.cpu_count())
+    with threadpool_limits(limits=threads):
         quad = O.quadrature(p["n_polar"], p["n_azim"])
         st = O.dlr_initial_state(p, quad)
         ca = 0
@@ -74,21 +92,29 @@ def cpu_baseline(p, steps, warm=0):
             st, s = O.dlr_step(p, quad, st)
             ca += s["si_iters"] * p["nx"] * p["ny"] * p["rank"]
         dt = time.perf_counter() - t0
-    return {"value": ca / dt, "unit": "cell-angle updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} DLR step(s) of the same workload from its cold start, FP64, 1 thread "
+    return {"value": ca / dt, "unit": "cell-angle updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} DLR step(s) of the same workload from its cold start, FP64, "
+                      f"{'1 thread' if threads == 1 else f'BLAS on {cores} threads, C sweep on one'} "
                       f"({dt:.1f} s, {ca} cell-angle updates)",
             "steps_per_s": steps / dt}
 
 
-def serving_leg(n_requests, max_s, budget_gib):
-    """Continuous batching over the first n_requests of the seeded Poisson request stream
-    (FP32 sweeps); p50/p99 time-to-solution and aggregate cell-angle updates/s."""
+def serving_leg(window_s, max_s, budget_gib, max_requests=10000):
+    """Continuous batching over the seeded Poisson request stream (200 requests/s) for a fixed
+    window of arrivals; the loop stops at max_s wall seconds.  FP32 sweeps.  Reports what
+    arrived, completed and is left (admitted or queued), p50/p99 time-to-solution of the
+    completed requests, and aggregate cell-angle updates/s."""
     from paper_2601_18705_amd import dlrtrt, serve
     from synth import problems
-    reqs = []
-    for t, prob in problems.request_stream(count=n_requests):
-        prob["precision"], prob["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
-        reqs.append((t, prob, int(prob["nsteps"])))
+    specs = problems.request_specs(count=max_requests, window_s=window_s)
+
+    def fp32(build):
+        def make():
+            prob = build()
+            prob["precision"], prob["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+            return prob
+        return make
+    reqs = [(t, fp32(build), ns) for t, build, ns, _ in specs]
 
     def progress(passes, done, inflight, queued):
         if passes % 50 == 0:
@@ -96,11 +122,14 @@ def serving_leg(n_requests, max_s, budget_gib):
                   file=sys.stderr, flush=True)
 
     res = serve.serve(reqs, hbm_budget=int(budget_gib * (1 << 30)), max_wall_s=max_s, progress=progress)
-    return {"requests": n_requests, "completed": res["completed"], "unfinished": res["unfinished"],
+    return {"requests_in_window": len(reqs), "arrival_window_s": window_s, "arrived": res["arrived"],
+            "completed": res["completed"], "failed": len(res["failed"]),
+            "unfinished_admitted": res["unfinished_admitted"], "unfinished_queued": res["unfinished_queued"],
+            "sustained_completions_per_s": res["completed"] / res["wall_s"],
             "p50_s": res["p50_s"], "p99_s": res["p99_s"], "ca_per_s": res["ca_per_s"], "wall_s": res["wall_s"],
             "hbm_budget_gib": budget_gib,
             "stream": "seeded Poisson 200 req/s; 64^2-1024^2 grids, ranks 8-32, 20-200 steps, 512 ordinates, "
-                      "checkerboard or log-normal medium"}
+                      "checkerboard or log-normal medium; latency counts from arrival (problem built on admission)"}
 
 
 def sn_leg(workload, precision, si_tol, steps, dlr_steps_per_s):
@@ -200,8 +229,9 @@ def batch_run(count, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed DLR steps from the cold start (200 = the whole configured trajectory)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps on a separate instance first")
     ap.add_argument("--workload", default="random_medium")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed for the CPU baseline (0 = skip; 4 take about 10 s)")
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
@@ -211,12 +241,14 @@ def main():
                     help="steps of the plain SN comparison leg over every ordinate (0 = skip)")
     ap.add_argument("--q1-reps", type=int, default=20,
                     help="timed launches of the bilinear DG sweep leg, 1024^2 cells x 32 directions (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=48,
-                    help="requests of the serving leg (0 = skip); p50/p99 time-to-solution")
-    ap.add_argument("--serve-max-s", type=float, default=60.0, help="wall-time cap of the serving leg")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="instances of the batched leg (0 = skip): 64^2-256^2 grids, ranks 4-24, 50 steps each")
+    ap.add_argument("--serve-window-s", type=float, default=30.0,
+                    help="arrival window of the serving leg in seconds (0 = skip)")
+    ap.add_argument("--serve-max-s", type=float, default=45.0, help="wall-time cap of the serving leg")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving batch")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
-                    help="run the batched-instances workload (COUNT problems, 50 steps) instead")
+                    help="run only the batched-instances workload (COUNT problems, 50 steps)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed run, run a plain elementwise kernel over a buffer of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -237,34 +269,45 @@ def main():
                           **res}), flush=True)
         return
 
-    p = make_problem(args.workload)
-    if args.fp64:
-        p["precision"], p["si_tol"] = dlrtrt.DLR_FP64, 1e-14
-    else:
-        p["precision"], p["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+    def problem():
+        p = make_problem(args.workload)
+        if args.fp64:
+            p["precision"], p["si_tol"] = dlrtrt.DLR_FP64, 1e-14
+        else:
+            p["precision"], p["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
+        return p
+
+    p = problem()
     N, r = p["nx"] * p["ny"], p["rank"]
     print(f"[bench] workload {p['name']} precision {'fp64' if args.fp64 else 'fp32-sweep'} "
           f"warmup {args.warmup} steps {args.steps}", file=sys.stderr, flush=True)
     torch.cuda.init()
+    if args.warmup > 0:
+        with dlrtrt.Instance(p) as warm:
+            warm.step(args.warmup)
+    torch.cuda.synchronize()
     inst = dlrtrt.Instance(p)
-    for _ in range(args.warmup):
-        inst.step(1)
     torch.cuda.synchronize()
     ca = 0
     sweep_ms = 0.0
     launches = 0
     step_ms = 0.0
     svd_sweeps = 0
+    si_hist = []
+    step_wall = []
     t0 = time.perf_counter()
     for k in range(args.steps):
+        ts = time.perf_counter()
         inst.step(1)
         st = inst.read_stats()
+        step_wall.append(time.perf_counter() - ts)
         ca += st["si_iters"] * N * r
         sweep_ms += st["sweep_ms"]
         launches += st["si_iters"]
         step_ms += st["step_ms"]
         svd_sweeps += st["svd_sweeps"]
-        if k % 5 == 4:
+        si_hist.append(int(st["si_iters"]))
+        if k % 50 == 49:
             print(f"[bench] step {k + 1}/{args.steps} si {st['si_iters']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -285,6 +328,7 @@ def main():
             torch.mul(a, 2.0, out=b)   # one elementwise kernel: reads and writes n * 4 bytes
         torch.cuda.synchronize()
 
+    last = step_wall[-20:]
     out = {
         "metric": METRIC,
         "value": ca / wall,
@@ -299,11 +343,14 @@ def main():
         "dtype": "f64" if args.fp64 else "f32",
         "data": "synthetic (seeded log-normal random medium; no dataset)",
         "config": {"workload": p["name"], "nx": p["nx"], "ny": p["ny"], "directions": p["n_polar"] * p["n_azim"],
-                   "rank": r, "dt": p["dt"], "si_tol": p["si_tol"],
+                   "rank": r, "dt": p["dt"], "si_tol": p["si_tol"], "timed_steps": "1..%d from the cold start" % args.steps,
                    "precision": "fp64" if args.fp64 else "fp32 sweeps+projections, fp64 selection/QR/SVD/L-step/T"},
         "dlr_steps_per_s": args.steps / wall,
+        "dlr_steps_per_s_last20": len(last) / sum(last),
         "sweep_cell_angle_updates_per_s": ca / (sweep_ms / 1e3),
         "si_iterations_per_step": launches / args.steps,
+        "si_iterations_per_step_last20": sum(si_hist[-20:]) / len(si_hist[-20:]),
+        "si_iterations_histogram": {str(k): si_hist.count(k) for k in sorted(set(si_hist))},
         "device_ms_per_step": step_ms / args.steps,
         "svd_sweeps_per_step": svd_sweeps / args.steps,
         "latency_p50_p99_s": None,
@@ -312,6 +359,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
         "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
+        "host": host_info(),
     }
     if args.fp64_steps > 0 and not args.fp64:
         print("[bench] FP64-sweep leg", file=sys.stderr, flush=True)
@@ -324,10 +372,11 @@ def main():
             i64.step(args.fp64_steps)
             torch.cuda.synchronize()
             w64 = time.perf_counter() - t64
-            E64, T64 = i64.read_fields()
-        out["fp64_sweep_leg"] = {"dlr_steps_per_s": args.fp64_steps / w64, "steps": args.fp64_steps,
+        f32_early = args.fp64_steps / sum(step_wall[2:2 + args.fp64_steps]) if len(step_wall) >= 2 + args.fp64_steps else None
+        out["fp64_sweep_leg"] = {"dlr_steps_per_s": args.fp64_steps / w64, "steps": f"3..{2 + args.fp64_steps}",
                                  "si_tol": p64["si_tol"],
-                                 "fp32_speedup": (args.steps / wall) / (args.fp64_steps / w64)}
+                                 "fp32_steps_per_s_same_steps": f32_early,
+                                 "fp32_speedup": (f32_early / (args.fp64_steps / w64)) if f32_early else None}
     if args.sn_steps > 0:
         print("[bench] plain SN leg", file=sys.stderr, flush=True)
         out["plain_sn_leg"] = sn_leg(args.workload, p["precision"], p["si_tol"], args.sn_steps,
@@ -335,14 +384,18 @@ def main():
     if args.q1_reps > 0:
         print("[bench] bilinear DG sweep leg", file=sys.stderr, flush=True)
         out["q1_sweep_leg"] = q1_leg(1024, 32, args.q1_reps)
-    if args.serve_requests > 0:
-        print(f"[bench] serving leg: {args.serve_requests} requests", file=sys.stderr, flush=True)
-        sv = serving_leg(args.serve_requests, args.serve_max_s, args.serve_budget_gib)
+    if args.batch_count > 0:
+        print(f"[bench] batched leg: {args.batch_count} instances", file=sys.stderr, flush=True)
+        out["batch_leg"] = batch_run(args.batch_count, 50)
+    if args.serve_window_s > 0:
+        print(f"[bench] serving leg: {args.serve_window_s:g} s of arrivals", file=sys.stderr, flush=True)
+        sv = serving_leg(args.serve_window_s, args.serve_max_s, args.serve_budget_gib)
         out["serving"] = sv
         out["latency_p50_p99_s"] = [sv["p50_s"], sv["p99_s"]]
     if args.cpu_steps > 0:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(make_problem(args.workload), args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(make_problem(args.workload), args.cpu_steps, threads=1)
+        out["cpu_baseline_all_cores"] = cpu_baseline(make_problem(args.workload), args.cpu_steps, threads=None)
     print(json.dumps(out), flush=True)
 
 

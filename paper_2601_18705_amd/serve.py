@@ -19,11 +19,14 @@ from . import dlrtrt
 
 
 def serve(requests, hbm_budget=0, max_wall_s=None, progress=None):
-    """requests: iterable of (t_arrival_s, problem_dict, n_steps), sorted by arrival.
+    """requests: iterable of (t_arrival_s, problem, n_steps), sorted by arrival; problem is
+    a problem dict or a callable that builds it (called when the request reaches the head of
+    the admission queue, so its build time counts in its latency).
 
     Returns a dict with per-request latency (s), completion order, the
     cell-angle updates done, wall time and how many requests were left when
-    max_wall_s stopped the loop (requests not yet finished are not counted)."""
+    max_wall_s stopped the loop (requests not yet finished are not counted), split
+    into admitted-but-unfinished and still queued."""
     pending = collections.deque(requests)
     waiting = collections.deque()
     inflight = {}
@@ -41,6 +44,9 @@ def serve(requests, hbm_budget=0, max_wall_s=None, progress=None):
                 waiting.append(pending.popleft())
             while waiting:
                 t_arr, prob, nsteps = waiting[0]
+                if callable(prob):
+                    prob = prob()
+                    waiting[0] = (t_arr, prob, nsteps)
                 slot = batch.admit(prob, nsteps)
                 if slot is None:
                     if not inflight:
@@ -76,6 +82,9 @@ def serve(requests, hbm_budget=0, max_wall_s=None, progress=None):
         "completed": len(latency),
         "failed": failed,
         "unfinished": len(inflight) + len(waiting) + len(pending),
+        "unfinished_admitted": len(inflight),
+        "unfinished_queued": len(waiting) + len(pending),
+        "arrived": len(latency) + len(failed) + len(inflight) + len(waiting),
         "wall_s": wall,
         "passes": passes,
         "cell_angle_updates": ca,

@@ -140,24 +140,39 @@ def batch_instances(count=256, seed=4, n_polar=16, n_azim=32, dt=0.005, nsteps=5
     return out
 
 
-def request_stream(seed=5, rate_hz=200.0, count=2000, n_polar=16, n_azim=32, dt=0.005,
-                   sizes=(64, 128, 256, 512, 1024), ranks=(8, 16, 24, 32), steps=(20, 200)):
-    """Poisson arrivals of checkerboard or random-medium problems: [(t_arrival, problem)]."""
+def request_specs(seed=5, rate_hz=200.0, count=2000, n_polar=16, n_azim=32, dt=0.005,
+                  sizes=(64, 128, 256, 512, 1024), ranks=(8, 16, 24, 32), steps=(20, 200), window_s=None):
+    """Poisson arrivals of checkerboard or random-medium problems as lazy specs:
+    [(t_arrival, build, n_steps, name)], build() returning the problem dict.  Stops after
+    `count` requests or at the first arrival past window_s (when given).  The draws do not
+    depend on when (or whether) a problem is built."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for k in range(count):
         t += rng.exponential(1.0 / rate_hz)
+        if window_s is not None and t > window_s:
+            break
         n = int(rng.choice(sizes))
         r = int(rng.choice(ranks))
         ns = int(rng.integers(steps[0], steps[1] + 1))
-        if rng.random() < 0.5:
-            p = checkerboard(n, n_polar, n_azim, r, dt, ns)
-        else:
-            p = random_medium(n, n_polar, n_azim, r, dt, ns, seed=int(rng.integers(0, 2 ** 31 - 1)))
-        p["name"] = f"req{k}_{p['name']}"
-        out.append((t, p))
+        board = rng.random() < 0.5
+        fseed = int(rng.integers(0, 2 ** 31 - 1))
+
+        def build(n=n, r=r, ns=ns, board=board, fseed=fseed, k=k):
+            if board:
+                p = checkerboard(n, n_polar, n_azim, r, dt, ns)
+            else:
+                p = random_medium(n, n_polar, n_azim, r, dt, ns, seed=fseed)
+            p["name"] = f"req{k}_{p['name']}"
+            return p
+        out.append((t, build, ns, f"req{k}"))
     return out
+
+
+def request_stream(seed=5, rate_hz=200.0, count=2000, **kw):
+    """Poisson arrivals of checkerboard or random-medium problems: [(t_arrival, problem)]."""
+    return [(t, build()) for t, build, _, _ in request_specs(seed, rate_hz, count, **kw)]
 
 
 WORKLOADS = {
