@@ -374,7 +374,11 @@ def sn_step(p, quad, st, tol=None, max_iter=None):
         ok = dphi <= tol * np.linalg.norm(phi_new)
         if refl:
             ok = ok and np.linalg.norm(psi - psi_prev) <= tol * np.linalg.norm(psi)
-        phi, psi_prev = phi_new, psi
+        if p.get("dsa") and not ok:
+            phi_next = dsa_correct(grid, lin, dsa_kappas(quad.w, quad.mu, quad.eta), phi_new, phi)
+        else:
+            phi_next = phi_new
+        phi, psi_prev = phi_next, psi
         if ok:
             break
         if it >= max_iter:
@@ -383,6 +387,105 @@ def sn_step(p, quad, st, tol=None, max_iter=None):
     inflow, outflow = boundary_flows(p, grid, quad, lambda side: psi[:, side_cells(grid, side)])
     return SNState(T, psi, phi), {"si_iters": it, "inflow": inflow, "outflow": outflow,
                                   "energy": total_energy(p, grid, T, phi)}
+
+
+# =========================================================================== diffusion synthetic acceleration
+
+def dsa_face_operators(grid):
+    """Central face operators F_x, F_y of the degree-0 elements: the part of the paper's face
+    matrix F_d that is linear in Omega (Sec. 4.4, F_d = Omega . F + F_d^[[]], and its DSA appendix),
+    v^T F_j u = - sum_faces h_f n_j [[v]] {{u}}, with [[v]] = v_minus - v_plus across a face of
+    normal n from the minus to the plus cell, {{u}} the face average, and exterior values 0
+    (reading: the boundary treatment is not printed; the error equation of source iteration has
+    homogeneous boundary data).  Degree-0 elements have no volume gradient term (G_j = 0).
+    Returns scipy sparse [ncell, ncell] matrices, cells e = j*nx + i."""
+    import scipy.sparse as sp
+    nx, ny = grid.nx, grid.ny
+    ops = []
+    for axis in (0, 1):
+        rows, cols, vals = [], [], []
+        h = grid.hy if axis == 0 else grid.hx      # face length
+        nfaces = (nx + 1, ny) if axis == 0 else (nx, ny + 1)
+        for b in range(nfaces[1]):
+            for a in range(nfaces[0]):
+                # face between the minus cell (index a-1 along the axis) and the plus cell (index a)
+                if axis == 0:
+                    minus = b * nx + (a - 1) if a > 0 else None
+                    plus = b * nx + a if a < nx else None
+                else:
+                    minus = (b - 1) * nx + a if b > 0 else None      # here b runs over faces along y
+                    plus = b * nx + a if b < ny else None
+                cells = [(minus, 1.0), (plus, -1.0)]              # [[v]] weights
+                for tv, jv in cells:
+                    if tv is None:
+                        continue
+                    for tu in (minus, plus):
+                        if tu is None:
+                            continue
+                        rows.append(tv)
+                        cols.append(tu)
+                        vals.append(-h * jv * 0.5)
+        ops.append(sp.csr_matrix((vals, (rows, cols)), shape=(grid.ncell, grid.ncell)))
+    return ops[0], ops[1]
+
+
+def dsa_penalty(grid, kappa_x, kappa_y):
+    """F_0 of eq. "penalty term": v^T F_0 u = (1/4pi) sum_faces (1/2) kappa_f h_f [[u]][[v]], with
+    kappa_f = sum_d c_d |Omega_d . n_f| (c = beta^T What^{-1}, the collocation weights), exterior
+    values 0."""
+    import scipy.sparse as sp
+    nx, ny = grid.nx, grid.ny
+    rows, cols, vals = [], [], []
+
+    def face(minus, plus, coef):
+        ends = [(minus, 1.0), (plus, -1.0)]
+        for tv, jv in ends:
+            if tv is None:
+                continue
+            for tu, ju in ends:
+                if tu is None:
+                    continue
+                rows.append(tv)
+                cols.append(tu)
+                vals.append(coef * jv * ju)
+
+    cx = kappa_x * grid.hy / (2.0 * FOUR_PI)
+    cy = kappa_y * grid.hx / (2.0 * FOUR_PI)
+    for j in range(ny):
+        for a in range(nx + 1):
+            face(j * nx + a - 1 if a > 0 else None, j * nx + a if a < nx else None, cx)
+    for b in range(ny + 1):
+        for i in range(nx):
+            face((b - 1) * nx + i if b > 0 else None, b * nx + i if b < ny else None, cy)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(grid.ncell, grid.ncell))
+
+
+def dsa_matrix(grid, sigma_t, sigma_s, kappa_x, kappa_y):
+    """The DSA matrix of the appendix derivation for degree-0 elements:
+    (1/3) sum_j F_j^T M_t^{-1} F_j + F_0 + M_a, with M_t = area sigma_t, M_a = area (sigma_t - sigma_s)
+    (sigma_t includes 1/(c dt) and sigma_s is the pseudo-scattering of the linearisation)."""
+    import scipy.sparse as sp
+    A = grid.area
+    Fx, Fy = dsa_face_operators(grid)
+    Mt_inv = sp.diags(1.0 / (A * sigma_t))
+    D = (Fx.T @ Mt_inv @ Fx + Fy.T @ Mt_inv @ Fy) / 3.0
+    D = D + dsa_penalty(grid, kappa_x, kappa_y) + sp.diags(A * (sigma_t - sigma_s))
+    return sp.csr_matrix(D)
+
+
+def dsa_kappas(cw, mu, eta):
+    """kappa_x = sum_d c_d |mu_d|, kappa_y = sum_d c_d |eta_d| (face normals along x and y)."""
+    return float(np.dot(cw, np.abs(mu))), float(np.dot(cw, np.abs(eta)))
+
+
+def dsa_correct(grid, lin, kappa, phi_half, phi_old):
+    """One DSA step of source iteration: the transport sweep took phi_old to phi_half; the
+    diffusion approximation of the remaining error, D delta = M_s (phi_half - phi_old), is added:
+    returns phi_half + delta (exact sparse solve)."""
+    import scipy.sparse.linalg as spla
+    D = dsa_matrix(grid, lin.sigma_t, lin.sigma_s, *kappa)
+    rhs = grid.area * lin.sigma_s * (phi_half - phi_old)
+    return phi_half + spla.spsolve(D.tocsc(), rhs)
 
 
 # =========================================================================== DLR helpers
@@ -601,7 +704,12 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
         ok = np.linalg.norm(phi_new - phi) <= tol * np.linalg.norm(phi_new)
         if refl:
             ok = ok and np.linalg.norm(Psi - Psi_prev) <= tol * np.linalg.norm(Psi)
-        phi, Psi_prev = phi_new, Psi
+        if p.get("dsa") and not ok:
+            # diffusion synthetic acceleration of the collocation source iteration (Sec. 4, DSA)
+            phi_next = dsa_correct(grid, lin, dsa_kappas(cw, mu_s, eta_s), phi_new, phi)
+        else:
+            phi_next = phi_new
+        phi, Psi_prev = phi_next, Psi
         if ok:
             break
         if it >= max_iter:
