@@ -189,6 +189,24 @@ dlr_status dlr_read_stats(dlr_handle h, dlr_step_stats *out);
  * indices in [0, n_polar*n_azim); NULL clears a pending override. */
 dlr_status dlr_force_selection(dlr_handle h, const int32_t *sel);
 
+/* Diffusion synthetic acceleration of the source iteration (Sec. 4, "Diffusion Synthetic
+ * Acceleration (DSA) for SN-like DLR method", and its appendix derivation), for DLR and plain SN
+ * handles.  After every sweep that has not met si_tol, the swept mean intensity phi_half is
+ * corrected to phi_half + delta, where delta solves the consistent diffusion system of the
+ * degree-0 cells
+ *   [(1/3) sum_j F_j^T M_t^{-1} F_j + F_0 + M_a] delta = M_s (phi_half - phi_old)
+ * (F_j: central face operators; F_0: jump penalty with kappa = sum_d c_d |Omega_d . n|, c the
+ * collocation weights, or the quadrature weights for SN; M_t, M_s, M_a: cell-area masses of
+ * sigma_t, the pseudo-scattering sigma_s and sigma_t - sigma_s; zero exterior values).  The
+ * system is solved by Jacobi-preconditioned conjugate gradients in FP64 on the device to the
+ * relative residual cg_tol (at most cg_max_iter iterations).  The converged step is the same fixed
+ * point as without acceleration; in optically thick, strongly scattering media it takes far fewer
+ * source iterations.  enable = 0 turns it off.  The first enable allocates a workspace of 7 FP64
+ * cell fields (through the allocator hook if set).
+ * Errors: DLR_ERR_ARG (cg_tol outside (0, 1), cg_max_iter outside [1, 100000]), DLR_ERR_OOM,
+ * DLR_ERR_STATE (poisoned handle), DLR_ERR_HIP. */
+dlr_status dlr_set_dsa(dlr_handle h, int32_t enable, double cg_tol, int32_t cg_max_iter);
+
 /* Free everything.  NULL-safe. */
 dlr_status dlr_destroy(dlr_handle h);
 

@@ -188,6 +188,16 @@ struct dlr_instance {
     double *ops = nullptr, *Binv = nullptr, *yv = nullptr, *red = nullptr, *vv = nullptr;
     double *Vsvd = nullptr, *beta = nullptr, *coef = nullptr, *gside = nullptr;
     int* status = nullptr;
+    // diffusion synthetic acceleration (dlr_set_dsa): workspace in its own allocation
+    bool dsa = false;
+    double dsa_tol = 1e-8;
+    int dsa_max_iter = 100;
+    DevMem dsa_mem;
+    double* dsa_ws = nullptr;     // [7 N] x, r, z, q, diag, p0, p1
+    double* dsa_part = nullptr;   // [2 * dsa_blocks]
+    double* dsa_scal = nullptr;   // [8]
+    double* dsa_kappa = nullptr;  // [2]
+    unsigned* dsa_count = nullptr;
     // plain SN only
     double *q_diag = nullptr, *phio = nullptr;
     int *orient = nullptr, *dirs = nullptr, *dir_off = nullptr;
@@ -421,6 +431,22 @@ dlr::TupdateArgs tupdate_args(dlr_instance* I, const double* X, const double* gs
     return A;
 }
 
+// DSA correction of the source iteration just checked (phi_cur = swept phi, phi_nxt = the iterate it
+// started from), queued on the instance's stream before its next sweep.
+void dsa_correct(dlr_instance* I) {
+    dlr::DsaArgs a{};
+    a.nx = I->nx; a.ny = I->ny; a.hx = I->hx; a.hy = I->hy; a.inv_cdt = 1.0 / (I->c * I->dt);
+    a.sigma = I->sigma; a.sig_s = I->sig_s; a.kappa = I->dsa_kappa;
+    a.phi_old = I->phi_nxt; a.phi = I->phi_cur;
+    const size_t n = (size_t)I->N;
+    double* w = I->dsa_ws;
+    a.x = w; a.r = w + n; a.z = w + 2 * n; a.q = w + 3 * n; a.dg = w + 4 * n; a.p[0] = w + 5 * n; a.p[1] = w + 6 * n;
+    a.partials = I->dsa_part; a.counter = I->dsa_count; a.scal = I->dsa_scal;
+    a.tol = I->dsa_tol; a.max_iter = I->dsa_max_iter;
+    a.s_e = I->s_e; a.ldg = I->ldg;
+    dlr::launch_dsa(I->stream, a, I->fp32());
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // One DLR step in phases, so that a batch can interleave the phases of many instances:
 //   phase_begin  linearise, DEIM, old solution at the new ordinates (Algorithm 1 steps 1-3)
@@ -449,6 +475,7 @@ void phase_begin(dlr_instance* I) {
     da.status = I->status;
     dlr::launch_deim(s, da);
     I->force_pending = false;
+    if (I->dsa) dlr::launch_dsa_kappa(s, r, I->cw, I->sel_mu, I->sel_eta, I->dsa_kappa);
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
     dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
                          static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e));
@@ -609,6 +636,7 @@ dlr_status step_once(dlr_instance* I) {
         I->sweep_ms_acc += ms;
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
+        if (!I->si_conv && I->dsa) dsa_correct(I);
     }
     // the DEIM status was checked with the last source iteration's status word (copied after it)
     phase_end<TS>(I);
@@ -651,6 +679,7 @@ dlr_status sn_step_once(dlr_instance* I) {
         I->sweep_ms_acc += ms;
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
+        if (!I->si_conv && I->dsa) dsa_correct(I);
     }
     dlr::launch_tupdate(s, tupdate_args(I, nullptr, nullptr), I->nb_cells);
     if (I->fp32())
@@ -1220,8 +1249,45 @@ dlr_status dlr_destroy(dlr_handle h) {
         if (ev) (void)hipEventDestroy(ev);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     if (h->h_status) (void)hipHostFree(h->h_status);
+    dev_free(h->dsa_mem);
     h->arena.release();
     delete h;
+    return DLR_OK;
+}
+
+dlr_status dlr_set_dsa(dlr_handle h, int32_t enable, double cg_tol, int32_t cg_max_iter) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (h->poisoned) return fail(DLR_ERR_STATE, "handle poisoned by an earlier device error");
+    if (!enable) {
+        h->dsa = false;
+        return DLR_OK;
+    }
+    if (!(cg_tol > 0.0 && cg_tol < 1.0) || cg_max_iter < 1 || cg_max_iter > 100000)
+        return fail(DLR_ERR_ARG, "need 0 < cg_tol < 1 and 1 <= cg_max_iter <= 100000");
+    try {
+        if (!h->dsa_mem.ptr) {
+            const size_t n = (size_t)h->N, nb = (size_t)dlr::dsa_blocks(h->nx, h->ny);
+            const size_t doubles = 7 * n + 2 * nb + 8 + 2;
+            const size_t bytes = ((doubles * sizeof(double) + 255) & ~size_t(255)) + 256;
+            hip_check(hipStreamSynchronize(h->stream), "stream sync");
+            if (!dev_alloc(h->dsa_mem, bytes, h->stream)) return fail(DLR_ERR_OOM, "DSA workspace");
+            double* base = static_cast<double*>(h->dsa_mem.ptr);
+            h->dsa_ws = base;
+            h->dsa_part = base + 7 * n;
+            h->dsa_scal = h->dsa_part + 2 * nb;
+            h->dsa_kappa = h->dsa_scal + 8;
+            h->dsa_count = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(base) + (bytes - 256));
+            hip_check(hipMemsetAsync(h->dsa_count, 0, 256, h->stream), "clear");
+        }
+        if (h->sn)   // every ordinate with its quadrature weight
+            dlr::launch_dsa_kappa(h->stream, h->nq, h->w, h->mu, h->eta, h->dsa_kappa);
+        hip_check(hipStreamSynchronize(h->stream), "stream sync");
+    } catch (const std::exception& ex) {
+        return fail(DLR_ERR_HIP, ex.what());
+    }
+    h->dsa = true;
+    h->dsa_tol = cg_tol;
+    h->dsa_max_iter = cg_max_iter;
     return DLR_OK;
 }
 

@@ -288,6 +288,32 @@ void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
                  double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr);
 
+// ----------------------------------------------------------------------------- diffusion synthetic acceleration
+// One DSA correction of the source iteration: phi <- phi + delta with D delta = M_s (phi - phi_old),
+// D the diffusion matrix of the degree-0 cells (k_dsa.hip), by Jacobi-preconditioned CG in FP64; then
+// the four orientation copies of s_e = sigma_s phi / (4 pi) in the sweep layout.  Cells column-major.
+struct DsaArgs {
+    int nx, ny;
+    double hx, hy, inv_cdt;
+    const double* sigma;       // [N] sigma (sigma_t = sigma + inv_cdt)
+    const double* sig_s;       // [N] pseudo-scattering opacity
+    const double* kappa;       // [2] sum_d c_d |mu_d|, sum_d c_d |eta_d| (launch_dsa_kappa)
+    const double* phi_old;     // [N] the iterate the sweep started from
+    double* phi;               // [N] in: the swept phi, out: corrected
+    double *x, *r, *z, *q, *dg;  // [N] each
+    double* p[2];              // [N] each, search direction (double-buffered)
+    double* partials;          // [2 * dsa_blocks]
+    unsigned* counter;         // zero between launches
+    double* scal;              // [8] CG scalars
+    double tol;                // relative residual of the CG solve
+    int max_iter;              // CG iterations launched (the rest return at once after convergence)
+    void* s_e;                 // [4][ldg] in the sweep precision, or nullptr
+    size_t ldg;
+};
+int dsa_blocks(int nx, int ny);
+void launch_dsa_kappa(hipStream_t s, int nd, const double* c, const double* mu, const double* eta, double* kappa);
+void launch_dsa(hipStream_t s, const DsaArgs& a, bool fp32_layout);
+
 // status words written by kernels
 enum DeviceStatus : int {
     kStatusOk = 0,

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
 EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
-            "dlr_read_stats", "dlr_force_selection", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
+            "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
             "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
             "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc", "dlr_status_string", "dlr_last_error"]
@@ -92,6 +92,7 @@ def library():
         lib.dlr_load_factors.argtypes = [h, _dp, _dp, _dp, _dp]
         lib.dlr_read_stats.argtypes = [h, ctypes.POINTER(DlrStepStats)]
         lib.dlr_force_selection.argtypes = [h, _ip]
+        lib.dlr_set_dsa.argtypes = [h, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
         lib.dlr_destroy.argtypes = [h]
         sz = ctypes.c_size_t
         i64 = ctypes.c_int64
@@ -120,7 +121,7 @@ def library():
         lib.dlr_last_error.argtypes = []
         lib.dlr_last_error.restype = ctypes.c_char_p
         for name in ("dlr_set_allocator", "dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
-                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_destroy",
+                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
                      "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
@@ -306,6 +307,12 @@ class Instance:
         self._p = p
         self._h = ctypes.c_void_p()
         _check(create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(self._h)))
+        if problem.get("dsa"):
+            self.set_dsa(True, float(problem.get("dsa_cg_tol", 1e-8)), int(problem.get("dsa_cg_max_iter", 100)))
+
+    def set_dsa(self, enable=True, cg_tol=1e-8, cg_max_iter=100):
+        """dlr_set_dsa: diffusion synthetic acceleration of the source iteration."""
+        _check(library().dlr_set_dsa(self._h, int(bool(enable)), float(cg_tol), int(cg_max_iter)))
 
     def step(self, n_steps=1):
         _check(library().dlr_step(self._h, int(n_steps)))
