@@ -198,6 +198,35 @@ def q1_leg(n, nd, reps):
     return out
 
 
+def dsa_leg(n, steps):
+    """Diffusion synthetic acceleration on an optically thick, hot checkerboard (sigma = 10^4 in
+    alternating unit blocks, T = 1, 512 ordinates, r = 16, FP64 sweeps, SI tolerance 1e-10): source
+    iterations and time per step without and with the acceleration (the same fixed point)."""
+    import numpy as np
+    import torch
+    from paper_2601_18705_amd import dlrtrt
+    from synth import problems
+    p = problems.checkerboard(n=n, nsteps=steps)
+    p["sigma_a"] = problems.checkerboard_sigma(p, thick=1e4, thin=1.0)
+    p["T_init"] = np.full(n * n, 1.0)
+    p["si_tol"], p["si_max_iter"] = 1e-10, 100000
+    out = {"workload": f"checkerboard {n}^2, sigma 1e4 / 1, T = 1, q16x32, r16, FP64, SI tol 1e-10"}
+    fields = {}
+    for name, dsa in (("plain", 0), ("dsa", 1)):
+        with dlrtrt.Instance(dict(p, dsa=dsa)) as inst:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            si = []
+            for _ in range(steps):
+                inst.step(1)
+                si.append(int(inst.read_stats()["si_iters"]))
+            wall = time.perf_counter() - t0
+            fields[name] = inst.read_fields()[1]
+        out[name] = {"si_iterations_per_step": si, "ms_per_step": wall * 1e3 / steps}
+    out["T_rel_diff"] = float(np.max(np.abs(fields["dsa"] - fields["plain"])) / np.max(np.abs(fields["plain"])))
+    return out
+
+
 def batch_run(count, steps):
     """The batched-instances workload: count independent problems admitted at once and
     advanced together for `steps` steps (FP32 sweeps, FP64 energy update)."""
@@ -241,6 +270,8 @@ def main():
                     help="steps of the plain SN comparison leg over every ordinate (0 = skip)")
     ap.add_argument("--q1-reps", type=int, default=20,
                     help="timed launches of the bilinear DG sweep leg, 1024^2 cells x 32 directions (0 = skip)")
+    ap.add_argument("--dsa-n", type=int, default=128,
+                    help="grid of the DSA leg (thick hot checkerboard, two steps without and with DSA; 0 = skip)")
     ap.add_argument("--batch-count", type=int, default=256,
                     help="instances of the batched leg (0 = skip): 64^2-256^2 grids, ranks 4-24, 50 steps each")
     ap.add_argument("--serve-window-s", type=float, default=30.0,
@@ -384,6 +415,9 @@ def main():
     if args.q1_reps > 0:
         print("[bench] bilinear DG sweep leg", file=sys.stderr, flush=True)
         out["q1_sweep_leg"] = q1_leg(1024, 32, args.q1_reps)
+    if args.dsa_n > 0:
+        print("[bench] DSA leg", file=sys.stderr, flush=True)
+        out["dsa_leg"] = dsa_leg(args.dsa_n, 2)
     if args.batch_count > 0:
         print(f"[bench] batched leg: {args.batch_count} instances", file=sys.stderr, flush=True)
         out["batch_leg"] = batch_run(args.batch_count, 50)

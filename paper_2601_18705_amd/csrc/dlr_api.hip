@@ -205,6 +205,10 @@ struct dlr_instance {
     double* h_norm = nullptr;   // pinned: SI norms [0, kPinnedNorm), then energy, margins[r], cw[r]
     int* h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // second stream for work that does not depend on the main stream's latency-bound kernels
+    // (the linearisation beside DEIM, the temperature update beside the SVD); nullptr: in order
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
 
@@ -461,9 +465,16 @@ void phase_begin(dlr_instance* I) {
     const int r = I->r, nq = I->nq;
     const double cdt = I->c * I->dt;
     hip_check(hipEventRecord(I->ev[0], s), "event");
-    // 1. effective scattering and source
-    dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
+    // 1. effective scattering and source (beside DEIM, which does not read them)
+    hipStream_t ls = s;
+    if (I->side) {
+        hip_check(hipEventRecord(I->ev_fork, s), "event");
+        hip_check(hipStreamWaitEvent(I->side, I->ev_fork, 0), "wait");
+        ls = I->side;
+    }
+    dlr::launch_linearize(ls, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
                           I->q, I->sig_t, I->sig_t32, I->ldg, nullptr);
+    if (I->side) hip_check(hipEventRecord(I->ev_join, I->side), "event");
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
@@ -476,6 +487,7 @@ void phase_begin(dlr_instance* I) {
     dlr::launch_deim(s, da);
     I->force_pending = false;
     if (I->dsa) dlr::launch_dsa_kappa(s, r, I->cw, I->sel_mu, I->sel_eta, I->dsa_kappa);
+    if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
     dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
                          static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e));
@@ -581,11 +593,23 @@ void phase_end(dlr_instance* I) {
     dlr::launch_small_matmul(s, r, I->R2, I->R1, I->Ra);
     dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
                              I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
+    // 9. temperature update with the mean intensity of the new factors, energy sum and outflow.  The
+    // state is psi = Xn Ra^T Wq^T; the SVD of S = Ra^T only rotates W and S (S' W'^T = Ra^T Wq^T), so
+    // the mean intensity coefficients and the outflow side vectors are formed from (Wq, Ra^T), and the
+    // temperature update runs beside the SVD on the second stream
+    hipStream_t ts = s;
+    if (I->side) {
+        hip_check(hipEventRecord(I->ev_fork, s), "event");
+        hip_check(hipStreamWaitEvent(I->side, I->ev_fork, 0), "wait");
+        ts = I->side;
+    }
+    dlr::launch_wsum(ts, nq, r, I->Wq, I->w, I->Ra, I->beta, I->coef, I->mu, I->eta, I->gside, true);
+    dlr::launch_tupdate(ts, tupdate_args(I, I->Xn, I->gside), I->nb_cells);
+    if (I->side) hip_check(hipEventRecord(I->ev_join, I->side), "event");
+    // 8 (end). SVD of S: W <- Wq V, S <- S V (columns U_k sigma_k)
     dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
-    dlr::launch_wsum(s, nq, r, I->W, I->w, I->Sn, I->beta, I->coef, I->mu, I->eta, I->gside);
-    // 9. temperature update with the mean intensity of the new factors, energy sum and outflow
-    dlr::launch_tupdate(s, tupdate_args(I, I->Xn, I->gside), I->nb_cells);
+    if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     std::swap(I->X, I->Xn);
     std::swap(I->S, I->Sn);
     hip_check(hipEventRecord(I->ev[1], s), "event");
@@ -965,6 +989,9 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
+        hip_check(hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking), "side stream");
+        hip_check(hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming), "event create");
+        hip_check(hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
         upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
@@ -1245,6 +1272,12 @@ dlr_status dlr_force_selection(dlr_handle h, const int32_t* selv) {
 dlr_status dlr_destroy(dlr_handle h) {
     if (!h) return DLR_OK;
     if (h->stream || h->arena.base) (void)hipStreamSynchronize(h->stream);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (auto& ev : h->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
@@ -1348,6 +1381,11 @@ dlr_status dlr_batch_admit(dlr_batch B, const dlr_problem* p, int32_t n_steps, i
     dlr_handle h = nullptr;
     const dlr_status c = dlr_create(p, B->pool[(size_t)(id % kBatchStreams)], &h);
     if (c != DLR_OK) return c;
+    // slots overlap with each other; they keep their phases in order on their pool stream
+    if (h->side) {
+        (void)hipStreamDestroy(h->side);
+        h->side = nullptr;
+    }
     BatchSlot sl;
     sl.id = id;
     sl.I = h;

@@ -285,8 +285,10 @@ void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, 
 // beta[k] = sum_q w_q W[k][q];  coef = S beta.  With mu, eta and gside set, also the side vectors
 // of the outflow tally: gside[s][i] = sum_j S[i][j] sum_{q leaving through side s} w_q |Omega_q . n_s| W[j][q]
 // (sides 0 left, 1 right, 2 bottom, 3 top).
+// s_transposed: the matrix given is S^T (as the angular QR's R factor, S = R^T).
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
-                 double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr);
+                 double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr,
+                 bool s_transposed = false);
 
 // ----------------------------------------------------------------------------- diffusion synthetic acceleration
 // One DSA correction of the source iteration: phi <- phi + delta with D delta = M_s (phi - phi_old),

@@ -913,7 +913,7 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
                                                const double* __restrict__ w, const double* __restrict__ S,
                                                double* __restrict__ beta, double* __restrict__ coef,
                                                const double* __restrict__ mu, const double* __restrict__ eta,
-                                               double* __restrict__ gside) {
+                                               double* __restrict__ gside, int transpose_s) {
     __shared__ double sb[kMaxRank];
     __shared__ double sgs[4][kMaxRank];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -974,17 +974,19 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
     __shared__ double sS[kMaxRank * kMaxRank];
     stage_lds(sS, S, r * r);
     __syncthreads();
+    // S[i][j] is sS[i * r + j], or sS[j * r + i] when the matrix given is S^T
+    const int si = transpose_s ? 1 : r, sj = transpose_s ? r : 1;
     for (int i = threadIdx.x; i < r; i += blockDim.x) {
         beta[i] = sb[i];
         double s = 0.0;
-        for (int j = 0; j < r; ++j) s += sS[i * r + j] * sb[j];
+        for (int j = 0; j < r; ++j) s += sS[i * si + j * sj] * sb[j];
         coef[i] = s;
     }
     if (sides)
         for (int t = threadIdx.x; t < 4 * r; t += blockDim.x) {
             const int sd = t / r, i = t - sd * r;
             double s = 0.0;
-            for (int j = 0; j < r; ++j) s += sS[i * r + j] * sgs[sd][j];
+            for (int j = 0; j < r; ++j) s += sS[i * si + j * sj] * sgs[sd][j];
             gside[t] = s;
         }
 }
@@ -1036,8 +1038,9 @@ void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, 
 }
 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
-                 double* coef, const double* mu, const double* eta, double* gside) {
-    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef, mu, eta, gside);
+                 double* coef, const double* mu, const double* eta, double* gside, bool s_transposed) {
+    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef, mu, eta, gside,
+                       s_transposed ? 1 : 0);
 }
 
 }  // namespace dlr
