@@ -204,6 +204,8 @@ struct dlr_instance {
     // pinned host mirrors
     double* h_norm = nullptr;   // pinned: SI norms [0, kPinnedNorm), then energy, margins[r], cw[r]
     int* h_status = nullptr;
+    double* d_h_norm = nullptr;   // the device's addresses of the two pinned areas
+    int* d_h_status = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // second stream for work that does not depend on the main stream's latency-bound kernels
     // (the linearisation beside DEIM, the temperature update beside the SVD); nullptr: in order
@@ -368,9 +370,11 @@ dlr_status validate(const dlr_problem* p, bool sn = false) {
 template <typename TS>
 dlr_status step_once(dlr_instance* I);
 
-dlr_status check_device_status(dlr_instance* I) {
-    hip_check(hipMemcpyAsync(I->h_status, I->status, 4 * sizeof(int), hipMemcpyDeviceToHost, I->stream),
-              "status copy");
+// published: a launch_publish of the four status words is already queued on the stream
+dlr_status check_device_status(dlr_instance* I, bool published = false) {
+    if (!published)
+        hip_check(hipMemcpyAsync(I->h_status, I->status, 4 * sizeof(int), hipMemcpyDeviceToHost, I->stream),
+                  "status copy");
     hip_check(hipStreamSynchronize(I->stream), "stream sync");
     const int st = *I->h_status;
     if (st == 0) return DLR_OK;
@@ -388,6 +392,19 @@ dlr_status check_device_status(dlr_instance* I) {
     I->poisoned = true;
     I->poison_code = code;
     return fail(code, m);
+}
+
+// Queue the copies of (up to three) runs of doubles into the pinned area from word `at`, and of the
+// first `nstatus` status words, as one kernel.
+void publish(dlr_instance* I, hipStream_t s, int at, const double* a, int na, const double* b, int nb, const double* c,
+             int nc, int nstatus) {
+    dlr::PublishArgs p{};
+    p.src[0] = a; p.n[0] = a ? na : 0;
+    p.src[1] = b; p.n[1] = b ? nb : 0;
+    p.src[2] = c; p.n[2] = c ? nc : 0;
+    p.dst = I->d_h_norm + at;
+    p.status = I->status; p.nstatus = nstatus; p.dst_status = I->d_h_status;
+    dlr::launch_publish(s, p);
 }
 
 // The sweep record of an instance (fixed for its life; DEIM rewrites the pointed-to direction data).
@@ -520,8 +537,7 @@ void si_phi(dlr_instance* I) {
                         I->phio, I->sig_s, I->phi_cur, I->phi_nxt, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
                         I->counters + 0, I->norm_out);
     std::swap(I->phi_cur, I->phi_nxt);
-    hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
-    hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
+    publish(I, s, 0, I->norm_out, 3, nullptr, 0, nullptr, 0, 1);
 }
 
 // After the stream has passed si_phi.  Returns DLR_OK with I->si_conv set, or an error (handle poisoned).
@@ -620,10 +636,8 @@ dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     // energy, DEIM margins and weights into pinned memory behind the step; the status check's copy
     // and stream synchronisation complete them (one host round trip per step instead of four)
     double* hf = I->h_norm + kPinnedNorm;
-    hip_check(hipMemcpyAsync(hf, I->energy_out, 2 * sizeof(double), hipMemcpyDeviceToHost, I->stream), "energy copy");
-    hip_check(hipMemcpyAsync(hf + 2, I->margins, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "margin copy");
-    hip_check(hipMemcpyAsync(hf + 2 + r, I->cw, r * sizeof(double), hipMemcpyDeviceToHost, I->stream), "cw copy");
-    const dlr_status st = check_device_status(I);
+    publish(I, I->stream, kPinnedNorm, I->energy_out, 2, I->margins, r, I->cw, r, 4);
+    const dlr_status st = check_device_status(I, true);
     if (st != DLR_OK) return st;
     const double en = hf[0];
     I->stats.outflow = hf[1];
@@ -695,8 +709,7 @@ dlr_status sn_step_once(dlr_instance* I) {
         sweep_alone<TS>(I);
         sn_phi<TS>(I, I->phi_cur, I->phi_nxt);
         std::swap(I->phi_cur, I->phi_nxt);
-        hip_check(hipMemcpyAsync(I->h_norm, I->norm_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "norm copy");
-        hip_check(hipMemcpyAsync(I->h_status, I->status, sizeof(int), hipMemcpyDeviceToHost, s), "status copy");
+        publish(I, s, 0, I->norm_out, 3, nullptr, 0, nullptr, 0, 1);
         hip_check(hipStreamSynchronize(s), "sync");
         float ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
@@ -716,8 +729,8 @@ dlr_status sn_step_once(dlr_instance* I) {
                                        I->counters + 2, I->energy_out);
     hip_check(hipEventRecord(I->ev[1], s), "event");
     double* hf = I->h_norm + kPinnedNorm;
-    hip_check(hipMemcpyAsync(hf, I->energy_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "energy copy");
-    const dlr_status st = check_device_status(I);   // its synchronisation completes the copy above
+    publish(I, s, kPinnedNorm, I->energy_out, 2, nullptr, 0, nullptr, 0, 4);
+    const dlr_status st = check_device_status(I, true);
     if (st != DLR_OK) return st;
     const double en = hf[0];
     I->stats.outflow = hf[1];
@@ -988,6 +1001,8 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostGetDevicePointer((void**)&I->d_h_norm, I->h_norm, 0), "pinned mapping");
+        hip_check(hipHostGetDevicePointer((void**)&I->d_h_status, I->h_status, 0), "pinned mapping");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         hip_check(hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking), "side stream");
         hip_check(hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming), "event create");
@@ -1039,6 +1054,8 @@ dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
         hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostGetDevicePointer((void**)&I->d_h_norm, I->h_norm, 0), "pinned mapping");
+        hip_check(hipHostGetDevicePointer((void**)&I->d_h_status, I->h_status, 0), "pinned mapping");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         const size_t n = I->N, Q = I->nq;
         // ordinates grouped by orientation, and their isotropic inflow values

@@ -290,6 +290,19 @@ void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w,
                  double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr,
                  bool s_transposed = false);
 
+// The few values the host reads after a source iteration or a step, written by one small kernel
+// straight into host-mapped pinned memory (system-scope stores): up to three runs of doubles,
+// placed one after the other from dst, and nstatus status words into dst_status.
+struct PublishArgs {
+    const double* src[3];
+    int n[3];
+    double* dst;
+    const int* status;
+    int nstatus;
+    int* dst_status;
+};
+void launch_publish(hipStream_t s, const PublishArgs& a);
+
 // ----------------------------------------------------------------------------- diffusion synthetic acceleration
 // One DSA correction of the source iteration: phi <- phi + delta with D delta = M_s (phi - phi_old),
 // D the diffusion matrix of the degree-0 cells (k_dsa.hip), by Jacobi-preconditioned CG in FP64; then

@@ -239,10 +239,14 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     // row q of W, and this group's part of beta = W^T w (wavefront sums, then wavefront order)
     double u[RT];
     const double wq = in ? a.w[q] : 0.0;
+    // every load issued unconditionally (clamped index), the unused values cleared by a bit mask:
+    // a select on `in` lets the compiler put each load under its own branch and wait for it there
+    const int qc = in ? q : nq - 1;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        const double v = a.W[(size_t)(i < r ? i : r - 1) * nq + (in ? q : 0)];
-        u[i] = (in && i < r) ? v : 0.0;
+        const double v = a.W[(size_t)(i < r ? i : r - 1) * nq + qc];
+        const unsigned long long keep = (in && i < r) ? ~0ull : 0ull;
+        u[i] = __longlong_as_double(__double_as_longlong(v) & keep);
     }
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
@@ -991,6 +995,21 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
         }
 }
 
+// One workgroup: the runs and the status words, each value by its own thread.
+__global__ __launch_bounds__(256) void k_publish(PublishArgs a) {
+    int off = 0;
+    for (int k = 0; k < 3; ++k) {
+        for (int i = threadIdx.x; i < a.n[k]; i += blockDim.x)
+            __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.dst) + off + i,
+                               (unsigned long long)__double_as_longlong(a.src[k][i]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        off += a.n[k];
+    }
+    for (int i = threadIdx.x; i < a.nstatus; i += blockDim.x)
+        __hip_atomic_store(a.dst_status + i, a.status[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
 }  // namespace
 
 void launch_deim(hipStream_t s, const DeimArgs& a) {
@@ -1035,6 +1054,10 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
     hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * r + 255) / 256)), dim3(256), 0, s, n, r, V, M, X);
+}
+
+void launch_publish(hipStream_t s, const PublishArgs& a) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, a);
 }
 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
