@@ -217,14 +217,16 @@ __device__ void group_sync(unsigned* arrive, unsigned target, int* stall) {
     __syncthreads();
 }
 
-template <int RT>
+// RT: rank bound; GM: bound on the number of workgroups.  With GM <= 8 the polling wavefront loads
+// every group's candidate row together with the maxima (one round trip fewer per column).
+template <int RT, int GM>
 __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     __shared__ double sv[kDeimWaves], sv2[kDeimWaves];
     __shared__ int si[kDeimWaves];
     __shared__ double sM, sSecond;
-    __shared__ int sP, sFallback;
+    __shared__ int sP, sFallback, sHaveRow;
     __shared__ size_t sSrc;   // offset of the pivot row's values in the exchange area
-    __shared__ double up[RT];
+    __shared__ double up[2][RT];   // pivot rows of the current and the previous column
     __shared__ double bw[kDeimWaves][RT];
     __shared__ int bad, stall;
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -236,11 +238,12 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         bad = 0;
         stall = 0;
     }
-    // row q of W, and this group's part of beta = W^T w (wavefront sums, then wavefront order)
+    for (int i = tid; i < 2 * RT; i += kDeimThreads) up[i / RT][i % RT] = 0.0;
+    // row q of W, and this group's part of beta = W^T w (wavefront sums, then wavefront order).
+    // Every load is issued unconditionally (clamped index) and the unused values cleared by a bit
+    // mask: a select on `in` lets the compiler put each load under its own branch and wait there.
     double u[RT];
     const double wq = in ? a.w[q] : 0.0;
-    // every load issued unconditionally (clamped index), the unused values cleared by a bit mask:
-    // a select on `in` lets the compiler put each load under its own branch and wait for it there
     const int qc = in ? q : nq - 1;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
@@ -261,12 +264,37 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         for (int w = 0; w < kDeimWaves; ++w) b += bw[w][i];
         xstore(&X[kXBeta + (size_t)g * kMaxRank + i], b);
     }
+    // Look-ahead elimination: when pivot j is known, a row forms its updated column j + 1 at once
+    // (the next column's search needs only that one) and applies the pivot to its whole row
+    // while the exchange of column j + 1 is in flight.  Each entry still receives the pivots'
+    // updates in column order, so the arithmetic is that of plain column-by-column elimination.
+    // The whole-row update has no per-column condition: columns up to j are no longer read (their
+    // values go stale), and the pivot rows are zero from column r on.
     bool pivoted = false;
+    bool defer = false;    // pivot j - 1 still to be applied to this row
+    double lprev = 0.0;    // this row's multiplier of pivot j - 1
+    double unext = 0.0;    // column j of this row with pivot j - 1 applied (when defer)
     unsigned nsync = 0;
     for (int j = 0; j < r; ++j) {
+        double* urow = up[j & 1];
+        const double* prow = up[(j + 1) & 1];
+        // The row update reads the pivot row whole, then updates every entry without a branch (a
+        // per-column condition had been compiled into a chain of uniform branches, each with its
+        // own LDS wait).
+        auto finish_prev = [&]() {
+            if (defer) {
+                double pr[RT];
+#pragma unroll
+                for (int i = 0; i < RT; ++i) pr[i] = prow[i];
+#pragma unroll
+                for (int i = 0; i < RT; ++i) u[i] = fma(-lprev, pr[i], u[i]);
+                defer = false;
+            }
+        };
         double uj = 0.0;
 #pragma unroll
         for (int i = 0; i < RT; ++i) uj = (i == j) ? u[i] : uj;
+        if (defer) uj = unext;
         const bool elig = in && !pivoted;
         const double v = elig ? fabs(uj) : -1.0;
         // the two-exchange step (2): lowest-index row at or above thr (or the forced row) with its
@@ -352,6 +380,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             const double tag = (double)(((a.launch_seq & 0xffffffffull) << 6) | (unsigned long long)j);
             double* slot = &X[kXExM + ((size_t)(j & 1) * kDeimMaxGroups + g) * (3 + kMaxRank)];
             if (q == pw) {
+                finish_prev();   // the published row carries every earlier pivot's update
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
                     if (i < r) xstore(&slot[3 + i], u[i]);
@@ -363,6 +392,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             wait_vm_stores();
             __syncthreads();
             if (tid == 0) xstore(&slot[2], tag * 32768.0 + (double)(pw < nq ? pw : 16384));
+            finish_prev();   // the rest of pivot j - 1's update, while the exchange is in flight
             if (wv == 0) {
                 const double* sl = &X[kXExM + ((size_t)(j & 1) * kDeimMaxGroups + lane) * (3 + kMaxRank)];
                 double word = 0.0;
@@ -380,8 +410,19 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
+                // every group's maxima and (GM <= 8) candidate row, complete once the words are seen
+                const double* base = &X[kXExM + (size_t)(j & 1) * kDeimMaxGroups * (3 + kMaxRank)];
                 const double mg = (lane < G) ? xload(&sl[0]) : -1.0;
                 const double sg = (lane < G) ? xload(&sl[1]) : 0.0;
+                constexpr int KS = GM <= 8 ? (8 * RT + 63) / 64 : 1;
+                double rv[KS];
+                if (GM <= 8) {
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        const int idx = lane + 64 * k, gg = idx / r, i = idx - gg * r;
+                        rv[k] = xload(&base[(size_t)(gg < G ? gg : 0) * (3 + kMaxRank) + 3 + (gg < G ? i : 0)]);
+                    }
+                }
                 const double ci = word - tag * 32768.0;
                 const double cg = (lane < G && ci < 16384.0) ? ci : 2147483647.0;
                 const double Mx = wave_max(mg);
@@ -393,26 +434,45 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
                 cand = wave_min(cand);
                 scnd = wave_max(scnd);
                 const bool fallback = __ballot(band) != 0ull;
+                const bool found = cand < 2147483647.0;
+                const int pg = found ? (int)cand / kDeimThreads : 0;
+                bool have = false;
+                if (!fallback && found) {
+                    // the pivot row into LDS: from the loaded rows, or one more load
+                    if (GM <= 8) {
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) {
+                            const int idx = lane + 64 * k, gg = idx / r, i = idx - gg * r;
+                            if (gg == pg) urow[i] = rv[k];
+                        }
+                    } else {
+                        for (int i = lane; i < r; i += 64) urow[i] = xload(&base[(size_t)pg * (3 + kMaxRank) + 3 + i]);
+                    }
+                    have = true;
+                }
                 if (lane == 0) {
                     sM = Mpos;
                     sFallback = fallback ? 1 : 0;
-                    sP = (cand < 2147483647.0) ? (int)cand : -1;
+                    sHaveRow = have ? 1 : 0;
+                    sP = found ? (int)cand : -1;
                     sSecond = scnd;
-                    sSrc = (cand < 2147483647.0)
-                               ? kXExM + ((size_t)(j & 1) * kDeimMaxGroups + (int)cand / kDeimThreads) * (3 + kMaxRank) + 3
-                               : 0;
+                    sSrc = found ? kXExM + ((size_t)(j & 1) * kDeimMaxGroups + pg) * (3 + kMaxRank) + 3 : 0;
                 }
             }
             __syncthreads();
             if (sFallback) exchange_above((1.0 - a.tie_tol) * sM);
         } else {
+            finish_prev();
             // (1) the maximum over the rows not yet chosen, (2) the rows at or above the threshold
             if (tid == 0) xstore(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + g], mw);
             group_sync(a.xcount, (++nsync) * (unsigned)G, &stall);
             if (wv == 0) {
                 const double mg =
                     wave_max((lane < G) ? xload(&X[kXEx1 + (size_t)(j & 1) * kDeimMaxGroups + lane]) : -1.0);
-                if (lane == 0) sM = fmax(mg, 0.0);
+                if (lane == 0) {
+                    sM = fmax(mg, 0.0);
+                    sHaveRow = 0;
+                }
             }
             __syncthreads();
             exchange_above((1.0 - a.tie_tol) * sM);
@@ -423,22 +483,25 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             if (tid == 0) bad = 1;
             break;
         }
-        for (int i = tid; i < r; i += kDeimThreads) up[i] = xload(&X[sSrc + i]);
-        if (tid == 0) {
-            if (g == 0) {
-                a.sel[j] = p;
-                a.margins[j] = (M > 0.0) ? (M - sSecond) / M : 0.0;
-            }
-            if (!(M > 0.0)) bad = 1;
+        const bool reload = sFallback || !sHaveRow;
+        if (reload) {
+            for (int i = tid; i < r; i += kDeimThreads) urow[i] = xload(&X[sSrc + i]);
+            __syncthreads();
         }
-        __syncthreads();
-        // eliminate column j from the rows not yet chosen
+        if (tid == 0 && g == 0) {
+            a.sel[j] = p;
+            a.margins[j] = (M > 0.0) ? (M - sSecond) / M : 0.0;
+        }
+        if (tid == 0 && !(M > 0.0)) bad = 1;
+        // pivot j: this row's multiplier, applied to column j + 1 now and to the rest later
         if (q == p) pivoted = true;
-        if (in && !pivoted) {
-            const double l = uj / up[j];
+        if (in && !pivoted && j + 1 < r) {
+            lprev = uj / urow[j];
+            double un = 0.0;
 #pragma unroll
-            for (int i = 0; i < RT; ++i)
-                if (i > j && i < r) u[i] -= l * up[i];
+            for (int i = 0; i < RT; ++i) un = (i == j + 1) ? u[i] : un;
+            unext = fma(-lprev, urow[j + 1], un);
+            defer = true;
         }
     }
     // the last group to leave resets the counters for the next launch
@@ -1014,14 +1077,25 @@ __global__ __launch_bounds__(256) void k_publish(PublishArgs a) {
 
 void launch_deim(hipStream_t s, const DeimArgs& a) {
     const unsigned groups = (unsigned)((a.nq + kDeimThreads - 1) / kDeimThreads);
-    if (a.r <= 8)
-        hipLaunchKernelGGL((k_deim<8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
-    else if (a.r <= 16)
-        hipLaunchKernelGGL((k_deim<16>), dim3(groups), dim3(kDeimThreads), 0, s, a);
-    else if (a.r <= 32)
-        hipLaunchKernelGGL((k_deim<32>), dim3(groups), dim3(kDeimThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_deim<64>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    if (groups <= 8) {
+        if (a.r <= 8)
+            hipLaunchKernelGGL((k_deim<8, 8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else if (a.r <= 16)
+            hipLaunchKernelGGL((k_deim<16, 8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else if (a.r <= 32)
+            hipLaunchKernelGGL((k_deim<32, 8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_deim<64, 8>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    } else {
+        if (a.r <= 8)
+            hipLaunchKernelGGL((k_deim<8, kDeimMaxGroups>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else if (a.r <= 16)
+            hipLaunchKernelGGL((k_deim<16, kDeimMaxGroups>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else if (a.r <= 32)
+            hipLaunchKernelGGL((k_deim<32, kDeimMaxGroups>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_deim<64, kDeimMaxGroups>), dim3(groups), dim3(kDeimThreads), 0, s, a);
+    }
     hipLaunchKernelGGL(k_deim_tail, dim3(1), dim3(kDeimThreads), 0, s, a, (int)groups);
 }
 
