@@ -48,9 +48,18 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
     scl[j] = sj;
     double a[RMAX], bm[RMAX];
     double dev = 0.0;   // max |G_ij - delta_ij| of this column
+    // The column's entries are loaded first, all at once, and cleared by a bit mask where unused:
+    // a select between a loaded value and a constant is compiled into a branch around the load,
+    // which then waits for each load in turn.
+    double gv[RMAX];
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) {
-        const double g = G[(i < r ? i : r - 1) * r + jc];
+        const unsigned long long keep = (i < r && col) ? ~0ull : 0ull;
+        gv[i] = __longlong_as_double(__double_as_longlong(G[(i < r ? i : r - 1) * r + jc]) & keep);
+    }
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+        const double g = gv[i];
         a[i] = (i < r && col) ? scl[i] * g * sj : (i == j ? 1.0 : 0.0);
         bm[i] = (i == j) ? 1.0 : 0.0;
         if (i < r && col) dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
