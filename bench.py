@@ -227,15 +227,17 @@ def dsa_leg(n, steps):
     return out
 
 
-def batch_run(count, steps):
+def batch_run(count, steps, graphs=True):
     """The batched-instances workload: count independent problems admitted at once and
-    advanced together for `steps` steps (FP32 sweeps, FP64 energy update)."""
+    advanced together for `steps` steps (FP32 sweeps, FP64 energy update); with graphs, the
+    steps after the first run from the recorded graphs of the composition."""
     from paper_2601_18705_amd import dlrtrt
     from synth import problems
     insts = problems.batch_instances(count=count, nsteps=steps)
     import torch
     torch.cuda.init()
     with dlrtrt.Batch() as b:
+        b.set_graphs(1 if graphs else 0)
         slots = {}
         for prob in insts:
             prob["precision"], prob["si_tol"] = dlrtrt.DLR_FP32_SWEEP, 1e-6
@@ -251,8 +253,9 @@ def batch_run(count, steps):
                 print(f"[bench] batch step {k + 1}/{steps}", file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
         done = b.poll()
+        recorded = b.graph_steps()
     return {"instances": count, "steps": steps, "wall_s": wall, "ca_per_s": ca / wall,
-            "instance_steps_per_s": count * steps / wall, "finished": len(done)}
+            "instance_steps_per_s": count * steps / wall, "finished": len(done), "graph_steps": recorded}
 
 
 def main():
@@ -421,6 +424,8 @@ def main():
     if args.batch_count > 0:
         print(f"[bench] batched leg: {args.batch_count} instances", file=sys.stderr, flush=True)
         out["batch_leg"] = batch_run(args.batch_count, 50)
+        eager = batch_run(args.batch_count, 50, graphs=False)
+        out["batch_leg"]["eager_steps"] = {k: eager[k] for k in ("wall_s", "ca_per_s", "instance_steps_per_s")}
     if args.serve_window_s > 0:
         print(f"[bench] serving leg: {args.serve_window_s:g} s of arrivals", file=sys.stderr, flush=True)
         sv = serving_leg(args.serve_window_s, args.serve_max_s, args.serve_budget_gib)

@@ -234,8 +234,26 @@ dlr_status dlr_batch_create(size_t hbm_budget, void *hip_stream, dlr_batch *out)
  * DLR_ERR_OOM: the footprint does not fit in what the budget has left; nothing was admitted. */
 dlr_status dlr_batch_admit(dlr_batch b, const dlr_problem *prob, int32_t n_steps, int64_t *slot);
 
-/* One DLR step of every active slot (slots that still have steps to take). */
+/* One DLR step of every active slot (slots that still have steps to take).  When the active
+ * slots are the same as at the previous advance, the step runs from HIP graphs recorded for that
+ * composition (every slot's kernels and the shared sweep launches, kernel nodes only; both
+ * parities of the ping-pong buffers; re-recorded when the composition or the number of source
+ * iterations changes): the source iteration is then decided on the device -- the scalar-flux
+ * kernel of each slot counts the iteration and raises a stop flag at convergence (or a
+ * non-finite change norm, or si_max_iter), and every later kernel of that slot's iteration,
+ * including its units of the shared sweep, returns at once.  A slot that needs more iterations
+ * than were recorded continues on the host's decision.  The arithmetic is the same on both paths
+ * (the per-slot results stay bitwise those of dlr_step).  The allocator hook serves the recorded
+ * tables; nothing is allocated while replaying. */
 dlr_status dlr_batch_advance(dlr_batch b);
+
+/* enable = 0: no recorded-graph steps for this batch; 1 (the default): recorded steps with up to
+ * 8 source iterations recorded per step; 2..64: that many at most.  Any change drops the recorded
+ * graphs.  Results do not depend on the setting.  Errors: DLR_ERR_ARG (enable outside [0, 64]). */
+dlr_status dlr_batch_set_graphs(dlr_batch b, int32_t enable);
+
+/* Steps advanced from recorded graphs since the batch was created (a diagnostic). */
+dlr_status dlr_batch_graph_steps(dlr_batch b, int64_t *steps);
 
 /* Slots that finished (all steps taken, or failed) since the last poll, oldest first:
  * up to cap ids in done[], their number in *n. */

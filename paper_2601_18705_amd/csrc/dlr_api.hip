@@ -170,6 +170,11 @@ struct dlr_instance {
     double *cw = nullptr, *C0 = nullptr, *a0 = nullptr, *margins = nullptr, *sel_mu = nullptr, *sel_eta = nullptr;
     double *inflow_x = nullptr, *inflow_y = nullptr, *deim_work = nullptr;
     unsigned* deim_count = nullptr;
+    int* si_flag = nullptr;         // [4] source-iteration control of the step (dlr::SiControl)
+    unsigned* deim_ctr = nullptr;   // DEIM tag counter of graph-recorded launches (from 2^31 on)
+    bool device_si = false;         // source iteration decided on the device (graph-recorded steps)
+    bool capturing = false;         // launches are being recorded into a graph: no timing events
+    bool untimed = false;           // this step's beginning ran from a recorded graph (no step timing)
     void* edge = nullptr;
     unsigned long long* progress = nullptr;
     unsigned* ticket = nullptr;
@@ -299,6 +304,8 @@ struct dlr_instance {
         inflow_y = A.take<double>(R);
         deim_work = A.take<double>(dlr::kDeimXchgDoubles);
         deim_count = A.take<unsigned>(4);
+        si_flag = A.take<int>(4);
+        deim_ctr = A.take<unsigned>(4);
         edge = A.take<char>(R * (size_t)nsuper * ny * sweep_bytes());
         progress = A.take<unsigned long long>(R * (size_t)nsuper);
         ticket = A.take<unsigned>(4);
@@ -424,6 +431,7 @@ dlr::SweepArgs<TS> make_sweep_record(const dlr_instance* I) {
     sa.edge = static_cast<TS*>(I->edge); sa.progress = I->progress;
     sa.status = I->status;
     sa.spin_limit = 1u << 20;
+    sa.skip = I->si_flag;   // zero except in graph-recorded steps once the source iteration has stopped
     return sa;
 }
 
@@ -465,6 +473,7 @@ void dsa_correct(dlr_instance* I) {
     a.partials = I->dsa_part; a.counter = I->dsa_count; a.scal = I->dsa_scal;
     a.tol = I->dsa_tol; a.max_iter = I->dsa_max_iter;
     a.s_e = I->s_e; a.ldg = I->ldg;
+    a.skip = I->device_si ? I->si_flag : nullptr;   // no correction once the iteration has stopped
     dlr::launch_dsa(I->stream, a, I->fp32());
 }
 
@@ -481,7 +490,7 @@ void phase_begin(dlr_instance* I) {
     hipStream_t s = I->stream;
     const int r = I->r, nq = I->nq;
     const double cdt = I->c * I->dt;
-    hip_check(hipEventRecord(I->ev[0], s), "event");
+    if (!I->capturing) hip_check(hipEventRecord(I->ev[0], s), "event");
     // 1. effective scattering and source (beside DEIM, which does not read them)
     hipStream_t ls = s;
     if (I->side) {
@@ -496,7 +505,8 @@ void phase_begin(dlr_instance* I) {
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
     da.forced = I->force_pending ? I->forced : nullptr;
-    da.xchg = I->deim_work; da.xcount = I->deim_count; da.launch_seq = dlr::next_sweep_launch_id(); da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
+    da.xchg = I->deim_work; da.xcount = I->deim_count; da.launch_seq = dlr::next_sweep_launch_id();
+    da.seq_ctr = I->device_si ? I->deim_ctr : nullptr; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
     da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
     da.mu = I->mu; da.eta = I->eta;
     for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];
@@ -507,7 +517,7 @@ void phase_begin(dlr_instance* I) {
     if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
     dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
-                         static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e));
+                         static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e), I->si_flag);
     I->phi_cur = I->phi;
     I->phi_nxt = I->phi2;
     I->si_it = 0;
@@ -533,11 +543,13 @@ void sweep_alone(dlr_instance* I) {
 template <typename TS>
 void si_phi(dlr_instance* I) {
     hipStream_t s = I->stream;
+    const dlr::SiControl ctl{I->si_flag, I->si_tol, I->si_max_iter};
     dlr::launch_phi<TS>(s, I->nx, I->ny, I->r, static_cast<const TS*>(I->psi), I->ldg, I->sel_mu, I->sel_eta, I->cw,
                         I->phio, I->sig_s, I->phi_cur, I->phi_nxt, static_cast<TS*>(I->s_e), I->partials, I->nb_phi,
-                        I->counters + 0, I->norm_out);
+                        I->counters + 0, I->norm_out, I->device_si ? &ctl : nullptr);
     std::swap(I->phi_cur, I->phi_nxt);
-    publish(I, s, 0, I->norm_out, 3, nullptr, 0, nullptr, 0, 1);
+    // with the iteration decided on the device the host reads the control words once, at the end
+    if (!I->device_si) publish(I, s, 0, I->norm_out, 3, nullptr, 0, nullptr, 0, 1);
 }
 
 // After the stream has passed si_phi.  Returns DLR_OK with I->si_conv set, or an error (handle poisoned).
@@ -551,13 +563,17 @@ dlr_status si_check(dlr_instance* I) {
         return fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
     }
     I->stats.si_residual = rel;
+    // I->phi names the converged flux after the step's iteration -- except in a step begun from a
+    // recorded graph, whose launches hold the buffers as recorded (a DLR step does not read the
+    // converged flux after the iteration: the temperature update forms phi from the new factors)
+    const bool rename = I->phi_cur != I->phi && !I->untimed;
     if (rel <= I->si_tol) {
         I->si_conv = true;
-        if (I->phi_cur != I->phi) std::swap(I->phi, I->phi2);
+        if (rename) std::swap(I->phi, I->phi2);
         return DLR_OK;
     }
     if (I->si_it >= I->si_max_iter) {
-        if (I->phi_cur != I->phi) std::swap(I->phi, I->phi2);
+        if (rename) std::swap(I->phi, I->phi2);
         I->poisoned = true;
         I->poison_code = DLR_ERR_NOT_CONVERGED;
         return fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
@@ -628,15 +644,19 @@ void phase_end(dlr_instance* I) {
     if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     std::swap(I->X, I->Xn);
     std::swap(I->S, I->Sn);
-    hip_check(hipEventRecord(I->ev[1], s), "event");
+    if (!I->capturing) hip_check(hipEventRecord(I->ev[1], s), "event");
 }
 
-dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
+// energy, DEIM margins and weights into pinned memory behind the step; the status check's
+// stream synchronisation completes them (one host round trip per step)
+void step_publish(dlr_instance* I) {
+    publish(I, I->stream, kPinnedNorm, I->energy_out, 2, I->margins, I->r, I->cw, I->r, 4);
+}
+
+// After the stream has passed step_publish.
+dlr_status step_read(dlr_instance* I, bool timed_sweeps) {
     const int r = I->r;
-    // energy, DEIM margins and weights into pinned memory behind the step; the status check's copy
-    // and stream synchronisation complete them (one host round trip per step instead of four)
     double* hf = I->h_norm + kPinnedNorm;
-    publish(I, I->stream, kPinnedNorm, I->energy_out, 2, I->margins, r, I->cw, r, 4);
     const dlr_status st = check_device_status(I, true);
     if (st != DLR_OK) return st;
     const double en = hf[0];
@@ -644,8 +664,8 @@ dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     I->stats.inflow = I->inflow_power;
     I->stats.source = I->source_power;
     const std::vector<double> marg(hf + 2, hf + 2 + r), cwv(hf + 2 + r, hf + 2 + 2 * r);
-    float step_ms = 0.f;
-    hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
+    float step_ms = 0.f;   // graph-recorded steps are not timed per instance
+    if (!I->device_si && !I->untimed) hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
     I->stats.si_iters = I->si_it;
     I->stats.energy = en;
     I->stats.deim_min_margin = *std::min_element(marg.begin(), marg.end());
@@ -660,6 +680,11 @@ dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
     ++I->steps_done;
     I->stats.steps_done = I->steps_done;
     return DLR_OK;
+}
+
+dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
+    step_publish(I);
+    return step_read(I, timed_sweeps);
 }
 
 template <typename TS>
@@ -843,6 +868,10 @@ dlr_status allocate_instance(dlr_instance* I) {
     if (!I->arena.allocate(need, I->stream)) return fail(DLR_ERR_OOM, "device allocation of the instance failed");
     I->carve(I->arena);
     hip_check(hipMemsetAsync(I->arena.base, 0, I->arena.cap, I->stream), "clear");
+    if (I->deim_ctr) {
+        const unsigned base = 1u << 31;
+        hip_check(hipMemcpyAsync(I->deim_ctr, &base, sizeof(base), hipMemcpyHostToDevice, I->stream), "counter");
+    }
     hip_check(hipStreamSynchronize(I->stream), "sync");
     return DLR_OK;
 }
@@ -878,6 +907,25 @@ struct dlr_batch_s {
     unsigned* d_ticket = nullptr;
     DevMem table_mem[2], unit_end_mem[2], ticket_mem;   // device memory behind the three above
     hipEvent_t ev_main = nullptr;
+    // Graph-recorded steps (a composition of slots that stays the same from one advance to the next):
+    // the steps of both parities of the ping-pong buffers are recorded once, with K source
+    // iterations decided on the device, and replayed until the composition changes.
+    bool graphs = true;                              // allowed (dlr_batch_set_graphs)
+    int max_rec = 8;                                 // most source iterations recorded per step
+    hipStream_t rec = nullptr;                       // recording / replay stream
+    std::vector<hipStream_t> rec_streams;            // one per slot while recording: independent chains
+    hipEvent_t ev_cap = nullptr;
+    DevMem gtable_mem[2], gunit_mem[2], gctr_mem, gptr_mem;
+    unsigned long long* d_sweep_ctr = nullptr;      // sweep launch counter of the recorded launches
+    size_t gcap = 0;                                 // entries of the recorded tables and gather arrays
+    int* h_gi = nullptr;                             // pinned [4 * gcap]: flags, status per slot
+    double* h_gd = nullptr;                          // pinned [gcap]: last relative change per slot
+    int* d_h_gi = nullptr;
+    double* d_h_gd = nullptr;
+    hipGraphExec_t gx_begin[2] = {nullptr, nullptr}, gx_end[2] = {nullptr, nullptr};
+    std::vector<int64_t> gkey, last_key;             // recorded composition; the previous advance's
+    int gK = 0, k_hint = 2, parity = 0;
+    int64_t graph_steps = 0;                         // steps advanced through the recorded graphs
 };
 
 namespace {
@@ -949,6 +997,177 @@ void slot_fail(dlr_batch_s* B, BatchSlot* sl, dlr_status st) {
 BatchSlot* find_slot(dlr_batch_s* B, int64_t id) {
     auto it = B->slots.find(id);
     return it == B->slots.end() ? nullptr : &it->second;
+}
+
+// ---------------------------------------------------------------------------------------------- recorded steps
+void graph_clear(dlr_batch_s* B) {
+    for (int p = 0; p < 2; ++p) {
+        if (B->gx_begin[p]) (void)hipGraphExecDestroy(B->gx_begin[p]);
+        if (B->gx_end[p]) (void)hipGraphExecDestroy(B->gx_end[p]);
+        B->gx_begin[p] = B->gx_end[p] = nullptr;
+    }
+    B->gkey.clear();
+    B->gK = 0;
+    B->parity = 0;
+}
+
+// Tables of the recorded sweep launches and the gather arrays, for n slots.
+void graph_reserve(dlr_batch_s* B, size_t n) {
+    if (n <= B->gcap) return;
+    size_t cap = std::max<size_t>(64, B->gcap);
+    while (cap < n) cap *= 2;
+    hip_check(hipStreamSynchronize(B->rec), "sync");
+    for (int g = 0; g < 2; ++g) {
+        dev_free(B->gtable_mem[g]);
+        dev_free(B->gunit_mem[g]);
+        if (!dev_alloc(B->gtable_mem[g], cap * kRecBytes, B->rec) ||
+            !dev_alloc(B->gunit_mem[g], cap * sizeof(unsigned), B->rec))
+            throw HipError("recorded sweep tables: device allocation failed");
+    }
+    dev_free(B->gptr_mem);
+    if (!dev_alloc(B->gptr_mem, 3 * cap * sizeof(void*), B->rec)) throw HipError("gather table: device allocation failed");
+    if (B->h_gi) (void)hipHostFree(B->h_gi);
+    if (B->h_gd) (void)hipHostFree(B->h_gd);
+    B->h_gi = nullptr;
+    B->h_gd = nullptr;
+    hip_check(hipHostMalloc((void**)&B->h_gi, 4 * cap * sizeof(int), hipHostMallocDefault), "pinned");
+    hip_check(hipHostMalloc((void**)&B->h_gd, cap * sizeof(double), hipHostMallocDefault), "pinned");
+    hip_check(hipHostGetDevicePointer((void**)&B->d_h_gi, B->h_gi, 0), "pinned mapping");
+    hip_check(hipHostGetDevicePointer((void**)&B->d_h_gd, B->h_gd, 0), "pinned mapping");
+    B->gcap = cap;
+}
+
+template <typename TS>
+void graph_sweep(dlr_batch_s* B, int n, unsigned units) {
+    if (n == 0) return;
+    const int g = sizeof(TS) == 4 ? 1 : 0;
+    dlr::SweepLaunch L{};
+    L.ninst = n;
+    L.total_units = units;
+    L.unit_end = static_cast<const unsigned*>(B->gunit_mem[g].ptr);
+    L.ticket = B->d_ticket;
+    L.launch_id = 0;
+    L.id_ctr = B->d_sweep_ctr;   // every replay tags its progress words apart
+    L.grid_blocks = (int)std::min<unsigned>(units, 1024u);
+    dlr::launch_sweep<TS>(B->rec, static_cast<const dlr::SweepArgs<TS>*>(B->gtable_mem[g].ptr), L);
+}
+
+// Record the step of the slots `act` for both parities of their ping-pong buffers: the beginning
+// (Algorithm 1 steps 1-3) with K source iterations (step 4) decided on the device, then the end
+// (steps 5-9) with the values the host reads.  Slots of one pool stream keep their order; the
+// shared sweep launches join every slot.  Kernel launches only: no memory operation is recorded.
+void graph_record(dlr_batch_s* B, const std::vector<BatchSlot*>& act, const std::vector<int64_t>& key, int K) {
+    graph_clear(B);
+    graph_reserve(B, act.size());
+    const size_t n = act.size();
+    std::vector<char> tab[2];
+    std::vector<unsigned> ue[2];
+    unsigned units[2] = {0u, 0u};
+    std::vector<const void*> ptrs(3 * n);
+    // Each slot records on a stream of its own, so that the graph holds one independent chain per
+    // slot (the pool streams would chain the slots that share one).
+    while (B->rec_streams.size() < n) {
+        hipStream_t st = nullptr;
+        hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream");
+        B->rec_streams.push_back(st);
+    }
+    std::vector<hipStream_t> used, home(n);
+    for (size_t k = 0; k < n; ++k) {
+        home[k] = act[k]->I->stream;
+        act[k]->I->stream = B->rec_streams[k];
+    }
+    for (size_t k = 0; k < n; ++k) {
+        dlr_instance* I = act[k]->I;
+        const int g = I->fp32() ? 1 : 0;
+        tab[g].insert(tab[g].end(), I->h_sweep_rec.begin(), I->h_sweep_rec.end());
+        units[g] += (unsigned)(I->nsuper * I->r);
+        ue[g].push_back(units[g]);
+        ptrs[k] = I->si_flag;
+        ptrs[n + k] = I->status;
+        ptrs[2 * n + k] = I->norm_out + 2;
+        if (std::find(used.begin(), used.end(), I->stream) == used.end()) used.push_back(I->stream);
+    }
+    for (int g = 0; g < 2; ++g)
+        if (!ue[g].empty()) {
+            hip_check(hipMemcpy(B->gtable_mem[g].ptr, tab[g].data(), tab[g].size(), hipMemcpyHostToDevice), "table");
+            hip_check(hipMemcpy(B->gunit_mem[g].ptr, ue[g].data(), ue[g].size() * sizeof(unsigned),
+                                hipMemcpyHostToDevice), "table");
+        }
+    hip_check(hipMemcpy(B->gptr_mem.ptr, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice), "table");
+    const int* const* dflags = static_cast<const int* const*>(B->gptr_mem.ptr);
+    const int* const* dstat = dflags + n;
+    const double* const* drel = reinterpret_cast<const double* const*>(dflags + 2 * n);
+    const int nd = (int)ue[0].size(), nf = (int)ue[1].size();
+    auto fork = [&]() {
+        hip_check(hipStreamBeginCapture(B->rec, hipStreamCaptureModeRelaxed), "begin capture");
+        hip_check(hipEventRecord(B->ev_cap, B->rec), "event");
+        for (hipStream_t st : used) hip_check(hipStreamWaitEvent(st, B->ev_cap, 0), "wait");
+    };
+    auto join = [&](hipGraphExec_t* out) {
+        for (BatchSlot* sl : act) hip_check(hipStreamWaitEvent(B->rec, sl->ev, 0), "wait");
+        hipGraph_t gr = nullptr;
+        hip_check(hipStreamEndCapture(B->rec, &gr), "end capture");
+        const hipError_t e = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        hip_check(e, "instantiate");
+    };
+    for (BatchSlot* sl : act) sl->I->capturing = true;
+    try {
+        for (int p = 0; p < 2; ++p) {
+            fork();
+            for (BatchSlot* sl : act) {
+                sl->I->device_si = true;
+                if (sl->I->fp32()) phase_begin<float>(sl->I); else phase_begin<double>(sl->I);
+                hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+            }
+            for (int it = 0; it < K; ++it) {
+                for (BatchSlot* sl : act) hip_check(hipStreamWaitEvent(B->rec, sl->ev, 0), "wait");
+                graph_sweep<double>(B, nd, units[0]);
+                graph_sweep<float>(B, nf, units[1]);
+                hip_check(hipEventRecord(B->ev_main, B->rec), "event");
+                for (BatchSlot* sl : act) {
+                    dlr_instance* I = sl->I;
+                    hip_check(hipStreamWaitEvent(I->stream, B->ev_main, 0), "wait");
+                    if (I->fp32()) si_phi<float>(I); else si_phi<double>(I);
+                    if (I->dsa) dsa_correct(I);
+                    hip_check(hipEventRecord(sl->ev, I->stream), "event");
+                }
+            }
+            for (BatchSlot* sl : act) hip_check(hipStreamWaitEvent(B->rec, sl->ev, 0), "wait");
+            dlr::launch_gather_si(B->rec, (int)n, dflags, dstat, drel, B->d_h_gi, B->d_h_gd);
+            join(&B->gx_begin[p]);
+            // the end of the step; phase_end swaps the host's X/Xn and S/Sn, so the next pass records
+            // the other parity and the second pass restores the present one
+            fork();
+            for (BatchSlot* sl : act) {
+                if (sl->I->fp32()) phase_end<float>(sl->I); else phase_end<double>(sl->I);
+                step_publish(sl->I);
+                hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+            }
+            join(&B->gx_end[p]);
+        }
+    } catch (...) {
+        for (size_t k = 0; k < n; ++k) act[k]->I->stream = home[k];
+        hipGraph_t junk = nullptr;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(B->rec, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            (void)hipStreamEndCapture(B->rec, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        for (BatchSlot* sl : act) {
+            sl->I->capturing = false;
+            sl->I->device_si = false;
+        }
+        graph_clear(B);
+        throw;
+    }
+    for (size_t k = 0; k < n; ++k) act[k]->I->stream = home[k];
+    for (BatchSlot* sl : act) {
+        sl->I->capturing = false;
+        sl->I->device_si = false;
+    }
+    B->gkey = key;
+    B->gK = K;
+    B->parity = 0;
 }
 
 }  // namespace
@@ -1379,6 +1598,13 @@ dlr_status dlr_batch_create(size_t hbm_budget, void* hip_stream, dlr_batch* out)
         hip_check(hipStreamSynchronize(B->main), "sync");
         hip_check(hipEventCreateWithFlags(&B->ev_main, hipEventDisableTiming), "event");
         batch_reserve(B, 64);
+        // recorded steps: their own stream, and the sweep launch counter (ids from 2^31 on)
+        hip_check(hipStreamCreateWithFlags(&B->rec, hipStreamNonBlocking), "stream");
+        hip_check(hipEventCreateWithFlags(&B->ev_cap, hipEventDisableTiming), "event");
+        if (!dev_alloc(B->gctr_mem, 256, B->rec)) throw HipError("counter: device allocation failed");
+        B->d_sweep_ctr = static_cast<unsigned long long*>(B->gctr_mem.ptr);
+        const unsigned long long base = 1ull << 31;
+        hip_check(hipMemcpy(B->d_sweep_ctr, &base, sizeof(base), hipMemcpyHostToDevice), "counter");
     } catch (const std::exception& ex) {
         dlr_batch_destroy(B);
         return fail(DLR_ERR_HIP, ex.what());
@@ -1422,16 +1648,84 @@ dlr_status dlr_batch_admit(dlr_batch B, const dlr_problem* p, int32_t n_steps, i
 dlr_status dlr_batch_advance(dlr_batch B) {
     if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
     std::vector<BatchSlot*> act;
+    std::vector<int64_t> key;
     for (auto& kv : B->slots)
-        if (!kv.second.finished && kv.second.remaining > 0) act.push_back(&kv.second);
+        if (!kv.second.finished && kv.second.remaining > 0) {
+            act.push_back(&kv.second);
+            key.push_back(kv.first);
+        }
     if (act.empty()) return DLR_OK;
     try {
         batch_reserve(B, act.size());
-        for (BatchSlot* sl : act) {
-            if (sl->I->fp32()) phase_begin<float>(sl->I); else phase_begin<double>(sl->I);
-            hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+        // A composition seen at two advances in a row runs from recorded graphs (recorded once per
+        // composition and count of source iterations); a forced selection (the parity replay) runs eagerly.
+        bool forced = false;
+        for (BatchSlot* sl : act) forced = forced || sl->I->force_pending;
+        const bool stable = B->graphs && B->rec && !forced && key == B->last_key;
+        B->last_key = key;
+        const int K = std::max(1, std::min(B->k_hint, B->max_rec));
+        if (!stable) {
+            if (!B->gkey.empty()) graph_clear(B);
+        } else if (B->gkey != key || B->gK != K) {
+            graph_record(B, act, key, K);
         }
-        std::vector<BatchSlot*> pending = act;
+        const bool replay = stable && B->gkey == key;
+        const int p = B->parity;
+        std::vector<BatchSlot*> pending;
+        bool broken = false;
+        if (replay) {
+            for (BatchSlot* sl : act) {
+                dlr_instance* I = sl->I;
+                I->phi_cur = I->phi;
+                I->phi_nxt = I->phi2;
+                I->si_it = 0;
+                I->si_conv = false;
+                I->sweep_ms_acc = 0.f;
+                I->force_pending = false;
+                I->device_si = true;
+                I->untimed = true;
+            }
+            hip_check(hipGraphLaunch(B->gx_begin[p], B->rec), "graph launch");
+            hip_check(hipStreamSynchronize(B->rec), "sync");
+            for (size_t k = 0; k < act.size(); ++k) {
+                BatchSlot* sl = act[k];
+                dlr_instance* I = sl->I;
+                const int* f = B->h_gi + 4 * k;
+                I->si_it = f[1];
+                I->stats.si_residual = B->h_gd[k];
+                if (f[1] & 1) std::swap(I->phi_cur, I->phi_nxt);   // the newest flux after an odd count
+                dlr_status st = DLR_OK;
+                if (f[3] != 0) {
+                    st = check_device_status(I);
+                } else if (f[2] == 2) {
+                    I->poisoned = true;
+                    I->poison_code = DLR_ERR_NONFINITE;
+                    st = fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
+                } else if (f[2] == 3) {
+                    I->poisoned = true;
+                    I->poison_code = DLR_ERR_NOT_CONVERGED;
+                    st = fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
+                } else if (f[2] == 1) {
+                    I->si_conv = true;
+                } else {
+                    I->device_si = false;   // more iterations than recorded: continued below
+                    hip_check(hipEventRecord(sl->ev, I->stream), "event");
+                    pending.push_back(sl);
+                }
+                if (st != DLR_OK) {
+                    slot_fail(B, sl, st);
+                    broken = true;
+                }
+            }
+        } else {
+            for (BatchSlot* sl : act) {
+                if (sl->I->fp32()) phase_begin<float>(sl->I); else phase_begin<double>(sl->I);
+                hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+            }
+            pending = act;
+        }
+        // source iterations on the host's decision: all of them without a recorded step, the
+        // remaining ones of slots that needed more than were recorded
         while (!pending.empty()) {
             for (BatchSlot* sl : pending) hip_check(hipStreamWaitEvent(B->main, sl->ev, 0), "wait");
             batch_sweep<double>(B, pending);
@@ -1446,18 +1740,41 @@ dlr_status dlr_batch_advance(dlr_batch B) {
             for (BatchSlot* sl : pending) {
                 hip_check(hipEventSynchronize(sl->ev), "sync");
                 const dlr_status st = si_check(sl->I);
-                if (st != DLR_OK) slot_fail(B, sl, st);
-                else if (!sl->I->si_conv) next.push_back(sl);
+                if (st != DLR_OK) {
+                    slot_fail(B, sl, st);
+                    broken = true;
+                } else if (!sl->I->si_conv) {
+                    if (sl->I->dsa) dsa_correct(sl->I);
+                    hip_check(hipEventRecord(sl->ev, sl->I->stream), "event");
+                    next.push_back(sl);
+                }
             }
             pending.swap(next);
         }
-        for (BatchSlot* sl : act)
-            if (!sl->finished) {
-                if (sl->I->fp32()) phase_end<float>(sl->I); else phase_end<double>(sl->I);
+        if (replay && !broken) {
+            hip_check(hipGraphLaunch(B->gx_end[p], B->rec), "graph launch");
+            hip_check(hipStreamSynchronize(B->rec), "sync");
+            B->parity ^= 1;
+            ++B->graph_steps;
+            for (BatchSlot* sl : act) {
+                std::swap(sl->I->X, sl->I->Xn);   // as the recorded end of the step did
+                std::swap(sl->I->S, sl->I->Sn);
             }
+        } else {
+            if (replay) graph_clear(B);
+            for (BatchSlot* sl : act)
+                if (!sl->finished) {
+                    if (sl->I->fp32()) phase_end<float>(sl->I); else phase_end<double>(sl->I);
+                    step_publish(sl->I);
+                }
+        }
+        int most = 1;
         for (BatchSlot* sl : act) {
             if (sl->finished) continue;
-            const dlr_status st = step_finish(sl->I, false);
+            most = std::max(most, sl->I->si_it);
+            const dlr_status st = step_read(sl->I, false);
+            sl->I->device_si = false;
+            sl->I->untimed = false;
             if (st != DLR_OK) {
                 slot_fail(B, sl, st);
                 continue;
@@ -1467,6 +1784,11 @@ dlr_status dlr_batch_advance(dlr_batch B) {
                 B->done.push_back(sl->id);
             }
         }
+        for (BatchSlot* sl : act) {
+            sl->I->device_si = false;
+            sl->I->untimed = false;
+        }
+        B->k_hint = most;
     } catch (const std::exception& ex) {
         return fail(DLR_ERR_HIP, ex.what());
     }
@@ -1503,6 +1825,10 @@ dlr_status dlr_batch_release(dlr_batch B, int64_t slot) {
     if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
     BatchSlot* sl = find_slot(B, slot);
     if (!sl) return fail(DLR_ERR_ARG, "no such slot");
+    if (std::find(B->gkey.begin(), B->gkey.end(), slot) != B->gkey.end()) {
+        if (B->rec) (void)hipStreamSynchronize(B->rec);
+        graph_clear(B);
+    }
     dlr_destroy(sl->I);
     if (sl->ev) (void)hipEventDestroy(sl->ev);
     B->used -= sl->bytes;
@@ -1539,9 +1865,37 @@ dlr_status dlr_batch_destroy(dlr_batch B) {
         if (B->h_unit_end[g]) (void)hipHostFree(B->h_unit_end[g]);
     }
     dev_free(B->ticket_mem);
+    graph_clear(B);
+    for (int g = 0; g < 2; ++g) {
+        dev_free(B->gtable_mem[g]);
+        dev_free(B->gunit_mem[g]);
+    }
+    dev_free(B->gptr_mem);
+    dev_free(B->gctr_mem);
+    if (B->h_gi) (void)hipHostFree(B->h_gi);
+    if (B->h_gd) (void)hipHostFree(B->h_gd);
+    if (B->ev_cap) (void)hipEventDestroy(B->ev_cap);
+    if (B->rec) (void)hipStreamDestroy(B->rec);
+    for (hipStream_t st : B->rec_streams) (void)hipStreamDestroy(st);
     if (B->ev_main) (void)hipEventDestroy(B->ev_main);
     for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
     delete B;
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_set_graphs(dlr_batch B, int32_t enable) {
+    if (!B) return fail(DLR_ERR_ARG, "batch is NULL");
+    if (enable < 0 || enable > 64) return fail(DLR_ERR_ARG, "enable must be in [0, 64]");
+    B->graphs = enable != 0;
+    if (enable > 0) B->max_rec = enable == 1 ? 8 : enable;
+    if (B->rec) (void)hipStreamSynchronize(B->rec);
+    graph_clear(B);   // re-recorded under the new setting
+    return DLR_OK;
+}
+
+dlr_status dlr_batch_graph_steps(dlr_batch B, int64_t* steps) {
+    if (!B || !steps) return fail(DLR_ERR_ARG, "batch or steps is NULL");
+    *steps = B->graph_steps;
     return DLR_OK;
 }
 

@@ -73,15 +73,26 @@ void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const 
                       const double* T, double dt, double a, double c, double* D, double* sig_s, double* q,
                       double* sig_t64, float* sig_t32, size_t ldg, double* q_diag /* nullable: q, 4 copies */);
 
+// zero4: nullptr, or four words set to 0 (the source-iteration control of the step)
 template <typename TS>
 void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
                  const double* q, const double* sig_s, double inv_cdt, const double* mu, const double* eta,
-                 TS* src0, size_t ldg, double* phi, TS* s_e);
+                 TS* src0, size_t ldg, double* phi, TS* s_e, int* zero4 = nullptr);
 
+// Source iteration decided on the device: the scalar-flux kernels return at once while flag[0] is
+// set; otherwise the last block of the second pass counts the iteration in flag[1] and sets
+// flag[0] (with the reason in flag[2]: 1 converged, 2 non-finite change norm, 3 iteration limit)
+// when the relative change is at most tol, is not finite, or the count reaches max_iter.
+struct SiControl {
+    int* flag;     // [4], zero at the start of each step
+    double tol;
+    int max_iter;
+};
 template <typename TS>
 void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
                 const double* cw, double* phio /* [4][ldg] work */, const double* sig_s, const double* phi_old,
-                double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter, double* out);
+                double* phi_new, TS* s_e, double* partials, int nblocks, unsigned* counter, double* out,
+                const SiControl* ctl = nullptr);
 
 // Psi (diagonal layouts) -> compact column-major cell planes [r][ld] (cell e = i * ny + j)
 template <typename TS>
@@ -146,6 +157,7 @@ struct SweepArgs {
     unsigned long long* progress;    // [nd][nsuper] (launch << 32) | rows published
     int* status;                     // kStatusSweepStall is raised if a wait exceeds spin_limit polls
     unsigned spin_limit;
+    const int* skip;                 // nullptr, or the instance's units are skipped while *skip is set
 };
 
 // One persistent launch sweeps the units of several instances: table[k] describes instance k,
@@ -158,6 +170,10 @@ struct SweepLaunch {
     unsigned* ticket;                // [2] work ticket, retired workgroups; zero before the launch, reset after
     unsigned long long launch_id;    // unique per launch in the process (tags progress words)
     int grid_blocks;
+    // nullptr, or the launch id is read here at the start (values from 2^31 on, disjoint from the
+    // host's ids) and advanced by the last workgroup to retire, so a launch recorded once in a
+    // graph still tags every replay apart
+    unsigned long long* id_ctr;
 };
 template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L);
@@ -235,6 +251,7 @@ struct DeimArgs {
     double* xchg;          // [kDeimXchgDoubles] exchange area among the workgroups
     unsigned* xcount;      // [2] arrival / departure counters, zero between launches
     unsigned long long launch_seq;   // unique per launch (>= 1): tags the exchanged words
+    unsigned* seq_ctr;     // nullptr, or the tag is read here (values from 2^31 on) and advanced by the last group
     int* sel;              // [r]
     double* cw;            // [r]
     double* C0;            // [r][r]  C0[k*r + d] = sum_j S[k][j] W[j][sel_d]
@@ -302,6 +319,10 @@ struct PublishArgs {
     int* dst_status;
 };
 void launch_publish(hipStream_t s, const PublishArgs& a);
+// For n instances: their source-iteration control words flag[0..2], status word and last relative
+// change norm into host-mapped pinned memory: dst_i[4 k + 0..3], dst_d[k] (system-scope stores).
+void launch_gather_si(hipStream_t s, int n, const int* const* flags, const int* const* status,
+                      const double* const* rel, int* dst_i, double* dst_d);
 
 // ----------------------------------------------------------------------------- diffusion synthetic acceleration
 // One DSA correction of the source iteration: phi <- phi + delta with D delta = M_s (phi - phi_old),
@@ -324,6 +345,7 @@ struct DsaArgs {
     int max_iter;              // CG iterations launched (the rest return at once after convergence)
     void* s_e;                 // [4][ldg] in the sweep precision, or nullptr
     size_t ldg;
+    const int* skip;           // nullptr, or every kernel returns at once while *skip is set
 };
 int dsa_blocks(int nx, int ny);
 void launch_dsa_kappa(hipStream_t s, int nd, const double* c, const double* mu, const double* eta, double* kappa);

@@ -147,7 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_psi0_wide(TileGrid g, int r, const d
                                                  const double* __restrict__ q, const double* __restrict__ sig_s,
                                                  double inv_cdt, const double* __restrict__ mu,
                                                  const double* __restrict__ eta, TS* __restrict__ src0, size_t ldg,
-                                                 double* __restrict__ phi, TS* __restrict__ s_e) {
+                                                 double* __restrict__ phi, TS* __restrict__ s_e, int* zero4) {
+    if (zero4 && blockIdx.x == 0 && threadIdx.x < 4) zero4[threadIdx.x] = 0;
     // C0, a0 and the orientations are uniform across the workgroup: they are read with scalar
     // loads (through the scalar cache), which keeps the inner product off the LDS pipe
     const long n = (long)g.nx * g.ny;
@@ -234,8 +235,10 @@ __global__ __launch_bounds__(kBlock) void k_psi0_mfma(int nx, int ny, int r, con
                                                       const double* __restrict__ q, const double* __restrict__ sig_s,
                                                       double inv_cdt, const double* __restrict__ mu,
                                                       const double* __restrict__ eta, TS* __restrict__ src0,
-                                                      size_t ldg, double* __restrict__ phi, TS* __restrict__ s_e) {
+                                                      size_t ldg, double* __restrict__ phi, TS* __restrict__ s_e,
+                                                      int* zero4) {
     static_assert(RMAX % 16 == 0 && RMAX <= 32 && RT % 16 == 0, "16-direction blocks, 16-cell pieces");
+    if (zero4 && blockIdx.x == 0 && threadIdx.x < 4) zero4[threadIdx.x] = 0;
     constexpr int NB = RMAX / 16, KS = RMAX / 4;
     constexpr int NP = 8 * RT / 16;                     // 16-cell pieces per tile
     constexpr int SD = 8 * RT + 32 / (int)sizeof(TS);   // LDS row stride: two-way bank access in both phases
@@ -589,8 +592,9 @@ __global__ __launch_bounds__(kBlock) void k_phi_partial(size_t ldg, int nd, cons
                                                         const int* __restrict__ off, const double* __restrict__ mu,
                                                         const double* __restrict__ eta,
                                                         const double* __restrict__ w, const TS* __restrict__ psi,
-                                                        double* __restrict__ phio) {
+                                                        double* __restrict__ phio, const int* ctl) {
     typedef TS tv4 __attribute__((ext_vector_type(4)));
+    if (ctl && *ctl) return;   // the source iteration has stopped
     const int o = blockIdx.y;
     // without a list, the block first lists the directions of orientation o in order (nd <= 64: the
     // selected directions of a rank-r factorisation), so the loop below has no per-direction branch
@@ -636,8 +640,10 @@ __global__ __launch_bounds__(kBlock) void k_phi_combine(TileGrid g, size_t ldg, 
                                                            const double* __restrict__ phi_old,
                                                            double* __restrict__ phi_new, TS* __restrict__ s_e,
                                                            double* __restrict__ partials, unsigned* counter,
-                                                           double* out) {
+                                                           double* out, SiControl ctl) {
     __shared__ double sh[kBlock];
+    // every block reads the flag before the last one of this launch can set it
+    if (ctl.flag && *ctl.flag) return;
     double d2 = 0.0, p2 = 0.0;
     for (int b = blockIdx.x; b < g.count(); b += gridDim.x) {
         // the loads of the thread's four cells first (cells outside the grid read cell (0, 0)), so
@@ -685,9 +691,19 @@ __global__ __launch_bounds__(kBlock) void k_phi_combine(TileGrid g, size_t ldg, 
         const double D2 = ordered_sum(partials, gridDim.x, 2, sh);
         const double P2 = ordered_sum(partials + 1, gridDim.x, 2, sh);
         if (threadIdx.x == 0) {
+            const double rel = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
             out[0] = D2;
             out[1] = P2;
-            out[2] = (P2 > 0.0) ? sqrt(D2) / sqrt(P2) : (D2 > 0.0 ? 1.0 : 0.0);
+            out[2] = rel;
+            if (ctl.flag) {
+                const int it = ctl.flag[1] + 1;
+                ctl.flag[1] = it;
+                const int why = !isfinite(rel) ? 2 : (rel <= ctl.tol ? 1 : (it >= ctl.max_iter ? 3 : 0));
+                if (why) {
+                    ctl.flag[2] = why;
+                    ctl.flag[0] = 1;
+                }
+            }
             reset_counter(counter);
         }
     }
@@ -729,13 +745,14 @@ template <typename TS>
 void launch_phi_two_pass(hipStream_t s, int nx, int ny, size_t ldg, int nd, const int* dirs, const int* off,
                          const double* mu, const double* eta, const double* w, const TS* psi, double* phio,
                          const double* sig_s, const double* phi_old, double* phi_new, TS* s_e, double* partials,
-                         int nblocks, unsigned* counter, double* out) {
+                         int nblocks, unsigned* counter, double* out, const SiControl* ctl = nullptr) {
     const unsigned bx = (unsigned)std::min<size_t>((ldg / 4 + kBlock - 1) / kBlock, 2048);
+    const SiControl c = ctl ? *ctl : SiControl{nullptr, 0.0, 0};
     hipLaunchKernelGGL((k_phi_partial<TS>), dim3(bx, 4), dim3(kBlock), 0, s, ldg, nd, dirs, off, mu, eta, w, psi,
-                       phio);
+                       phio, c.flag);
     const TileGrid g = tile_grid(nx, ny);
     hipLaunchKernelGGL((k_phi_combine<TS>), dim3(nblocks), dim3(kBlock), 0, s, g, ldg, phio, sig_s, phi_old, phi_new,
-                       s_e, partials, counter, out);
+                       s_e, partials, counter, out, c);
 }
 template <typename TS>
 void launch_sn_phi(hipStream_t s, int nx, int ny, size_t ldg, const int* dirs, const int* off, const double* w,
@@ -773,42 +790,42 @@ void launch_linearize(hipStream_t s, int nx, int ny, const double* sigma, const 
 template <typename TS>
 void launch_psi0(hipStream_t s, int nx, int ny, int r, const double* X, const double* C0, const double* a0,
                  const double* q, const double* sig_s, double inv_cdt, const double* mu, const double* eta,
-                 TS* src0, size_t ldg, double* phi, TS* s_e) {
+                 TS* src0, size_t ldg, double* phi, TS* s_e, int* zero4) {
     constexpr int RT = sizeof(TS) == 4 ? 64 : 32;
     const int tiles = ((nx + 7) / 8) * ((ny + RT - 1) / RT);
     const dim3 b(kBlock), gm(std::min(tiles, 4096));
     if (r <= 16) {
         hipLaunchKernelGGL((k_psi0_mfma<TS, 16, RT>), gm, b, 0, s, nx, ny, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta,
-                           src0, ldg, phi, s_e);
+                           src0, ldg, phi, s_e, zero4);
     } else if (r <= 32) {
         hipLaunchKernelGGL((k_psi0_mfma<TS, 32, RT>), gm, b, 0, s, nx, ny, r, X, C0, a0, q, sig_s, inv_cdt, mu, eta,
-                           src0, ldg, phi, s_e);
+                           src0, ldg, phi, s_e, zero4);
     } else {
         const TileGrid g = tile_grid(nx, ny);
         hipLaunchKernelGGL((k_psi0_wide<TS, 64>), dim3(std::min(g.ntx * g.nty, kMaxTileBlocks)), b, 0, s, g, r, X, C0,
-                           a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e);
+                           a0, q, sig_s, inv_cdt, mu, eta, src0, ldg, phi, s_e, zero4);
     }
 }
 template void launch_psi0<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
                                   const double*, const double*, double, const double*, const double*, double*, size_t,
-                                  double*, double*);
+                                  double*, double*, int*);
 template void launch_psi0<float>(hipStream_t, int, int, int, const double*, const double*, const double*,
                                  const double*, const double*, double, const double*, const double*, float*, size_t,
-                                 double*, float*);
+                                 double*, float*, int*);
 
 template <typename TS>
 void launch_phi(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu, const double* eta,
                 const double* cw, double* phio, const double* sig_s, const double* phi_old, double* phi_new, TS* s_e,
-                double* partials, int nblocks, unsigned* counter, double* out) {
+                double* partials, int nblocks, unsigned* counter, double* out, const SiControl* ctl) {
     launch_phi_two_pass<TS>(s, nx, ny, ldg, r, nullptr, nullptr, mu, eta, cw, psi, phio, sig_s, phi_old, phi_new, s_e,
-                            partials, nblocks, counter, out);
+                            partials, nblocks, counter, out, ctl);
 }
 template void launch_phi<double>(hipStream_t, int, int, int, const double*, size_t, const double*, const double*,
                                  const double*, double*, const double*, const double*, double*, double*, double*, int,
-                                 unsigned*, double*);
+                                 unsigned*, double*, const SiControl*);
 template void launch_phi<float>(hipStream_t, int, int, int, const float*, size_t, const double*, const double*,
                                 const double*, double*, const double*, const double*, double*, float*, double*, int,
-                                unsigned*, double*);
+                                unsigned*, double*, const SiControl*);
 
 template <typename TS>
 void launch_psi_to_cm(hipStream_t s, int nx, int ny, int r, const TS* psi, size_t ldg, const double* mu,

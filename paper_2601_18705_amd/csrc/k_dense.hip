@@ -234,6 +234,10 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
     const int q = g * kDeimThreads + tid;
     const bool in = q < nq;
     double* X = a.xchg;
+    // the launch's tag: from the host, or read from the counter before the last group advances it
+    const unsigned long long seq =
+        a.seq_ctr ? (unsigned long long)__hip_atomic_load(a.seq_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : a.launch_seq;
     if (tid == 0) {
         bad = 0;
         stall = 0;
@@ -377,7 +381,7 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
             // poll it instead of a shared arrival counter.  A group cannot reach column j + 2 (and
             // overwrite this slot) before every group has published column j + 1, i.e. finished
             // reading column j.
-            const double tag = (double)(((a.launch_seq & 0xffffffffull) << 6) | (unsigned long long)j);
+            const double tag = (double)(((seq & 0xffffffffull) << 6) | (unsigned long long)j);
             double* slot = &X[kXExM + ((size_t)(j & 1) * kDeimMaxGroups + g) * (3 + kMaxRank)];
             if (q == pw) {
                 finish_prev();   // the published row carries every earlier pivot's update
@@ -511,6 +515,11 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim(DeimArgs a) {
         if (prev == (unsigned)G - 1u) {
             __hip_atomic_store(&a.xcount[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.xcount[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.seq_ctr) {   // stays at 2^31 or above (the host's tags are below)
+                const unsigned nx = (unsigned)seq + 1u;
+                __hip_atomic_store(a.seq_ctr, nx < (1u << 31) ? nx + (1u << 31) : nx, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (stall) atomicOr(a.status, (int)kStatusDeimStall);
         if (bad) atomicOr(a.status, a.forced ? (int)kStatusBadForcedSel : (int)kStatusSingularSolve);
@@ -1058,6 +1067,21 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
         }
 }
 
+// One thread per instance.
+__global__ __launch_bounds__(256) void k_gather_si(int n, const int* const* flags, const int* const* status,
+                                                   const double* const* rel, int* dst_i, double* dst_d) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int* f = flags[k];
+    __hip_atomic_store(dst_i + 4 * k, f[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(dst_i + 4 * k + 1, f[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(dst_i + 4 * k + 2, f[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(dst_i + 4 * k + 3, status[k][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(dst_d) + k,
+                       (unsigned long long)__double_as_longlong(rel[k][0]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
 // One workgroup: the runs and the status words, each value by its own thread.
 __global__ __launch_bounds__(256) void k_publish(PublishArgs a) {
     int off = 0;
@@ -1128,6 +1152,11 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
     hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * r + 255) / 256)), dim3(256), 0, s, n, r, V, M, X);
+}
+
+void launch_gather_si(hipStream_t s, int n, const int* const* flags, const int* const* status,
+                      const double* const* rel, int* dst_i, double* dst_d) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_si, dim3((n + 255) / 256), dim3(256), 0, s, n, flags, status, rel, dst_i, dst_d);
 }
 
 void launch_publish(hipStream_t s, const PublishArgs& a) {

@@ -144,6 +144,7 @@ __device__ __forceinline__ Stencil make_stencil(const DsaArgs& a) {
 // r = A sigma_s (phi_half - phi_old), x = 0, z = r / diag, p = 0; rz, rr
 __global__ __launch_bounds__(kDsaBlock) void k_dsa_init(DsaArgs a) {
     __shared__ double sh[kDsaBlock];
+    if (a.skip && *a.skip) return;
     const Stencil S = make_stencil(a);
     const size_t n = (size_t)a.nx * a.ny;
     double rz = 0.0, rr = 0.0;
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kDsaBlock) void k_dsa_init(DsaArgs a) {
 // p_new = z + beta p_old (formed at the stencil points), q = D p_new; alpha = rz / (p_new . q)
 __global__ __launch_bounds__(kDsaBlock) void k_dsa_apply(DsaArgs a, int par) {
     __shared__ double sh[kDsaBlock];
-    if (a.scal[kDone] != 0.0) return;
+    if ((a.skip && *a.skip) || a.scal[kDone] != 0.0) return;
     const Stencil S = make_stencil(a);
     const double beta = a.scal[kBeta];
     const double* __restrict__ z = a.z;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kDsaBlock) void k_dsa_apply(DsaArgs a, int par) {
 // x += alpha p, r -= alpha q, z = r / diag; beta = rz_new / rz; done when |r| <= tol |r0|
 __global__ __launch_bounds__(kDsaBlock) void k_dsa_update(DsaArgs a, int par) {
     __shared__ double sh[kDsaBlock];
-    if (a.scal[kDone] != 0.0) return;
+    if ((a.skip && *a.skip) || a.scal[kDone] != 0.0) return;
     const double alpha = a.scal[kAlpha];
     const double* __restrict__ p = a.p[par ^ 1];
     const size_t n = (size_t)a.nx * a.ny;
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(kDsaBlock) void k_dsa_update(DsaArgs a, int par) {
 // phi += delta and the four orientation copies of s_e = sigma_s phi / (4 pi) in the sweep layout
 template <typename TS>
 __global__ __launch_bounds__(kDsaBlock) void k_dsa_finish(DsaArgs a) {
+    if (a.skip && *a.skip) return;
     TS* s_e = static_cast<TS*>(a.s_e);
     const size_t n = (size_t)a.nx * a.ny;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {

@@ -345,8 +345,11 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned lon
 template <typename TS, int P>
 __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>* __restrict__ table, SweepLaunch L) {
     __shared__ Shared<TS> sh;
-    __shared__ int inst;
+    __shared__ int inst, skip;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // with a launch counter every workgroup reads the id before the last one to retire advances it
+    const unsigned long long launch_id = L.id_ctr ? __hip_atomic_load(L.id_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                  : L.launch_id;
     for (;;) {
         if (threadIdx.x == 0) {
             sh.task = atomicAdd(&L.ticket[0], 1u);
@@ -358,6 +361,9 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
                 if (L.unit_end[mid] > sh.task) hi = mid; else lo = mid + 1;
             }
             inst = lo;
+            const int* sk = table[lo].skip;
+            skip = (sh.task < L.total_units && sk) ? __hip_atomic_load(sk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                   : 0;
         }
         if (threadIdx.x <= kWaves) {
             sh.prod[threadIdx.x] = 0;
@@ -371,10 +377,12 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
         const unsigned local = n - (k > 0 ? L.unit_end[k - 1] : 0u);
         const int S = (int)(local / (unsigned)a.nd);
         const int d = (int)(local % (unsigned)a.nd);
-        if (w < kWaves) {
+        if (skip) {
+            // the instance's source iteration has stopped: none of its units runs, so none waits
+        } else if (w < kWaves) {
             if ((S * kWaves + w) * 64 < a.nx) compute_wave<TS, P>(a, sh, S, d, w, lane);
         } else if ((S * kWaves) * 64 < a.nx) {
-            helper_wave<TS>(a, L.launch_id, sh, S, d, lane);
+            helper_wave<TS>(a, launch_id, sh, S, d, lane);
         }
         __syncthreads();
         if (threadIdx.x == 0 && sh.stall) atomicOr(a.status, (int)kStatusSweepStall);
@@ -385,6 +393,12 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
         if (prev == (unsigned)L.grid_blocks - 1u) {
             __hip_atomic_store(&L.ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&L.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (L.id_ctr) {
+                // the tags compare the low 32 bits: keep those at 2^31 or above (the host's ids are below)
+                unsigned long long nx = launch_id + 1ull;
+                if ((nx & 0xffffffffull) < (1ull << 31)) nx += 1ull << 31;
+                __hip_atomic_store(L.id_ctr, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }
@@ -399,9 +413,11 @@ void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& 
 template void launch_sweep<double>(hipStream_t, const SweepArgs<double>*, const SweepLaunch&);
 template void launch_sweep<float>(hipStream_t, const SweepArgs<float>*, const SweepLaunch&);
 
+// Host ids stay in [1, 2^31) (the tags compare the low 32 bits; device launch counters use the
+// upper half of that range).
 unsigned long long next_sweep_launch_id() {
     static std::atomic<unsigned long long> id{0};
-    return ++id;
+    return (++id - 1ull) % ((1ull << 31) - 1ull) + 1ull;
 }
 
 }  // namespace dlr

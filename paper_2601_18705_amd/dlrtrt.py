@@ -24,8 +24,9 @@ DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
             "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
-            "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
-            "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc", "dlr_status_string", "dlr_last_error"]
+            "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_batch_set_graphs", "dlr_batch_graph_steps",
+            "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync", "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc",
+            "dlr_status_string", "dlr_last_error"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -106,6 +107,8 @@ def library():
         lib.dlr_batch_release.argtypes = [h, i64]
         lib.dlr_batch_usage.argtypes = [h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)]
         lib.dlr_batch_destroy.argtypes = [h]
+        lib.dlr_batch_set_graphs.argtypes = [h, ctypes.c_int32]
+        lib.dlr_batch_graph_steps.argtypes = [h, ctypes.POINTER(i64)]
         vp = ctypes.c_void_p
         lib.dlr_q1_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                       _dp, _dp, ctypes.c_int32, vp, ctypes.POINTER(h)]
@@ -124,7 +127,8 @@ def library():
                      "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
-                     "dlr_batch_usage", "dlr_batch_destroy", "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
+                     "dlr_batch_usage", "dlr_batch_destroy", "dlr_batch_set_graphs", "dlr_batch_graph_steps",
+                     "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync",
                      "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -263,6 +267,16 @@ class Batch:
         b = ctypes.c_size_t()
         _check(library().dlr_batch_usage(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, int(b.value)
+
+    def set_graphs(self, enable):
+        """0: eager steps only; 1: recorded-graph steps (default); 2..64: at most that many source
+        iterations recorded per step."""
+        _check(library().dlr_batch_set_graphs(self._h, int(enable)))
+
+    def graph_steps(self):
+        n = ctypes.c_int64()
+        _check(library().dlr_batch_graph_steps(self._h, ctypes.byref(n)))
+        return n.value
 
     def close(self):
         if self._h:

@@ -96,3 +96,33 @@ def test_failing_slot_is_isolated():
         assert b.poll() == [sg]
         E, T = b.read(sg)
     assert np.array_equal(E, ref[0]) and np.array_equal(T, ref[1])
+
+
+def test_recorded_steps_equal_alone():
+    """A composition that stays the same runs from recorded graphs with the source iteration
+    decided on the device; every slot's result is still bitwise that of the problem stepped
+    alone, also with at most two recorded source iterations per step, where the FP64 slots
+    (tolerance 1e-14) continue their iteration on the host's decision."""
+    from paper_2601_18705_amd import dlrtrt
+    probs = mixed_problems()
+    nsteps = 5
+    ref = [alone(p, nsteps) for p in probs]
+    for enable in (1, 2):
+        got = {}
+        with dlrtrt.Batch() as b:
+            b.set_graphs(enable)
+            slots = {b.admit(p, nsteps): k for k, p in enumerate(probs)}
+            for _ in range(nsteps):
+                b.advance()
+            for slot in b.poll():
+                got[slots[slot]] = b.read(slot)
+                si = b.read_stats(slot)["si_iters"]
+                assert si >= 1
+            recorded = b.graph_steps()
+        print(f"[batch] recorded-graph steps {recorded} of {nsteps} (at most {enable if enable > 1 else 8} "
+              f"iterations recorded)", flush=True)
+        assert recorded == nsteps - 1          # the first advance meets a new composition
+        assert sorted(got) == list(range(len(probs)))
+        for k in range(len(probs)):
+            assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1]), \
+                f"problem {k}, enable {enable}"
