@@ -346,6 +346,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     E, T = inst.read_fields()
+    shape = inst.sweep_shape()   # chosen by the library's tuner on the warm-up instance
     inst.close()
 
     sweep_bytes = 4 if not args.fp64 else 8
@@ -391,7 +392,8 @@ def main():
         "serving": None,
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3},
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
+                     "launch_shape": {"prefetch_chunks": shape[0], "grid_blocks": shape[1], "chosen_by": "tuner"}},
         "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
         "host": host_info(),
     }

@@ -207,6 +207,19 @@ dlr_status dlr_force_selection(dlr_handle h, const int32_t *sel);
  * DLR_ERR_STATE (poisoned handle), DLR_ERR_HIP. */
 dlr_status dlr_set_dsa(dlr_handle h, int32_t enable, double cg_tol, int32_t cg_max_iter);
 
+/* Launch shape of the instance's transport sweeps (Algorithm 1 step 4): *prefetch = chunks of
+ * loads each compute wavefront keeps in flight (2, 4 or 8), *grid_blocks = persistent
+ * workgroups; both 0 before the first sweep.  Unless set below, the shape is chosen at the first
+ * sweep by timing the candidates (prefetch 2, 4 and, with FP32 sweeps, 8; 256, 512 or 1024
+ * workgroups) on the instance's own data, and kept for the life of the process per grid, number
+ * of swept directions and sweep precision.  The shape changes no arithmetic: results are bitwise
+ * the same for every shape.  Errors: DLR_ERR_ARG (NULL argument). */
+dlr_status dlr_sweep_shape(dlr_handle h, int32_t *prefetch, int32_t *grid_blocks);
+
+/* Fix the launch shape (prefetch 2 or 4, or 8 with FP32 sweeps; 1 <= grid_blocks <= 65535), or
+ * (0, 0): back to the tuner's choice.  Errors: DLR_ERR_ARG (other values). */
+dlr_status dlr_set_sweep_shape(dlr_handle h, int32_t prefetch, int32_t grid_blocks);
+
 /* Free everything.  NULL-safe. */
 dlr_status dlr_destroy(dlr_handle h);
 

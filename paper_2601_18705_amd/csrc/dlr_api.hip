@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <cmath>
 #include <cstdio>
@@ -175,6 +176,7 @@ struct dlr_instance {
     bool device_si = false;         // source iteration decided on the device (graph-recorded steps)
     bool capturing = false;         // launches are being recorded into a graph: no timing events
     bool untimed = false;           // this step's beginning ran from a recorded graph (no step timing)
+    int sw_prefetch = 0, sw_grid = 0;   // sweep launch shape (0: chosen by the tuner at the first sweep)
     void* edge = nullptr;
     unsigned long long* progress = nullptr;
     unsigned* ticket = nullptr;
@@ -525,18 +527,83 @@ void phase_begin(dlr_instance* I) {
     I->sweep_ms_acc = 0.f;
 }
 
-// this instance alone: one sweep launch on its own stream, timed with events
+// ---------------------------------------------------------------------------------------------- sweep shape tuner
+// The launch shape of an instance's sweep -- the chunks of loads each compute wavefront keeps in
+// flight (the register prefetch depth) and the number of persistent workgroups -- is chosen by
+// timing the candidates on the instance's own data at its first sweep, and kept per grid, count
+// of swept directions and precision for the life of the process.  A sweep reads only its inputs,
+// so the timing launches leave the results as they are, and the shape changes no arithmetic.
+struct TuneKey {
+    int nx, ny, nd, bytes;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(nx, ny, nd, bytes) < std::tie(o.nx, o.ny, o.nd, o.bytes);
+    }
+};
+struct SweepShape {
+    int prefetch, grid;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, SweepShape> g_tuned;
+
 template <typename TS>
-void sweep_alone(dlr_instance* I) {
+void sweep_launch(dlr_instance* I, int prefetch, int grid) {
     dlr::SweepLaunch L{};
     L.ninst = 1;
     L.total_units = (unsigned)(I->nsuper * I->nsweep());
     L.unit_end = I->unit_end;
     L.ticket = I->ticket;
     L.launch_id = dlr::next_sweep_launch_id();
-    L.grid_blocks = (int)std::min<unsigned>(L.total_units, I->sn ? 1024u : 512u);
+    L.grid_blocks = (int)std::min<unsigned>(L.total_units, (unsigned)grid);
+    dlr::launch_sweep<TS>(I->stream, reinterpret_cast<const dlr::SweepArgs<TS>*>(I->sweep_rec), L, prefetch);
+}
+
+template <typename TS>
+void sweep_tune(dlr_instance* I) {
+    const TuneKey key{I->nx, I->ny, I->nsweep(), (int)sizeof(TS)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            I->sw_prefetch = it->second.prefetch;
+            I->sw_grid = it->second.grid;
+            return;
+        }
+    }
+    // FP64 with 8 chunks in flight does not fit the register file (it spills)
+    const int pre[3] = {2, 4, 8};
+    const int npre = sizeof(TS) == 4 ? 3 : 2;
+    const int grids[3] = {256, 512, 1024};
+    SweepShape best{4, I->sn ? 1024 : 512};
+    float best_ms = 0.f;
+    bool have = false;
+    for (int a = 0; a < npre; ++a)
+        for (int b = 0; b < 3; ++b) {
+            sweep_launch<TS>(I, pre[a], grids[b]);   // warm-up
+            hip_check(hipEventRecord(I->ev[2], I->stream), "event");
+            sweep_launch<TS>(I, pre[a], grids[b]);
+            sweep_launch<TS>(I, pre[a], grids[b]);
+            hip_check(hipEventRecord(I->ev[3], I->stream), "event");
+            hip_check(hipEventSynchronize(I->ev[3]), "sync");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+            if (!have || ms < best_ms) {
+                best = SweepShape{pre[a], grids[b]};
+                best_ms = ms;
+                have = true;
+            }
+        }
+    I->sw_prefetch = best.prefetch;
+    I->sw_grid = best.grid;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.emplace(key, best);
+}
+
+// this instance alone: one sweep launch on its own stream, timed with events
+template <typename TS>
+void sweep_alone(dlr_instance* I) {
+    if (I->sw_prefetch == 0) sweep_tune<TS>(I);
     hip_check(hipEventRecord(I->ev[2], I->stream), "event");
-    dlr::launch_sweep<TS>(I->stream, reinterpret_cast<const dlr::SweepArgs<TS>*>(I->sweep_rec), L);
+    sweep_launch<TS>(I, I->sw_prefetch, I->sw_grid);
     hip_check(hipEventRecord(I->ev[3], I->stream), "event");
 }
 
@@ -1521,6 +1588,27 @@ dlr_status dlr_destroy(dlr_handle h) {
     dev_free(h->dsa_mem);
     h->arena.release();
     delete h;
+    return DLR_OK;
+}
+
+dlr_status dlr_sweep_shape(dlr_handle h, int32_t* prefetch, int32_t* grid_blocks) {
+    if (!h || !prefetch || !grid_blocks) return fail(DLR_ERR_ARG, "handle or outputs NULL");
+    *prefetch = h->sw_prefetch;
+    *grid_blocks = h->sw_grid;
+    return DLR_OK;
+}
+
+dlr_status dlr_set_sweep_shape(dlr_handle h, int32_t prefetch, int32_t grid_blocks) {
+    if (!h) return fail(DLR_ERR_ARG, "handle is NULL");
+    if (prefetch == 0 && grid_blocks == 0) {
+        h->sw_prefetch = h->sw_grid = 0;   // the tuner chooses (or its earlier choice for this shape)
+        return DLR_OK;
+    }
+    if (!(prefetch == 2 || prefetch == 4 || (prefetch == 8 && h->fp32())))
+        return fail(DLR_ERR_ARG, "prefetch must be 2 or 4 (or 8 with FP32 sweeps)");
+    if (grid_blocks < 1 || grid_blocks > 65535) return fail(DLR_ERR_ARG, "grid_blocks must be in [1, 65535]");
+    h->sw_prefetch = prefetch;
+    h->sw_grid = grid_blocks;
     return DLR_OK;
 }
 

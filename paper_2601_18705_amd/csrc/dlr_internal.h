@@ -175,8 +175,9 @@ struct SweepLaunch {
     // graph still tags every replay apart
     unsigned long long* id_ctr;
 };
+// prefetch: chunks of loads each compute wavefront keeps in flight (2, 4 or 8)
 template <typename TS>
-void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L);
+void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L, int prefetch = 4);
 // next process-wide sweep launch id
 unsigned long long next_sweep_launch_id();
 

@@ -161,7 +161,8 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
     const bool has_next = (strip + 1) * 64 < a.nx;
     const int out_ring = (w < kWaves - 1) ? w + 1 : kWaves;
     const int nch = s.nch;
-    // chunks [0, m0) carry the skewed head (masked), with m0 a multiple of P; nch >= 4 always
+    // chunks [0, m0) carry the skewed head (masked), with m0 a multiple of P; nch >= 4 always, and
+    // with P = 8 a short column (ny < 50) has fewer than m0 chunks: the head loop stops at nch
     const int m0 = (4 + P - 1) / P * P;
 
     TS bs[P][kC], bq[P][kC], be[P][kC];
@@ -235,6 +236,7 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int m = mb + p;
+            if (P > 4 && m >= nch) break;
             TS edgev[kC], ob[kC];
             left_values(m, edgev);
             run_chunk<TS, true>(s, m, bs[p], bq[p], be[p], edgev, mine, ob);
@@ -406,12 +408,17 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
 }  // namespace
 
 template <typename TS>
-void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L) {
-    constexpr int P = 4;
-    hipLaunchKernelGGL((k_sweep<TS, P>), dim3(L.grid_blocks), dim3(64 * (kWaves + 1)), 0, s, table, L);
+void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L, int prefetch) {
+    const dim3 g(L.grid_blocks), b(64 * (kWaves + 1));
+    if (prefetch == 2)
+        hipLaunchKernelGGL((k_sweep<TS, 2>), g, b, 0, s, table, L);
+    else if (prefetch == 8)
+        hipLaunchKernelGGL((k_sweep<TS, 8>), g, b, 0, s, table, L);
+    else
+        hipLaunchKernelGGL((k_sweep<TS, 4>), g, b, 0, s, table, L);
 }
-template void launch_sweep<double>(hipStream_t, const SweepArgs<double>*, const SweepLaunch&);
-template void launch_sweep<float>(hipStream_t, const SweepArgs<float>*, const SweepLaunch&);
+template void launch_sweep<double>(hipStream_t, const SweepArgs<double>*, const SweepLaunch&, int);
+template void launch_sweep<float>(hipStream_t, const SweepArgs<float>*, const SweepLaunch&, int);
 
 // Host ids stay in [1, 2^31) (the tags compare the low 32 bits; device launch counters use the
 // upper half of that range).

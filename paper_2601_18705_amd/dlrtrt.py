@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
 EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
-            "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
+            "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_sweep_shape", "dlr_set_sweep_shape",
+            "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
             "dlr_batch_release", "dlr_batch_usage", "dlr_batch_destroy", "dlr_batch_set_graphs", "dlr_batch_graph_steps",
             "dlr_q1_create", "dlr_q1_sweep", "dlr_q1_sync", "dlr_q1_time", "dlr_q1_destroy", "dlr_q1_sweep_noalloc",
@@ -94,6 +95,8 @@ def library():
         lib.dlr_read_stats.argtypes = [h, ctypes.POINTER(DlrStepStats)]
         lib.dlr_force_selection.argtypes = [h, _ip]
         lib.dlr_set_dsa.argtypes = [h, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
+        lib.dlr_sweep_shape.argtypes = [h, _ip, _ip]
+        lib.dlr_set_sweep_shape.argtypes = [h, ctypes.c_int32, ctypes.c_int32]
         lib.dlr_destroy.argtypes = [h]
         sz = ctypes.c_size_t
         i64 = ctypes.c_int64
@@ -124,7 +127,8 @@ def library():
         lib.dlr_last_error.argtypes = []
         lib.dlr_last_error.restype = ctypes.c_char_p
         for name in ("dlr_set_allocator", "dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
-                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_destroy",
+                     "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_sweep_shape",
+                     "dlr_set_sweep_shape", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
                      "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats", "dlr_batch_release",
                      "dlr_batch_usage", "dlr_batch_destroy", "dlr_batch_set_graphs", "dlr_batch_graph_steps",
@@ -327,6 +331,17 @@ class Instance:
     def set_dsa(self, enable=True, cg_tol=1e-8, cg_max_iter=100):
         """dlr_set_dsa: diffusion synthetic acceleration of the source iteration."""
         _check(library().dlr_set_dsa(self._h, int(bool(enable)), float(cg_tol), int(cg_max_iter)))
+
+    def sweep_shape(self):
+        """dlr_sweep_shape: (prefetch depth, persistent workgroups) of the sweeps; (0, 0) before the first."""
+        p = ctypes.c_int32()
+        g = ctypes.c_int32()
+        _check(library().dlr_sweep_shape(self._h, ctypes.byref(p), ctypes.byref(g)))
+        return p.value, g.value
+
+    def set_sweep_shape(self, prefetch=0, grid_blocks=0):
+        """dlr_set_sweep_shape: a fixed launch shape, or (0, 0) for the tuner's choice."""
+        _check(library().dlr_set_sweep_shape(self._h, int(prefetch), int(grid_blocks)))
 
     def step(self, n_steps=1):
         _check(library().dlr_step(self._h, int(n_steps)))
