@@ -12,6 +12,9 @@ records kept with the repository.  Reads CSV files only; runs nothing.
     python -m paper_2601_18705_amd.profiling traffic-table <fetch counter_collection.csv>
         <write counter_collection.csv> <calibration MiB> <title> <command>...
 
+    python -m paper_2601_18705_amd.profiling mfma <counter_collection.csv> <agent_info.csv>
+        <kernel_stats.csv> <title> <command>...
+
 The kernel name prefix (default k_sweep, the degree-0 sweep) selects the dispatches
 averaged, e.g. "k_q1_sweep<double>" for the FP64 bilinear DG sweep.
 """
@@ -111,12 +114,58 @@ def traffic_table_md(fetch_csv, write_csv, calib_mib, title, commands, min_mb=20
     return "\n".join(out) + "\n"
 
 
+# dense matrix-core peaks of the MI355X (TFLOP/s), by operand type
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
+
+
+def mfma_md(counter_csv, agent_csv, stats_csv, title, commands, kernel_mark="mfma"):
+    """Markdown table of matrix-core use per kernel from one counter run with
+    SQ_INSTS_VALU_MFMA_MOPS_F32, SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and
+    GRBM_GUI_ACTIVE: MFMA flops per dispatch (MOPS x 512), the achieved rate over the kernel's average
+    duration in the kernel-trace run (stats_csv) against the dense peak of its operand type, and the
+    matrix-core busy fraction busy / (GUI_ACTIVE per XCC x SIMDs).  GRBM_GUI_ACTIVE comes summed over
+    the XCCs; the agent record gives their number and the SIMD count."""
+    gpu = [r for r in csv.DictReader(open(agent_csv)) if r.get("Agent_Type", r.get("Type")) == "GPU"][0]
+    n_xcc = int(gpu["Num_Xcc"])
+    simds = int(gpu["Simd_Count"])
+    per = {}
+    for r in csv.DictReader(open(counter_csv)):
+        k = short_name(r["Kernel_Name"])
+        if kernel_mark not in k:
+            continue
+        d = per.setdefault(k, {}).setdefault(r["Dispatch_Id"], {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    avg_ns = {short_name(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    out = [f"# {title}", "", "Commands (from the repository root on an MI355X, ROCm 7.2):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp", *commands, "```", "",
+           f"MFMA flops = MOPS x 512 per dispatch; rate over the average duration of the kernel-trace run; "
+           f"busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {n_xcc} XCC x {simds} SIMDs).  Dense peaks: "
+           + ", ".join(f"{t} {v} TFLOP/s" for t, v in MFMA_PEAK_TFLOPS.items()) + ".", "",
+           "| kernel | dispatches | type | GFLOP per dispatch | average (us) | TFLOP/s | of peak (%) | MFMA busy (%) |",
+           "|---|---:|---|---:|---:|---:|---:|---:|"]
+    for k, ds in per.items():
+        n = len(ds)
+        f32 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) for d in ds.values()) / n * 512.0
+        f64 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for d in ds.values()) / n * 512.0
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in ds.values()) / n
+        gui = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in ds.values()) / n
+        kind, flops = ("F32", f32) if f32 >= f64 else ("F64", f64)
+        t = avg_ns.get(k)
+        rate = flops / (t * 1e-9) / 1e12 if t else float("nan")
+        util = 100.0 * busy / (gui / n_xcc * simds) if gui > 0 else float("nan")
+        out.append(f"| `{k}` | {n} | {kind} | {flops / 1e9:.3f} | {t / 1e3 if t else float('nan'):.1f} | "
+                   f"{rate:.1f} | {100.0 * rate / MFMA_PEAK_TFLOPS[kind]:.1f} | {util:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(kernel_stats_md(argv[1], argv[2], argv[3], argv[4] if len(argv) > 4 else "",
                                          argv[5].split(",") if len(argv) > 5 else ()))
     elif len(argv) >= 6 and argv[0] == "traffic-table":
         sys.stdout.write(traffic_table_md(argv[1], argv[2], float(argv[3]), argv[4], argv[5:]))
+    elif len(argv) >= 6 and argv[0] == "mfma":
+        sys.stdout.write(mfma_md(argv[1], argv[2], argv[3], argv[4], argv[5:]))
     elif len(argv) in (6, 7) and argv[0] == "traffic":
         rec = sweep_traffic(argv[1], argv[2], float(argv[3]), argv[4], *argv[6:7])
         with open(argv[5], "w") as fh:

@@ -100,29 +100,36 @@ def test_failing_slot_is_isolated():
 
 def test_recorded_steps_equal_alone():
     """A composition that stays the same runs from recorded graphs with the source iteration
-    decided on the device; every slot's result is still bitwise that of the problem stepped
+    decided on the device; after every advance (every replay, with the host's own work and
+    synchronisations between them) each slot's fields are bitwise those of the problem stepped
     alone, also with at most two recorded source iterations per step, where the FP64 slots
     (tolerance 1e-14) continue their iteration on the host's decision."""
     from paper_2601_18705_amd import dlrtrt
     probs = mixed_problems()
     nsteps = 5
-    ref = [alone(p, nsteps) for p in probs]
+    ref = []
+    for p in probs:
+        with dlrtrt.Instance(p) as inst:
+            per_step = []
+            for _ in range(nsteps):
+                inst.step(1)
+                per_step.append(inst.read_fields())
+            ref.append(per_step)
     for enable in (1, 2):
-        got = {}
         with dlrtrt.Batch() as b:
             b.set_graphs(enable)
             slots = {b.admit(p, nsteps): k for k, p in enumerate(probs)}
-            for _ in range(nsteps):
+            for step in range(nsteps):
                 b.advance()
-            for slot in b.poll():
-                got[slots[slot]] = b.read(slot)
-                si = b.read_stats(slot)["si_iters"]
-                assert si >= 1
+                for slot, k in slots.items():
+                    E, T = b.read(slot)
+                    assert np.array_equal(E, ref[k][step][0]) and np.array_equal(T, ref[k][step][1]), \
+                        f"problem {k}, step {step}, enable {enable}"
+            done = b.poll()
+            for slot in done:
+                assert b.read_stats(slot)["si_iters"] >= 1
             recorded = b.graph_steps()
         print(f"[batch] recorded-graph steps {recorded} of {nsteps} (at most {enable if enable > 1 else 8} "
               f"iterations recorded)", flush=True)
         assert recorded == nsteps - 1          # the first advance meets a new composition
-        assert sorted(got) == list(range(len(probs)))
-        for k in range(len(probs)):
-            assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1]), \
-                f"problem {k}, enable {enable}"
+        assert sorted(slots[s] for s in done) == list(range(len(probs)))

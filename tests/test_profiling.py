@@ -69,3 +69,43 @@ def test_kernel_stats_exclusion_recomputes_the_shares(tmp_path):
     shares = {line.split("`")[1]: float(line.strip().strip("|").split("|")[-1]) for line in md.splitlines()
               if "`k_" in line}
     assert shares == {"k_sweep<float, 4>": 75.0, "k_svd": 25.0}
+
+
+def test_mfma_table_rates_and_busy_fraction(tmp_path):
+    """Flops = MOPS x 512 per dispatch, the rate over the kernel-trace average duration against the
+    operand type's dense peak, busy = busy cycles / (GUI_ACTIVE summed over XCCs / XCCs x SIMDs)."""
+    proj = "void dlr::(anonymous namespace)::k_project_mfma<2, float, false>(int)"
+    gram = "void dlr::(anonymous namespace)::k_gram_mfma<double, 2>(long)"
+    counters = tmp_path / "mfma.csv"
+    with open(counters, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for disp, name, f32, f64, busy, gui in [(1, proj, 2.0e7, 0.0, 409.6e3, 8.0e3),
+                                                (2, proj, 2.0e7, 0.0, 409.6e3, 8.0e3),
+                                                (3, gram, 0.0, 1.0e6, 1024.0e3, 8.0e3)]:
+            for cname, v in [("SQ_INSTS_VALU_MFMA_MOPS_F32", f32), ("SQ_INSTS_VALU_MFMA_MOPS_F64", f64),
+                             ("SQ_VALU_MFMA_BUSY_CYCLES", busy), ("GRBM_GUI_ACTIVE", gui)]:
+                w.writerow({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": cname, "Counter_Value": v})
+    agent = tmp_path / "agent.csv"
+    with open(agent, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Agent_Type", "Simd_Count", "Num_Xcc"])
+        w.writeheader()
+        w.writerow({"Agent_Type": "CPU", "Simd_Count": 0, "Num_Xcc": 0})
+        w.writerow({"Agent_Type": "GPU", "Simd_Count": 1024, "Num_Xcc": 8})
+    stats = tmp_path / "stats.csv"
+    with open(stats, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "AverageNs"])
+        w.writeheader()
+        w.writerow({"Name": proj, "AverageNs": 200000.0})   # 200 us
+        w.writerow({"Name": gram, "AverageNs": 10000.0})    # 10 us
+    md = profiling.mfma_md(str(counters), str(agent), str(stats), "t", ["cmd"])
+    rows = {line.split("`")[1]: [c.strip() for c in line.strip().strip("|").split("|")] for line in md.splitlines()
+            if "`k_" in line}
+    p = rows["k_project_mfma<2, float, false>"]
+    assert p[1] == "2" and p[2] == "F32"
+    assert float(p[3]) == round(2.0e7 * 512 / 1e9, 3)                  # 10.240 GFLOP
+    rate = 2.0e7 * 512 / 200e-6 / 1e12                                   # 51.2 TFLOP/s
+    assert float(p[5]) == round(rate, 1) and float(p[6]) == round(100 * rate / 157.3, 1)
+    assert float(p[7]) == round(100 * 409.6e3 / (8.0e3 / 8 * 1024), 1)   # 40 % of 1000 cycles x 1024 SIMDs
+    g = rows["k_gram_mfma<double, 2>"]
+    assert g[2] == "F64" and float(g[6]) == round(100 * (1.0e6 * 512 / 10e-6 / 1e12) / 78.6, 1)
