@@ -518,7 +518,8 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
     V [n, r] -> Q [n, r], R [r, r] with V = Q R, Q^T diag(weight) Q = I, R upper
     triangular with R_kk >= 0.  A column whose residual norm is at most
     defect_tol times its own norm is replaced by the next completion vector
-    (orthogonalised twice, skipped when dependent) and gets R_kk = 0.
+    (orthogonalised twice, skipped when dependent) and gets R_kk = 0; r > n raises
+    ValueError, since the completion could never fill the missing columns.
     (The accepted columns are kept as contiguous rows of Qt = Q^T.)
     """
     n, r = V.shape
@@ -544,6 +545,8 @@ def cgs2(V, weight, completion, defect_tol=1e-12, skip_tol=1e-10):
             Qt[k] = v2 / nrm
             R[k, k] = nrm
             continue
+        if k >= n:
+            raise ValueError(f"cgs2: {r} columns do not fit a space of dimension {n}")
         while True:
             u = next(comp)
             un = math.sqrt(ip(u, u))
@@ -651,6 +654,13 @@ def upwind_difference_ops(grid, X):
 def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e-14):
     """One SN-like DLR time step, Algorithm 1 steps 1-9, plus the SVD rotation.
 
+    With p["augment"] set, the augmented variant: step 5 orthonormalises the swept
+    columns together with the old basis X0 (rank 2r, so the old solution lies in the
+    Galerkin space), steps 6-8 run on that basis, and the SVD of step 8 truncates the
+    rank-2r result back to its r largest singular values -- the rank-2r -> r truncation
+    of the paper's PN-like scheme (Sec. 3, the updated solution of rank 2r and its
+    truncated SVD) applied to the SN-like step.
+
     Returns the new state and a stats dict (SI iterations, DEIM picks/margins,
     singular values, DEIM weights)."""
     grid = grid_of(p)
@@ -718,6 +728,14 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
     # 5. orthonormalise the swept columns: Psi = X R
     X, _ = cgs2(Psi.T, np.full(grid.ncell, A), spatial_completion(grid))
     X_pre = X
+    augment = bool(p.get("augment"))
+    if augment:
+        # the swept basis and the old one, orthonormalised together: 2r columns
+        if 2 * r > min(quad.n, grid.ncell):
+            raise ValueError("augmented step needs 2 r <= min(ordinates, cells)")
+        X, _ = cgs2(np.hstack([X, X0]), np.full(grid.ncell, A), spatial_completion(grid))
+
+    X_gal = X
 
     # 6. project the old solution onto the new spatial basis: Lt0_j = sum_i L0_i <X0_i, X_j>
     P = ip(X0, X)
@@ -729,6 +747,10 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
     # 8. orthonormalise L = W S^T in the quadrature inner product, then rotate by the SVD of S
     W, R = cgs2(L, quad.w, angular_completion(quad))
     X, S, W = svd_rotate(X, R.T, W)
+    sig_all = np.diag(S).copy()
+    if augment:
+        # truncated SVD: the r largest singular values and their vectors
+        X, S, W = X[:, :r], S[:r, :r], W[:, :r]
     sig = np.diag(S).copy()
 
     # 9. temperature update with the new mean intensity
@@ -737,10 +759,11 @@ def dlr_step(p, quad, st, forced_sel=None, tol=None, max_iter=None, lstep_tol=1e
     new.T = temperature_update(p, T0, lin, phi_new)
     G = S @ W.T                          # psi on any set of cells = X[cells] G
     inflow, outflow = boundary_flows(p, grid, quad, lambda side: (X[side_cells(grid, side)] @ G).T)
-    stats = {"si_iters": it, "sel": sel, "margins": margins, "deim_edge": edges, "sigma": sig, "cw": cw,
+    stats = {"si_iters": it, "sel": sel, "margins": margins, "deim_edge": edges, "sigma": sig,
+             "sigma_all": sig_all, "cw": cw,
              "inflow": inflow, "outflow": outflow, "energy": total_energy(p, grid, new.T, phi_new),
              "phi": phi_new, "sum_abs_cw_over_4pi": float(np.abs(cw).sum() / FOUR_PI),
-             "Psi": Psi, "Psi0": Psi0, "X_pre": X_pre, "L": L, "lin": lin, "Lt0": Lt0}
+             "Psi": Psi, "Psi0": Psi0, "X_pre": X_pre, "X_gal": X_gal, "L": L, "lin": lin, "Lt0": Lt0}
     return new, stats
 
 

@@ -474,16 +474,9 @@ def _apply_transport(p, grid, mu, eta, sigma_t, u):
     return out.ravel() + sigma_t * u
 
 
-def test_l_step_is_galerkin_projection():
-    """L from the L-step makes the residual of the transport equation, applied
-    to psi_q = X L_q by a stencil, orthogonal to every X_i."""
-    p = _warm_tiny(nx=5, ny=4, npol=2, naz=8, rank=5)
-    quad = O.quadrature(p["n_polar"], p["n_azim"])
-    grid = O.grid_of(p)
-    st = O.dlr_initial_state(p, quad)
-    st, _ = O.dlr_step(p, quad, st)
-    _, stats = O.dlr_step(p, quad, st)
-    X, L, lin, Lt0 = stats["X_pre"], stats["L"], stats["lin"], stats["Lt0"]
+def _galerkin_residual(p, grid, quad, X, L, lin, Lt0):
+    """Largest scaled X-projection of the transport residual of psi_q = X L_q,
+    applied by a stencil; zero when L solves the Galerkin system on span(X)."""
     A = grid.area
     phi_L = X @ (quad.w @ L)
     psi0 = X @ Lt0.T   # projection of the old solution; only its X-components enter
@@ -501,7 +494,19 @@ def test_l_step_is_galerkin_projection():
         proj = A * X.T @ res
         scale = A * np.abs(X.T) @ (np.abs(lin.sigma_t * u) + np.abs(lin.q))
         worst = max(worst, float(np.max(np.abs(proj) / scale)))
-    assert worst < 1e-12
+    return worst
+
+
+def test_l_step_is_galerkin_projection():
+    """L from the L-step makes the residual of the transport equation, applied
+    to psi_q = X L_q by a stencil, orthogonal to every X_i."""
+    p = _warm_tiny(nx=5, ny=4, npol=2, naz=8, rank=5)
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    grid = O.grid_of(p)
+    st = O.dlr_initial_state(p, quad)
+    st, _ = O.dlr_step(p, quad, st)
+    _, stats = O.dlr_step(p, quad, st)
+    assert _galerkin_residual(p, grid, quad, stats["X_pre"], stats["L"], stats["lin"], stats["Lt0"]) < 1e-12
 
 
 # ============================================================================ DEIM, QR, SVD
@@ -609,3 +614,93 @@ def test_sn_positivity_and_mirror_symmetry():
     assert np.max(np.abs(f - mirrored)) < 1e-14 * f.max()
     T = st.T.reshape(12, 12)
     assert np.max(np.abs(T - T[::-1])) < 1e-14
+
+
+# ============================================================================ augmented basis (rank 2r -> r)
+
+def _augmented(p):
+    q = dict(p)
+    q["augment"] = True
+    return q
+
+
+@pytest.mark.parametrize("rank", [1, 2, 4])
+def test_augmented_infinite_medium_matches_closed_form(rank):
+    """The uniform isotropic state has rank one, so the truncation loses nothing and
+    the augmented step follows the same scalar recurrence as plain SN."""
+    p, Tm = _infinite_medium(rank=rank, nsteps=4)
+    p = _augmented(p)
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    st = O.dlr_initial_state(p, quad)
+    st.T = Tm.copy()
+    ref = _closed_form_recurrence(0.5, 1.0, 1.0, 1.0, p["dt"], nsteps=4)
+    for n in range(4):
+        st, stats = O.dlr_step(p, quad, st)
+        assert st.X.shape[1] == rank and stats["X_gal"].shape[1] == 2 * rank
+        assert np.max(np.abs(st.T / ref[n][0] - 1)) < 1e-13
+        assert np.max(np.abs(stats["phi"] / ref[n][1] - 1)) < 1e-13
+
+
+def _warm_augmented(rank=3, nsteps=2):
+    p = _augmented(_warm_tiny(nx=5, ny=4, npol=2, naz=8, rank=rank))
+    quad = O.quadrature(p["n_polar"], p["n_azim"])
+    st = O.dlr_initial_state(p, quad)
+    for _ in range(nsteps - 1):
+        st, _ = O.dlr_step(p, quad, st)
+    return p, quad, O.grid_of(p), st
+
+
+def test_augmented_basis_holds_the_old_solution():
+    """With X0 inside the Galerkin space, projecting the old intensity onto it is
+    exact: X_gal Lt0^T = X0 S0 W0^T.  The plain basis does not have this property,
+    which the second half checks so that the pin can tell the two apart."""
+    p, quad, grid, st = _warm_augmented()
+    old = st.X @ st.S @ st.W.T
+    _, stats = O.dlr_step(p, quad, st)
+    Xg = stats["X_gal"]
+    assert np.max(np.abs(grid.area * Xg.T @ Xg - np.eye(Xg.shape[1]))) < 1e-13
+    assert rel(Xg @ stats["Lt0"].T, old) < 1e-13
+    q = dict(p)
+    q["augment"] = False
+    _, plain = O.dlr_step(q, quad, st)
+    assert rel(plain["X_gal"] @ plain["Lt0"].T, old) > 1e-6
+
+
+def test_augmented_l_step_is_galerkin_projection_on_2r_columns():
+    p, quad, grid, st = _warm_augmented()
+    _, stats = O.dlr_step(p, quad, st)
+    assert stats["L"].shape == (quad.n, 2 * st.X.shape[1])
+    assert _galerkin_residual(p, grid, quad, stats["X_gal"], stats["L"], stats["lin"], stats["Lt0"]) < 1e-12
+
+
+def test_augmented_truncation_is_the_best_weighted_rank_r_approximation():
+    """Eckart-Young in the discrete inner product: the new X S W^T is the best
+    rank-r approximation of the rank-2r Galerkin result X_gal L^T, computed here by
+    one library SVD of the weighted matrix sqrt(A) psi diag(sqrt(w))."""
+    p, quad, grid, st = _warm_augmented(rank=3, nsteps=3)
+    r = st.X.shape[1]
+    new, stats = O.dlr_step(p, quad, st)
+    psi2r = stats["X_gal"] @ stats["L"].T                        # [ncell, nq]
+    sa, sw = math.sqrt(grid.area), np.sqrt(quad.w)
+    U, s, Vt = np.linalg.svd(sa * psi2r * sw[None, :], full_matrices=False)
+    best = (U[:, :r] * s[:r]) @ Vt[:r] / sa / sw[None, :]
+    got = new.X @ new.S @ new.W.T
+    assert rel(got, best) < 1e-12
+    assert np.allclose(stats["sigma_all"], s[:2 * r], rtol=1e-11, atol=1e-14 * s[0])
+    assert np.all(s[2 * r:] <= 1e-12 * s[0])                     # the Galerkin result has rank 2r
+    assert s[r] > 1e-8 * s[0]                                    # and the truncation is not empty
+    err = math.sqrt(grid.area) * np.linalg.norm((psi2r - got) * sw[None, :])
+    assert abs(err - np.linalg.norm(s[r:])) < 1e-10 * s[0]
+    assert np.max(np.abs(grid.area * new.X.T @ new.X - np.eye(r))) < 1e-13
+    assert np.max(np.abs(new.W.T @ (quad.w[:, None] * new.W) - np.eye(r))) < 1e-13
+
+
+def test_augmented_rank_limit_and_space_exhaustion_raise():
+    q = _augmented(_warm_tiny(nx=5, ny=4, npol=2, naz=4, rank=5))   # 2 r = 10 > 8 ordinates
+    quad8 = O.quadrature(2, 4)
+    st8 = O.dlr_initial_state(q, quad8)
+    with pytest.raises(ValueError):
+        O.dlr_step(q, quad8, st8)
+    rng = np.random.default_rng(0)
+    with pytest.raises(ValueError):
+        O.cgs2(rng.standard_normal((4, 6)), np.ones(4), O.angular_completion(quad8))
