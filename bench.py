@@ -163,6 +163,37 @@ def sn_leg(workload, precision, si_tol, steps, dlr_steps_per_s):
             "dlr_speedup_steps_per_s": dlr_steps_per_s / (steps / wall)}
 
 
+def augmented_leg(workload, precision, si_tol, steps, plain_step_wall):
+    """The augmented-basis variant on the same problem and precision: the Galerkin space of the step
+    holds the swept columns and the old basis (2r columns) and the SVD truncates back to rank r.
+    Steps 3..steps+2 are timed (after two untimed ones), beside the plain step's same steps."""
+    import torch
+    from paper_2601_18705_amd import dlrtrt
+    p = make_problem(workload)
+    p["precision"], p["si_tol"] = precision, si_tol
+    N, r = p["nx"] * p["ny"], p["rank"]
+    with dlrtrt.Instance(p, method="augmented") as inst:
+        inst.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ca, dev_ms, si = 0, 0.0, []
+        for _ in range(steps):
+            inst.step(1)
+            st = inst.read_stats()
+            ca += st["si_iters"] * N * r
+            dev_ms += st["step_ms"]
+            si.append(int(st["si_iters"]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    same = plain_step_wall[2:2 + steps]
+    plain = len(same) / sum(same) if len(same) == steps else None
+    return {"galerkin_rank": 2 * r, "steps": f"3..{2 + steps}", "steps_per_s": steps / wall,
+            "cell_angle_updates_per_s": ca / wall, "device_ms_per_step": dev_ms / steps,
+            "si_iterations_per_step": sum(si) / steps,
+            "plain_steps_per_s_same_steps": plain,
+            "cost_vs_plain": (plain / (steps / wall)) if plain else None}
+
+
 def q1_leg(n, nd, reps):
     """The bilinear (Q1) DG sweep operator on its own: n x n cells, nd directions, sigma_t of
     the random medium plus 1/(c dt), FP32 and FP64, inputs resident in HBM."""
@@ -269,6 +300,8 @@ def main():
     ap.add_argument("--fp64", action="store_true", help="plain FP64 path (sweeps in FP64, SI tol 1e-14)")
     ap.add_argument("--fp64-steps", type=int, default=10,
                     help="steps of the FP64-sweep comparison leg at the same SI tolerance (0 = skip)")
+    ap.add_argument("--aug-steps", type=int, default=20,
+                    help="steps of the augmented-basis variant on the same workload (0 = skip)")
     ap.add_argument("--sn-steps", type=int, default=3,
                     help="steps of the plain SN comparison leg over every ordinate (0 = skip)")
     ap.add_argument("--q1-reps", type=int, default=20,
@@ -413,6 +446,9 @@ def main():
                                  "si_tol": p64["si_tol"],
                                  "fp32_steps_per_s_same_steps": f32_early,
                                  "fp32_speedup": (f32_early / (args.fp64_steps / w64)) if f32_early else None}
+    if args.aug_steps > 0:
+        print("[bench] augmented-basis leg", file=sys.stderr, flush=True)
+        out["augmented_leg"] = augmented_leg(args.workload, p["precision"], p["si_tol"], args.aug_steps, step_wall)
     if args.sn_steps > 0:
         print("[bench] plain SN leg", file=sys.stderr, flush=True)
         out["plain_sn_leg"] = sn_leg(args.workload, p["precision"], p["si_tol"], args.sn_steps,

@@ -144,6 +144,24 @@ typedef struct {
  * (reflecting walls), DLR_ERR_OOM, DLR_ERR_HIP.  *out is NULL on error. */
 dlr_status dlr_create(const dlr_problem *prob, void *hip_stream, dlr_handle *out);
 
+/* Create an instance of the augmented-basis variant of the SN-like step.  Each
+ * step orthonormalises the r swept columns together with the old spatial basis
+ * X0, so the Galerkin space of the L-step has 2r columns and holds the old
+ * solution exactly; the L-step, the angular QR and the SVD of S run at rank 2r,
+ * and the SVD result is truncated back to its r largest singular values (the
+ * rank-2r representation of Sec. 3 rounded back to rank r, applied to the
+ * SN-like step).  After a step the state is X = Xa Q, S = R, W = Wq V_r, where
+ * Xa is the 2r-column basis, Wq S^T its angular factor, S = U Sigma V^T, and
+ * (U Sigma)_r = Q R (Q with orthonormal columns; a column of a zero singular
+ * value is completed with the unit vector of largest remainder, R_kk = 0).  The
+ * temperature update, the energy and the outflow use the truncated state.
+ * The handle takes every call of dlr_create's handles except batch admission;
+ * dlr_read_factors returns rank-r factors as usual.  Requires 2 rank <= min(64,
+ * n_polar * n_azim, nx * ny).  Device memory: the spatial bases take 4r planes
+ * of cells (against 2r), the per-ordinate L-step matrices (2r)^2 doubles per
+ * ordinate.  Errors as dlr_create; DLR_ERR_ARG when the rank condition fails. */
+dlr_status dlr_create_augmented(const dlr_problem *prob, void *hip_stream, dlr_handle *out);
+
 /* Create a plain discrete-ordinates (SN) instance of the same problem: the
  * full-rank method the DLR step approximates (Sec. 2: backward Euler with the
  * linearised emission, source iteration on the scalar flux, every ordinate of

@@ -132,7 +132,10 @@ constexpr int kPinnedDoubles = kPinnedNorm + 2 + 2 * dlr::kMaxRank;   // + energ
 struct dlr_instance {
     // ---- problem (host copies)
     bool sn = false;   // plain discrete ordinates (every ordinate swept, no factors)
-    int nx = 0, ny = 0, N = 0, npol = 0, naz = 0, nq = 0, r = 0, prec = 0;
+    // augmented basis: the step's Galerkin space is spanned by the swept columns and the old basis
+    // (ra = 2r columns) and the SVD truncates the result back to rank r; otherwise ra = r
+    bool augment = false;
+    int nx = 0, ny = 0, N = 0, npol = 0, naz = 0, nq = 0, r = 0, ra = 0, prec = 0;
     double x0 = 0, x1 = 0, y0 = 0, y1 = 0, hx = 0, hy = 0, area = 0, dt = 0, c = 0, a = 0;
     double si_tol = 0, tie = 0;
     int si_max_iter = 0;
@@ -163,6 +166,7 @@ struct dlr_instance {
     double *D = nullptr, *sig_s = nullptr, *q = nullptr, *sig_t = nullptr;
     float* sig_t32 = nullptr;
     double *X = nullptr, *Xn = nullptr;
+    double* Va = nullptr;   // augmented: [swept basis | X] (2r planes; X is its second half)
     double *S = nullptr, *Sn = nullptr;
     double *W = nullptr, *Wt = nullptr, *Wq = nullptr, *L = nullptr;
     void *psi = nullptr, *src0 = nullptr, *s_e = nullptr, *psi_cm = nullptr;
@@ -267,6 +271,7 @@ struct dlr_instance {
     void carve(Arena& A) {
         if (sn) return carve_sn(A);
         const size_t n = (size_t)N, R = (size_t)r, Q = (size_t)nq;
+        const size_t RA = (size_t)ra;   // Galerkin rank of the step's dense work
         mu = A.take<double>(Q);
         eta = A.take<double>(Q);
         w = A.take<double>(Q);
@@ -279,14 +284,19 @@ struct dlr_instance {
         q = A.take<double>(n);
         sig_t = fp32() ? nullptr : A.take<double>(4 * ldg);
         sig_t32 = fp32() ? A.take<float>(4 * ldg) : nullptr;
-        X = A.take<double>(R * n);
-        Xn = A.take<double>(R * n);
+        if (augment) {
+            Va = A.take<double>(2 * R * n);
+            X = Va ? Va + R * n : nullptr;
+        } else {
+            X = A.take<double>(R * n);
+        }
+        Xn = A.take<double>(RA * n);
         S = A.take<double>(R * R);
-        Sn = A.take<double>(R * R);
-        W = A.take<double>(R * Q);
-        Wt = A.take<double>(R * Q);
-        Wq = A.take<double>(R * Q);
-        L = A.take<double>(R * Q);
+        Sn = A.take<double>(RA * RA);
+        W = A.take<double>(RA * Q);   // planes past r stay zero (the L-step reads ra planes of W0)
+        Wt = A.take<double>(RA * Q);
+        Wq = A.take<double>(RA * Q);
+        L = A.take<double>(RA * Q);
         psi = A.take<char>(R * ldg * sweep_bytes());
         src0 = A.take<char>(R * ldg * sweep_bytes());
         s_e = A.take<char>(4 * ldg * sweep_bytes());
@@ -317,21 +327,21 @@ struct dlr_instance {
         norm_out = A.take<double>(4);
         energy_out = A.take<double>(2);
         counters = A.take<unsigned>(8);
-        Gm = A.take<double>(R * R);
-        Ra = A.take<double>(R * R);
-        R1 = A.take<double>(R * R);
-        R1i = A.take<double>(R * R);
-        R2 = A.take<double>(R * R);
-        R2i = A.take<double>(R * R);
-        ops = A.take<double>(12 * R * R + 10 * R);
-        Binv = A.take<double>(Q * R * R);
-        yv = A.take<double>(Q * R);
-        red = A.take<double>((size_t)red_blocks * (R * R + R));
-        vv = A.take<double>(R);
-        Vsvd = A.take<double>(R * R);
-        beta = A.take<double>(R);
-        coef = A.take<double>(R);
-        gside = A.take<double>(4 * R);
+        Gm = A.take<double>(RA * RA);
+        Ra = A.take<double>(RA * RA);
+        R1 = A.take<double>(RA * RA);
+        R1i = A.take<double>(RA * RA);
+        R2 = A.take<double>(RA * RA);
+        R2i = A.take<double>(RA * RA);
+        ops = A.take<double>(12 * RA * RA + 10 * RA);
+        Binv = A.take<double>(Q * RA * RA);
+        yv = A.take<double>(Q * RA);
+        red = A.take<double>((size_t)red_blocks * (RA * RA + RA));
+        vv = A.take<double>(RA);
+        Vsvd = A.take<double>(RA * RA);
+        beta = A.take<double>(RA);
+        coef = A.take<double>(RA);
+        gside = A.take<double>(4 * RA);
         status = A.take<int>(4);
     }
 };
@@ -651,10 +661,12 @@ dlr_status si_check(dlr_instance* I) {
 template <typename TS>
 void phase_end(dlr_instance* I) {
     hipStream_t s = I->stream;
-    const int N = I->N, r = I->r, nq = I->nq;
+    const int N = I->N, r = I->r, nq = I->nq, rg = I->ra;
     const double cdt = I->c * I->dt;
     TS* psi = static_cast<TS*>(I->psi);
     TS* psi_cm = static_cast<TS*>(I->psi_cm);
+    // the orthonormal swept basis: the new X, or with the augmented basis the first half of Va
+    double* Xq = I->augment ? I->Va : I->Xn;
     // 5. X from the swept columns: Cholesky QR (column-scaled) in the cell-area inner product; the
     // second pass re-orthonormalises in place unless the first already left the Gram matrix within
     // tol of the identity (1e-11 with FP64 sweeps, 1e-8 with FP32 sweeps: X then differs from the
@@ -662,20 +674,35 @@ void phase_end(dlr_instance* I) {
     dlr::launch_psi_to_cm<TS>(s, I->nx, I->ny, r, psi, I->ldg, I->sel_mu, I->sel_eta, psi_cm, I->ld);
     dlr::launch_gram<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
-    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, I->Xn);
-    dlr::launch_gram<double>(s, N, r, I->Xn, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+    dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, Xq);
+    dlr::launch_gram<double>(s, N, r, Xq, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
     dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3,
                      I->fp32() ? 1e-8 : 1e-11);
-    dlr::launch_trmm_inplace(s, N, r, I->Xn, I->R2i, I->status + 3);
+    dlr::launch_trmm_inplace(s, N, r, Xq, I->R2i, I->status + 3);
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
-    dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, I->Xn,
+    dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, Xq,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
-    // 6-7. projections on the new basis and the L-step for every ordinate
-    dlr::launch_project(s, I->nx, I->ny, r, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj,
-                        I->prec == DLR_FP32_SWEEP_BF16_PROJ ? 16 : (I->fp32() ? 32 : 64));
-    dlr::launch_project_finalize(s, r, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops);
+    if (I->augment) {
+        // 5 (augmented basis). Va = [swept basis | X0] (contiguous planes) -> Xn, 2r orthonormal
+        // columns whose span holds the old solution: the same Cholesky QR twice, and the CGS2 with
+        // spatial completion when X0 has columns (nearly) inside the swept span
+        dlr::launch_gram<double>(s, N, rg, I->Va, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+        dlr::launch_chol(s, rg, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
+        dlr::launch_trmm<double>(s, N, rg, I->Va, (size_t)N, I->R1i, I->Xn);
+        dlr::launch_gram<double>(s, N, rg, I->Xn, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+        dlr::launch_chol(s, rg, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3, 1e-11);
+        dlr::launch_trmm_inplace(s, N, rg, I->Xn, I->R2i, I->status + 3);
+        dlr::launch_cgs2<double>(s, N, rg, I->Va, (size_t)N, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr,
+                                 I->Xn, I->R1, I->status, dlr::kStatusQrBreakdownX, I->status,
+                                 dlr::kStatusNoCompletion);
+    }
+    // 6-7. projections on the new basis (rg columns; the old basis X has r) and the L-step for every
+    // ordinate
+    dlr::launch_project(s, I->nx, I->ny, rg, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj,
+                        I->prec == DLR_FP32_SWEEP_BF16_PROJ ? 16 : (I->fp32() ? 32 : 64), r);
+    dlr::launch_project_finalize(s, rg, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops, r);
     dlr::LstepArgs la{};
-    la.nq = nq; la.r = r; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;
+    la.nq = nq; la.r = rg; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;
     la.inv_cdt = 1.0 / cdt;
     for (int k = 0; k < 4; ++k) la.psib[k] = I->psib[k];
     la.Binv = I->Binv; la.y = I->yv; la.red_partials = I->red; la.red_blocks = I->red_blocks; la.v = I->vv;
@@ -683,15 +710,28 @@ void phase_end(dlr_instance* I) {
     dlr::launch_lstep(s, la);
     // 8. L = W S^T in the quadrature inner product: Cholesky QR twice, R = R2 R1; the CGS2 with
     // angular completion recomputes W and R on the device when a pivot flagged near-dependent columns
-    dlr::launch_gram<double>(s, nq, r, I->L, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
-    dlr::launch_trmm<double>(s, nq, r, I->L, (size_t)nq, I->R1i, I->Wt);
-    dlr::launch_gram<double>(s, nq, r, I->Wt, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
-    dlr::launch_trmm<double>(s, nq, r, I->Wt, (size_t)nq, I->R2i, I->Wq);
-    dlr::launch_small_matmul(s, r, I->R2, I->R1, I->Ra);
-    dlr::launch_cgs2<double>(s, nq, r, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
+    dlr::launch_gram<double>(s, nq, rg, I->L, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_chol(s, rg, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_trmm<double>(s, nq, rg, I->L, (size_t)nq, I->R1i, I->Wt);
+    dlr::launch_gram<double>(s, nq, rg, I->Wt, (size_t)nq, I->w, 1.0, I->partials, I->nb_gram_ang, I->Gm);
+    dlr::launch_chol(s, rg, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownW);
+    dlr::launch_trmm<double>(s, nq, rg, I->Wt, (size_t)nq, I->R2i, I->Wq);
+    dlr::launch_small_matmul(s, rg, I->R2, I->R1, I->Ra);
+    dlr::launch_cgs2<double>(s, nq, rg, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
                              I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
+    if (I->augment) {
+        // 8 (end, augmented basis). SVD of the 2r x 2r S = Ra^T and truncation to its r largest singular
+        // values: with (U Sigma)_r = Q R, the new state is X = Xn Q, S = R, W = Wq V_r.  The temperature
+        // update then takes the mean intensity and outflow of the truncated state.
+        dlr::launch_svd(s, rg, I->Ra, I->Vsvd, I->Sn, I->status);
+        dlr::launch_trunc(s, rg, r, I->Sn, I->R1, I->S);
+        dlr::launch_gemm_tall(s, N, rg, r, I->Xn, I->R1, r, I->X);
+        dlr::launch_rmul_rect(s, nq, rg, r, I->Wq, I->Vsvd, rg, I->W);
+        dlr::launch_wsum(s, nq, r, I->W, I->w, I->S, I->beta, I->coef, I->mu, I->eta, I->gside, false);
+        dlr::launch_tupdate(s, tupdate_args(I, I->X, I->gside), I->nb_cells);
+        if (!I->capturing) hip_check(hipEventRecord(I->ev[1], s), "event");
+        return;
+    }
     // 9. temperature update with the mean intensity of the new factors, energy sum and outflow.  The
     // state is psi = Xn Ra^T Wq^T; the SVD of S = Ra^T only rotates W and S (S' W'^T = Ra^T Wq^T), so
     // the mean intensity coefficients and the outflow side vectors are formed from (Wq, Ra^T), and the
@@ -867,10 +907,12 @@ void refresh_phi(dlr_instance* I) {
 }
 
 // Problem fields, launch shapes and the quadrature of a new instance (no device work).
-void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool sn = false) {
+void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool sn = false, bool augment = false) {
     I->sn = sn;
+    I->augment = augment && !sn;
     I->nx = p->nx; I->ny = p->ny; I->N = p->nx * p->ny; I->npol = p->n_polar; I->naz = p->n_azim;
     I->nq = p->n_polar * p->n_azim; I->r = sn ? 0 : p->rank; I->prec = p->precision;
+    I->ra = I->augment ? 2 * I->r : I->r;
     I->x0 = p->x0; I->x1 = p->x1; I->y0 = p->y0; I->y1 = p->y1;
     I->hx = (p->x1 - p->x0) / p->nx; I->hy = (p->y1 - p->y0) / p->ny; I->area = I->hx * I->hy;
     I->dt = p->dt; I->c = p->c; I->a = p->a;
@@ -898,8 +940,9 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     // temperature update: about four blocks per CU keep enough of the r plane loads in flight
     // (one block per CU left the kernel latency-bound)
     I->nb_cells = (int)std::max<long>(1, std::min<long>(((long)I->N + 255) / 256, 1024));
-    const size_t rr = (size_t)I->r * I->r;
-    I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_proj * (5 * rr + 5 * I->r),
+    const size_t rr = (size_t)I->ra * I->ra;
+    I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_gram_ang * rr,
+                                  (size_t)I->nb_proj * (5 * rr + 5 * I->ra),
                                   (size_t)I->nb_cells * 2, (size_t)I->nb_phi * 2, (size_t)(sn ? 1024 : 0)});
     dlr::build_quadrature(I->npol, I->naz, I->h_mu, I->h_eta, I->h_w);
     // constant terms of the energy balance: the inflow power (each inflow face takes
@@ -1269,16 +1312,21 @@ const char* dlr_status_string(dlr_status s) {
 
 const char* dlr_last_error(void) { return g_last_error.c_str(); }
 
-dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
+namespace {
+
+dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, bool augment) {
     if (!out) return fail(DLR_ERR_ARG, "out is NULL");
     *out = nullptr;
     g_last_error.clear();
     const dlr_status v = validate(p);
     if (v != DLR_OK) return v;
+    if (augment && (2LL * p->rank > dlr::kMaxRank || 2LL * p->rank > (long long)p->n_polar * p->n_azim ||
+                    2LL * p->rank > (long long)p->nx * p->ny))
+        return fail(DLR_ERR_ARG, "the augmented basis needs 2 rank <= min(64, ordinates, cells)");
     dlr_instance* I = new (std::nothrow) dlr_instance();
     if (!I) return fail(DLR_ERR_OOM, "host allocation failed");
     try {
-        init_fields(I, p, static_cast<hipStream_t>(hip_stream));
+        init_fields(I, p, static_cast<hipStream_t>(hip_stream), false, augment);
         const dlr_status am = allocate_instance(I);
         if (am != DLR_OK) {
             delete I;
@@ -1311,6 +1359,23 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
         upload(I->X, X.data(), X.size() * sizeof(double));
         upload(I->S, S.data(), S.size() * sizeof(double));
         upload(I->W, W.data(), W.size() * sizeof(double));
+        if (augment) {
+            // The augmented Galerkin space takes the whole span of the old basis, so the completion
+            // of the rank-one initial state is part of the method here (the plain step meets those
+            // columns only through zero entries of S): X = CGS2 of [B(T_init) | 0 ...] with the
+            // graded spatial monomials filling the zero columns, as the cgs2 fallback does.
+            hip_check(hipMemsetAsync(I->Xn, 0, (size_t)I->r * n * sizeof(double), I->stream), "clear");
+            hip_check(hipMemcpyAsync(I->Xn, I->X, n * sizeof(double), hipMemcpyDeviceToDevice, I->stream), "copy");
+            dlr::launch_cgs2<double>(I->stream, (long)n, I->r, I->Xn, n, nullptr, I->area, 0, I->nx, I->ny, nullptr,
+                                     nullptr, I->X, I->R1, nullptr, 0, I->status, dlr::kStatusNoCompletion);
+            int st0 = 0;
+            hip_check(hipMemcpyAsync(&st0, I->status, sizeof(int), hipMemcpyDeviceToHost, I->stream), "status");
+            hip_check(hipStreamSynchronize(I->stream), "sync");
+            if (st0 != 0) {
+                dlr_destroy(I);
+                return fail(DLR_ERR_NUMERIC, "no spatial completion of the initial basis");
+            }
+        }
         refresh_phi(I);
         I->s_is_usigma = true;   // S = diag(s, 0, ...)
         hip_check(hipDeviceSynchronize(), "sync");
@@ -1320,6 +1385,16 @@ dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
     }
     *out = I;
     return DLR_OK;
+}
+
+}  // namespace
+
+dlr_status dlr_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
+    return create_dlr(p, hip_stream, out, false);
+}
+
+dlr_status dlr_create_augmented(const dlr_problem* p, void* hip_stream, dlr_handle* out) {
+    return create_dlr(p, hip_stream, out, true);
 }
 
 dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out) {

@@ -226,16 +226,23 @@ void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv,
 void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip);
 template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X);
+// X = V M for a general rin x rout matrix M (row-major, leading dimension ldm): n x rin column-major V
+// (planes of n cells) -> n x rout X, rin <= 64, rout <= 32; X must not overlap V
+void launch_gemm_tall(hipStream_t s, int n, int rin, int rout, const double* V, const double* M, int ldm,
+                      double* X);
 // Raw projection sums per block, [nblocks][5 r^2 + 5 r] (layout in k_mfma.hip); the matrix sums use
 // FP64 MFMA operands (operand_bits 64), FP32 operands (32) or BF16 operands (16), the last two with
-// FP32 accumulation per block; the vector sums and the sum over blocks are FP64.
+// FP32 accumulation per block; the vector sums and the sum over blocks are FP64.  X0 has r0 columns
+// (r0 < 0: r); the rows of <X0_i, X_j> past r0 are zero.
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits);
+                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits,
+                    int r0 = -1);
 // raw[o] = area * sum over blocks of partials[b][o]
 void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw);
-// Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r]
+// Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r];
+// S0 is r0 x r0 (r0 < 0: r) and the rows of G past r0 are zero.
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
-                             double inv_cdt, const double* S0, double* ops);
+                             double inv_cdt, const double* S0, double* ops, int r0 = -1);
 
 // ----------------------------------------------------------------------------- small dense FP64 work
 // DEIM exchange area: per column two exchanges among up to 64 workgroups (double-buffered),
@@ -300,6 +307,15 @@ void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const do
                  int flag_mask, int* status, int status_code);
 // X[k][c] = sum_j V[j][c] M[j][k] for a [r][n] column-major V (general r x r right multiply)
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X);
+// the same with rin input planes, rout output planes and M of leading dimension ldm
+void launch_rmul_rect(hipStream_t s, int n, int rin, int rout, const double* V, const double* M, int ldm,
+                      double* X);
+// Truncation of an SVD result to rank r (Sec. 3, the rank-2r representation rounded back to rank r):
+// Sv (ra x ra, row-major) holds U_k sigma_k in column k, singular values descending.  Its first r
+// columns are factored as Q R with Q^T Q = I (two Gram-Schmidt passes; a column whose remainder is at
+// most 1e-12 of its own norm, or zero, is replaced by the unit vector that keeps the largest remainder,
+// with R_kk = 0).  Q -> [ra][r] row-major, R -> [r][r] row-major.  One workgroup.
+void launch_trunc(hipStream_t s, int ra, int r, const double* Sv, double* Q, double* R);
 // beta[k] = sum_q w_q W[k][q];  coef = S beta.  With mu, eta and gside set, also the side vectors
 // of the outflow tally: gside[s][i] = sum_j S[i][j] sum_{q leaving through side s} w_q |Omega_q . n_s| W[j][q]
 // (sides 0 left, 1 right, 2 bottom, 3 top).

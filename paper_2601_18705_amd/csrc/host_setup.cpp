@@ -155,7 +155,8 @@ void build_initial_factors(const ProblemHost& P, const std::vector<double>& mu, 
     // Columns 2..r: a Householder completion in the area-weighted inner product.
     // With u = x0 - e_1 (e_1 = cell 0 / sqrt(area)), H = I - 2 u u^T A / (u^T A u)
     // maps e_1 to x0, so H e_k (k >= 2) are orthonormal and orthogonal to x0.
-    // These columns only meet zero entries of S, so they do not affect the step.
+    // These columns only meet zero entries of S, so they do not affect the plain step (instances
+    // with the augmented basis, whose Galerkin space takes all of span X, replace them on the device).
     X.assign((size_t)r * n, 0.0);
     for (int e = 0; e < n; ++e) X[e] = x0[e];
     if (r > 1) {

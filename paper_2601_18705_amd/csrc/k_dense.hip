@@ -21,78 +21,6 @@ namespace {
 constexpr int kMaxOrdinates = 16384;
 
 // ---------------------------------------------------------------------------------------------- Gauss-Jordan
-// In-place Gauss-Jordan with partial pivoting on an r x ld augmented matrix in LDS
-// (first r columns = the matrix); afterwards columns r.. hold the solutions.  Per pivot k:
-// wavefront 0 finds the pivot row (largest |A_ik|, i >= k, lowest index on ties); then the
-// new row k (the pivot row scaled by 1/pivot) goes to prow while the old row k moves to the
-// pivot row's place, and the factors of the other rows are read; then every other row is
-// updated and row k written.  Three barriers per pivot; r <= 64.
-__device__ void gauss_jordan(double* Aug, int r, int ld, double* fac, double* prow, int* pivrow, double* pivval,
-                             int* bad) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int k = 0; k < r; ++k) {
-        if (tid < 64) {
-            const int i = k + tid;
-            double v = (i < r) ? fabs(Aug[i * ld + k]) : -1.0;
-            int idx = (i < r) ? i : 0x7fffffff;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(v, off);
-                const int oi = __shfl_xor(idx, off);
-                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-            }
-            if (tid == 0) {
-                const int p = (idx < r) ? idx : k;
-                *pivrow = p;
-                *pivval = Aug[p * ld + k];
-                if (!(v > 0.0) || !isfinite(v)) *bad = 1;
-            }
-        }
-        __syncthreads();
-        const int pr = *pivrow;
-        const double inv = 1.0 / *pivval;   // read before this phase moves the old row k
-        for (int c = tid; c < ld; c += nt) {
-            const double ak = Aug[k * ld + c], ap = Aug[pr * ld + c];
-            prow[c] = ap * inv;
-            if (pr != k) Aug[pr * ld + c] = ak;
-        }
-        for (int i = tid; i < r; i += nt)
-            fac[i] = (i == k) ? 0.0 : ((i == pr) ? Aug[k * ld + k] : Aug[i * ld + k]);
-        __syncthreads();
-        // rows by wavefront (i = wave + 4 a), columns by lane (c = lane + 64 b): no integer division
-        {
-            const int lane = tid & 63, wv = tid >> 6;
-            const int nw = nt >> 6;
-            double pv[3];   // ld <= 2 * 64 + 1 columns
-#pragma unroll
-            for (int b = 0; b < 3; ++b) pv[b] = prow[lane + 64 * b < ld ? lane + 64 * b : ld - 1];
-            for (int i0 = wv; i0 < r; i0 += 4 * nw) {
-                double x[12], f[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int i = i0 + a * nw;
-                    f[a] = fac[i < r ? i : r - 1];
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const int c = lane + 64 * b;
-                        x[a * 3 + b] = Aug[(i < r ? i : r - 1) * ld + (c < ld ? c : ld - 1)];
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int i = i0 + a * nw;
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const int c = lane + 64 * b;
-                        if (i < r && c < ld) Aug[i * ld + c] = (i == k) ? pv[b] : x[a * 3 + b] - f[a] * pv[b];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // The same solve on one wavefront without barriers, for systems of a single workgroup's
 // critical path: lane i holds row i of the augmented system in registers, the pivot of
 // column k is the largest remaining |A_ik| (ties to the lowest row) found by a DPP wavefront
@@ -605,61 +533,103 @@ __global__ __launch_bounds__(kDeimThreads) void k_deim_tail(DeimArgs a, int grou
 
 constexpr int kLsThreads = 256;
 
-// per ordinate: B_q^{-1} and y_q = B_q^{-1} Q_q
-__global__ __launch_bounds__(kLsThreads) void k_lstep_solve(LstepArgs a) {
-    extern __shared__ double dyn[];
-    __shared__ double fac[kMaxRank];
-    __shared__ double prow[2 * kMaxRank + 1];
-    __shared__ double pivval;
-    __shared__ int pivrow, bad;
-    const int r = a.r, rr = r * r, q = blockIdx.x, tid = threadIdx.x;
-    const int ld = 2 * r + 1;
-    double* Aug = dyn;
+// Right-hand sides of the L-step for ranks 33 to 64, one thread per (ordinate, basis index):
+// Q_q = qX + (old solution on the new basis) / (c dt) + inflow, with G = S0^T P staged in LDS; written
+// to y, which the solve below reads and overwrites with B_q^{-1} Q_q.
+__global__ __launch_bounds__(256) void k_lstep_rhs(LstepArgs a) {
+    __shared__ double sG[kMaxRank * kMaxRank];
+    const int r = a.r, rr = r * r;
+    stage_lds(sG, a.ops + 6 * rr, rr);
+    __syncthreads();
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)a.nq * r) return;
+    const int q = (int)(o / r), i = (int)(o % r);
+    const double* qX = a.ops + 7 * rr;
+    const double* bv = qX + r;
+    const double mu = a.mu[q], eta = a.eta[q];
+    const int sx = mu > 0.0 ? 0 : 1, sy = eta > 0.0 ? 2 : 3;
+    double lt = 0.0;   // sum_j W0_j(q) G[j][i]
+#pragma unroll 8
+    for (int j = 0; j < r; ++j) lt = fma(a.W0[(size_t)j * a.nq + q], sG[j * r + i], lt);
+    a.y[o] = qX[i] + lt * a.inv_cdt + fabs(mu) * a.psib[sx] * bv[sx * r + i] + fabs(eta) * a.psib[sy] * bv[sy * r + i];
+}
+
+// Ranks 33 to 64: two wavefronts per ordinate (one workgroup).  Wavefront 0 lane c holds column c of
+// B_q (the identity past r), wavefront 1 lane c column c of the identity; the rows are in registers.
+// Per pivot k, lane k of wavefront 0 copies its column to LDS, both wavefronts read it and eliminate
+// column k from their columns; the copies alternate between two buffers, so one barrier per pivot
+// keeps a buffer from being overwritten while it is read.  As in the one-wavefront form no rows are
+// exchanged (B_q's symmetric part is positive definite; a zero or non-finite pivot flags a singular
+// solve).  Afterwards wavefront 1 holds B_q^{-1} column by column; it goes to memory and to LDS, where
+// wavefront 0 forms y_q = B_q^{-1} Q_q (Q_q from k_lstep_rhs, staged in LDS before the elimination).
+__global__ __launch_bounds__(128) void k_lstep_solve_w2(LstepArgs a) {
+    constexpr int RT = 64;
+    __shared__ double colk[2][RT];
+    __shared__ double Bs[RT * (RT + 1)];
+    __shared__ double Qs[RT];
+    __shared__ int bad;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = a.r, rr = r * r, q = blockIdx.x;
     const double mu = a.mu[q], eta = a.eta[q];
     const double* Ax = a.ops + (mu > 0.0 ? 0 : 1) * rr;
     const double* Ay = a.ops + (eta > 0.0 ? 2 : 3) * rr;
     const double* Mt = a.ops + 4 * rr;
-    const double* G = a.ops + 6 * rr;
-    const double* qX = a.ops + 7 * rr;
-    const double* b = qX + r;
-    const int sx = mu > 0.0 ? 0 : 1, sy = eta > 0.0 ? 2 : 3;
     const double amu = fabs(mu), aeta = fabs(eta);
-    if (tid == 0) bad = 0;
-    double* sG = dyn + (size_t)r * ld;   // r x r after the augmented matrix
-    __shared__ double sW0[kMaxRank];
-    stage_lds(sG, G, rr);
-    for (int j = tid; j < r; j += kLsThreads) sW0[j] = a.W0[(size_t)j * a.nq + q];
-    __syncthreads();
-    // rows by wavefront, columns by lane (ld <= 129)
-    const int lane = tid & 63, wv = tid >> 6;
-    constexpr int kLsWaves = kLsThreads / 64;
-#pragma unroll 2
-    for (int i = wv; i < r; i += kLsWaves) {
+    if (threadIdx.x == 0) bad = 0;
+    double acol[RT];
+    if (wv == 0) {
+        // column lane of [B | I]: entries past r are those of the identity (0/1 masks, no selects of loads)
+        const int cc = lane < r ? lane : r - 1;
 #pragma unroll
-        for (int bc = 0; bc < 3; ++bc) {
-            const int c = lane + 64 * bc;
-            if (c >= ld) continue;
-            double v;
-            if (c < r) {
-                v = amu * Ax[i * r + c] + aeta * Ay[i * r + c] + Mt[i * r + c];
-            } else if (c < 2 * r) {
-                v = (c - r == i) ? 1.0 : 0.0;
-            } else {
-                double lt = 0.0;   // old solution projected on the new basis: sum_j W0_j(q) G[j][i]
-                for (int j = 0; j < r; ++j) lt += sW0[j] * sG[j * r + i];
-                v = qX[i] + lt * a.inv_cdt + amu * a.psib[sx] * b[(sx - 0) * r + i] +
-                    aeta * a.psib[sy] * b[sy * r + i];
-            }
-            Aug[i * ld + c] = v;
+        for (int i = 0; i < RT; ++i) {
+            const int ic = i < r ? i : r - 1;
+            const double v = amu * Ax[ic * r + cc] + aeta * Ay[ic * r + cc] + Mt[ic * r + cc];
+            const double keep = (i < r && lane < r) ? 1.0 : 0.0;
+            acol[i] = keep * v + (i == lane ? 1.0 - keep : 0.0);
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) acol[i] = (i == lane) ? 1.0 : 0.0;
+        const double Q = a.y[(size_t)q * r + (lane < r ? lane : r - 1)];
+        Qs[lane] = lane < r ? Q : 0.0;
+    }
+    // The rows move up one register per pivot (row k + j sits in acol[j] at pivot k), so the pivot row
+    // is always acol[0] and no register is indexed by k: the loop stays rolled without dynamic
+    // indexing, and each update writes straight into the register below its source.  After RT pivots
+    // every row is back in its own register.
+    bool sing = false;
+#pragma unroll 1
+    for (int k = 0; k < RT; ++k) {
+        double* ck = colk[k & 1];
+        if (wv == 0 && lane == k) {
+#pragma unroll
+            for (int j = 0; j < RT; ++j) ck[j] = acol[j];
+        }
+        __syncthreads();
+        const double piv = ck[0];
+        if (!(fabs(piv) > 0.0) || !isfinite(piv)) sing = true;
+        const double akk = acol[0] / piv;
+#pragma unroll
+        for (int j = 1; j < RT; ++j) acol[j - 1] = fma(-ck[j], akk, acol[j]);
+        acol[RT - 1] = akk;
+    }
+    if (sing) bad = 1;
+    if (wv == 1 && lane < r) {
+        double* Bi = a.Binv + (size_t)q * rr;
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+            if (i < r) {
+                Bi[i * r + lane] = acol[i];
+                Bs[i * (RT + 1) + lane] = acol[i];
+            }
     }
     __syncthreads();
-    gauss_jordan(Aug, r, ld, fac, prow, &pivrow, &pivval, &bad);
-    double* Bi = a.Binv + (size_t)q * rr;
-    for (int i = wv; i < r; i += kLsWaves)
-        if (lane < r) Bi[i * r + lane] = Aug[i * ld + r + lane];
-    for (int i = tid; i < r; i += kLsThreads) a.y[(size_t)q * r + i] = Aug[i * ld + 2 * r];
-    if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
+    if (wv == 0 && lane < r) {
+        double y = 0.0;
+        for (int j = 0; j < r; ++j) y = fma(Bs[lane * (RT + 1) + j], Qs[j], y);
+        a.y[(size_t)q * r + lane] = y;
+    }
+    if (threadIdx.x == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
 }
 
 // Ranks up to 32: one wavefront per ordinate, lane c holding column c of [B_q | I] (2 RT <= 64
@@ -970,18 +940,102 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
 }
 
 // X[k][c] = sum_j V[j][c] M[j][k]; one thread per output, consecutive threads along c
-__global__ __launch_bounds__(256) void k_rmul(int n, int r, const double* __restrict__ V, const double* __restrict__ M,
-                                              double* __restrict__ X) {
+__global__ __launch_bounds__(256) void k_rmul(int n, int rin, int rout, int ldm, const double* __restrict__ V,
+                                              const double* __restrict__ M, double* __restrict__ X) {
     __shared__ double sM[kMaxRank * kMaxRank];
-    stage_lds(sM, M, r * r);
+    stage_lds(sM, M, rin * ldm);
     __syncthreads();
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (long)n * r) return;
+    if (o >= (long)n * rout) return;
     const int k = (int)(o / n), c = (int)(o % n);
     double s = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < r; ++j) s += V[(size_t)j * n + c] * sM[j * r + k];
+    for (int j = 0; j < rin; ++j) s += V[(size_t)j * n + c] * sM[j * ldm + k];
     X[(size_t)k * n + c] = s;
+}
+
+// Rank-r truncation of an SVD result held as U Sigma (columns U_k sigma_k of the ra x ra row-major Sv):
+// Q R of its first r columns by classical Gram-Schmidt with two passes.  Sv is staged in LDS once; the
+// working column sits in LDS, thread j forms its product with accepted column j serially over the rows
+// (rows padded to 65 doubles, so the threads' reads fall in different banks), then 64 threads subtract
+// them.  Norms are serial sums in one thread, so nothing depends on timing.  A column with nothing left
+// after the passes (a zero singular value) takes the unit vector with the largest remainder, which
+// keeps Q orthonormal; R_kk is then 0.
+__global__ __launch_bounds__(256) void k_trunc(int ra, int r, const double* __restrict__ Sv, double* __restrict__ Q,
+                                               double* __restrict__ R) {
+    constexpr int kC = kMaxRank / 2, kP = 65;
+    __shared__ double sQ[kC * kP];
+    __shared__ double sv[64];
+    __shared__ double sh[kC];
+    __shared__ double sR[kC * kC];
+    __shared__ double sS[kMaxRank * kMaxRank];
+    __shared__ double snrm[2];
+    const int t = threadIdx.x;
+    for (int o = t; o < r * r; o += 256) sR[o] = 0.0;
+    stage_lds(sS, Sv, ra * ra);
+    __syncthreads();
+    // two passes of v -= Q_{<k} (Q_{<k}^T v) on the vector in sv; with rcol >= 0 the coefficients are
+    // added to column rcol of R.  Called by every thread (it holds barriers).
+    auto orth = [&](int k, int rcol) {
+        for (int pass = 0; pass < 2; ++pass) {
+            if (t < k) {
+                double d = 0.0;
+                for (int i = 0; i < 64; ++i) d = fma(sQ[t * kP + i], sv[i], d);
+                sh[t] = d;
+                if (rcol >= 0) sR[t * r + rcol] += d;
+            }
+            __syncthreads();
+            if (t < 64) {
+                double v = sv[t];
+                for (int j = 0; j < k; ++j) v = fma(-sh[j], sQ[j * kP + t], v);
+                sv[t] = v;
+            }
+            __syncthreads();
+        }
+    };
+    auto norm = [&](int slot) {
+        if (t == 0) {
+            double s2 = 0.0;
+            for (int i = 0; i < 64; ++i) s2 = fma(sv[i], sv[i], s2);
+            snrm[slot] = sqrt(s2);
+        }
+        __syncthreads();
+    };
+    for (int k = 0; k < r; ++k) {
+        if (t < 64) sv[t] = t < ra ? sS[t * ra + k] : 0.0;
+        __syncthreads();
+        norm(0);
+        orth(k, k);
+        norm(1);
+        const double own = snrm[0], nrm = snrm[1];
+        double rkk = nrm;
+        if (!(own > 0.0 && nrm > 1e-12 * own)) {   // the same decision in every thread
+            double bn = -1.0;
+            int best = 0;
+            for (int m = 0; m < ra; ++m) {
+                if (t < 64) sv[t] = (t == m) ? 1.0 : 0.0;
+                __syncthreads();
+                orth(k, -1);
+                norm(1);
+                if (snrm[1] > bn) bn = snrm[1], best = m;
+                __syncthreads();
+            }
+            if (t < 64) sv[t] = (t == best) ? 1.0 : 0.0;
+            __syncthreads();
+            orth(k, -1);
+            norm(1);
+            rkk = 0.0;
+        }
+        const double scale = 1.0 / snrm[1];
+        if (t < 64) {
+            const double qv = t < ra ? sv[t] * scale : 0.0;
+            sQ[k * kP + t] = qv;
+            if (t < ra) Q[t * r + k] = qv;
+        }
+        if (t == 0) sR[k * r + k] = rkk;
+        __syncthreads();
+    }
+    for (int o = t; o < r * r; o += 256) R[o] = sR[o];
 }
 
 // beta_k = sum_q w_q W_k(q), coef = S beta; wavefront k sums column k (fixed lane order)
@@ -1125,7 +1179,6 @@ void launch_deim(hipStream_t s, const DeimArgs& a) {
 
 void launch_lstep(hipStream_t s, const LstepArgs& a) {
     const int r = a.r;
-    const size_t solve_lds = ((size_t)r * (2 * r + 1) + (size_t)r * r) * sizeof(double);
     const size_t schur_lds = (size_t)r * (r + 1) * sizeof(double);
     const unsigned wave_blocks = (unsigned)((a.nq + 3) / 4);
     if (r <= 8) {
@@ -1135,10 +1188,9 @@ void launch_lstep(hipStream_t s, const LstepArgs& a) {
     } else if (r <= 32) {
         hipLaunchKernelGGL((k_lstep_solve_wave<32>), dim3(wave_blocks), dim3(256), 0, s, a);
     } else {
-        if (solve_lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_lstep_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)solve_lds);
-        hipLaunchKernelGGL(k_lstep_solve, dim3(a.nq), dim3(kLsThreads), solve_lds, s, a);
+        const long tot = (long)a.nq * r;
+        hipLaunchKernelGGL(k_lstep_rhs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_lstep_solve_w2, dim3(a.nq), dim3(128), 0, s, a);
     }
     hipLaunchKernelGGL(k_lstep_reduce, dim3(a.red_blocks), dim3(kLsThreads), 0, s, a);
     hipLaunchKernelGGL(k_lstep_schur, dim3(1), dim3(kLsThreads), schur_lds, s, a);
@@ -1151,7 +1203,17 @@ void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, 
 }
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
-    hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * r + 255) / 256)), dim3(256), 0, s, n, r, V, M, X);
+    hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * r + 255) / 256)), dim3(256), 0, s, n, r, r, r, V, M, X);
+}
+
+void launch_rmul_rect(hipStream_t s, int n, int rin, int rout, const double* V, const double* M, int ldm,
+                      double* X) {
+    hipLaunchKernelGGL(k_rmul, dim3((unsigned)(((long)n * rout + 255) / 256)), dim3(256), 0, s, n, rin, rout, ldm,
+                       V, M, X);
+}
+
+void launch_trunc(hipStream_t s, int ra, int r, const double* Sv, double* Q, double* R) {
+    hipLaunchKernelGGL(k_trunc, dim3(1), dim3(256), 0, s, ra, r, Sv, Q, R);
 }
 
 void launch_gather_si(hipStream_t s, int n, const int* const* flags, const int* const* status,

@@ -203,7 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_mfma(long n, int r, const TV*
 // Partial layout per block: [5 r^2 matrices][5 r vectors]
 //   M0 = sum X_i(i,j) X_j(i-1,j)   (x-upwind neighbour, 0 on column 0)
 //   M1 = sum X_i(i,j) X_j(i,j-1)   (y-upwind neighbour, 0 on row 0)
-//   M2 = sum sigma X_i X_j,  M3 = sum sigma_s X_i X_j,  M4 = sum X0_i X_j
+//   M2 = sum sigma X_i X_j,  M3 = sum sigma_s X_i X_j,  M4 = sum X0_i X_j (rows i >= r0 zero: X0
+//   has r0 <= r columns, fewer than X when the basis was augmented)
 //   v0 = sum q X_i,  v1..v4 = sums of X_i over the left / right / bottom / top cells
 // Column-major cells e = i*ny + j: (i-1,j) = e - ny and (i,j-1) = e - 1.
 //
@@ -221,7 +222,7 @@ struct ProjShape {
 };
 
 template <int RT, typename TO, bool BF16 = false>
-__global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r, const double* __restrict__ X,
+__global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r, int r0, const double* __restrict__ X,
                                                            const double* __restrict__ X0,
                                                            const double* __restrict__ sigma,
                                                            const double* __restrict__ sig_s,
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int nx, int ny, int r
             const bool ok = p < r && e < n;
             gX[u] = ok ? X[(size_t)p * n + e] : 0.0;
             gL[u] = (ok && e >= ny) ? X[(size_t)p * n + e - ny] : 0.0;
-            g0[u] = ok ? X0[(size_t)p * n + e] : 0.0;
+            g0[u] = (ok && p < r0) ? X0[(size_t)p * n + e] : 0.0;
         }
         if (threadIdx.x < RP) gH = (threadIdx.x < r && c0 > 0) ? X[(size_t)threadIdx.x * n + c0 - 1] : 0.0;
         gq = e < n ? q[e] : 0.0;
@@ -501,27 +502,32 @@ template void launch_gram<float>(hipStream_t, long, int, const float*, size_t, c
                                  double*);
 
 template <typename TO, bool BF16>
-void launch_project_t(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                      const double* sig_s, const double* q, double* partials, int nblocks) {
+void launch_project_t(hipStream_t s, int nx, int ny, int r, int r0, const double* X, const double* X0,
+                      const double* sigma, const double* sig_s, const double* q, double* partials, int nblocks) {
     const dim3 g(nblocks), b(kThreads);
     if (r <= 16)
-        hipLaunchKernelGGL((k_project_mfma<1, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<1, TO, BF16>), g, b, 0, s, nx, ny, r, r0, X, X0, sigma, sig_s, q,
+                           partials);
     else if (r <= 32)
-        hipLaunchKernelGGL((k_project_mfma<2, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<2, TO, BF16>), g, b, 0, s, nx, ny, r, r0, X, X0, sigma, sig_s, q,
+                           partials);
     else if (r <= 48)
-        hipLaunchKernelGGL((k_project_mfma<3, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<3, TO, BF16>), g, b, 0, s, nx, ny, r, r0, X, X0, sigma, sig_s, q,
+                           partials);
     else
-        hipLaunchKernelGGL((k_project_mfma<4, TO, BF16>), g, b, 0, s, nx, ny, r, X, X0, sigma, sig_s, q, partials);
+        hipLaunchKernelGGL((k_project_mfma<4, TO, BF16>), g, b, 0, s, nx, ny, r, r0, X, X0, sigma, sig_s, q,
+                           partials);
 }
 
 void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const double* X0, const double* sigma,
-                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits) {
+                    const double* sig_s, const double* q, double* partials, int nblocks, int operand_bits, int r0) {
+    if (r0 < 0) r0 = r;
     if (operand_bits == 16)
-        launch_project_t<float, true>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
+        launch_project_t<float, true>(s, nx, ny, r, r0, X, X0, sigma, sig_s, q, partials, nblocks);
     else if (operand_bits == 32)
-        launch_project_t<float, false>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
+        launch_project_t<float, false>(s, nx, ny, r, r0, X, X0, sigma, sig_s, q, partials, nblocks);
     else
-        launch_project_t<double, false>(s, nx, ny, r, X, X0, sigma, sig_s, q, partials, nblocks);
+        launch_project_t<double, false>(s, nx, ny, r, r0, X, X0, sigma, sig_s, q, partials, nblocks);
 }
 
 void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw) {

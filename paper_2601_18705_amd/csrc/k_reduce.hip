@@ -111,16 +111,18 @@ __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G
 // A[l%16][l/16] and B[l/16][l%16]; its accumulator element v is D[4 v + l/16][l%16], so a store writes
 // 16 consecutive cells of four planes.  V may be X (in place): a wavefront loads all rows of its tiles
 // before it stores any, and the tiles of different wavefronts are disjoint.  Nothing is done when skip
-// is given and set.
+// is given and set.  With GEN the matrix is a general rin x rout one (row-major, leading dimension
+// ldm) and every k-step of every output block is taken; otherwise rin = rout = ldm = r.
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
-template <typename TV, int RMAX, int T>
+template <typename TV, int RMAX, int T, bool GEN = false>
 __global__ __launch_bounds__(kBlock) void k_trmm_mfma(int n, int r, const TV* V, size_t ldv,
                                                       const double* __restrict__ Rinv, double* X,
-                                                      const int* __restrict__ skip) {
+                                                      const int* __restrict__ skip, int rout = 0, int ldm = 0) {
     static_assert(RMAX % 16 == 0, "16-plane blocks");
     if (skip && *skip) return;
     constexpr int NB = RMAX / 16, KS = RMAX / 4;
+    if (!GEN) rout = r, ldm = r;
     const int lane = threadIdx.x & 63, c = lane & 15, kr = lane >> 4;
     double A[NB][KS];
 #pragma unroll
@@ -128,7 +130,8 @@ __global__ __launch_bounds__(kBlock) void k_trmm_mfma(int n, int r, const TV* V,
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int j = 4 * ks + kr, k = 16 * mb + c;
-            A[mb][ks] = (ks <= 4 * mb + 3 && j <= k && k < r) ? Rinv[j * r + k] : 0.0;
+            const bool in = GEN ? (j < r && k < rout) : (ks <= 4 * mb + 3 && j <= k && k < r);
+            A[mb][ks] = in ? Rinv[j * ldm + k] : 0.0;
         }
     const long tiles = ((long)n + 15) / 16;
     const long wave = ((long)blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_trmm_mfma(int n, int r, const TV* V,
                 acc[mb] = dv4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
-                    if (ks <= 4 * mb + 3)
+                    if (GEN || ks <= 4 * mb + 3)
                         acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[mb][ks], xb[u][ks], acc[mb], 0, 0, 0);
             }
             if ((t0 + u) * 16 + c < n) {
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_trmm_mfma(int n, int r, const TV* V,
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int k = 16 * mb + 4 * v + kr;
-                        if (k < r) X[(size_t)k * n + e[u]] = acc[mb][v];
+                        if (k < rout) X[(size_t)k * n + e[u]] = acc[mb][v];
                     }
             }
         }
@@ -183,14 +186,14 @@ void launch_trmm_any(hipStream_t s, int n, int r, const TV* V, size_t ldv, const
 // ops layout: Axp, Axm, Ayp, Aym, Mt, Ms, G (r x r each), qX[r], b[4][r]
 //   A_x^+ = <X, D_x^+ X> = (I - M0)/hx   (X orthonormal), A_x^- = (I - M0^T)/hx, same for y;
 //   M_t = <X, sigma X> + I/(c dt);  G = S0^T P with P_ik = <X0_i, X_k> (old solution onto new X)
-__global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __restrict__ raw, double hx, double hy,
-                                                        double inv_cdt, const double* __restrict__ S0,
+__global__ __launch_bounds__(kBlock) void k_project_ops(int r, int r0, const double* __restrict__ raw, double hx,
+                                                        double hy, double inv_cdt, const double* __restrict__ S0,
                                                         double* __restrict__ ops) {
     __shared__ double sM4[kMaxRank * kMaxRank];
     __shared__ double sS[kMaxRank * kMaxRank];
     const int rr = r * r;
     stage_lds(sM4, raw + 4 * rr, rr);
-    stage_lds(sS, S0, rr);
+    stage_lds(sS, S0, r0 * r0);
     __syncthreads();
     const double* M0 = raw;
     const double* M1 = raw + rr;
@@ -206,8 +209,9 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, const double* __r
         ops[3 * rr + o] = (id - M1[j * r + i]) / hy;
         ops[4 * rr + o] = M2[o] + id * inv_cdt;
         ops[5 * rr + o] = M3[o];
-        double g = 0.0;
-        for (int m = 0; m < r; ++m) g += sS[m * r + i] * sM4[m * r + j];
+        double g = 0.0;   // S0 is r0 x r0; rows of G past r0 stay zero
+        if (i < r0)
+            for (int m = 0; m < r0; ++m) g += sS[m * r0 + i] * sM4[m * r + j];
         ops[6 * rr + o] = g;
     }
     for (int o = threadIdx.x; o < 5 * r; o += blockDim.x) {
@@ -243,6 +247,18 @@ template <typename TV>
 void launch_trmm(hipStream_t s, int n, int r, const TV* V, size_t ldv, const double* Rinv, double* X) {
     launch_trmm_any<TV>(s, n, r, V, ldv, Rinv, X, nullptr);
 }
+
+void launch_gemm_tall(hipStream_t s, int n, int rin, int rout, const double* V, const double* M, int ldm,
+                      double* X) {
+    const long tiles = ((long)n + 15) / 16;
+    const dim3 b(kBlock), g((unsigned)std::min<long>((tiles + 3) / 4, 2048));
+    if (rin <= 32)
+        hipLaunchKernelGGL((k_trmm_mfma<double, 32, 1, true>), g, b, 0, s, n, rin, V, (size_t)n, M, X, nullptr,
+                           rout, ldm);
+    else
+        hipLaunchKernelGGL((k_trmm_mfma<double, 64, 1, true>), g, b, 0, s, n, rin, V, (size_t)n, M, X, nullptr,
+                           rout, ldm);
+}
 template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, const double*, double*);
 template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, const double*, double*);
 
@@ -265,13 +281,14 @@ void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B,
 }
 
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
-                             double inv_cdt, const double* S0, double* ops) {
+                             double inv_cdt, const double* S0, double* ops, int r0) {
+    if (r0 < 0) r0 = r;
     // raw sums go into the tail of ops (beyond the operator block) as scratch
     const int rr = r * r;
     double* raw = ops + 7 * rr + 5 * r;
     const double area = hx * hy;
     launch_project_sum(s, r, partials, nblocks, area, raw);
-    hipLaunchKernelGGL(k_project_ops, dim3(1), dim3(kBlock), 0, s, r, raw, hx, hy, inv_cdt, S0, ops);
+    hipLaunchKernelGGL(k_project_ops, dim3(1), dim3(kBlock), 0, s, r, r0, raw, hx, hy, inv_cdt, S0, ops);
 }
 
 }  // namespace dlr

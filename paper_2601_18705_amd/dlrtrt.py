@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_
                 -9: "DLR_ERR_TIMEOUT"}
 DLR_FP64, DLR_FP32_SWEEP, DLR_FP32_SWEEP_BF16_PROJ = 0, 1, 2
 
-EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
+EXPORTED = ["dlr_set_allocator", "dlr_create", "dlr_create_augmented", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors", "dlr_load_factors",
             "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_sweep_shape", "dlr_set_sweep_shape",
             "dlr_destroy", "dlr_batch_footprint", "dlr_batch_create",
             "dlr_batch_admit", "dlr_batch_advance", "dlr_batch_poll", "dlr_batch_read", "dlr_batch_read_stats",
@@ -86,6 +86,7 @@ def library():
         lib = ctypes.CDLL(LIB_PATH)
         h = ctypes.c_void_p
         lib.dlr_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
+        lib.dlr_create_augmented.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
         lib.dlr_sn_create.argtypes = [ctypes.POINTER(DlrProblem), ctypes.c_void_p, ctypes.POINTER(h)]
         lib.dlr_step.argtypes = [h, ctypes.c_int32]
         lib.dlr_sync.argtypes = [h]
@@ -126,7 +127,7 @@ def library():
         lib.dlr_status_string.restype = ctypes.c_char_p
         lib.dlr_last_error.argtypes = []
         lib.dlr_last_error.restype = ctypes.c_char_p
-        for name in ("dlr_set_allocator", "dlr_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
+        for name in ("dlr_set_allocator", "dlr_create", "dlr_create_augmented", "dlr_sn_create", "dlr_step", "dlr_sync", "dlr_read_fields", "dlr_read_factors",
                      "dlr_load_factors", "dlr_read_stats", "dlr_force_selection", "dlr_set_dsa", "dlr_sweep_shape",
                      "dlr_set_sweep_shape", "dlr_destroy",
                      "dlr_batch_footprint", "dlr_batch_create", "dlr_batch_admit", "dlr_batch_advance",
@@ -303,9 +304,10 @@ class Batch:
 class Instance:
     """One problem resident on the device (dlr_create ... dlr_destroy).
 
-    method="dlr" steps the low-rank method; method="sn" creates a plain
-    discrete-ordinates instance of the same problem (dlr_sn_create), which has
-    no factors."""
+    method="dlr" steps the low-rank method; method="augmented" its variant with
+    the old basis added to the Galerkin space and a rank-2r -> r truncation
+    (dlr_create_augmented); method="sn" creates a plain discrete-ordinates
+    instance of the same problem (dlr_sn_create), which has no factors."""
 
     def __init__(self, problem, stream=None, method="dlr"):
         lib = library()
@@ -316,9 +318,9 @@ class Instance:
             self.rank = self.nq
             problem = dict(problem, rank=1)
             create = lib.dlr_sn_create
-        elif method == "dlr":
+        elif method in ("dlr", "augmented"):
             self.rank = int(problem["rank"])
-            create = lib.dlr_create
+            create = lib.dlr_create if method == "dlr" else lib.dlr_create_augmented
         else:
             raise ValueError(f"unknown method {method!r}")
         p, self._keep = marshal_problem(problem)
