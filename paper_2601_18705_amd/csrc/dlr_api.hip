@@ -167,6 +167,11 @@ struct dlr_instance {
     float* sig_t32 = nullptr;
     double *X = nullptr, *Xn = nullptr;
     double* Va = nullptr;   // augmented: [swept basis | X] (2r planes; X is its second half)
+    // The plain step stores its spatial basis after one Cholesky QR pass: the orthonormal basis is
+    // X Rxi (Rxi = Rx^{-1}, r x r, from the second pass), and the stored S carries Rxi, so that
+    // psi = X S W^T holds for the stored pair.  Identity after creation and load, and for the
+    // augmented basis (its X is orthonormal).
+    double *Rx = nullptr, *Rxi = nullptr;
     double *S = nullptr, *Sn = nullptr;
     double *W = nullptr, *Wt = nullptr, *Wq = nullptr, *L = nullptr;
     void *psi = nullptr, *src0 = nullptr, *s_e = nullptr, *psi_cm = nullptr;
@@ -291,6 +296,8 @@ struct dlr_instance {
             X = A.take<double>(R * n);
         }
         Xn = A.take<double>(RA * n);
+        Rx = A.take<double>(R * R);
+        Rxi = A.take<double>(R * R);
         S = A.take<double>(R * R);
         Sn = A.take<double>(RA * RA);
         W = A.take<double>(RA * Q);   // planes past r stay zero (the L-step reads ra planes of W0)
@@ -676,9 +683,17 @@ void phase_end(dlr_instance* I) {
     dlr::launch_chol(s, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
     dlr::launch_trmm<TS>(s, N, r, psi_cm, I->ld, I->R1i, Xq);
     dlr::launch_gram<double>(s, N, r, Xq, (size_t)N, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
-    dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3,
-                     I->fp32() ? 1e-8 : 1e-11);
-    dlr::launch_trmm_inplace(s, N, r, Xq, I->R2i, I->status + 3);
+    if (I->augment) {
+        dlr::launch_chol(s, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3,
+                         I->fp32() ? 1e-8 : 1e-11);
+        dlr::launch_trmm_inplace(s, N, r, Xq, I->R2i, I->status + 3);
+    } else {
+        // The second pass's factor is not multiplied into the cell planes: the orthonormal basis is
+        // Xq Rxi, and the projections, the temperature update's coefficients and the new S take Rxi
+        // instead (r x r work in place of a pass over the r planes).  When the first pass flagged the
+        // columns, the fallback below rebuilds an orthonormal basis and Rxi is the identity.
+        dlr::launch_chol(s, r, I->Gm, I->Rx, I->Rxi, I->status, dlr::kStatusQrBreakdownX, nullptr, 0.0, true);
+    }
     // fallback (runs on the device only if a Cholesky pivot flagged near-dependent columns)
     dlr::launch_cgs2<TS>(s, N, r, psi_cm, I->ld, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr, Xq,
                          I->R1, I->status, dlr::kStatusQrBreakdownX, I->status, dlr::kStatusNoCompletion);
@@ -700,7 +715,8 @@ void phase_end(dlr_instance* I) {
     // ordinate
     dlr::launch_project(s, I->nx, I->ny, rg, I->Xn, I->X, I->sigma, I->sig_s, I->q, I->partials, I->nb_proj,
                         I->prec == DLR_FP32_SWEEP_BF16_PROJ ? 16 : (I->fp32() ? 32 : 64), r);
-    dlr::launch_project_finalize(s, rg, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops, r);
+    dlr::launch_project_finalize(s, rg, I->partials, I->nb_proj, I->hx, I->hy, 1.0 / cdt, I->S, I->ops, r,
+                                 I->augment ? nullptr : I->Rxi);
     dlr::LstepArgs la{};
     la.nq = nq; la.r = rg; la.mu = I->mu; la.eta = I->eta; la.w = I->w; la.ops = I->ops; la.W0 = I->W;
     la.inv_cdt = 1.0 / cdt;
@@ -733,20 +749,20 @@ void phase_end(dlr_instance* I) {
         return;
     }
     // 9. temperature update with the mean intensity of the new factors, energy sum and outflow.  The
-    // state is psi = Xn Ra^T Wq^T; the SVD of S = Ra^T only rotates W and S (S' W'^T = Ra^T Wq^T), so
-    // the mean intensity coefficients and the outflow side vectors are formed from (Wq, Ra^T), and the
-    // temperature update runs beside the SVD on the second stream
+    // state is psi = (Xn Rxi) Ra^T Wq^T; the SVD of S = Ra^T only rotates W and S (S' W'^T = Ra^T Wq^T),
+    // so the mean intensity coefficients and the outflow side vectors are formed from (Wq, Rxi Ra^T)
+    // for the stored Xn, and the temperature update runs beside the SVD on the second stream
     hipStream_t ts = s;
     if (I->side) {
         hip_check(hipEventRecord(I->ev_fork, s), "event");
         hip_check(hipStreamWaitEvent(I->side, I->ev_fork, 0), "wait");
         ts = I->side;
     }
-    dlr::launch_wsum(ts, nq, r, I->Wq, I->w, I->Ra, I->beta, I->coef, I->mu, I->eta, I->gside, true);
+    dlr::launch_wsum(ts, nq, r, I->Wq, I->w, I->Ra, I->beta, I->coef, I->mu, I->eta, I->gside, true, I->Rxi);
     dlr::launch_tupdate(ts, tupdate_args(I, I->Xn, I->gside), I->nb_cells);
     if (I->side) hip_check(hipEventRecord(I->ev_join, I->side), "event");
-    // 8 (end). SVD of S: W <- Wq V, S <- S V (columns U_k sigma_k)
-    dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status);
+    // 8 (end). SVD of S: W <- Wq V, S <- S V (columns U_k sigma_k), stored as Rxi S V for Xn
+    dlr::launch_svd(s, r, I->Ra, I->Vsvd, I->Sn, I->status, I->Rxi);
     dlr::launch_rmul(s, nq, r, I->Wq, I->Vsvd, I->W);
     if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     std::swap(I->X, I->Xn);
@@ -900,6 +916,15 @@ void download(void* dst, const void* src, size_t bytes) {
 
 // Mean intensity of the current factors, for E_r before the first step / after a load: beta = W^T w,
 // coef = S beta, phi = X coef, on the device.
+// The stored basis is orthonormal as it stands (creation, load): Rx = Rxi = I.
+void reset_basis_factor(dlr_instance* I) {
+    const size_t R = (size_t)I->r;
+    std::vector<double> id(R * R, 0.0);
+    for (size_t k = 0; k < R; ++k) id[k * R + k] = 1.0;
+    upload(I->Rx, id.data(), id.size() * sizeof(double));
+    upload(I->Rxi, id.data(), id.size() * sizeof(double));
+}
+
 void refresh_phi(dlr_instance* I) {
     dlr::launch_wsum(I->stream, I->nq, I->r, I->W, I->w, I->S, I->beta, I->coef);
     dlr::launch_phi_of_factors(I->stream, I->N, I->r, I->X, I->coef, I->phi);
@@ -1359,6 +1384,7 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
         upload(I->X, X.data(), X.size() * sizeof(double));
         upload(I->S, S.data(), S.size() * sizeof(double));
         upload(I->W, W.data(), W.size() * sizeof(double));
+        reset_basis_factor(I);
         if (augment) {
             // The augmented Galerkin space takes the whole span of the old basis, so the completion
             // of the rank-one initial state is part of the method here (the plain step meets those
@@ -1512,10 +1538,20 @@ dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, in
     try {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const size_t n = h->N, R = h->r, Q = h->nq;
-        std::vector<double> X(R * n), S(R * R), W(R * Q);
+        std::vector<double> X(R * n), Ss(R * R), W(R * Q), Rx(R * R), Rxi(R * R);
         download(X.data(), h->X, X.size() * sizeof(double));
-        download(S.data(), h->S, S.size() * sizeof(double));
+        download(Ss.data(), h->S, Ss.size() * sizeof(double));
         download(W.data(), h->W, W.size() * sizeof(double));
+        download(Rx.data(), h->Rx, Rx.size() * sizeof(double));
+        download(Rxi.data(), h->Rxi, Rxi.size() * sizeof(double));
+        // the stored pair is (X, Ss) with the orthonormal basis X Rxi: its coupling is S = Rx Ss
+        std::vector<double> S(R * R, 0.0);
+        for (size_t i = 0; i < R; ++i)
+            for (size_t j = 0; j < R; ++j) {
+                double acc = 0.0;
+                for (size_t k = 0; k < R; ++k) acc += Rx[i * R + k] * Ss[k * R + j];
+                S[i * R + j] = acc;
+            }
         std::vector<double> U(R * R, 0.0), sig(R, 0.0);
         if (h->s_is_usigma) {
             // S holds U Sigma column-wise: sigma_k = ||S_k||, U_k = S_k / sigma_k; zero
@@ -1552,12 +1588,20 @@ dlr_status dlr_read_factors(dlr_handle h, double* Xo, double* So, double* Wo, in
             for (size_t k = 0; k < R; ++k) U[k * R + k] = 1.0;
         }
         if (Xo) {
+            // orthonormal basis rotated to the singular vectors: X Rxi U
+            std::vector<double> M(R * R, 0.0);
+            for (size_t i = 0; i < R; ++i)
+                for (size_t k = 0; k < R; ++k) {
+                    double acc = 0.0;
+                    for (size_t j = 0; j < R; ++j) acc += Rxi[i * R + j] * U[j * R + k];
+                    M[i * R + k] = acc;
+                }
             const size_t nx = h->nx, ny = h->ny;
             for (size_t e = 0; e < n; ++e) {
                 const size_t erm = (e % ny) * nx + (e / ny);   // device cell e = i*ny + j -> j*nx + i
                 for (size_t k = 0; k < R; ++k) {
                     double s = 0.0;
-                    for (size_t j = 0; j < R; ++j) s += X[j * n + e] * U[j * R + k];
+                    for (size_t j = 0; j < R; ++j) s += X[j * n + e] * M[j * R + k];
                     Xo[erm * R + k] = s;
                 }
             }
@@ -1602,6 +1646,7 @@ dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, co
         upload(h->S, Si, R * R * sizeof(double));
         upload(h->W, W.data(), W.size() * sizeof(double));
         upload(h->T, to_cm(Ti, h->nx, h->ny).data(), n * sizeof(double));
+        reset_basis_factor(h);
         refresh_phi(h);
         hip_check(hipDeviceSynchronize(), "sync");
         h->s_is_usigma = false;

@@ -215,13 +215,16 @@ void launch_q1_sweep(hipStream_t s, const Q1Args<TS>& a);
 template <typename TV>
 void launch_gram(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight, double scale,
                  double* work, int nblocks, double* G);
-// C = A B for r x r row-major matrices
-void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C);
+// C = A B (or A B^T) for r x r row-major matrices
+void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C,
+                         bool b_transposed = false);
 // Cholesky QR step: the Gram matrix G -> R, Rinv; a pivot too small for Cholesky QR sets
 // status_code in *status.  With near_identity, also writes 1 there when max |G - I| < identity_tol
 // (the basis is already orthonormal to that tolerance), else 0.
+// With identity_on_flag, a status_code bit already set in *status (an earlier pass flagged the columns
+// for the CGS2 fallback) makes R = Rinv = I.
 void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code,
-                 int* near_identity = nullptr, double identity_tol = 0.0);
+                 int* near_identity = nullptr, double identity_tol = 0.0, bool identity_on_flag = false);
 // X = X Rinv in place for n x r column-major X; nothing when *skip is set
 void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip);
 template <typename TV>
@@ -240,9 +243,11 @@ void launch_project(hipStream_t s, int nx, int ny, int r, const double* X, const
 // raw[o] = area * sum over blocks of partials[b][o]
 void launch_project_sum(hipStream_t s, int r, const double* partials, int nblocks, double area, double* raw);
 // Produces Axp, Axm, Ayp, Aym, Mt, Ms (r x r each, row-major), qX[r], b[4][r], G = S0^T P [r][r];
-// S0 is r0 x r0 (r0 < 0: r) and the rows of G past r0 are zero.
+// S0 is r0 x r0 (r0 < 0: r) and the rows of G past r0 are zero.  With T given, the sums were taken on
+// a basis Xq whose orthonormal form is X = Xq T, and the operators are those of X.
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
-                             double inv_cdt, const double* S0, double* ops, int r0 = -1);
+                             double inv_cdt, const double* S0, double* ops, int r0 = -1,
+                             const double* T = nullptr);
 
 // ----------------------------------------------------------------------------- small dense FP64 work
 // DEIM exchange area: per column two exchanges among up to 64 workgroups (double-buffered),
@@ -295,8 +300,10 @@ struct LstepArgs {
 };
 void launch_lstep(hipStream_t s, const LstepArgs& a);
 
-// one-sided Jacobi SVD of S = R^T; writes V [r][r] and S' = S V (columns U_k sigma_k)
-void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status);
+// one-sided Jacobi SVD of S = R^T; writes V [r][r] and S' = S V (columns U_k sigma_k), or Tl S V
+// with Tl given
+void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status,
+                const double* Tl = nullptr);
 // weighted CGS2 with monomial completion, one workgroup: V [r][n] -> Q [r][n], R [r][r] upper.
 // comp_kind 0: spatial monomials on the nx x ny cell centres, 1: angular monomials in (mu, eta).
 // With flag != nullptr the kernel runs only if (*flag & flag_mask) and then clears those bits.
@@ -319,10 +326,11 @@ void launch_trunc(hipStream_t s, int ra, int r, const double* Sv, double* Q, dou
 // beta[k] = sum_q w_q W[k][q];  coef = S beta.  With mu, eta and gside set, also the side vectors
 // of the outflow tally: gside[s][i] = sum_j S[i][j] sum_{q leaving through side s} w_q |Omega_q . n_s| W[j][q]
 // (sides 0 left, 1 right, 2 bottom, 3 top).
-// s_transposed: the matrix given is S^T (as the angular QR's R factor, S = R^T).
+// s_transposed: the matrix given is S^T (as the angular QR's R factor, S = R^T).  Tl: the matrix
+// used is Tl S (Tl r x r, row-major), for a spatial basis stored as X Tl^{-1}.
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
                  double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr,
-                 bool s_transposed = false);
+                 bool s_transposed = false, const double* Tl = nullptr);
 
 // The few values the host reads after a source iteration or a step, written by one small kernel
 // straight into host-mapped pinned memory (system-scope stores): up to three runs of doubles,

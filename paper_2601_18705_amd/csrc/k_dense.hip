@@ -827,13 +827,16 @@ __device__ inline double row16_sum(double v) {
 
 __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __restrict__ Rin,
                                                      double* __restrict__ Vout, double* __restrict__ Sout,
-                                                     int* status) {
+                                                     int* status, const double* __restrict__ Tl) {
     __shared__ double S[kMaxRank * kMaxRank];
     __shared__ double V[kMaxRank * kMaxRank];
     __shared__ double nrm[kMaxRank];
     __shared__ int order[kMaxRank];
+    __shared__ double sTl[kMaxRank * kMaxRank];   // with Tl: Tl; sP: the sorted S V
+    __shared__ double sP[kMaxRank * kMaxRank];
     const int tid = threadIdx.x;
     const int rr = r * r;
+    if (Tl) stage_lds(sTl, Tl, rr);   // read at the end; the barriers of the sweeps order it
     // column-major: column c of S = R^T is row c of R, S[c * r + i] = R[c][i]; the lanes of a pair
     // read consecutive rows of a column (no bank conflicts)
     for (int o = tid; o < rr; o += kSvdThreads) {
@@ -934,7 +937,19 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
         const double sg = (V[src * r + m] < 0.0) ? -1.0 : 1.0;
         for (int i = 0; i < r; ++i) {
             Vout[i * r + c] = sg * V[src * r + i];
-            Sout[i * r + c] = sg * S[src * r + i];
+            if (Tl)
+                sP[i * r + c] = sg * S[src * r + i];
+            else
+                Sout[i * r + c] = sg * S[src * r + i];
+        }
+    }
+    if (Tl) {   // Sout = Tl (S V), one output per thread and pass (consecutive threads: consecutive columns)
+        __syncthreads();
+        for (int o = tid; o < rr; o += kSvdThreads) {
+            const int i = o / r, c = o % r;
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc = fma(sTl[i * r + k], sP[k * r + c], acc);
+            Sout[o] = acc;
         }
     }
 }
@@ -1043,7 +1058,8 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
                                                const double* __restrict__ w, const double* __restrict__ S,
                                                double* __restrict__ beta, double* __restrict__ coef,
                                                const double* __restrict__ mu, const double* __restrict__ eta,
-                                               double* __restrict__ gside, int transpose_s) {
+                                               double* __restrict__ gside, int transpose_s,
+                                               const double* __restrict__ Tl) {
     __shared__ double sb[kMaxRank];
     __shared__ double sgs[4][kMaxRank];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1102,10 +1118,34 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
     }
     __syncthreads();
     __shared__ double sS[kMaxRank * kMaxRank];
+    __shared__ double sT[kMaxRank * kMaxRank];
+    __shared__ double sE[kMaxRank * (kMaxRank + 1)];
     stage_lds(sS, S, r * r);
+    if (Tl) stage_lds(sT, Tl, r * r);
     __syncthreads();
-    // S[i][j] is sS[i * r + j], or sS[j * r + i] when the matrix given is S^T
-    const int si = transpose_s ? 1 : r, sj = transpose_s ? r : 1;
+    // S[i][j] is sS[i * r + j], or sS[j * r + i] when the matrix given is S^T; with Tl the matrix used
+    // is Tl S (formed in LDS first)
+    int si = transpose_s ? 1 : r, sj = transpose_s ? r : 1;
+    if (Tl) {
+        // sE = Tl S.  S[k][j] is read as a row of the (transposed) matrix given when transpose_s, so
+        // it is first copied with an odd stride (r + 1): consecutive threads (consecutive j) then read
+        // different LDS banks instead of one bank r doubles apart
+        const int ld = r + 1;
+        for (int o = threadIdx.x; o < r * r; o += blockDim.x) {
+            const int k = o / r, j = o % r;
+            sE[j * ld + k] = sS[k * si + j * sj];   // sE holds S^T with stride ld
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < r * r; o += blockDim.x) {
+            const int i = o / r, j = o % r;
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc = fma(sT[i * r + k], sE[j * ld + k], acc);
+            sS[o] = acc;   // every read of the old sS was before the barrier above
+        }
+        __syncthreads();
+        si = r;
+        sj = 1;
+    }
     for (int i = threadIdx.x; i < r; i += blockDim.x) {
         beta[i] = sb[i];
         double s = 0.0;
@@ -1198,8 +1238,8 @@ void launch_lstep(hipStream_t s, const LstepArgs& a) {
     hipLaunchKernelGGL(k_lstep_apply, dim3((unsigned)((tot + kLsThreads - 1) / kLsThreads)), dim3(kLsThreads), 0, s, a);
 }
 
-void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status) {
-    hipLaunchKernelGGL(k_svd, dim3(1), dim3(kSvdThreads), 0, s, r, R, V, Snew, status);
+void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status, const double* Tl) {
+    hipLaunchKernelGGL(k_svd, dim3(1), dim3(kSvdThreads), 0, s, r, R, V, Snew, status, Tl);
 }
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
@@ -1226,9 +1266,10 @@ void launch_publish(hipStream_t s, const PublishArgs& a) {
 }
 
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
-                 double* coef, const double* mu, const double* eta, double* gside, bool s_transposed) {
+                 double* coef, const double* mu, const double* eta, double* gside, bool s_transposed,
+                 const double* Tl) {
     hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, s, nq, r, W, w, S, beta, coef, mu, eta, gside,
-                       s_transposed ? 1 : 0);
+                       s_transposed ? 1 : 0, Tl);
 }
 
 }  // namespace dlr

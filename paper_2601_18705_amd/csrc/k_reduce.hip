@@ -34,8 +34,16 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 template <int RMAX>
 __global__ __launch_bounds__(64) void k_chol(int r, const double* __restrict__ G, double* __restrict__ R,
                                              double* __restrict__ Rinv, int* status, int status_code,
-                                             int* near_identity, double identity_tol) {
+                                             int* near_identity, double identity_tol, int identity_on_flag) {
     static_assert(RMAX <= 64, "one lane per column");
+    if (identity_on_flag && (*status & status_code)) {
+        for (int o = threadIdx.x; o < r * r; o += 64) {
+            const double v = (o / r == o % r) ? 1.0 : 0.0;
+            R[o] = v;
+            Rinv[o] = v;
+        }
+        return;
+    }
     __shared__ double row[64];
     __shared__ double scl[64];
     const int j = threadIdx.x;
@@ -224,19 +232,20 @@ __global__ __launch_bounds__(kBlock) void k_project_ops(int r, int r0, const dou
 }  // namespace
 
 void launch_chol(hipStream_t s, int r, const double* G, double* R, double* Rinv, int* status, int status_code,
-                 int* near_identity, double identity_tol) {
+                 int* near_identity, double identity_tol, bool identity_on_flag) {
+    const int f = identity_on_flag ? 1 : 0;
     if (r <= 8)
         hipLaunchKernelGGL(k_chol<8>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
-                           identity_tol);
+                           identity_tol, f);
     else if (r <= 16)
         hipLaunchKernelGGL(k_chol<16>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
-                           identity_tol);
+                           identity_tol, f);
     else if (r <= 32)
         hipLaunchKernelGGL(k_chol<32>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
-                           identity_tol);
+                           identity_tol, f);
     else
         hipLaunchKernelGGL(k_chol<64>, dim3(1), dim3(64), 0, s, r, G, R, Rinv, status, status_code, near_identity,
-                           identity_tol);
+                           identity_tol, f);
 }
 
 void launch_trmm_inplace(hipStream_t s, int n, int r, double* X, const double* Rinv, const int* skip) {
@@ -263,31 +272,77 @@ template void launch_trmm<double>(hipStream_t, int, int, const double*, size_t, 
 template void launch_trmm<float>(hipStream_t, int, int, const float*, size_t, const double*, double*);
 
 __global__ __launch_bounds__(kBlock) void k_small_matmul(int r, const double* __restrict__ A,
-                                                         const double* __restrict__ B, double* __restrict__ C) {
+                                                         const double* __restrict__ B, double* __restrict__ C,
+                                                         int b_transposed) {
     __shared__ double sA[kMaxRank * kMaxRank], sB[kMaxRank * kMaxRank];
     stage_lds(sA, A, r * r);
     stage_lds(sB, B, r * r);
     __syncthreads();
+    // B[k][j] is sB[k * r + j], or sB[j * r + k] when B^T is wanted
+    const int bk = b_transposed ? 1 : r, bj = b_transposed ? r : 1;
     for (int o = threadIdx.x; o < r * r; o += blockDim.x) {
         const int i = o / r, j = o % r;
         double s = 0.0;
-        for (int k = 0; k < r; ++k) s += sA[i * r + k] * sB[k * r + j];
+        for (int k = 0; k < r; ++k) s += sA[i * r + k] * sB[k * bk + j * bj];
         C[o] = s;
     }
 }
 
-void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C) {
-    hipLaunchKernelGGL(k_small_matmul, dim3(1), dim3(kBlock), 0, s, r, A, B, C);
+void launch_small_matmul(hipStream_t s, int r, const double* A, const double* B, double* C, bool b_transposed) {
+    hipLaunchKernelGGL(k_small_matmul, dim3(1), dim3(kBlock), 0, s, r, A, B, C, b_transposed ? 1 : 0);
+}
+
+
+// Raw projection sums taken on a basis Xq whose orthonormal form is X = Xq T (T = R^{-1} of a Cholesky
+// QR pass, r x r): the matrices with X on both sides become T^T M T, <X0, X> becomes M4 T and the
+// vectors T^T v.  Block b < 5 transforms matrix b, block 5 the five vectors (in place).
+__global__ __launch_bounds__(kBlock) void k_project_rotate(int r, const double* __restrict__ T,
+                                                           double* __restrict__ raw) {
+    __shared__ double sT[kMaxRank * kMaxRank], sM[kMaxRank * kMaxRank], sP[kMaxRank * kMaxRank];
+    const int rr = r * r, b = blockIdx.x;
+    stage_lds(sT, T, rr);
+    if (b < 5)
+        stage_lds(sM, raw + (size_t)b * rr, rr);
+    else
+        stage_lds(sM, raw + 5 * (size_t)rr, 5 * r);
+    __syncthreads();
+    if (b < 5) {
+        for (int o = threadIdx.x; o < rr; o += kBlock) {   // sP = M T
+            const int i = o / r, j = o % r;
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc = fma(sM[i * r + k], sT[k * r + j], acc);
+            sP[o] = acc;
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < rr; o += kBlock) {
+            double v = sP[o];
+            if (b != 4) {   // T^T (M T)
+                const int i = o / r, j = o % r;
+                double acc = 0.0;
+                for (int k = 0; k < r; ++k) acc = fma(sT[k * r + i], sP[k * r + j], acc);
+                v = acc;
+            }
+            raw[(size_t)b * rr + o] = v;
+        }
+    } else {
+        for (int o = threadIdx.x; o < 5 * r; o += kBlock) {
+            const int kind = o / r, i = o % r;
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc = fma(sT[k * r + i], sM[kind * r + k], acc);
+            raw[5 * (size_t)rr + o] = acc;
+        }
+    }
 }
 
 void launch_project_finalize(hipStream_t s, int r, const double* partials, int nblocks, double hx, double hy,
-                             double inv_cdt, const double* S0, double* ops, int r0) {
+                             double inv_cdt, const double* S0, double* ops, int r0, const double* T) {
     if (r0 < 0) r0 = r;
     // raw sums go into the tail of ops (beyond the operator block) as scratch
     const int rr = r * r;
     double* raw = ops + 7 * rr + 5 * r;
     const double area = hx * hy;
     launch_project_sum(s, r, partials, nblocks, area, raw);
+    if (T) hipLaunchKernelGGL(k_project_rotate, dim3(6), dim3(kBlock), 0, s, r, T, raw);
     hipLaunchKernelGGL(k_project_ops, dim3(1), dim3(kBlock), 0, s, r, r0, raw, hx, hy, inv_cdt, S0, ops);
 }
 
