@@ -950,7 +950,8 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     }
     I->has_qext = p->q_ext != nullptr;
     I->stream = stream;
-    I->nsuper = (I->nx + 64 * dlr::kSweepWaves - 1) / (64 * dlr::kSweepWaves);
+    const int sw = dlr::sweep_waves(I->prec == DLR_FP64);
+    I->nsuper = (I->nx + 64 * sw - 1) / (64 * sw);
     I->ld = ((size_t)I->N + 63) / 64 * 64;   // compact column-major cell planes (e = i * ny + j)
     I->ldg = dlr::diag_plane(I->nx, I->ny);
     I->nb_phi = std::min(((I->nx + 7) / 8) * ((I->ny + 127) / 128), 1024);

@@ -137,12 +137,15 @@ void launch_sn_outflow(hipStream_t s, int nx, int ny, int nq, size_t ldg, const 
                        unsigned* counter, double* out);
 
 // ----------------------------------------------------------------------------- sweep
-constexpr int kSweepWaves = 2;     // compute wavefronts (64-column strips) per sweep workgroup
+// compute wavefronts (64-column strips) per sweep workgroup: two with FP32 planes, one with FP64
+// (measured at 1024^2 x 32 directions: FP32 158 us with two against 168 with one; FP64 sweeps the
+// other way round)
+constexpr int sweep_waves(bool fp64) { return fp64 ? 1 : 2; }
 // One instance's sweep: everything but the launch-level fields below is fixed for the life of
 // the instance, so the record is uploaded once and reused by every launch.
 template <typename TS>
 struct SweepArgs {
-    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of kSweepWaves x 64 columns; units = nsuper * nd
+    int nx, ny, nd, nsuper, total_units;   // nsuper = superstrips of sweep_waves x 64 columns; units = nsuper * nd
     size_t ldg;                            // diagonal plane stride (elements), diag_plane
     const TS* src0;      // [nd][ldg] fixed source q + psi0 / (c dt), each in its direction's orientation
     const TS* sig_t;     // [4][ldg] one copy per orientation

@@ -5,7 +5,7 @@
 //
 // Work decomposition.  In each direction's own sweep coordinates (i', j') --
 // i' = i for mu > 0 else nx-1-i, likewise j' -- the grid is cut into strips of
-// 64 columns, kSweepWaves consecutive strips forming a superstrip.  A workgroup
+// 64 columns, sweep_waves(precision) consecutive strips forming a superstrip.  A workgroup
 // takes one (superstrip S, direction d) unit with one compute wavefront per
 // strip and one helper wavefront.  Lane l of a compute wavefront owns column
 // i' = 64 strip + l and at step t updates row j' = t - l: the x-upwind value is
@@ -36,7 +36,6 @@ namespace dlr {
 
 namespace {
 
-constexpr int kWaves = kSweepWaves;   // compute wavefronts per workgroup
 constexpr int kC = 16;                // rows per chunk
 constexpr int kRing = 256;            // LDS ring length (rows)
 
@@ -88,8 +87,13 @@ __device__ __forceinline__ double step_value(double rhs, double sig, double axy,
     return num / (sig + axy);
 }
 
+// compute wavefronts per workgroup for planes of type TS
+template <typename TS>
+constexpr int kWavesOf = sweep_waves(sizeof(TS) == 8);
+
 template <typename TS>
 struct Shared {
+    static constexpr int kWaves = kWavesOf<TS>;
     TS ring[kWaves + 1][kRing] __attribute__((aligned(16)));   // ring[w]: left inflow of compute wave w;
                                                                 // ring[kWaves]: outgoing edge; row j in slot (j+63) % kRing
     int prod[kWaves + 1];         // rows published into ring[w]
@@ -139,6 +143,7 @@ __device__ __forceinline__ void run_chunk(const Strip<TS>& s, int m, const TS (&
 
 template <typename TS, int P>
 __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>& sh, int S, int d, int w, int lane) {
+    constexpr int kWaves = kWavesOf<TS>;
     const int ny = a.ny;
     const int strip = S * kWaves + w;
     const double mu = a.mu[d], eta = a.eta[d];
@@ -280,6 +285,7 @@ __device__ __forceinline__ void compute_wave(const SweepArgs<TS>& a, Shared<TS>&
 template <typename TS>
 __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned long long launch_id, Shared<TS>& sh, int S,
                                             int d, int lane) {
+    constexpr int kWaves = kWavesOf<TS>;
     const int nx = a.nx, ny = a.ny;
     const bool incoming = S > 0;
     const bool outgoing = ((S + 1) * kWaves) * 64 < nx;   // the next superstrip has columns
@@ -345,7 +351,9 @@ __device__ __forceinline__ void helper_wave(const SweepArgs<TS>& a, unsigned lon
 }
 
 template <typename TS, int P>
-__global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>* __restrict__ table, SweepLaunch L) {
+__global__ __launch_bounds__(64 * (kWavesOf<TS> + 1)) void k_sweep(const SweepArgs<TS>* __restrict__ table,
+                                                                  SweepLaunch L) {
+    constexpr int kWaves = kWavesOf<TS>;
     __shared__ Shared<TS> sh;
     __shared__ int inst, skip;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -409,7 +417,7 @@ __global__ __launch_bounds__(64 * (kWaves + 1)) void k_sweep(const SweepArgs<TS>
 
 template <typename TS>
 void launch_sweep(hipStream_t s, const SweepArgs<TS>* table, const SweepLaunch& L, int prefetch) {
-    const dim3 g(L.grid_blocks), b(64 * (kWaves + 1));
+    const dim3 g(L.grid_blocks), b(64 * (kWavesOf<TS> + 1));
     if (prefetch == 2)
         hipLaunchKernelGGL((k_sweep<TS, 2>), g, b, 0, s, table, L);
     else if (prefetch == 8)
