@@ -1390,11 +1390,29 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
             // The augmented Galerkin space takes the whole span of the old basis, so the completion
             // of the rank-one initial state is part of the method here (the plain step meets those
             // columns only through zero entries of S): X = CGS2 of [B(T_init) | 0 ...] with the
-            // graded spatial monomials filling the zero columns, as the cgs2 fallback does.
-            hip_check(hipMemsetAsync(I->Xn, 0, (size_t)I->r * n * sizeof(double), I->stream), "clear");
-            hip_check(hipMemcpyAsync(I->Xn, I->X, n * sizeof(double), hipMemcpyDeviceToDevice, I->stream), "copy");
-            dlr::launch_cgs2<double>(I->stream, (long)n, I->r, I->Xn, n, nullptr, I->area, 0, I->nx, I->ny, nullptr,
-                                     nullptr, I->X, I->R1, nullptr, 0, I->status, dlr::kStatusNoCompletion);
+            // graded spatial monomials filling the zero columns.  Unless a monomial is (nearly)
+            // dependent, that CGS2 keeps B(T_init) and the next r - 1 monomials (skipping the
+            // constant when B(T_init) is constant), and its Q is the unique QR factor of that matrix:
+            // formed here by Cholesky QR twice on all of the cells at once.  When a pivot flags a
+            // nearly dependent column, the one-workgroup CGS2 of [B(T_init) | 0 ...] decides instead.
+            bool b0_const = true;
+            for (long e = 1; e < (long)n && b0_const; ++e) b0_const = p->T_init[e] == p->T_init[0];
+            const int r = I->r;
+            hipStream_t st = I->stream;
+            hip_check(hipMemcpyAsync(I->Xn, I->X, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            dlr::launch_monomials(st, I->nx, I->ny, b0_const ? 1 : 0, r - 1, I->Xn + n, n);
+            dlr::launch_gram<double>(st, (long)n, r, I->Xn, n, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+            dlr::launch_chol(st, r, I->Gm, I->R1, I->R1i, I->status, dlr::kStatusQrBreakdownX);
+            dlr::launch_trmm<double>(st, (int)n, r, I->Xn, n, I->R1i, I->X);
+            dlr::launch_gram<double>(st, (long)n, r, I->X, n, nullptr, I->area, I->partials, I->nb_gram, I->Gm);
+            dlr::launch_chol(st, r, I->Gm, I->R2, I->R2i, I->status, dlr::kStatusQrBreakdownX, I->status + 3, 1e-15);
+            dlr::launch_trmm_inplace(st, (int)n, r, I->X, I->R2i, I->status + 3);
+            // the exact rule, on the device only when a pivot above flagged the columns
+            hip_check(hipMemsetAsync(I->Va, 0, (size_t)r * n * sizeof(double), st), "clear");
+            hip_check(hipMemcpyAsync(I->Va, I->Xn, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            dlr::launch_cgs2<double>(st, (long)n, r, I->Va, n, nullptr, I->area, 0, I->nx, I->ny, nullptr, nullptr,
+                                     I->X, I->R1, I->status, dlr::kStatusQrBreakdownX, I->status,
+                                     dlr::kStatusNoCompletion);
             int st0 = 0;
             hip_check(hipMemcpyAsync(&st0, I->status, sizeof(int), hipMemcpyDeviceToHost, I->stream), "status");
             hip_check(hipStreamSynchronize(I->stream), "sync");

@@ -315,6 +315,9 @@ void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const do
                  int comp_kind,
                  int nx, int ny, const double* mu, const double* eta, double* Q, double* R, int* flag,
                  int flag_mask, int* status, int status_code);
+// planes k = 0 .. count-1 of V: graded spatial monomial number first + k (the CGS2 completion's order) at the
+// cell centres of the nx x ny grid, column-major cells
+void launch_monomials(hipStream_t s, int nx, int ny, int first, int count, double* V, size_t ldv);
 // X[k][c] = sum_j V[j][c] M[j][k] for a [r][n] column-major V (general r x r right multiply)
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X);
 // the same with rin input planes, rout output planes and M of leading dimension ldm

@@ -11,6 +11,8 @@
 // residual is below 1e-10 of its own norm; R_kk is then 0.
 #include "dlr_internal.h"
 
+#include <algorithm>
+
 namespace dlr {
 
 namespace {
@@ -199,7 +201,37 @@ __global__ __launch_bounds__(kOrthThreads) void k_cgs2(long n, int r, const TV* 
     }
 }
 
+// Planes k = 0 .. count-1 of V (leading dimension ldv): the graded spatial monomial number first + k, in the
+// completion's order (1, x, y, x^2, x y, y^2, ...: degree d, then the power of x from d down to 0) at the
+// cell centres mapped to [-1, 1]^2, column-major cells e = i*ny + j.
+__global__ __launch_bounds__(256) void k_monomials(int nx, int ny, int first, int count, double* __restrict__ V,
+                                                  size_t ldv) {
+    const long n = (long)nx * ny;
+    const long total = n * count;
+    for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(o / n);
+        const long e = o - (long)k * n;
+        const int idx = first + k;
+        int d = 0;
+        while ((d + 1) * (d + 2) / 2 <= idx) ++d;
+        const int a = d - (idx - d * (d + 1) / 2);   // power of x
+        const long i = e / ny, j = e % ny;
+        const double bx = -1.0 + (i + 0.5) * 2.0 / nx, by = -1.0 + (j + 0.5) * 2.0 / ny;
+        double m = 1.0;
+        for (int p = 0; p < a; ++p) m *= bx;
+        for (int p = 0; p < d - a; ++p) m *= by;
+        V[(size_t)k * ldv + e] = m;
+    }
+}
+
 }  // namespace
+
+void launch_monomials(hipStream_t s, int nx, int ny, int first, int count, double* V, size_t ldv) {
+    const long total = (long)nx * ny * count;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_monomials, dim3((unsigned)std::min<long>((total + 255) / 256, 65536)), dim3(256), 0, s, nx, ny,
+                       first, count, V, ldv);
+}
 
 template <typename TV>
 void launch_cgs2(hipStream_t s, long n, int r, const TV* V, size_t ldv, const double* weight,

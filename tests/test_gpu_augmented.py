@@ -152,6 +152,29 @@ def test_truncated_factors_match_the_oracle():
         assert rel(X @ S @ W.T, psi_ref) < 1e-10, n
 
 
+@pytest.mark.parametrize("uniform", [True, False])
+def test_initial_basis_is_the_oracles_completion(uniform):
+    """The rank-one initial state's spatial basis, completed by the graded monomials: Cholesky QR of
+    [B(T_init), monomials] on the device (the constant left out when B(T_init) is constant) against the
+    oracle's CGS2 of [B(T_init), 0, ...]."""
+    from paper_2601_18705_amd import dlrtrt
+    p = problems.slab_beam(nx=30, n_polar=4, n_azim=8, rank=9, nsteps=1)
+    p["ny"] = 21
+    n = 30 * 21
+    p["sigma_a"], p["rho_cv"], p["q_ext"] = np.ones(n), np.ones(n), np.zeros(n)
+    if not uniform:
+        rng = np.random.default_rng(5)
+        p["T_init"] = rng.uniform(0.2, 0.9, n)
+    else:
+        p["T_init"] = np.full(n, 0.4)
+    quad = O.quadrature(4, 8)
+    ref = O.dlr_initial_state(augmented(p), quad)
+    with dlrtrt.Instance(p, method="augmented") as inst:
+        X, S, W, _ = inst.read_factors()
+    assert np.max(np.abs(X - ref.X)) < 1e-11 * np.max(np.abs(ref.X))
+    assert np.max(np.abs(S - ref.S)) < 1e-12 * abs(ref.S[0, 0])
+
+
 def test_checkpoint_resume():
     from paper_2601_18705_amd import dlrtrt
     p = problems.slab_beam(nx=40, n_polar=4, n_azim=8, rank=6, nsteps=6)
