@@ -554,82 +554,110 @@ __global__ __launch_bounds__(256) void k_lstep_rhs(LstepArgs a) {
     a.y[o] = qX[i] + lt * a.inv_cdt + fabs(mu) * a.psib[sx] * bv[sx * r + i] + fabs(eta) * a.psib[sy] * bv[sy * r + i];
 }
 
-// Ranks 33 to 64: two wavefronts per ordinate (one workgroup).  Wavefront 0 lane c holds column c of
-// B_q (the identity past r), wavefront 1 lane c column c of the identity; the rows are in registers.
-// Per pivot k, lane k of wavefront 0 copies its column to LDS, both wavefronts read it and eliminate
-// column k from their columns; the copies alternate between two buffers, so one barrier per pivot
-// keeps a buffer from being overwritten while it is read.  As in the one-wavefront form no rows are
-// exchanged (B_q's symmetric part is positive definite; a zero or non-finite pivot flags a singular
-// solve).  Afterwards wavefront 1 holds B_q^{-1} column by column; it goes to memory and to LDS, where
-// wavefront 0 forms y_q = B_q^{-1} Q_q (Q_q from k_lstep_rhs, staged in LDS before the elimination).
+// Ranks 33 to 64: one workgroup of 128 threads per ordinate, Gauss-Jordan on [B_q | I] (64 x 128, the
+// identity past r).  Thread t holds the 8 x 8 block of rows 8 (t / 16) .. + 7 and columns 8 (t % 16) .. + 7
+// in registers.  Per pivot k the threads of block column k / 8 copy their entries of column k, and those
+// of block row k / 8 their entries of row k, to LDS (two buffers each, one barrier per pivot); every
+// thread then reads 8 column and 8 row values and updates its block.  As in the one-wavefront form no
+// rows are exchanged (B_q's symmetric part is positive definite; a zero or non-finite pivot flags a
+// singular solve).  Afterwards the threads of block columns 8..15 hold B_q^{-1}; it goes to memory and
+// to LDS, where 64 threads form y_q = B_q^{-1} Q_q (Q_q from k_lstep_rhs).
 __global__ __launch_bounds__(128) void k_lstep_solve_w2(LstepArgs a) {
-    constexpr int RT = 64;
+    constexpr int RT = 64, NB = 8;
     __shared__ double colk[2][RT];
+    __shared__ double rowk[2][2 * RT];
     __shared__ double Bs[RT * (RT + 1)];
     __shared__ double Qs[RT];
     __shared__ int bad;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t = threadIdx.x, pb = t >> 4, sb = t & 15;   // block row, block column
     const int r = a.r, rr = r * r, q = blockIdx.x;
     const double mu = a.mu[q], eta = a.eta[q];
     const double* Ax = a.ops + (mu > 0.0 ? 0 : 1) * rr;
     const double* Ay = a.ops + (eta > 0.0 ? 2 : 3) * rr;
     const double* Mt = a.ops + 4 * rr;
     const double amu = fabs(mu), aeta = fabs(eta);
-    if (threadIdx.x == 0) bad = 0;
-    double acol[RT];
-    if (wv == 0) {
-        // column lane of [B | I]: entries past r are those of the identity (0/1 masks, no selects of loads)
-        const int cc = lane < r ? lane : r - 1;
+    if (t == 0) bad = 0;
+    if (t < RT) {
+        const double Q = a.y[(size_t)q * r + (t < r ? t : r - 1)];
+        Qs[t] = t < r ? Q : 0.0;
+    }
+    double blk[NB][NB];
+    if (sb < NB) {
+        // columns 8 sb .. of B (the identity past r); clamped loads, 0/1 masks instead of selects of loads
 #pragma unroll
-        for (int i = 0; i < RT; ++i) {
-            const int ic = i < r ? i : r - 1;
-            const double v = amu * Ax[ic * r + cc] + aeta * Ay[ic * r + cc] + Mt[ic * r + cc];
-            const double keep = (i < r && lane < r) ? 1.0 : 0.0;
-            acol[i] = keep * v + (i == lane ? 1.0 - keep : 0.0);
+        for (int ii = 0; ii < NB; ++ii) {
+            const int i = NB * pb + ii, ic = i < r ? i : r - 1;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int c = NB * sb + jj, cc = c < r ? c : r - 1;
+                const double v = amu * Ax[ic * r + cc] + aeta * Ay[ic * r + cc] + Mt[ic * r + cc];
+                const double keep = (i < r && c < r) ? 1.0 : 0.0;
+                blk[ii][jj] = keep * v + (i == c ? 1.0 - keep : 0.0);
+            }
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < RT; ++i) acol[i] = (i == lane) ? 1.0 : 0.0;
-        const double Q = a.y[(size_t)q * r + (lane < r ? lane : r - 1)];
-        Qs[lane] = lane < r ? Q : 0.0;
+        for (int ii = 0; ii < NB; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) blk[ii][jj] = (NB * pb + ii == NB * (sb - NB) + jj) ? 1.0 : 0.0;
     }
-    // The rows move up one register per pivot (row k + j sits in acol[j] at pivot k), so the pivot row
-    // is always acol[0] and no register is indexed by k: the loop stays rolled without dynamic
-    // indexing, and each update writes straight into the register below its source.  After RT pivots
-    // every row is back in its own register.
+    // The eight pivots of a block are unrolled, so the block-local index k % 8 is a constant: the owners
+    // copy fixed registers, every entry takes the same update, and the pivot row is then overwritten
+    // by the threads that hold it (no selects on the pivot index)
     bool sing = false;
 #pragma unroll 1
-    for (int k = 0; k < RT; ++k) {
-        double* ck = colk[k & 1];
-        if (wv == 0 && lane == k) {
+    for (int kb = 0; kb < NB; ++kb) {
 #pragma unroll
-            for (int j = 0; j < RT; ++j) ck[j] = acol[j];
+        for (int kk = 0; kk < NB; ++kk) {
+            const int k = NB * kb + kk, buf = kk & 1;
+            if (sb == kb) {   // column k of this thread's rows
+#pragma unroll
+                for (int ii = 0; ii < NB; ++ii) colk[buf][NB * pb + ii] = blk[ii][kk];
+            }
+            if (pb == kb) {   // row k of this thread's columns
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) rowk[buf][NB * sb + jj] = blk[kk][jj];
+            }
+            __syncthreads();
+            const double piv = colk[buf][k];
+            if (!(fabs(piv) > 0.0) || !isfinite(piv)) sing = true;
+            const double inv = 1.0 / piv;
+            double f[NB], cv[NB];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) f[jj] = rowk[buf][NB * sb + jj] * inv;
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii) cv[ii] = colk[buf][NB * pb + ii];
+#pragma unroll
+            for (int ii = 0; ii < NB; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) blk[ii][jj] = fma(-cv[ii], f[jj], blk[ii][jj]);
+            if (pb == kb) {   // the pivot row becomes row k / pivot
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) blk[kk][jj] = f[jj];
+            }
         }
-        __syncthreads();
-        const double piv = ck[0];
-        if (!(fabs(piv) > 0.0) || !isfinite(piv)) sing = true;
-        const double akk = acol[0] / piv;
-#pragma unroll
-        for (int j = 1; j < RT; ++j) acol[j - 1] = fma(-ck[j], akk, acol[j]);
-        acol[RT - 1] = akk;
     }
     if (sing) bad = 1;
-    if (wv == 1 && lane < r) {
+    if (sb >= NB) {
         double* Bi = a.Binv + (size_t)q * rr;
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
-            if (i < r) {
-                Bi[i * r + lane] = acol[i];
-                Bs[i * (RT + 1) + lane] = acol[i];
+        for (int ii = 0; ii < NB; ++ii) {
+            const int i = NB * pb + ii;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int c = NB * (sb - NB) + jj;
+                Bs[i * (RT + 1) + c] = blk[ii][jj];
+                if (i < r && c < r) Bi[i * r + c] = blk[ii][jj];
             }
+        }
     }
     __syncthreads();
-    if (wv == 0 && lane < r) {
+    if (t < r) {
         double y = 0.0;
-        for (int j = 0; j < r; ++j) y = fma(Bs[lane * (RT + 1) + j], Qs[j], y);
-        a.y[(size_t)q * r + lane] = y;
+        for (int j = 0; j < r; ++j) y = fma(Bs[t * (RT + 1) + j], Qs[j], y);
+        a.y[(size_t)q * r + t] = y;
     }
-    if (threadIdx.x == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
+    if (t == 0 && bad) atomicOr(a.status, (int)kStatusSingularSolve);
 }
 
 // Ranks up to 32: one wavefront per ordinate, lane c holding column c of [B_q | I] (2 RT <= 64
