@@ -198,6 +198,18 @@ def test_runs_are_bitwise_reproducible():
         assert np.array_equal(x["E_r"], y["E_r"]) and np.array_equal(x["T"], y["T"])
 
 
+def test_with_dsa_on_a_thick_checkerboard():
+    """The augmented step under diffusion synthetic acceleration (sigma = 10^4 in alternating blocks,
+    hot start): the accelerated source iteration reaches the oracle's fixed point, FP64 to 1e-10."""
+    p = problems.checkerboard(n=28, n_polar=4, n_azim=8, rank=6, nsteps=2)
+    p["sigma_a"] = problems.checkerboard_sigma(p, thick=1e4, thin=1.0)
+    p["T_init"] = np.full(p["nx"] * p["ny"], 1.0)
+    p["si_tol"] = 1e-13
+    p["dsa"] = 1
+    g, ref = compare(p, 2, 1e-10, "thick checkerboard with DSA")
+    assert max(a["stats"]["si_iters"] for a in g) <= 8
+
+
 def test_rank_limit_is_rejected():
     from paper_2601_18705_amd import dlrtrt
     for p in (problems.slab_beam(nx=16, n_polar=2, n_azim=4, rank=5, nsteps=1),    # 2 r > 8 ordinates
