@@ -357,6 +357,7 @@ def main():
     torch.cuda.synchronize()
     ca = 0
     sweep_ms = 0.0
+    si_ms = 0.0
     launches = 0
     step_ms = 0.0
     svd_sweeps = 0
@@ -370,6 +371,7 @@ def main():
         step_wall.append(time.perf_counter() - ts)
         ca += st["si_iters"] * N * r
         sweep_ms += st["sweep_ms"]
+        si_ms += st["si_ms"]
         launches += st["si_iters"]
         step_ms += st["step_ms"]
         svd_sweeps += st["svd_sweeps"]
@@ -386,6 +388,11 @@ def main():
     bytes_per_launch = N * r * 2 * sweep_bytes + N * 2 * sweep_bytes   # src0 read, psi write; sigma_t, s_e read
     avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    # the whole source-iteration phase (Algorithm 1 step 4): the sweep plus the scalar-flux passes, which
+    # read Psi and write phi and the four orientation copies of s_e (reading phi_old and sigma_s)
+    flux_bytes = N * r * sweep_bytes + 3 * N * 8 + 4 * N * sweep_bytes
+    avg_iter_s = si_ms / 1e3 / max(launches, 1)
+    a4_achieved = (bytes_per_launch + flux_bytes) / avg_iter_s / 1e9 if avg_iter_s > 0 else None
     traffic = load_traffic("sweep_counters_" + p["name"] + ("_fp64" if args.fp64 else "_fp32"))
 
     if args.calibrate_copy_mib:
@@ -427,6 +434,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
                      "launch_shape": {"prefetch_chunks": shape[0], "grid_blocks": shape[1], "chosen_by": "tuner"}},
+        "a4_phase": {"what": "sweep + scalar-flux passes per source iteration", "avg_iteration_ms": avg_iter_s * 1e3,
+                     "algorithmic_bytes": bytes_per_launch + flux_bytes, "achieved": a4_achieved,
+                     "unit": "GB/s", "frac": (a4_achieved / HBM_PEAK_GBS) if a4_achieved else None},
         "checksum": {"E_r_sum": float(E.sum()), "T_sum": float(T.sum())},
         "host": host_info(),
     }

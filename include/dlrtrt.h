@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define DLR_ABI_VERSION 2
+#define DLR_ABI_VERSION 3
 
 typedef enum {
     DLR_OK = 0,
@@ -136,6 +136,8 @@ typedef struct {
     double inflow;                /* power entering through DLR_BC_INFLOW sides */
     double outflow;               /* power leaving through all sides */
     double source;                /* sum over cells of area * q_ext */
+    double si_ms;                 /* device time of the last step's source iterations: the sweeps and the
+                                     scalar-flux passes (Algorithm 1 step 4); 0 for batch slots */
 } dlr_step_stats;
 
 /* Create an instance: validates the problem, copies fields to the device and

@@ -159,6 +159,7 @@ struct dlr_instance {
     int si_it = 0;
     bool si_conv = false;
     float sweep_ms_acc = 0.f;
+    float si_ms_acc = 0.f;   // sweeps and scalar-flux passes of the step's source iterations
     // ---- device memory
     Arena arena;
     double *mu = nullptr, *eta = nullptr, *w = nullptr;
@@ -222,7 +223,7 @@ struct dlr_instance {
     int* h_status = nullptr;
     double* d_h_norm = nullptr;   // the device's addresses of the two pinned areas
     int* d_h_status = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     // second stream for work that does not depend on the main stream's latency-bound kernels
     // (the linearisation beside DEIM, the temperature update beside the SVD); nullptr: in order
     hipStream_t side = nullptr;
@@ -542,6 +543,7 @@ void phase_begin(dlr_instance* I) {
     I->si_it = 0;
     I->si_conv = false;
     I->sweep_ms_acc = 0.f;
+    I->si_ms_acc = 0.f;
 }
 
 // ---------------------------------------------------------------------------------------------- sweep shape tuner
@@ -796,6 +798,7 @@ dlr_status step_read(dlr_instance* I, bool timed_sweeps) {
     for (double v : cwv) sa_ += std::fabs(v);
     I->stats.sum_abs_cw_over_4pi = sa_ / dlr::kFourPi;
     I->stats.sweep_ms = timed_sweeps ? I->sweep_ms_acc : 0.f;
+    I->stats.si_ms = timed_sweeps ? I->si_ms_acc : 0.f;
     I->stats.svd_sweeps = I->h_status[2];   // written by the SVD kernel of this step
     I->stats.step_ms = step_ms;
     I->s_is_usigma = true;
@@ -816,10 +819,13 @@ dlr_status step_once(dlr_instance* I) {
     while (!I->si_conv) {
         sweep_alone<TS>(I);
         si_phi<TS>(I);
+        hip_check(hipEventRecord(I->ev[4], I->stream), "event");
         hip_check(hipStreamSynchronize(I->stream), "sync");
-        float ms = 0.f;
+        float ms = 0.f, si_ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+        hip_check(hipEventElapsedTime(&si_ms, I->ev[2], I->ev[4]), "elapsed");
         I->sweep_ms_acc += ms;
+        I->si_ms_acc += si_ms;
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
         if (!I->si_conv && I->dsa) dsa_correct(I);
@@ -853,15 +859,19 @@ dlr_status sn_step_once(dlr_instance* I) {
     I->si_it = 0;
     I->si_conv = false;
     I->sweep_ms_acc = 0.f;
+    I->si_ms_acc = 0.f;
     while (!I->si_conv) {
         sweep_alone<TS>(I);
         sn_phi<TS>(I, I->phi_cur, I->phi_nxt);
+        hip_check(hipEventRecord(I->ev[4], s), "event");
         std::swap(I->phi_cur, I->phi_nxt);
         publish(I, s, 0, I->norm_out, 3, nullptr, 0, nullptr, 0, 1);
         hip_check(hipStreamSynchronize(s), "sync");
-        float ms = 0.f;
+        float ms = 0.f, si_ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, I->ev[2], I->ev[3]), "elapsed");
+        hip_check(hipEventElapsedTime(&si_ms, I->ev[2], I->ev[4]), "elapsed");
         I->sweep_ms_acc += ms;
+        I->si_ms_acc += si_ms;
         const dlr_status st = si_check(I);
         if (st != DLR_OK) return st;
         if (!I->si_conv && I->dsa) dsa_correct(I);
@@ -891,6 +901,7 @@ dlr_status sn_step_once(dlr_instance* I) {
     I->stats.deim_min_margin = 0.0;
     I->stats.sum_abs_cw_over_4pi = 1.0;
     I->stats.sweep_ms = I->sweep_ms_acc;
+    I->stats.si_ms = I->si_ms_acc;
     I->stats.step_ms = step_ms;
     ++I->steps_done;
     I->stats.steps_done = I->steps_done;
@@ -1908,6 +1919,7 @@ dlr_status dlr_batch_advance(dlr_batch B) {
                 I->si_it = 0;
                 I->si_conv = false;
                 I->sweep_ms_acc = 0.f;
+                I->si_ms_acc = 0.f;
                 I->force_pending = false;
                 I->device_si = true;
                 I->untimed = true;

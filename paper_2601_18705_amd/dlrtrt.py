@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdlrtrt.so")
 
-DLR_ABI_VERSION = 2
+DLR_ABI_VERSION = 3
 DLR_OK = 0
 STATUS_NAMES = {0: "DLR_OK", -1: "DLR_ERR_ARG", -2: "DLR_ERR_OOM", -3: "DLR_ERR_HIP", -4: "DLR_ERR_NOT_CONVERGED",
                 -5: "DLR_ERR_NONFINITE", -6: "DLR_ERR_STATE", -7: "DLR_ERR_UNSUPPORTED", -8: "DLR_ERR_NUMERIC",
@@ -50,7 +50,8 @@ class DlrStepStats(ctypes.Structure):
                 ("sum_abs_cw_over_4pi", ctypes.c_double), ("energy", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("svd_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("inflow", ctypes.c_double), ("outflow", ctypes.c_double), ("source", ctypes.c_double)]
+                ("inflow", ctypes.c_double), ("outflow", ctypes.c_double), ("source", ctypes.c_double),
+                ("si_ms", ctypes.c_double)]
 
 
 # dlr_set_allocator callbacks: alloc(bytes, stream, user) -> device pointer or NULL,
