@@ -91,6 +91,7 @@ def test_slab_beam_fp64():
     (130, 20, 4, 8, 12),     # three strips, Galerkin rank 24 (two 16-plane tiles)
     (7, 64, 3, 4, 1),        # single partial strip, rank one
     (33, 29, 4, 8, 16),      # Galerkin rank 32
+    (36, 30, 8, 8, 20),      # Galerkin rank 40: the three-tile matrix-core paths, the 8 x 8-block L-step
     (40, 33, 8, 8, 32),      # Galerkin rank 64 = every ordinate: the four-tile paths
 ])
 def test_ragged_shapes_fp64(nx, ny, npol, naz, rank):
@@ -112,6 +113,14 @@ def test_random_medium_fp64_and_fp32():
     ref = oracle_run(p, 6)
     compare(p, 6, 1e-10, "random medium 128^2 fp64", ref=ref)
     compare(p, 6, 1e-4, "random medium 128^2 fp32", FP32, ref=ref)
+
+
+@pytest.mark.parametrize("rank", [12, 20])
+def test_bf16_projections(rank):
+    """Split-BF16 projection operands (with FP32 sweeps) on the 2r-column basis, whose old-basis rows of
+    <X0_i, X_j> are a separate count: within 1e-4 of the FP64 oracle."""
+    p = problems.slab_beam(nx=24, n_polar=8, n_azim=8, rank=rank, nsteps=3)
+    compare(p, 3, 1e-4, f"slab 24^2 rank {rank} bf16 projections", {"precision": 2, "si_tol": 1e-6})
 
 
 _FULL = {}
