@@ -136,6 +136,21 @@ def test_full_rank_gpu_equals_plain_sn():
             assert balance_residual(g[n - 1]["stats"]["energy"], a["stats"], p["dt"]) < 1e-12
 
 
+def test_step_timings_are_consistent():
+    """dlr_step_stats timings of a single instance: the source-iteration phase (sweeps and scalar-flux
+    passes) takes at least the sweeps' time and at most the step's; a plain SN handle reports the same."""
+    from paper_2601_18705_amd import dlrtrt
+    p = problems.slab_beam(nx=64, n_polar=4, n_azim=8, rank=8, nsteps=3)
+    for method in ("dlr", "sn"):
+        with dlrtrt.Instance(p, method=method) as inst:
+            for _ in range(3):
+                inst.step(1)
+                st = inst.read_stats()
+                assert 0.0 < st["sweep_ms"] <= st["si_ms"], (method, st)
+                if method == "dlr":
+                    assert st["si_ms"] <= st["step_ms"], st
+
+
 def test_runs_are_bitwise_reproducible():
     p = problems.checkerboard(n=96, n_polar=4, n_azim=8, rank=6, nsteps=3)
     a = gpu_run(p, 3)
