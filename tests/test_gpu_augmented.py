@@ -219,6 +219,29 @@ def test_with_dsa_on_a_thick_checkerboard():
     assert max(a["stats"]["si_iters"] for a in g) <= 8
 
 
+def test_equilibrium_stays_put_through_the_fallbacks():
+    """T_init = T_b on all four sides and no source: psi stays B(T) everywhere.  The swept columns are
+    then all alike, the completion monomials fill both bases, and the 2r Cholesky QR meets exactly
+    dependent columns, so the CGS2 fallbacks run; the truncated state has a single nonzero singular
+    value (its other factors are arbitrary, so the DEIM picks are not compared).  The fields hold the
+    closed form, and the energy tallies equal the oracle's."""
+    from paper_2601_18705_amd import dlrtrt
+    p = problems.slab_beam(nx=20, n_polar=4, n_azim=8, rank=5, nsteps=3)
+    n = p["nx"] * p["ny"]
+    p["T_init"] = np.full(n, 0.5)
+    p["bc"] = [1, 1, 1, 1]
+    p["T_b"] = [0.5] * 4
+    ref = oracle_run(p, 3)
+    with dlrtrt.Instance(p, method="augmented") as inst:
+        for n_, b in enumerate(ref):
+            inst.step(1)
+            E, T = inst.read_fields()
+            st = inst.read_stats()
+            assert np.max(np.abs(T - 0.5)) < 1e-13, n_
+            assert np.max(np.abs(E - 0.5 ** 4)) < 1e-13 * 0.5 ** 4, n_
+            check_balance(st, b, 1e-12, f"equilibrium step {n_}")
+
+
 def test_rank_limit_is_rejected():
     from paper_2601_18705_amd import dlrtrt
     for p in (problems.slab_beam(nx=16, n_polar=2, n_azim=4, rank=5, nsteps=1),    # 2 r > 8 ordinates
