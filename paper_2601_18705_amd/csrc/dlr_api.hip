@@ -128,6 +128,8 @@ struct Arena {
 
 constexpr int kPinnedNorm = 4;                                     // SI norm words
 constexpr int kPinnedDoubles = kPinnedNorm + 2 + 2 * dlr::kMaxRank;   // + energy, outflow, margins, weights
+constexpr int kPinnedInts = 8;   // status words [0, 4), source-iteration control words [4, 7)
+constexpr int kSiSpec = 6;       // source iterations queued at once before the host looks (at most)
 
 struct dlr_instance {
     // ---- problem (host copies)
@@ -186,6 +188,8 @@ struct dlr_instance {
     bool device_si = false;         // source iteration decided on the device (graph-recorded steps)
     bool capturing = false;         // launches are being recorded into a graph: no timing events
     bool untimed = false;           // this step's beginning ran from a recorded graph (no step timing)
+    bool lin_ready = false;         // the last step queued the next step's linearisation behind its statistics
+    int si_last = 0;                // source iterations of the last step: how many the next step queues at once
     int sw_prefetch = 0, sw_grid = 0;   // sweep launch shape (0: chosen by the tuner at the first sweep)
     void* edge = nullptr;
     unsigned long long* progress = nullptr;
@@ -228,6 +232,8 @@ struct dlr_instance {
     // (the linearisation beside DEIM, the temperature update beside the SVD); nullptr: in order
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep start, sweep end, flux end
+    hipEvent_t ev_pub = nullptr;          // behind a step's statistics
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
 
@@ -397,12 +403,16 @@ dlr_status validate(const dlr_problem* p, bool sn = false) {
 template <typename TS>
 dlr_status step_once(dlr_instance* I);
 
-// published: a launch_publish of the four status words is already queued on the stream
-dlr_status check_device_status(dlr_instance* I, bool published = false) {
+// published: a launch_publish of the four status words is already queued on the stream (then `after`,
+// if given, is an event recorded behind it, and the host waits for that instead of the whole stream)
+dlr_status check_device_status(dlr_instance* I, bool published = false, hipEvent_t after = nullptr) {
     if (!published)
         hip_check(hipMemcpyAsync(I->h_status, I->status, 4 * sizeof(int), hipMemcpyDeviceToHost, I->stream),
                   "status copy");
-    hip_check(hipStreamSynchronize(I->stream), "stream sync");
+    if (published && after)
+        hip_check(hipEventSynchronize(after), "event sync");
+    else
+        hip_check(hipStreamSynchronize(I->stream), "stream sync");
     const int st = *I->h_status;
     if (st == 0) return DLR_OK;
     std::string m = "device status";
@@ -497,6 +507,12 @@ void dsa_correct(dlr_instance* I) {
     dlr::launch_dsa(I->stream, a, I->fp32());
 }
 
+// Algorithm 1 step 1 on the instance's current temperature.
+void launch_linearize(dlr_instance* I, hipStream_t s) {
+    dlr::launch_linearize(s, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
+                          I->q, I->sig_t, I->sig_t32, I->ldg, nullptr);
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // One DLR step in phases, so that a batch can interleave the phases of many instances:
 //   phase_begin  linearise, DEIM, old solution at the new ordinates (Algorithm 1 steps 1-3)
@@ -504,23 +520,28 @@ void dsa_correct(dlr_instance* I) {
 //   si_phi       scalar flux, convergence norm and status -> pinned host memory (step 4)
 //   si_check     after the stream has reached si_phi: converged / failed / go on
 //   phase_end    X, projections, L-step, W and S, temperature (steps 5-9)
-//   step_finish  status check and statistics
+//   step_publish, step_read  status check and statistics
+// A step alone (step_once) queues its source iterations several at a time, decided on the device
+// (si_queue), and the next step's linearisation behind its statistics.
 template <typename TS>
 void phase_begin(dlr_instance* I) {
     hipStream_t s = I->stream;
     const int r = I->r, nq = I->nq;
     const double cdt = I->c * I->dt;
     if (!I->capturing) hip_check(hipEventRecord(I->ev[0], s), "event");
-    // 1. effective scattering and source (beside DEIM, which does not read them)
+    // 1. effective scattering and source (beside DEIM, which does not read them), unless the last step
+    // queued them behind its statistics (a step alone: they ran while the host read those)
+    const bool lin = !I->lin_ready;
+    I->lin_ready = false;
+    const bool fork = lin && I->side;
     hipStream_t ls = s;
-    if (I->side) {
+    if (fork) {
         hip_check(hipEventRecord(I->ev_fork, s), "event");
         hip_check(hipStreamWaitEvent(I->side, I->ev_fork, 0), "wait");
         ls = I->side;
     }
-    dlr::launch_linearize(ls, I->nx, I->ny, I->sigma, I->rho_cv, I->q_ext, I->T, I->dt, I->a, I->c, I->D, I->sig_s,
-                          I->q, I->sig_t, I->sig_t32, I->ldg, nullptr);
-    if (I->side) hip_check(hipEventRecord(I->ev_join, I->side), "event");
+    if (lin) launch_linearize(I, ls);
+    if (fork) hip_check(hipEventRecord(I->ev_join, I->side), "event");
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
     dlr::DeimArgs da{};
     da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
@@ -534,7 +555,7 @@ void phase_begin(dlr_instance* I) {
     dlr::launch_deim(s, da);
     I->force_pending = false;
     if (I->dsa) dlr::launch_dsa_kappa(s, r, I->cw, I->sel_mu, I->sel_eta, I->dsa_kappa);
-    if (I->side) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
+    if (fork) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
     dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
                          static_cast<TS*>(I->src0), I->ldg, I->phi, static_cast<TS*>(I->s_e), I->si_flag);
@@ -779,10 +800,10 @@ void step_publish(dlr_instance* I) {
 }
 
 // After the stream has passed step_publish.
-dlr_status step_read(dlr_instance* I, bool timed_sweeps) {
+dlr_status step_read(dlr_instance* I, bool timed_sweeps, hipEvent_t after = nullptr) {
     const int r = I->r;
     double* hf = I->h_norm + kPinnedNorm;
-    const dlr_status st = check_device_status(I, true);
+    const dlr_status st = check_device_status(I, true, after);
     if (st != DLR_OK) return st;
     const double en = hf[0];
     I->stats.outflow = hf[1];
@@ -808,14 +829,84 @@ dlr_status step_read(dlr_instance* I, bool timed_sweeps) {
     return DLR_OK;
 }
 
-dlr_status step_finish(dlr_instance* I, bool timed_sweeps) {
-    step_publish(I);
-    return step_read(I, timed_sweeps);
+
+// Source iterations decided on the device, K of them queued at once.  The scalar-flux pass of each
+// raises the control flag when the iteration has converged, gone non-finite or reached its limit, and
+// the sweeps, flux passes and DSA corrections queued behind it then return at once; the host waits
+// once, reads the flag, and goes on by its own decisions if K iterations were not enough.  The device
+// takes the host loop's decisions (the same test on the same residual), so the results are those of
+// the host loop.  Each iteration is timed as in the host loop; the ones that did not run are left out.
+template <typename TS>
+dlr_status si_queue(dlr_instance* I, int K) {
+    hipStream_t s = I->stream;
+    if (I->sw_prefetch == 0) sweep_tune<TS>(I);
+    I->device_si = true;
+    for (int k = 0; k < K; ++k) {
+        hip_check(hipEventRecord(I->ev_si[3 * k], s), "event");
+        sweep_launch<TS>(I, I->sw_prefetch, I->sw_grid);
+        hip_check(hipEventRecord(I->ev_si[3 * k + 1], s), "event");
+        si_phi<TS>(I);   // swaps the host's names of the two flux buffers
+        hip_check(hipEventRecord(I->ev_si[3 * k + 2], s), "event");
+        if (I->dsa && k + 1 < K) dsa_correct(I);
+    }
+    I->device_si = false;
+    // the last flux pass's norms, the status word and the control words into pinned memory
+    dlr::PublishArgs pa{};
+    pa.src[0] = I->norm_out; pa.n[0] = 3;
+    pa.dst = I->d_h_norm;
+    pa.status = I->status; pa.nstatus = 1; pa.dst_status = I->d_h_status;
+    pa.isrc = I->si_flag; pa.ni = 3; pa.idst = I->d_h_status + 4;
+    dlr::launch_publish(s, pa);
+    hip_check(hipStreamSynchronize(s), "sync");
+    const int* f = I->h_status + 4;   // stopped, iterations run, why (1 converged, 2 non-finite, 3 limit)
+    const int ran = f[1];
+    if (ran < 1 || ran > K) {
+        I->poisoned = true;
+        I->poison_code = DLR_ERR_HIP;
+        return fail(DLR_ERR_HIP, "source-iteration control words out of range");
+    }
+    for (int k = 0; k < ran; ++k) {
+        float ms = 0.f, si_ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, I->ev_si[3 * k], I->ev_si[3 * k + 1]), "elapsed");
+        hip_check(hipEventElapsedTime(&si_ms, I->ev_si[3 * k], I->ev_si[3 * k + 2]), "elapsed");
+        I->sweep_ms_acc += ms;
+        I->si_ms_acc += si_ms;
+    }
+    if ((K - ran) & 1) std::swap(I->phi_cur, I->phi_nxt);   // the newest flux after `ran` iterations
+    I->si_it = ran;
+    if (*I->h_status != 0) return check_device_status(I);
+    const double rel = I->h_norm[2];
+    I->stats.si_residual = rel;
+    const bool rename = I->phi_cur != I->phi && !I->untimed;
+    if (f[2] == 2 || (f[0] == 0 && !std::isfinite(rel))) {
+        I->poisoned = true;
+        I->poison_code = DLR_ERR_NONFINITE;
+        return fail(DLR_ERR_NONFINITE, "non-finite scalar flux in source iteration");
+    }
+    if (f[2] == 1) {
+        I->si_conv = true;
+        if (rename) std::swap(I->phi, I->phi2);
+        return DLR_OK;
+    }
+    if (f[2] == 3) {
+        if (rename) std::swap(I->phi, I->phi2);
+        I->poisoned = true;
+        I->poison_code = DLR_ERR_NOT_CONVERGED;
+        return fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
+    }
+    if (I->dsa) dsa_correct(I);   // the correction after the last queued iteration (host loop from here)
+    return DLR_OK;
 }
 
 template <typename TS>
 dlr_status step_once(dlr_instance* I) {
     phase_begin<TS>(I);
+    // as many source iterations at once as the last step needed (one host wait instead of one each)
+    const int K = std::min(std::min(I->si_last, kSiSpec), I->si_max_iter);
+    if (K >= 2) {
+        const dlr_status st = si_queue<TS>(I, K);
+        if (st != DLR_OK) return st;
+    }
     while (!I->si_conv) {
         sweep_alone<TS>(I);
         si_phi<TS>(I);
@@ -832,7 +923,15 @@ dlr_status step_once(dlr_instance* I) {
     }
     // the DEIM status was checked with the last source iteration's status word (copied after it)
     phase_end<TS>(I);
-    return step_finish(I, true);
+    step_publish(I);
+    // The next step's linearisation (step 1 on the new temperature) behind the statistics: it runs while
+    // the host reads them.  Loading new factors and temperature clears it.
+    hip_check(hipEventRecord(I->ev_pub, I->stream), "event");
+    launch_linearize(I, I->stream);
+    I->lin_ready = true;
+    const dlr_status st = step_read(I, true, I->ev_pub);
+    I->si_last = I->si_it;
+    return st;
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -1371,13 +1470,15 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
         }
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
-        hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, kPinnedInts * sizeof(int), hipHostMallocDefault), "pinned");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_norm, I->h_norm, 0), "pinned mapping");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_status, I->h_status, 0), "pinned mapping");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         hip_check(hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking), "side stream");
         hip_check(hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming), "event create");
         hip_check(hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming), "event create");
+        for (auto& ev : I->ev_si) hip_check(hipEventCreate(&ev), "event create");
+        hip_check(hipEventCreateWithFlags(&I->ev_pub, hipEventDisableTiming), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
         upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
@@ -1470,7 +1571,7 @@ dlr_status dlr_sn_create(const dlr_problem* p, void* hip_stream, dlr_handle* out
         }
         upload_sweep_record(I);
         hip_check(hipHostMalloc((void**)&I->h_norm, kPinnedDoubles * sizeof(double), hipHostMallocDefault), "pinned");
-        hip_check(hipHostMalloc((void**)&I->h_status, 4 * sizeof(int), hipHostMallocDefault), "pinned");
+        hip_check(hipHostMalloc((void**)&I->h_status, kPinnedInts * sizeof(int), hipHostMallocDefault), "pinned");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_norm, I->h_norm, 0), "pinned mapping");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_status, I->h_status, 0), "pinned mapping");
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
@@ -1676,6 +1777,8 @@ dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, co
         upload(h->S, Si, R * R * sizeof(double));
         upload(h->W, W.data(), W.size() * sizeof(double));
         upload(h->T, to_cm(Ti, h->nx, h->ny).data(), n * sizeof(double));
+        h->lin_ready = false;   // the linearisation queued behind the last step used the old temperature
+        h->si_last = 0;
         reset_basis_factor(h);
         refresh_phi(h);
         hip_check(hipDeviceSynchronize(), "sync");
@@ -1731,6 +1834,9 @@ dlr_status dlr_destroy(dlr_handle h) {
     }
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_pub) (void)hipEventDestroy(h->ev_pub);
+    for (auto& ev : h->ev_si)
+        if (ev) (void)hipEventDestroy(ev);
     for (auto& ev : h->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (h->h_norm) (void)hipHostFree(h->h_norm);

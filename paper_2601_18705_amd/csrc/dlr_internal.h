@@ -348,6 +348,9 @@ struct PublishArgs {
     const int* status;
     int nstatus;
     int* dst_status;
+    const int* isrc;   // optional: ni more ints to idst
+    int ni;
+    int* idst;
 };
 void launch_publish(hipStream_t s, const PublishArgs& a);
 // For n instances: their source-iteration control words flag[0..2], status word and last relative

@@ -1216,6 +1216,8 @@ __global__ __launch_bounds__(256) void k_publish(PublishArgs a) {
     }
     for (int i = threadIdx.x; i < a.nstatus; i += blockDim.x)
         __hip_atomic_store(a.dst_status + i, a.status[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (int i = threadIdx.x; i < a.ni; i += blockDim.x)
+        __hip_atomic_store(a.idst + i, a.isrc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
 }
 
