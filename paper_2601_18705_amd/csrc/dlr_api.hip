@@ -1073,9 +1073,12 @@ void init_fields(dlr_instance* I, const dlr_problem* p, hipStream_t stream, bool
     I->nb_gram = (int)std::max<long>(1, std::min<long>((passes + 3) / 4, 512));
     I->nb_gram_ang = std::max(1, std::min((((int)I->nq + 31) / 32 + 3) / 4, 32));
     I->nb_proj = std::max(1, std::min(chunks, 512));
-    // temperature update: about four blocks per CU keep enough of the r plane loads in flight
-    // (one block per CU left the kernel latency-bound)
-    I->nb_cells = (int)std::max<long>(1, std::min<long>(((long)I->N + 255) / 256, 1024));
+    // temperature update: four blocks per CU keep enough of the r plane loads in flight (one block per
+    // CU left the kernel latency-bound), on all CUs but one per XCD.  The kernel runs beside the
+    // single-workgroup SVD, whose CU has room for only two of its blocks, and workgroups are dealt
+    // round-robin over the eight XCDs: with four blocks on every CU (1024) two blocks of that XCD
+    // waited for a whole block's time.  (256 CUs in 8 XCDs.)
+    I->nb_cells = (int)std::max<long>(1, std::min<long>(((long)I->N + 255) / 256, 4 * (256 - 8)));
     const size_t rr = (size_t)I->ra * I->ra;
     I->partials_count = std::max({(size_t)I->nb_gram * rr, (size_t)I->nb_gram_ang * rr,
                                   (size_t)I->nb_proj * (5 * rr + 5 * I->ra),

@@ -448,6 +448,11 @@ __global__ __launch_bounds__(kBlock) void k_tupdate(TupdateArgs A) {
     double en = 0.0, ob = 0.0;
     bool bad = false;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        // The coefficients and side vectors are read from LDS in every pass: held in registers across
+        // the loop (5 r doubles, the compiler's choice without this barrier) they left room for one
+        // wavefront per SIMD, and a CU that holds another kernel's workgroup (the SVD beside this
+        // kernel) took none of these blocks.
+        asm volatile("" ::: "memory");
         double ph = 0.0;
         double v[RMAX];
         if (A.X) {

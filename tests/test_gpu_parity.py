@@ -206,6 +206,51 @@ def test_nonconvergence_is_reported_and_poisons_handle():
         assert ei2.value.status == -6
 
 
+def heated_slab(dt_factor):
+    """Slab beam on 24^2, 32 ordinates, rank 4, at a tenfold (hundredfold) time step and SI tolerance
+    1e-13: the medium heats up, scattering gains weight, and the oracle takes 3, 3, 4 (3, 7, 9, 10, 10)
+    source iterations per step, the same counts for tolerances 10% either way."""
+    p = problems.slab_beam(nx=24, n_polar=4, n_azim=8, rank=4, nsteps=5)
+    p["dt"] *= dt_factor
+    p["si_tol"] = 1e-13
+    return p
+
+
+def test_queued_source_iterations_follow_the_oracle():
+    """From its second step an instance queues as many source iterations as the last step took (at
+    most six), decided on the device; with the count rising from 3 to 10 the host goes on after the
+    queued ones.  Fields as the oracle's at every step, and the same iteration counts."""
+    from paper_2601_18705_amd import dlrtrt
+    p = heated_slab(100)
+    ref = oracle_run(p, 5)
+    assert [h["si_iters"] for h in ref] == [3, 7, 9, 10, 10]
+    compare(p, 5, 1e-10, "heated slab, queued source iterations", ref=ref)
+    with dlrtrt.Instance(p) as inst:
+        for n in range(5):
+            inst.step(1)
+            st = inst.read_stats()
+            assert st["si_iters"] == ref[n]["si_iters"], (n, st["si_iters"])
+            assert 0.0 < st["sweep_ms"] <= st["si_ms"] <= st["step_ms"], st
+
+
+def test_iteration_limit_in_queued_source_iterations():
+    """The iteration limit met inside the queued iterations (the device's decision) is reported as the
+    host loop reports it: NOT_CONVERGED, and the handle is poisoned."""
+    from paper_2601_18705_amd import dlrtrt
+    ref = oracle_run(heated_slab(10), 3)
+    assert [h["si_iters"] for h in ref] == [3, 3, 4]
+    with dlrtrt.Instance(dict(heated_slab(10), si_max_iter=3)) as inst:
+        for n in range(2):
+            inst.step(1)
+            assert inst.read_stats()["si_iters"] == 3
+        with pytest.raises(dlrtrt.DlrError) as ei:
+            inst.step(1)
+        assert ei.value.status == -4
+        with pytest.raises(dlrtrt.DlrError) as ei2:
+            inst.step(1)
+        assert ei2.value.status == -6
+
+
 FP32 = {"precision": 1, "si_tol": 1e-6}
 
 
