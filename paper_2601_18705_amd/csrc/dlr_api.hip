@@ -202,6 +202,7 @@ struct dlr_instance {
     size_t ldg = 0;   // elements of one diagonal sweep plane (psi, src0, and the 4 copies of sigma_t, s_e)
     double* partials = nullptr;
     size_t partials_count = 0;
+    double* tpart = nullptr;   // the temperature update's block sums (it runs beside kernels that use partials)
     double* norm_out = nullptr;
     double* energy_out = nullptr;
     unsigned* counters = nullptr;
@@ -338,6 +339,7 @@ struct dlr_instance {
         sweep_rec = A.take<char>(sizeof(dlr::SweepArgs<double>));
         unit_end = A.take<unsigned>(4);
         partials = A.take<double>(partials_count);
+        tpart = A.take<double>(2 * (size_t)nb_cells);
         norm_out = A.take<double>(4);
         energy_out = A.take<double>(2);
         counters = A.take<unsigned>(8);
@@ -486,7 +488,8 @@ dlr::TupdateArgs tupdate_args(dlr_instance* I, const double* X, const double* gs
     A.sigma = I->sigma; A.rho_cv = I->rho_cv; A.D = I->D;
     A.dt = I->dt; A.a = I->a; A.c = I->c; A.area = I->area; A.hx = I->hx; A.hy = I->hy;
     A.T = I->T; A.phi = I->phi;
-    A.partials = I->partials; A.counter = I->counters + 1; A.out = I->energy_out; A.status = I->status;
+    A.partials = I->tpart ? I->tpart : I->partials;
+    A.counter = I->counters + 1; A.out = I->energy_out; A.status = I->status;
     return A;
 }
 
@@ -772,16 +775,18 @@ void phase_end(dlr_instance* I) {
         return;
     }
     // 9. temperature update with the mean intensity of the new factors, energy sum and outflow.  The
-    // state is psi = (Xn Rxi) Ra^T Wq^T; the SVD of S = Ra^T only rotates W and S (S' W'^T = Ra^T Wq^T),
-    // so the mean intensity coefficients and the outflow side vectors are formed from (Wq, Rxi Ra^T)
-    // for the stored Xn, and the temperature update runs beside the SVD on the second stream
+    // mean intensity of the new state is X S W^T w with X = Xn Rxi and S W^T = L^T (the L-step's
+    // result; the angular QR and the SVD only factor it), so the coefficients are Rxi L^T w and the
+    // outflow side vectors Rxi L^T f_side: the temperature update needs nothing the SVD writes and
+    // runs beside it on the second stream.  (Started right after the L-step instead, it took the CUs
+    // that the angular QR's small kernels wait for.)
     hipStream_t ts = s;
     if (I->side) {
         hip_check(hipEventRecord(I->ev_fork, s), "event");
         hip_check(hipStreamWaitEvent(I->side, I->ev_fork, 0), "wait");
         ts = I->side;
     }
-    dlr::launch_wsum(ts, nq, r, I->Wq, I->w, I->Ra, I->beta, I->coef, I->mu, I->eta, I->gside, true, I->Rxi);
+    dlr::launch_wsum(ts, nq, r, I->L, I->w, nullptr, I->beta, I->coef, I->mu, I->eta, I->gside, false, I->Rxi);
     dlr::launch_tupdate(ts, tupdate_args(I, I->Xn, I->gside), I->nb_cells);
     if (I->side) hip_check(hipEventRecord(I->ev_join, I->side), "event");
     // 8 (end). SVD of S: W <- Wq V, S <- S V (columns U_k sigma_k), stored as Rxi S V for Xn

@@ -333,7 +333,8 @@ void launch_trunc(hipStream_t s, int ra, int r, const double* Sv, double* Q, dou
 // of the outflow tally: gside[s][i] = sum_j S[i][j] sum_{q leaving through side s} w_q |Omega_q . n_s| W[j][q]
 // (sides 0 left, 1 right, 2 bottom, 3 top).
 // s_transposed: the matrix given is S^T (as the angular QR's R factor, S = R^T).  Tl: the matrix
-// used is Tl S (Tl r x r, row-major), for a spatial basis stored as X Tl^{-1}.
+// used is Tl S (Tl r x r, row-major), for a spatial basis stored as X Tl^{-1}.  S = nullptr stands for
+// the identity (then Tl is required): W is then L = W S^T itself.
 void launch_wsum(hipStream_t s, int nq, int r, const double* W, const double* w, const double* S, double* beta,
                  double* coef, const double* mu = nullptr, const double* eta = nullptr, double* gside = nullptr,
                  bool s_transposed = false, const double* Tl = nullptr);

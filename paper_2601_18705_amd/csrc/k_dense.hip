@@ -833,7 +833,6 @@ __global__ __launch_bounds__(kLsThreads) void k_lstep_apply(LstepArgs a) {
 // pairs of a round are disjoint, so the sixteen lanes of pair k compute its rotation
 // from their own rows and apply it at once: one barrier per round.
 constexpr int kSvdLanes = 16;   // lanes per column pair: one DPP row
-constexpr int kSvdThreads = kSvdLanes * kMaxRank / 2;
 
 // v moved across the lanes of a DPP row (ctrl: quad_perm, row_half_mirror, row_mirror)
 template <int CTRL>
@@ -853,21 +852,24 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __restrict__ Rin,
-                                                     double* __restrict__ Vout, double* __restrict__ Sout,
-                                                     int* status, const double* __restrict__ Tl) {
-    __shared__ double S[kMaxRank * kMaxRank];
-    __shared__ double V[kMaxRank * kMaxRank];
-    __shared__ double nrm[kMaxRank];
-    __shared__ int order[kMaxRank];
-    __shared__ double sTl[kMaxRank * kMaxRank];   // with Tl: Tl; sP: the sorted S V
-    __shared__ double sP[kMaxRank * kMaxRank];
+// RMAX: rank bound (32 or 64); RMAX / 2 column pairs of 16 lanes, each lane RMAX / 16 rows.
+template <int RMAX>
+__global__ __launch_bounds__(kSvdLanes * RMAX / 2) void k_svd(int r, const double* __restrict__ Rin,
+                                                               double* __restrict__ Vout, double* __restrict__ Sout,
+                                                               int* status, const double* __restrict__ Tl) {
+    constexpr int NT = kSvdLanes * RMAX / 2, RT = RMAX / kSvdLanes;
+    __shared__ double S[RMAX * RMAX];
+    __shared__ double V[RMAX * RMAX];
+    __shared__ double nrm[RMAX];
+    __shared__ int order[RMAX];
+    __shared__ double sTl[RMAX * RMAX];   // with Tl: Tl; sP: the sorted S V
+    __shared__ double sP[RMAX * RMAX];
     const int tid = threadIdx.x;
     const int rr = r * r;
     if (Tl) stage_lds(sTl, Tl, rr);   // read at the end; the barriers of the sweeps order it
     // column-major: column c of S = R^T is row c of R, S[c * r + i] = R[c][i]; the lanes of a pair
     // read consecutive rows of a column (no bank conflicts)
-    for (int o = tid; o < rr; o += kSvdThreads) {
+    for (int o = tid; o < rr; o += NT) {
         const int c = o / r, i = o % r;
         S[o] = Rin[o];
         V[o] = (i == c) ? 1.0 : 0.0;
@@ -892,9 +894,9 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
                 const int q = 1 + tq;
                 if (p < r && q < r) {
                     // the pair's rows of this lane (i = lane + 16 t), loaded once, clamped and masked
-                    double sp[4], sq[4], vp[4], vq[4];
+                    double sp[RT], sq[RT], vp[RT], vq[RT];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
+                    for (int t = 0; t < RT; ++t) {
                         const int i = lane + kSvdLanes * t;
                         const int ic = i < r ? i : r - 1;
                         sp[t] = S[p * r + ic];
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
                     }
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
+                    for (int t = 0; t < RT; ++t) {
                         const bool on = lane + kSvdLanes * t < r;
                         const double x = on ? sp[t] : 0.0, y = on ? sq[t] : 0.0;
                         al += x * x;
@@ -916,15 +918,23 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
                     ga = row16_sum(ga);
                     if (ga != 0.0 && ga * ga > tol * tol * (al * be)) {
                         // tan of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
-                        // zeta = (be - al) / (2 ga), written without forming zeta
+                        // zeta = (be - al) / (2 ga), written without forming zeta.  The angle need not be
+                        // exact (a slightly different rotation is still a rotation; the sweeps go on until
+                        // every pair is orthogonal), so the quotient takes the hardware reciprocal and two
+                        // Newton steps; cos and sin come from an exact reciprocal square root, which keeps
+                        // the rotation orthogonal to working precision.
                         const double d = be - al;
                         const double sgn = (d * ga >= 0.0) ? 1.0 : -1.0;
-                        const double tt = sgn * (2.0 * fabs(ga)) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+                        const double den = fabs(d) + sqrt(d * d + 4.0 * ga * ga);   // >= 2 |ga| > 0
+                        double rc = __builtin_amdgcn_rcp(den);
+                        rc = fma(rc, fma(-den, rc, 1.0), rc);
+                        rc = fma(rc, fma(-den, rc, 1.0), rc);
+                        const double tt = sgn * (2.0 * fabs(ga)) * rc;
                         const double c = rsqrt(1.0 + tt * tt);
                         const double sn = c * tt;
                         rotated = 1;
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) {
+                        for (int t = 0; t < RT; ++t) {
                             const int i = lane + kSvdLanes * t;
                             if (i < r) {
                                 S[p * r + i] = c * sp[t] - sn * sq[t];
@@ -942,7 +952,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
     }
     if (tid == 0 && !converged) atomicOr(status, (int)kStatusSvdNoConv);
     if (tid == 0) status[2] = sweep;   // diagnostic: sweeps taken
-    for (int c = tid; c < r; c += kSvdThreads) {
+    for (int c = tid; c < r; c += NT) {
         double sum = 0.0;
         for (int i = 0; i < r; ++i) sum += S[c * r + i] * S[c * r + i];
         nrm[c] = sqrt(sum);
@@ -950,13 +960,13 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
     __syncthreads();
     // stable descending order: rank of column c = columns with a larger norm, or an equal norm
     // and a smaller index
-    for (int c = tid; c < r; c += kSvdThreads) {
+    for (int c = tid; c < r; c += NT) {
         int rank = 0;
         for (int m = 0; m < r; ++m) rank += (nrm[m] > nrm[c] || (nrm[m] == nrm[c] && m < c)) ? 1 : 0;
         order[rank] = c;
     }
     __syncthreads();
-    for (int c = tid; c < r; c += kSvdThreads) {
+    for (int c = tid; c < r; c += NT) {
         const int src = order[c];
         int m = 0;
         double best = -1.0;
@@ -973,7 +983,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd(int r, const double* __rest
     }
     if (Tl) {   // Sout = Tl (S V), one output per thread and pass (consecutive threads: consecutive columns)
         __syncthreads();
-        for (int o = tid; o < rr; o += kSvdThreads) {
+        for (int o = tid; o < rr; o += NT) {
             const int i = o / r, c = o % r;
             double acc = 0.0;
             for (int k = 0; k < r; ++k) acc = fma(sTl[i * r + k], sP[k * r + c], acc);
@@ -1148,13 +1158,14 @@ __global__ __launch_bounds__(1024) void k_wsum(int nq, int r, const double* __re
     __shared__ double sS[kMaxRank * kMaxRank];
     __shared__ double sT[kMaxRank * kMaxRank];
     __shared__ double sE[kMaxRank * (kMaxRank + 1)];
-    stage_lds(sS, S, r * r);
-    if (Tl) stage_lds(sT, Tl, r * r);
+    // without S (the identity) the matrix used is Tl itself
+    stage_lds(sS, S ? S : Tl, r * r);
+    if (S && Tl) stage_lds(sT, Tl, r * r);
     __syncthreads();
     // S[i][j] is sS[i * r + j], or sS[j * r + i] when the matrix given is S^T; with Tl the matrix used
     // is Tl S (formed in LDS first)
-    int si = transpose_s ? 1 : r, sj = transpose_s ? r : 1;
-    if (Tl) {
+    int si = (S && transpose_s) ? 1 : r, sj = (S && transpose_s) ? r : 1;
+    if (S && Tl) {
         // sE = Tl S.  S[k][j] is read as a row of the (transposed) matrix given when transpose_s, so
         // it is first copied with an odd stride (r + 1): consecutive threads (consecutive j) then read
         // different LDS banks instead of one bank r doubles apart
@@ -1269,7 +1280,10 @@ void launch_lstep(hipStream_t s, const LstepArgs& a) {
 }
 
 void launch_svd(hipStream_t s, int r, const double* R, double* V, double* Snew, int* status, const double* Tl) {
-    hipLaunchKernelGGL(k_svd, dim3(1), dim3(kSvdThreads), 0, s, r, R, V, Snew, status, Tl);
+    if (r <= 32)
+        hipLaunchKernelGGL(k_svd<32>, dim3(1), dim3(kSvdLanes * 16), 0, s, r, R, V, Snew, status, Tl);
+    else
+        hipLaunchKernelGGL(k_svd<64>, dim3(1), dim3(kSvdLanes * 32), 0, s, r, R, V, Snew, status, Tl);
 }
 
 void launch_rmul(hipStream_t s, int n, int r, const double* V, const double* M, double* X) {
