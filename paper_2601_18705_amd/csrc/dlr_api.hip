@@ -233,7 +233,7 @@ struct dlr_instance {
     // (the linearisation beside DEIM, the temperature update beside the SVD); nullptr: in order
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep start, sweep end, flux end
+    hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep starts, sweep ends, flux ends
     hipEvent_t ev_pub = nullptr;          // behind a step's statistics
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
@@ -846,13 +846,29 @@ dlr_status si_queue(dlr_instance* I, int K) {
     hipStream_t s = I->stream;
     if (I->sw_prefetch == 0) sweep_tune<TS>(I);
     I->device_si = true;
+    // events: iteration k's sweep runs from ev_si[st[k]] to ev_si[sw[k]], the iteration to ev_si[en[k]];
+    // without DSA the end of one iteration is the start of the next (one event fewer per iteration:
+    // each event costs a few microseconds of idle GPU between the kernels around it)
+    int st[kSiSpec], sw[kSiSpec], en[kSiSpec];
+    int ne = 0;
+    st[0] = ne;
+    hip_check(hipEventRecord(I->ev_si[ne++], s), "event");
     for (int k = 0; k < K; ++k) {
-        hip_check(hipEventRecord(I->ev_si[3 * k], s), "event");
         sweep_launch<TS>(I, I->sw_prefetch, I->sw_grid);
-        hip_check(hipEventRecord(I->ev_si[3 * k + 1], s), "event");
+        sw[k] = ne;
+        hip_check(hipEventRecord(I->ev_si[ne++], s), "event");
         si_phi<TS>(I);   // swaps the host's names of the two flux buffers
-        hip_check(hipEventRecord(I->ev_si[3 * k + 2], s), "event");
-        if (I->dsa && k + 1 < K) dsa_correct(I);
+        en[k] = ne;
+        hip_check(hipEventRecord(I->ev_si[ne++], s), "event");
+        if (k + 1 < K) {
+            if (I->dsa) {
+                dsa_correct(I);
+                st[k + 1] = ne;
+                hip_check(hipEventRecord(I->ev_si[ne++], s), "event");
+            } else {
+                st[k + 1] = en[k];
+            }
+        }
     }
     I->device_si = false;
     // the last flux pass's norms, the status word and the control words into pinned memory
@@ -872,8 +888,8 @@ dlr_status si_queue(dlr_instance* I, int K) {
     }
     for (int k = 0; k < ran; ++k) {
         float ms = 0.f, si_ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, I->ev_si[3 * k], I->ev_si[3 * k + 1]), "elapsed");
-        hip_check(hipEventElapsedTime(&si_ms, I->ev_si[3 * k], I->ev_si[3 * k + 2]), "elapsed");
+        hip_check(hipEventElapsedTime(&ms, I->ev_si[st[k]], I->ev_si[sw[k]]), "elapsed");
+        hip_check(hipEventElapsedTime(&si_ms, I->ev_si[st[k]], I->ev_si[en[k]]), "elapsed");
         I->sweep_ms_acc += ms;
         I->si_ms_acc += si_ms;
     }
