@@ -235,6 +235,7 @@ struct dlr_instance {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep starts, sweep ends, flux ends
     hipEvent_t ev_pub = nullptr;          // behind a step's statistics
+    hipEvent_t ev_siq = nullptr;          // behind the queued source iterations' control words
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
 
@@ -691,8 +692,12 @@ dlr_status si_check(dlr_instance* I) {
     return DLR_OK;
 }
 
+// Steps 5 to 8 up to the angular QR.  Everything this part writes is scratch (the new basis, the
+// projections, the L-step, the angular factors); the state (X, S, W, T) is written only by
+// phase_end_b, so a step alone can queue this part before the host knows that the source iteration
+// has converged, and queue it again after further iterations if it had not.
 template <typename TS>
-void phase_end(dlr_instance* I) {
+void phase_end_a(dlr_instance* I) {
     hipStream_t s = I->stream;
     const int N = I->N, r = I->r, nq = I->nq, rg = I->ra;
     const double cdt = I->c * I->dt;
@@ -761,6 +766,14 @@ void phase_end(dlr_instance* I) {
     dlr::launch_small_matmul(s, rg, I->R2, I->R1, I->Ra);
     dlr::launch_cgs2<double>(s, nq, rg, I->L, (size_t)nq, I->w, 0.0, 1, I->nx, I->ny, I->mu, I->eta, I->Wq, I->Ra,
                              I->status, dlr::kStatusQrBreakdownW, I->status, dlr::kStatusNoCompletion);
+}
+
+// The rest of steps 8 and 9: SVD (and the truncation of the augmented basis), new W and S, the
+// temperature update; the new state.
+template <typename TS>
+void phase_end_b(dlr_instance* I) {
+    hipStream_t s = I->stream;
+    const int N = I->N, r = I->r, nq = I->nq, rg = I->ra;
     if (I->augment) {
         // 8 (end, augmented basis). SVD of the 2r x 2r S = Ra^T and truncation to its r largest singular
         // values: with (U Sigma)_r = Q R, the new state is X = Xn Q, S = R, W = Wq V_r.  The temperature
@@ -796,6 +809,12 @@ void phase_end(dlr_instance* I) {
     std::swap(I->X, I->Xn);
     std::swap(I->S, I->Sn);
     if (!I->capturing) hip_check(hipEventRecord(I->ev[1], s), "event");
+}
+
+template <typename TS>
+void phase_end(dlr_instance* I) {
+    phase_end_a<TS>(I);
+    phase_end_b<TS>(I);
 }
 
 // energy, DEIM margins and weights into pinned memory behind the step; the status check's
@@ -841,8 +860,12 @@ dlr_status step_read(dlr_instance* I, bool timed_sweeps, hipEvent_t after = null
 // once, reads the flag, and goes on by its own decisions if K iterations were not enough.  The device
 // takes the host loop's decisions (the same test on the same residual), so the results are those of
 // the host loop.  Each iteration is timed as in the host loop; the ones that did not run are left out.
+// With `ahead`, the first part of the step's end (phase_end_a, which writes only scratch) is queued
+// behind them before the host looks, so the GPU is not idle while it does; if the iteration turns out
+// not to have converged, that part is queued again later and the status bits it may have raised on
+// the unconverged data are cleared (the status word read before it was clean).
 template <typename TS>
-dlr_status si_queue(dlr_instance* I, int K) {
+dlr_status si_queue(dlr_instance* I, int K, bool ahead) {
     hipStream_t s = I->stream;
     if (I->sw_prefetch == 0) sweep_tune<TS>(I);
     I->device_si = true;
@@ -878,7 +901,9 @@ dlr_status si_queue(dlr_instance* I, int K) {
     pa.status = I->status; pa.nstatus = 1; pa.dst_status = I->d_h_status;
     pa.isrc = I->si_flag; pa.ni = 3; pa.idst = I->d_h_status + 4;
     dlr::launch_publish(s, pa);
-    hip_check(hipStreamSynchronize(s), "sync");
+    hip_check(hipEventRecord(I->ev_siq, s), "event");
+    if (ahead) phase_end_a<TS>(I);
+    hip_check(hipEventSynchronize(I->ev_siq), "sync");
     const int* f = I->h_status + 4;   // stopped, iterations run, why (1 converged, 2 non-finite, 3 limit)
     const int ran = f[1];
     if (ran < 1 || ran > K) {
@@ -915,6 +940,7 @@ dlr_status si_queue(dlr_instance* I, int K) {
         I->poison_code = DLR_ERR_NOT_CONVERGED;
         return fail(DLR_ERR_NOT_CONVERGED, "source iteration reached si_max_iter");
     }
+    if (ahead) hip_check(hipMemsetAsync(I->status, 0, sizeof(int), s), "status reset");
     if (I->dsa) dsa_correct(I);   // the correction after the last queued iteration (host loop from here)
     return DLR_OK;
 }
@@ -924,9 +950,11 @@ dlr_status step_once(dlr_instance* I) {
     phase_begin<TS>(I);
     // as many source iterations at once as the last step needed (one host wait instead of one each)
     const int K = std::min(std::min(I->si_last, kSiSpec), I->si_max_iter);
+    bool ended_a = false;   // phase_end_a is queued behind the converged iteration
     if (K >= 2) {
-        const dlr_status st = si_queue<TS>(I, K);
+        const dlr_status st = si_queue<TS>(I, K, true);
         if (st != DLR_OK) return st;
+        ended_a = I->si_conv;
     }
     while (!I->si_conv) {
         sweep_alone<TS>(I);
@@ -943,7 +971,8 @@ dlr_status step_once(dlr_instance* I) {
         if (!I->si_conv && I->dsa) dsa_correct(I);
     }
     // the DEIM status was checked with the last source iteration's status word (copied after it)
-    phase_end<TS>(I);
+    if (!ended_a) phase_end_a<TS>(I);
+    phase_end_b<TS>(I);
     step_publish(I);
     // The next step's linearisation (step 1 on the new temperature) behind the statistics: it runs while
     // the host reads them.  Loading new factors and temperature clears it.
@@ -1503,6 +1532,7 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
         hip_check(hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming), "event create");
         for (auto& ev : I->ev_si) hip_check(hipEventCreate(&ev), "event create");
         hip_check(hipEventCreateWithFlags(&I->ev_pub, hipEventDisableTiming), "event create");
+        hip_check(hipEventCreateWithFlags(&I->ev_siq, hipEventDisableTiming), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
         upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
@@ -1859,6 +1889,7 @@ dlr_status dlr_destroy(dlr_handle h) {
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->ev_pub) (void)hipEventDestroy(h->ev_pub);
+    if (h->ev_siq) (void)hipEventDestroy(h->ev_siq);
     for (auto& ev : h->ev_si)
         if (ev) (void)hipEventDestroy(ev);
     for (auto& ev : h->ev)
