@@ -180,6 +180,7 @@ struct dlr_instance {
     void *psi = nullptr, *src0 = nullptr, *s_e = nullptr, *psi_cm = nullptr;
     double *phi = nullptr, *phi2 = nullptr;
     int *sel = nullptr, *forced = nullptr;
+    int* sel_alt = nullptr;     // picks of a selection queued for the next step (swapped with sel when it starts)
     double *cw = nullptr, *C0 = nullptr, *a0 = nullptr, *margins = nullptr, *sel_mu = nullptr, *sel_eta = nullptr;
     double *inflow_x = nullptr, *inflow_y = nullptr, *deim_work = nullptr;
     unsigned* deim_count = nullptr;
@@ -189,6 +190,7 @@ struct dlr_instance {
     bool capturing = false;         // launches are being recorded into a graph: no timing events
     bool untimed = false;           // this step's beginning ran from a recorded graph (no step timing)
     bool lin_ready = false;         // the last step queued the next step's linearisation behind its statistics
+    bool deim_ready = false;        // ... and its start event and angle selection (DEIM)
     int si_last = 0;                // source iterations of the last step: how many the next step queues at once
     int sw_prefetch = 0, sw_grid = 0;   // sweep launch shape (0: chosen by the tuner at the first sweep)
     void* edge = nullptr;
@@ -234,7 +236,7 @@ struct dlr_instance {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep starts, sweep ends, flux ends
-    hipEvent_t ev_pub = nullptr;          // behind a step's statistics
+    hipEvent_t ev_pub = nullptr;          // behind a step's statistics (and the next step's start)
     hipEvent_t ev_siq = nullptr;          // behind the queued source iterations' control words
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
@@ -322,6 +324,7 @@ struct dlr_instance {
         phi2 = A.take<double>(n);
         sel = A.take<int>(R);
         forced = A.take<int>(R);
+        sel_alt = A.take<int>(R);
         cw = A.take<double>(R);
         C0 = A.take<double>(R * R);
         a0 = A.take<double>(R);
@@ -517,6 +520,24 @@ void launch_linearize(dlr_instance* I, hipStream_t s) {
                           I->q, I->sig_t, I->sig_t32, I->ldg, nullptr);
 }
 
+// Algorithm 1 step 2 on the instance's current W and S: DEIM (forced picks if pending), the weights,
+// C0 = S W[sel]^T, a0 = S beta, and the DSA coefficients of the picks.
+void launch_selection(dlr_instance* I, hipStream_t s, int* sel_out) {
+    const int r = I->r;
+    dlr::DeimArgs da{};
+    da.nq = I->nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
+    da.forced = I->force_pending ? I->forced : nullptr;
+    da.xchg = I->deim_work; da.xcount = I->deim_count; da.launch_seq = dlr::next_sweep_launch_id();
+    da.seq_ctr = I->device_si ? I->deim_ctr : nullptr; da.sel = sel_out; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
+    da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
+    da.mu = I->mu; da.eta = I->eta;
+    for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];
+    da.status = I->status;
+    dlr::launch_deim(s, da);
+    I->force_pending = false;
+    if (I->dsa) dlr::launch_dsa_kappa(s, r, I->cw, I->sel_mu, I->sel_eta, I->dsa_kappa);
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // One DLR step in phases, so that a batch can interleave the phases of many instances:
 //   phase_begin  linearise, DEIM, old solution at the new ordinates (Algorithm 1 steps 1-3)
@@ -530,11 +551,20 @@ void launch_linearize(dlr_instance* I, hipStream_t s) {
 template <typename TS>
 void phase_begin(dlr_instance* I) {
     hipStream_t s = I->stream;
-    const int r = I->r, nq = I->nq;
+    const int r = I->r;
     const double cdt = I->c * I->dt;
-    if (!I->capturing) hip_check(hipEventRecord(I->ev[0], s), "event");
+    // A step alone queues the next step's start behind its statistics (start event, linearisation,
+    // selection): they run while the host reads those.  A selection forced since is made again here.
+    const bool queued = I->deim_ready;
+    I->deim_ready = false;
+    if (queued) {
+        std::swap(I->ev[0], I->ev_pub);   // the last step's statistics event starts this step
+        std::swap(I->sel, I->sel_alt);    // the queued selection's picks
+    } else if (!I->capturing) {
+        hip_check(hipEventRecord(I->ev[0], s), "event");
+    }
     // 1. effective scattering and source (beside DEIM, which does not read them), unless the last step
-    // queued them behind its statistics (a step alone: they ran while the host read those)
+    // queued them behind its statistics
     const bool lin = !I->lin_ready;
     I->lin_ready = false;
     const bool fork = lin && I->side;
@@ -547,18 +577,7 @@ void phase_begin(dlr_instance* I) {
     if (lin) launch_linearize(I, ls);
     if (fork) hip_check(hipEventRecord(I->ev_join, I->side), "event");
     // 2. DEIM angle selection on W (and the weights, C0 = S W[sel]^T, a0 = S beta)
-    dlr::DeimArgs da{};
-    da.nq = nq; da.r = r; da.W = I->W; da.S = I->S; da.w = I->w; da.tie_tol = I->tie;
-    da.forced = I->force_pending ? I->forced : nullptr;
-    da.xchg = I->deim_work; da.xcount = I->deim_count; da.launch_seq = dlr::next_sweep_launch_id();
-    da.seq_ctr = I->device_si ? I->deim_ctr : nullptr; da.sel = I->sel; da.cw = I->cw; da.C0 = I->C0; da.a0 = I->a0; da.margins = I->margins;
-    da.sel_mu = I->sel_mu; da.sel_eta = I->sel_eta; da.inflow_x = I->inflow_x; da.inflow_y = I->inflow_y;
-    da.mu = I->mu; da.eta = I->eta;
-    for (int k = 0; k < 4; ++k) da.psib[k] = I->psib[k];
-    da.status = I->status;
-    dlr::launch_deim(s, da);
-    I->force_pending = false;
-    if (I->dsa) dlr::launch_dsa_kappa(s, r, I->cw, I->sel_mu, I->sel_eta, I->dsa_kappa);
+    if (!queued || I->force_pending) launch_selection(I, s, I->sel);
     if (fork) hip_check(hipStreamWaitEvent(s, I->ev_join, 0), "wait");
     // 3. old solution at the selected ordinates -> fixed source; SI start phi = X S beta
     dlr::launch_psi0<TS>(s, I->nx, I->ny, r, I->X, I->C0, I->a0, I->q, I->sig_s, 1.0 / cdt, I->sel_mu, I->sel_eta,
@@ -974,11 +993,16 @@ dlr_status step_once(dlr_instance* I) {
     if (!ended_a) phase_end_a<TS>(I);
     phase_end_b<TS>(I);
     step_publish(I);
-    // The next step's linearisation (step 1 on the new temperature) behind the statistics: it runs while
-    // the host reads them.  Loading new factors and temperature clears it.
+    // The next step's start behind the statistics: the statistics event starts it, and its
+    // linearisation (step 1 on the new temperature) and selection (step 2 on the new W and S, picks
+    // into sel_alt: sel keeps this step's for read-back) run while the host reads them.  Loading new
+    // factors and temperature or switching DSA on makes the next step do its part again, and a forced
+    // selection its selection.
     hip_check(hipEventRecord(I->ev_pub, I->stream), "event");
     launch_linearize(I, I->stream);
     I->lin_ready = true;
+    launch_selection(I, I->stream, I->sel_alt);
+    I->deim_ready = true;
     const dlr_status st = step_read(I, true, I->ev_pub);
     I->si_last = I->si_it;
     return st;
@@ -1531,7 +1555,7 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
         hip_check(hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming), "event create");
         hip_check(hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming), "event create");
         for (auto& ev : I->ev_si) hip_check(hipEventCreate(&ev), "event create");
-        hip_check(hipEventCreateWithFlags(&I->ev_pub, hipEventDisableTiming), "event create");
+        hip_check(hipEventCreate(&I->ev_pub), "event create");
         hip_check(hipEventCreateWithFlags(&I->ev_siq, hipEventDisableTiming), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
@@ -1831,7 +1855,8 @@ dlr_status dlr_load_factors(dlr_handle h, const double* Xi, const double* Si, co
         upload(h->S, Si, R * R * sizeof(double));
         upload(h->W, W.data(), W.size() * sizeof(double));
         upload(h->T, to_cm(Ti, h->nx, h->ny).data(), n * sizeof(double));
-        h->lin_ready = false;   // the linearisation queued behind the last step used the old temperature
+        h->lin_ready = false;   // the linearisation and selection queued behind the last step used the old state
+        h->deim_ready = false;
         h->si_last = 0;
         reset_basis_factor(h);
         refresh_phi(h);
@@ -1956,6 +1981,7 @@ dlr_status dlr_set_dsa(dlr_handle h, int32_t enable, double cg_tol, int32_t cg_m
     h->dsa = true;
     h->dsa_tol = cg_tol;
     h->dsa_max_iter = cg_max_iter;
+    h->deim_ready = false;   // a selection queued without DSA lacks the DSA coefficients of its picks
     return DLR_OK;
 }
 
