@@ -124,7 +124,9 @@ typedef struct {
     double sum_abs_cw_over_4pi;   /* sum |c_d| / (4 pi) of the DEIM quadrature weights */
     double energy;                /* sum over cells of area * (rho c_v T + phi / c) */
     double sweep_ms;              /* device time in the sweep kernels of the last step */
-    double step_ms;               /* device time of the whole last step */
+    double step_ms;               /* device time of the whole last step; from the second step on from the
+                                     previous step's statistics, behind which this step's linearisation and
+                                     angle selection were queued */
     int32_t svd_sweeps;           /* Jacobi sweeps of the last step's SVD of S (0 for plain SN) */
     int32_t reserved;
     /* Energy balance of the step (Sec. 2 time-discrete balance, Algorithm 1 step 9).  Powers
