@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <deque>
 #include <map>
 #include <tuple>
@@ -128,7 +130,7 @@ struct Arena {
 
 constexpr int kPinnedNorm = 4;                                     // SI norm words
 constexpr int kPinnedDoubles = kPinnedNorm + 2 + 2 * dlr::kMaxRank;   // + energy, outflow, margins, weights
-constexpr int kPinnedInts = 8;   // status words [0, 4), source-iteration control words [4, 7)
+constexpr int kPinnedInts = 8;   // status words [0, 4), source-iteration control words [4, 7), publish number [7]
 constexpr int kSiSpec = 6;       // source iterations queued at once before the host looks (at most)
 
 struct dlr_instance {
@@ -236,8 +238,7 @@ struct dlr_instance {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_si[3 * kSiSpec] = {};   // queued source iterations: sweep starts, sweep ends, flux ends
-    hipEvent_t ev_pub = nullptr;          // behind a step's statistics (and the next step's start)
-    hipEvent_t ev_siq = nullptr;          // behind the queued source iterations' control words
+    unsigned pub_seq = 0;                 // number of the last publish the host waits for by polling
     // launch shapes
     int nb_cells = 256, nb_phi = 1024, nb_gram = 512, nb_gram_ang = 32, nb_proj = 512, red_blocks = 64;
 
@@ -409,14 +410,36 @@ dlr_status validate(const dlr_problem* p, bool sn = false) {
 template <typename TS>
 dlr_status step_once(dlr_instance* I);
 
-// published: a launch_publish of the four status words is already queued on the stream (then `after`,
-// if given, is an event recorded behind it, and the host waits for that instead of the whole stream)
-dlr_status check_device_status(dlr_instance* I, bool published = false, hipEvent_t after = nullptr) {
+// The host waits for a publish by polling the number it writes last (after every value it publishes
+// is visible): no event on the stream, whose marker would leave the GPU idle for a few microseconds
+// between the kernels around it.  After 50 ms of polling the wait becomes a stream synchronisation,
+// which also reports a device error that kept the publish from running.
+unsigned next_publish(dlr_instance* I) {
+    if (++I->pub_seq == 0) I->pub_seq = 1;
+    return I->pub_seq;
+}
+void wait_published(dlr_instance* I, unsigned seq) {
+    const volatile unsigned* word = reinterpret_cast<const volatile unsigned*>(I->h_status + 7);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned n = 1; *word != seq; ++n) {
+        __builtin_ia32_pause();
+        if ((n & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+            hip_check(hipStreamSynchronize(I->stream), "stream sync");
+            if (*word != seq) throw std::runtime_error("a publish did not arrive although its stream has drained");
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+}
+
+// published: a launch_publish of the four status words is already queued on the stream (then `seq`, if
+// not 0, is its number, and the host waits for that instead of the whole stream)
+dlr_status check_device_status(dlr_instance* I, bool published = false, unsigned seq = 0) {
     if (!published)
         hip_check(hipMemcpyAsync(I->h_status, I->status, 4 * sizeof(int), hipMemcpyDeviceToHost, I->stream),
                   "status copy");
-    if (published && after)
-        hip_check(hipEventSynchronize(after), "event sync");
+    if (published && seq)
+        wait_published(I, seq);
     else
         hip_check(hipStreamSynchronize(I->stream), "stream sync");
     const int st = *I->h_status;
@@ -440,15 +463,20 @@ dlr_status check_device_status(dlr_instance* I, bool published = false, hipEvent
 // Queue the copies of (up to three) runs of doubles into the pinned area from word `at`, and of the
 // first `nstatus` status words, as one kernel.
 void publish(dlr_instance* I, hipStream_t s, int at, const double* a, int na, const double* b, int nb, const double* c,
-             int nc, int nstatus) {
+             int nc, int nstatus, unsigned seq = 0) {
     dlr::PublishArgs p{};
     p.src[0] = a; p.n[0] = a ? na : 0;
     p.src[1] = b; p.n[1] = b ? nb : 0;
     p.src[2] = c; p.n[2] = c ? nc : 0;
     p.dst = I->d_h_norm + at;
     p.status = I->status; p.nstatus = nstatus; p.dst_status = I->d_h_status;
+    if (seq) {
+        p.seq_dst = reinterpret_cast<unsigned*>(I->d_h_status + 7);
+        p.seq = seq;
+    }
     dlr::launch_publish(s, p);
 }
+
 
 // The sweep record of an instance (fixed for its life; DEIM rewrites the pointed-to direction data).
 template <typename TS>
@@ -558,7 +586,7 @@ void phase_begin(dlr_instance* I) {
     const bool queued = I->deim_ready;
     I->deim_ready = false;
     if (queued) {
-        std::swap(I->ev[0], I->ev_pub);   // the last step's statistics event starts this step
+        std::swap(I->ev[0], I->ev[1]);    // the last step's end event starts this step
         std::swap(I->sel, I->sel_alt);    // the queued selection's picks
     } else if (!I->capturing) {
         hip_check(hipEventRecord(I->ev[0], s), "event");
@@ -838,15 +866,15 @@ void phase_end(dlr_instance* I) {
 
 // energy, DEIM margins and weights into pinned memory behind the step; the status check's
 // stream synchronisation completes them (one host round trip per step)
-void step_publish(dlr_instance* I) {
-    publish(I, I->stream, kPinnedNorm, I->energy_out, 2, I->margins, I->r, I->cw, I->r, 4);
+void step_publish(dlr_instance* I, unsigned seq = 0) {
+    publish(I, I->stream, kPinnedNorm, I->energy_out, 2, I->margins, I->r, I->cw, I->r, 4, seq);
 }
 
 // After the stream has passed step_publish.
-dlr_status step_read(dlr_instance* I, bool timed_sweeps, hipEvent_t after = nullptr) {
+dlr_status step_read(dlr_instance* I, bool timed_sweeps, unsigned seq = 0) {
     const int r = I->r;
     double* hf = I->h_norm + kPinnedNorm;
-    const dlr_status st = check_device_status(I, true, after);
+    const dlr_status st = check_device_status(I, true, seq);
     if (st != DLR_OK) return st;
     const double en = hf[0];
     I->stats.outflow = hf[1];
@@ -854,7 +882,10 @@ dlr_status step_read(dlr_instance* I, bool timed_sweeps, hipEvent_t after = null
     I->stats.source = I->source_power;
     const std::vector<double> marg(hf + 2, hf + 2 + r), cwv(hf + 2 + r, hf + 2 + 2 * r);
     float step_ms = 0.f;   // graph-recorded steps are not timed per instance
-    if (!I->device_si && !I->untimed) hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
+    if (!I->device_si && !I->untimed) {
+        if (seq) hip_check(hipEventSynchronize(I->ev[1]), "sync");   // ahead of the publish: done already
+        hip_check(hipEventElapsedTime(&step_ms, I->ev[0], I->ev[1]), "elapsed");
+    }
     I->stats.si_iters = I->si_it;
     I->stats.energy = en;
     I->stats.deim_min_margin = *std::min_element(marg.begin(), marg.end());
@@ -919,10 +950,13 @@ dlr_status si_queue(dlr_instance* I, int K, bool ahead) {
     pa.dst = I->d_h_norm;
     pa.status = I->status; pa.nstatus = 1; pa.dst_status = I->d_h_status;
     pa.isrc = I->si_flag; pa.ni = 3; pa.idst = I->d_h_status + 4;
+    const unsigned seq = next_publish(I);
+    pa.seq_dst = reinterpret_cast<unsigned*>(I->d_h_status + 7);
+    pa.seq = seq;
     dlr::launch_publish(s, pa);
-    hip_check(hipEventRecord(I->ev_siq, s), "event");
     if (ahead) phase_end_a<TS>(I);
-    hip_check(hipEventSynchronize(I->ev_siq), "sync");
+    wait_published(I, seq);
+    hip_check(hipEventSynchronize(I->ev_si[en[K - 1]]), "sync");   // ahead of the publish: done already
     const int* f = I->h_status + 4;   // stopped, iterations run, why (1 converged, 2 non-finite, 3 limit)
     const int ran = f[1];
     if (ran < 1 || ran > K) {
@@ -992,18 +1026,18 @@ dlr_status step_once(dlr_instance* I) {
     // the DEIM status was checked with the last source iteration's status word (copied after it)
     if (!ended_a) phase_end_a<TS>(I);
     phase_end_b<TS>(I);
-    step_publish(I);
-    // The next step's start behind the statistics: the statistics event starts it, and its
+    const unsigned seq = next_publish(I);
+    step_publish(I, seq);
+    // The next step's start behind the statistics: this step's end event starts it, and its
     // linearisation (step 1 on the new temperature) and selection (step 2 on the new W and S, picks
     // into sel_alt: sel keeps this step's for read-back) run while the host reads them.  Loading new
     // factors and temperature or switching DSA on makes the next step do its part again, and a forced
     // selection its selection.
-    hip_check(hipEventRecord(I->ev_pub, I->stream), "event");
     launch_linearize(I, I->stream);
     I->lin_ready = true;
     launch_selection(I, I->stream, I->sel_alt);
     I->deim_ready = true;
-    const dlr_status st = step_read(I, true, I->ev_pub);
+    const dlr_status st = step_read(I, true, seq);
     I->si_last = I->si_it;
     return st;
 }
@@ -1550,13 +1584,12 @@ dlr_status create_dlr(const dlr_problem* p, void* hip_stream, dlr_handle* out, b
         hip_check(hipHostMalloc((void**)&I->h_status, kPinnedInts * sizeof(int), hipHostMallocDefault), "pinned");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_norm, I->h_norm, 0), "pinned mapping");
         hip_check(hipHostGetDevicePointer((void**)&I->d_h_status, I->h_status, 0), "pinned mapping");
+        std::memset(I->h_status, 0, kPinnedInts * sizeof(int));
         for (auto& ev : I->ev) hip_check(hipEventCreate(&ev), "event create");
         hip_check(hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking), "side stream");
         hip_check(hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming), "event create");
         hip_check(hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming), "event create");
         for (auto& ev : I->ev_si) hip_check(hipEventCreate(&ev), "event create");
-        hip_check(hipEventCreate(&I->ev_pub), "event create");
-        hip_check(hipEventCreateWithFlags(&I->ev_siq, hipEventDisableTiming), "event create");
         const size_t n = I->N;
         upload(I->mu, I->h_mu.data(), I->nq * sizeof(double));
         upload(I->eta, I->h_eta.data(), I->nq * sizeof(double));
@@ -1913,8 +1946,6 @@ dlr_status dlr_destroy(dlr_handle h) {
     }
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-    if (h->ev_pub) (void)hipEventDestroy(h->ev_pub);
-    if (h->ev_siq) (void)hipEventDestroy(h->ev_siq);
     for (auto& ev : h->ev_si)
         if (ev) (void)hipEventDestroy(ev);
     for (auto& ev : h->ev)

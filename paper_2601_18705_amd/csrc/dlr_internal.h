@@ -352,6 +352,8 @@ struct PublishArgs {
     const int* isrc;   // optional: ni more ints to idst
     int ni;
     int* idst;
+    unsigned* seq_dst;   // optional: seq written last, after every other value is visible to the host
+    unsigned seq;
 };
 void launch_publish(hipStream_t s, const PublishArgs& a);
 // For n instances: their source-iteration control words flag[0..2], status word and last relative

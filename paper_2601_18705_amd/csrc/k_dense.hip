@@ -1230,6 +1230,10 @@ __global__ __launch_bounds__(256) void k_publish(PublishArgs a) {
     for (int i = threadIdx.x; i < a.ni; i += blockDim.x)
         __hip_atomic_store(a.idst + i, a.isrc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
+    if (a.seq_dst) {   // every thread's values are fenced before the barrier; the word the host polls comes last
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(a.seq_dst, a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 }  // namespace
